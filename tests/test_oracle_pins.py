@@ -1,0 +1,458 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics (closed forms, invariants, exact reproduction, brute force).
+
+None of these tests re-types the oracle's own formulas: each checks a
+property that a dropped term, a wrong sign or index, or a transposed operand
+in the oracle would violate.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import assemble as asm
+from oracle.direct import solve_stokes, solve_viscous, stokes_matrix
+from oracle.legendre import gauss, legendre_derivs, legendre_values
+from oracle.mesh import DIRICHLET, NAVIER, NEUMANN, Mesh
+from oracle.multigrid import (BlockJacobi, Hierarchy, StokesSolver,
+                              ViscousSolver, arnoldi_lambda_max, chebyshev,
+                              fgmres, h_prolongation, p_cd, p_prolongation)
+from oracle.rng import splitmix64, splitmix64_scalar
+from paper_1607_03777_amd import inputs as gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def modal_of(func, m: Mesh):
+    return gen.project_modal(func, m.nx, m.ny, m.k, m.lx, m.ly).reshape(-1)
+
+
+# --------------------------------------------------------------------- P1 --
+def test_legendre_closed_forms():
+    """Legendre orthogonality, end values L_i(+-1) = (+-1)^i and
+    L_i'(+-1) = (+-1)^(i+1) i(i+1)/2; values equal numpy's legval."""
+    nmax = 8
+    g, w = gauss(12)
+    L = legendre_values(nmax, g)
+    M = (L * w) @ L.T
+    assert np.allclose(M, np.diag(2.0 / (2 * np.arange(nmax + 1) + 1)), atol=1e-14)
+    for s in (-1.0, 1.0):
+        v = legendre_values(nmax, np.array([s]))[:, 0]
+        d = legendre_derivs(nmax, np.array([s]))[:, 0]
+        for i in range(nmax + 1):
+            assert v[i] == pytest.approx(s ** i, abs=1e-14)
+            assert d[i] == pytest.approx(s ** (i + 1) * i * (i + 1) / 2, abs=1e-12)
+    x = np.linspace(-1, 1, 7)
+    for i in range(nmax + 1):
+        c = np.zeros(i + 1)
+        c[i] = 1
+        assert np.allclose(legendre_values(nmax, x)[i],
+                           np.polynomial.legendre.legval(x, c), atol=1e-14)
+        assert np.allclose(legendre_derivs(nmax, x)[i],
+                           np.polynomial.legendre.legval(x, np.polynomial.legendre.legder(c)),
+                           atol=1e-12)
+
+
+def test_splitmix64_golden():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    out = splitmix64(0, len(rows))
+    for idx, hx in rows:
+        assert int(out[int(idx)]) == int(hx, 16)
+        assert splitmix64_scalar(0, int(idx)) == int(hx, 16)
+
+
+def test_paper_parameters_golden():
+    """The oracle's defaults are the values the paper prints."""
+    p = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))
+    assert asm.PENALTY_NF == p["penalty_nF"]["value"]
+    m = Mesh(2, 2, 3)
+    eta = np.array([1.0, 2.0, 3.0, 5.0])
+    fd = asm.face_data(m, eta)
+    mm, pp, etaf, sig = fd[0]
+    C = (m.k + 1) ** 2 / m.hx
+    assert np.allclose(sig, 4 * np.maximum(eta[mm], eta[pp]) * C)
+    for side, e, fi, kind, etb, sg in fd["boundary"]:
+        assert sg == pytest.approx(4 * 2 * eta[e] * (m.k + 1) ** 2 / m.hx)
+    import inspect
+    sig_h = inspect.signature(Hierarchy.__init__).parameters
+    assert sig_h["lo"].default == p["chebyshev_lo"]["value"]
+    assert sig_h["hi"].default == p["chebyshev_hi"]["value"]
+    assert sig_h["eig_steps"].default == p["eig_gmres_steps"]["value"]
+    assert sig_h["smooth_dg"].default == p["smooth_p_level"]["value"]
+    assert sig_h["smooth_h"].default == p["smooth_h_level"]["value"]
+
+
+# --------------------------------------------------------------------- P2 --
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_rigid_motions_in_kernel_all_neumann(k):
+    """eps(r) = 0 and r has no jumps for rigid motions, so A r = 0 for any
+    viscosity when no side carries a boundary term."""
+    m = Mesh(3, 4, k, bc=(NEUMANN,) * 4)
+    rng = np.random.default_rng(k)
+    eta = 10 ** rng.uniform(-3, 3, m.nel)
+    A = asm.assemble_A(m, eta)
+    scale = np.abs(A.data).max()
+    for fn in [lambda x, y: (1 + 0 * x, 0 * y), lambda x, y: (0 * x, 1 + 0 * y),
+               lambda x, y: (-y, x)]:
+        r = modal_of(fn, m)
+        assert np.abs(A @ r).max() < 1e-11 * scale * np.abs(r).max()
+    # a non-rigid linear field is not in the kernel
+    r = modal_of(lambda x, y: (x, 0 * y), m)
+    assert np.abs(A @ r).max() > 1e-3 * scale * np.abs(r).max() * 1e-3
+
+
+# --------------------------------------------------------------------- P3 --
+@pytest.mark.parametrize("n,k", [(2, 2), (4, 2), (4, 3), (3, 4)])
+def test_manufactured_stokes_reproduced(n, k):
+    """SIP reproduces a divergence-free u in Q_k^2 with p in Q_{k-1}
+    (consistency of the discretisation, Section 4)."""
+    P = gen.manufactured_stokes(n, k)
+    m = Mesh(n, n, k, bc=P.bc)
+    u, p = solve_stokes(m, P.eta, P.f, P.g, dense=(n <= 4))
+    ue, pe = P.meta["u_exact"], P.meta["p_exact"]
+    assert np.linalg.norm(u - ue) <= 1e-10 * np.linalg.norm(ue)
+    assert np.linalg.norm(p - pe) <= 1e-8 * np.linalg.norm(pe)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_manufactured_viscous_reproduced(k):
+    """A u = F for a non-solenoidal polynomial u in Q_k^2 with
+    f = -div(2 eta eps(u)) and Dirichlet data g = u, piecewise-constant eta
+    is not allowed (flux jumps), so eta is constant 3."""
+    m = Mesh(3, 3, k, bc=(DIRICHLET,) * 4)
+    eta = np.full(m.nel, 3.0)
+    ue = lambda x, y: (x * x * y + 0.5 * y, x * y * y - x)
+    # -div(2 eps(u)) = -(lap u + grad div u); div u = 2xy + 2xy = 4xy
+    # lap u = (2y, 2x); grad div = (4y, 4x)
+    fe = lambda x, y: (-3.0 * 6.0 * y, -3.0 * 6.0 * x)
+    f = gen.project_modal(fe, 3, 3, k)
+    g = gen.project_boundary(ue, 3, 3, k)
+    u = solve_viscous(m, eta, f, g, dense=True)
+    uex = gen.project_modal(ue, 3, 3, k).reshape(-1)
+    assert np.linalg.norm(u - uex) <= 1e-11 * np.linalg.norm(uex)
+
+
+# --------------------------------------------------------------------- P4 --
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_symmetric_positive_definite(k):
+    """A = A^T and A is positive definite at the lower-bound penalty, for
+    element viscosity contrasts up to 1e8 (discrete coercivity lemma)."""
+    n = 3 if k <= 4 else 2
+    rng = np.random.default_rng(10 + k)
+    for bc in [(NAVIER,) * 4, (NAVIER, NEUMANN, NAVIER, NAVIER),
+               (DIRICHLET,) * 4]:
+        m = Mesh(n, n, k, bc=bc)
+        eta = 10 ** rng.uniform(0, 8, m.nel)
+        A = asm.assemble_A(m, eta).toarray()
+        assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+        d = 1.0 / np.sqrt(np.diag(A))
+        As = d[:, None] * A * d[None, :]
+        lam = np.linalg.eigvalsh(As)
+        assert lam.min() > 1e-9, (bc, lam.min())
+
+
+def test_penalty_below_bound_loses_definiteness():
+    """With the penalty far below the bound the form is indefinite: the
+    positivity above depends on the penalty term being present and large."""
+    m = Mesh(3, 3, 3)
+    eta = np.ones(m.nel)
+    A = asm.assemble_A(m, eta, penalty_nf=0.05).toarray()
+    assert np.linalg.eigvalsh(A).min() < 0
+
+
+# --------------------------------------------------------------------- P5 --
+def test_constant_pressure_nullspace():
+    """B^T 1 = 0 without Neumann sides (divergence theorem per element);
+    not so with a Neumann side."""
+    for k in (1, 2, 4):
+        m = Mesh(3, 2, k)
+        B = asm.assemble_B(m)
+        c = asm.pressure_mean_vector(m)
+        assert np.abs(B @ c).max() < 1e-13
+        m2 = Mesh(3, 2, k, bc=(NAVIER, NAVIER, NAVIER, NEUMANN))
+        assert np.abs(asm.assemble_B(m2) @ c).max() > 1e-3
+
+
+def test_divergence_form_on_linear_field():
+    """B^T u = -int div(u) q for a continuous u with u.n = 0 on the
+    boundary: faces drop out.  u = (x(1-x), 0) has div = 1 - 2x."""
+    m = Mesh(4, 4, 2)
+    u = modal_of(lambda x, y: (x * (1 - x), 0 * y), m)
+    q = gen.project_scalar(lambda x, y: -(1 - 2 * x), 4, 4, 2).reshape(-1)
+    B = asm.assemble_B(m)
+    assert np.allclose(B.T @ u, q, atol=1e-13)
+
+
+# --------------------------------------------------------------------- P6 --
+def test_eta_homogeneity_and_mirror():
+    k = 3
+    m = Mesh(4, 3, k)
+    rng = np.random.default_rng(3)
+    eta = 10 ** rng.uniform(-2, 4, m.nel)
+    A = asm.assemble_A(m, eta)
+    A7 = asm.assemble_A(m, 7.0 * eta)
+    assert abs(A7 - 7.0 * A).max() <= 1e-13 * abs(A7).max()
+    # mirror x -> 1 - x: element (ix, iy) -> (nx-1-ix, iy), mode i flips by
+    # (-1)^i, the x component flips sign.
+    k1 = k + 1
+    perm = np.zeros(m.nu, dtype=int)
+    sign = np.zeros(m.nu)
+    for iy in range(m.ny):
+        for ix in range(m.nx):
+            e, e2 = m.elem(ix, iy), m.elem(m.nx - 1 - ix, iy)
+            for d in range(2):
+                for j in range(k1):
+                    for i in range(k1):
+                        a = e * m.nbu + (d * k1 + j) * k1 + i
+                        b = e2 * m.nbu + (d * k1 + j) * k1 + i
+                        perm[b] = a
+                        sign[b] = (-1.0) ** i * (-1.0 if d == 0 else 1.0)
+    eta2 = eta.reshape(m.ny, m.nx)[:, ::-1].ravel()
+    A2 = asm.assemble_A(m, eta2).toarray()
+    Ad = A.toarray()
+    Pm = np.zeros((m.nu, m.nu))
+    Pm[np.arange(m.nu), perm] = sign
+    assert np.abs(Pm @ Ad @ Pm.T - A2).max() <= 1e-12 * np.abs(Ad).max()
+
+
+# --------------------------------------------------------------------- P7 --
+def test_block_jacobi_is_diagonal_of_A():
+    """M_k (eq. smoother, written out separately) = diagonal blocks of A."""
+    for k in (1, 3):
+        m = Mesh(3, 3, k, bc=(NAVIER, NEUMANN, DIRICHLET, NAVIER))
+        rng = np.random.default_rng(k)
+        eta = 10 ** rng.uniform(-3, 3, m.nel)
+        A = asm.assemble_A(m, eta).toarray()
+        Mf = asm.smoother_blocks_from_form(m, eta)
+        nb = m.nbu
+        for e in range(m.nel):
+            blk = A[e * nb:(e + 1) * nb, e * nb:(e + 1) * nb]
+            assert np.abs(blk - Mf[e]).max() <= 1e-12 * np.abs(blk).max()
+        BJ = BlockJacobi(asm.assemble_A(m, eta), nb)
+        r = rng.normal(size=m.nu)
+        z = BJ(r)
+        for e in range(m.nel):
+            assert np.allclose(Mf[e] @ z[e * nb:(e + 1) * nb], r[e * nb:(e + 1) * nb],
+                               rtol=1e-9, atol=1e-12 * np.abs(r).max())
+
+
+# --------------------------------------------------------------------- P8 --
+def _eval_dg(m: Mesh, u, pts):
+    """Evaluate a modal DG field at physical points (tests only)."""
+    out = []
+    for x, y in pts:
+        ix = min(int(x / m.hx), m.nx - 1)
+        iy = min(int(y / m.hy), m.ny - 1)
+        e = m.elem(ix, iy)
+        xi = 2 * (x - ix * m.hx) / m.hx - 1
+        et = 2 * (y - iy * m.hy) / m.hy - 1
+        val, _ = asm.velocity_basis(m.k, m.hx, m.hy, np.array([xi]), np.array([et]))
+        out.append(np.einsum("a,ac->c", u[e * m.nbu:(e + 1) * m.nbu], val[:, 0, :]))
+    return np.array(out)
+
+
+def test_p_transfer_and_pcd():
+    m = Mesh(3, 2, 4)
+    P = p_prolongation(m)
+    assert abs((P.T @ P) - np.eye(P.shape[1])).max() == 0.0  # R P = I
+    Pcd = p_cd(m)
+    # nodal values of a bilinear-per-element continuous field
+    fn = lambda x, y: (1 + 2 * x - y + 3 * x * y, -x + 0.5 * y * x)
+    nodes = [(jx * m.hx, jy * m.hy) for jy in range(m.ny + 1) for jx in range(m.nx + 1)]
+    v = np.array([fn(x, y) for x, y in nodes]).ravel()  # interleaved d
+    u = P @ (Pcd @ v)
+    pts = np.random.default_rng(0).uniform(0, 1, (20, 2)) * [m.lx, m.ly]
+    assert np.allclose(_eval_dg(m, u, pts), np.array([fn(x, y) for x, y in pts]), atol=1e-13)
+
+
+def _q1_fem(m: Mesh, eta, penalty_k):
+    """Continuous Q1 FEM matrix of 2 eta eps:eps plus the Navier boundary
+    terms with the fine-order penalty, assembled from nodal hat functions
+    (tests only)."""
+    hx, hy = m.hx, m.hy
+    g, w = gauss(3)
+    nn = (m.nx + 1) * (m.ny + 1)
+    K = np.zeros((2 * nn, 2 * nn))
+
+    def hats(xi, et):
+        v = np.array([(1 - xi) * (1 - et), (1 + xi) * (1 - et), (1 - xi) * (1 + et),
+                      (1 + xi) * (1 + et)]) / 4
+        dx = np.array([-(1 - et), (1 - et), -(1 + et), (1 + et)]) / 4 * (2 / hx)
+        dy = np.array([-(1 - xi), -(1 + xi), (1 - xi), (1 + xi)]) / 4 * (2 / hy)
+        return v, dx, dy
+
+    for iy in range(m.ny):
+        for ix in range(m.nx):
+            e = m.elem(ix, iy)
+            gl = [(iy + b) * (m.nx + 1) + ix + a for b in range(2) for a in range(2)]
+            for qa, wa in zip(g, w):
+                for qb, wb in zip(g, w):
+                    v, dx, dy = hats(qa, qb)
+                    W = wa * wb * hx * hy / 4
+                    for a in range(4):
+                        for c in range(2):
+                            ga = np.zeros((2, 2))
+                            ga[c] = [dx[a], dy[a]]
+                            ea = (ga + ga.T) / 2
+                            for b in range(4):
+                                for d in range(2):
+                                    gb = np.zeros((2, 2))
+                                    gb[d] = [dx[b], dy[b]]
+                                    eb = (gb + gb.T) / 2
+                                    K[2 * gl[a] + c, 2 * gl[b] + d] += W * 2 * eta[e] * np.sum(ea * eb)
+    return K
+
+
+def test_coarse_dg_to_cg_operator_is_q1_fem():
+    """For continuous Q1 fields all interior-face terms vanish (no jumps), so
+    A_{1,c} = P_cd^T A_1 P_cd is the continuous Q1 operator; with Neumann
+    sides that is plain Q1 FEM, which also kills rigid motions."""
+    m = Mesh(3, 3, 3, bc=(NEUMANN,) * 4)
+    rng = np.random.default_rng(5)
+    eta = 10 ** rng.uniform(-2, 2, m.nel)
+    A = asm.assemble_A(m, eta).tocsr()
+    P = p_prolongation(m)
+    Pcd = p_cd(m)
+    A1c = (Pcd.T @ (P.T @ A @ P) @ Pcd).toarray()
+    K = _q1_fem(m, eta, m.k)
+    assert np.abs(A1c - K).max() <= 1e-11 * np.abs(K).max()
+
+
+def test_h_prolongation_exact_on_bilinear():
+    P = h_prolongation(2, 3)
+    fn = lambda x, y: (1 + x + 2 * y + 0.5 * x * y, 3 - y + x * y)
+    c = np.array([fn(jx / 2, jy / 3) for jy in range(4) for jx in range(3)]).ravel()
+    f = np.array([fn(jx / 4, jy / 6) for jy in range(7) for jx in range(5)]).ravel()
+    assert np.allclose(P @ c, f, atol=1e-14)
+
+
+# ------------------------------------------------------------------- P10 --
+def test_vcycle_symmetric_positive():
+    P = gen.single_inclusion(16, 2, eta_in=1e3)
+    m = Mesh(16, 16, 2)
+    H = Hierarchy(m, P.eta, coarsest_n=4)
+    assert len(H.levels) == 3
+    rng = np.random.default_rng(1)
+    v, w = rng.normal(size=m.nu), rng.normal(size=m.nu)
+    a, b = w @ H.vcycle(v), v @ H.vcycle(w)
+    assert abs(a - b) <= 1e-9 * abs(a)
+    for _ in range(3):
+        x = rng.normal(size=m.nu)
+        assert x @ H.vcycle(x) > 0
+
+
+def test_arnoldi_estimate_bounds_true_spectrum():
+    """Ritz values lie inside the spectrum: lambda* <= lambda_max(M^-1 A),
+    and ten steps get close to it."""
+    m = Mesh(4, 4, 2)
+    rng = np.random.default_rng(2)
+    eta = 10 ** rng.uniform(0, 2, m.nel)
+    A = asm.assemble_A(m, eta)
+    M = BlockJacobi(A, m.nbu)
+    lam, H = arnoldi_lambda_max(A.tocsr(), M, 0, 0)
+    Mb = sla.block_diag(*M.blocks)
+    ev = sla.eigh(A.toarray(), Mb, eigvals_only=True)
+    assert lam <= ev.max() * (1 + 1e-10)
+    assert lam >= 0.9 * ev.max()
+
+
+def test_chebyshev_error_bound():
+    """With exact spectral bounds the Chebyshev error contracts at least by
+    1/T_m((l1+l0)/(l1-l0)) in the A-norm (textbook bound)."""
+    m = Mesh(3, 3, 2)
+    rng = np.random.default_rng(4)
+    eta = 10 ** rng.uniform(0, 1, m.nel)
+    A = asm.assemble_A(m, eta)
+    M = BlockJacobi(A, m.nbu)
+    ev = sla.eigh(A.toarray(), sla.block_diag(*M.blocks), eigvals_only=True)
+    l0, l1 = ev.min(), ev.max()
+    Ad = A.toarray()
+    xs = rng.normal(size=m.nu)
+    b = Ad @ xs
+    for mm in (1, 2, 3, 5):
+        x = chebyshev(Ad, M, b, np.zeros(m.nu), l0, l1, mm, x_is_zero=True)
+        e = x - xs
+        ratio = np.sqrt(e @ Ad @ e) / np.sqrt(xs @ Ad @ xs)
+        bound = 1.0 / np.cosh(mm * np.arccosh((l1 + l0) / (l1 - l0)))
+        assert ratio <= bound * (1 + 1e-8)
+
+
+# ------------------------------------------------------------------- P11 --
+def test_exact_block_preconditioner_two_iterations():
+    """Exact A^-1 and S = B^T A^-1 B in the upper block-triangular
+    preconditioner: FGMRES converges in at most two iterations (Section 5)."""
+    m = Mesh(3, 3, 2, bc=(NAVIER, NAVIER, NAVIER, NEUMANN))
+    rng = np.random.default_rng(6)
+    eta = 10 ** rng.uniform(0, 3, m.nel)
+    A = asm.assemble_A(m, eta).toarray()
+    B = asm.assemble_B(m).toarray()
+    S = B.T @ np.linalg.solve(A, B)
+    K = np.block([[A, B], [B.T, np.zeros((m.np_, m.np_))]])
+    nu = m.nu
+
+    def prec(x):
+        yp = np.linalg.solve(S, x[nu:])
+        return np.concatenate([np.linalg.solve(A, x[:nu] - B @ yp), yp])
+
+    b = rng.normal(size=nu + m.np_)
+    # exact arithmetic: zero residual after two steps; in FP64 the residual
+    # after two steps is at rounding level times the conditioning
+    x, its, hist = fgmres(lambda v: K @ v, b, prec, 1e-8, 30, 10)
+    assert its <= 2
+    assert hist[1] > 1e-3  # one step is not enough
+    assert np.linalg.norm(K @ x - b) <= 1e-8 * np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------- P12 --
+def test_iterative_matches_direct_viscous():
+    P = gen.single_inclusion(16, 3, eta_in=1e4)
+    m = Mesh(16, 16, 3)
+    ud = solve_viscous(m, P.eta, P.f)
+    S = ViscousSolver(m, P.eta, coarsest_n=4)
+    F, _ = asm.assemble_rhs(m, P.eta, P.f)
+    u, its, hist = S.solve(F, rtol=1e-12)
+    assert np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
+
+
+def test_iterative_matches_direct_stokes():
+    P = gen.single_inclusion(8, 2, eta_in=1e2)
+    m = Mesh(8, 8, 2)
+    ud, pd = solve_stokes(m, P.eta, P.f)
+    S = StokesSolver(m, P.eta, coarsest_n=4, inner_rtol=1e-6)
+    F, G = asm.assemble_rhs(m, P.eta, P.f)
+    u, p, its, _ = S.solve(F, G, rtol=1e-13, maxit=400)
+    assert np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
+    assert np.linalg.norm(p - pd) <= 1e-7 * np.linalg.norm(pd)
+
+
+# ------------------------------------------------------------------- P13 --
+@pytest.mark.slow
+def test_convergence_order_navier():
+    """Smooth free-slip solution u = (sin pi x cos pi y, -cos pi x sin pi y),
+    p = cos pi x cos pi y, eta = 1: L2 velocity error O(h^{k+1}), pressure
+    O(h^k) (the orders observed in the paper's SolCx table)."""
+    pi = np.pi
+    ue = lambda x, y: (np.sin(pi * x) * np.cos(pi * y), -np.cos(pi * x) * np.sin(pi * y))
+    pe = lambda x, y: np.cos(pi * x) * np.cos(pi * y)
+    fe = lambda x, y: (2 * pi * pi * np.sin(pi * x) * np.cos(pi * y) - pi * np.sin(pi * x) * np.cos(pi * y),
+                       -2 * pi * pi * np.cos(pi * x) * np.sin(pi * y) - pi * np.cos(pi * x) * np.sin(pi * y))
+    for k in (1, 2):
+        eu, ep = [], []
+        for n in (4, 8):
+            m = Mesh(n, n, k)
+            f = gen.project_modal(fe, n, n, k)
+            u, p = solve_stokes(m, np.ones(n * n), f)
+            uex = gen.project_modal(ue, n, n, k, nq=k + 8).reshape(-1)
+            pex = gen.project_scalar(pe, n, n, k, nq=k + 8).reshape(-1)
+            pex = pex - (asm.pressure_mean_vector(m) @ pex) / (m.lx * m.ly) * asm.pressure_mean_vector(m)
+            # projection error is of the same order as the discretisation error
+            eu.append(np.linalg.norm(u - uex))
+            ep.append(np.linalg.norm(p - pex))
+        ru = np.log2(eu[0] / eu[1])
+        rp = np.log2(ep[0] / ep[1])
+        assert ru > k + 1 - 0.35, (k, ru)
+        assert rp > k - 0.35, (k, rp)
