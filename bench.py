@@ -1,0 +1,210 @@
+"""Benchmark: Stokes solves/s of the SIP-DG block-preconditioned solver on one
+MI355X, with the SIP viscous operator throughput, solve latency, a roofline
+figure for the dominant kernel and the FP64 CPU oracle as baseline.
+
+Workload (one step): the 64 x 64 element, Q_4^2-Q_3 single-inclusion Stokes
+problem (disk radius 0.25 centred, viscosity 1e4 inside, 1 outside, body
+force (0, -1) on elements fully inside, free slip on all sides), set up and
+solved to a relative residual of 1e-8 with right-preconditioned FGMRES, the
+upper block-triangular preconditioner and inner CG (rtol 1e-3) with the
+hp-multilevel preconditioner.  Inputs (viscosity, modal force) are resident
+in HBM before the timed region; setup is inside the step.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, K, ETA_IN = 64, 4, 1e4
+RTOL = 1e-8
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_time_us(torch, fn, reps):
+    """Average duration of one launch, HIP events on the current stream."""
+    for _ in range(5):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    t1.synchronize()
+    return t0.elapsed_time(t1) * 1e3 / reps
+
+
+def cpu_baseline(prob_in, gpu_outer_its, budget_s=25.0):
+    """Oracle (plain FP64 numpy/scipy) on a bounded sample: its setup plus
+    two outer FGMRES iterations of the same Stokes solve, scaled to one whole
+    solve with the outer-iteration count the GPU needed."""
+    import oracle.assemble as asm
+    from oracle.mesh import Mesh
+    from oracle.multigrid import StokesSolver, fgmres
+
+    from threadpoolctl import threadpool_limits
+
+    m = Mesh(N, N, K)
+    limits = threadpool_limits(1)
+    t0 = time.perf_counter()
+    S = StokesSolver(m, prob_in.eta, inner_rtol=1e-3)
+    F, G = asm.assemble_rhs(m, prob_in.eta, prob_in.f)
+    t_setup = time.perf_counter() - t0
+    sample_its = 2
+    t1 = time.perf_counter()
+    fgmres(S.matvec, np.concatenate([F, G]), S.prec, 1e-30, restart=30, maxit=sample_its,
+           project=S.project)
+    t_it = (time.perf_counter() - t1) / sample_its
+    limits.unregister()
+    t_solve = t_setup + t_it * gpu_outer_its
+    return {
+        "value": 1.0 / t_solve, "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle setup ({t_setup:.1f}s) + {sample_its} outer FGMRES iterations "
+                   f"({t_it:.1f}s each, inner CG rtol 1e-3) of the same 64x64 Q4 inclusion "
+                   f"Stokes solve, scaled to the {gpu_outer_its} outer iterations of one solve"),
+        "setup_s": t_setup, "s_per_outer_it": t_it,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver library runs each problem on a single "
+              "MI355X (multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1607_03777_amd import inputs as gen
+    from paper_1607_03777_amd import sdg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ctx = sdg.sdg_create(0, 0)
+    P0 = gen.single_inclusion(N, K, eta_in=ETA_IN)
+    nel = N * N
+    nb = 2 * (K + 1) ** 2
+    nu, npr = nel * nb, nel * K * K
+    eta = torch.as_tensor(P0.eta, device="cuda")
+    f = torch.as_tensor(P0.f.reshape(-1), device="cuda")
+    u = torch.zeros(nu, dtype=torch.float64, device="cuda")
+    p = torch.zeros(npr, dtype=torch.float64, device="cuda")
+    mesh = sdg.make_mesh(N, N, K)
+    opts = sdg.make_options(rtol=RTOL, inner_rtol=1e-3, max_it=2000)
+    stream = sdg.current_stream()
+
+    def step():
+        h = sdg.sdg_problem_create(ctx, mesh, opts, eta, stream)
+        rc, st = sdg.sdg_solve_stokes_dev(h, f, None, u, p)
+        sdg.sdg_problem_destroy(h)
+        return st
+
+    log(f"[bench] warmup {args.warmup} steps")
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup step {i}: status={st['status']} outer={st['outer_its']} "
+            f"inner={st['inner_its_total']} solve_ms={st['solve_ms']:.1f}")
+    torch.cuda.synchronize()
+    lat = []
+    stats = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        st = step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        stats.append(st)
+        log(f"[bench] step {i}: {lat[-1]:.1f} ms status={st['status']} outer={st['outer_its']} "
+            f"inner={st['inner_its_total']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    st = stats[-1]
+
+    # accuracy of the last solution: true residual with the oracle's matrices
+    import oracle.assemble as asm
+    from oracle.mesh import Mesh
+    m = Mesh(N, N, K)
+    A = asm.assemble_A(m, P0.eta).tocsr()
+    B = asm.assemble_B(m).tocsr()
+    F, G = asm.assemble_rhs(m, P0.eta, P0.f)
+    uh, ph = u.cpu().numpy(), p.cpu().numpy()
+    r = np.concatenate([F - A @ uh - B @ ph, G - B.T @ uh])
+    oracle_res = float(np.linalg.norm(r) / np.linalg.norm(np.concatenate([F, G])))
+    log(f"[bench] oracle true residual of the GPU solution: {oracle_res:.3e}")
+
+    # dominant kernel: the fused SIP residual r = b - A u (FP64, k = 4), as
+    # launched by the Chebyshev smoother; timed on the problem's stream
+    h = sdg.sdg_problem_create(ctx, mesh, opts, eta, stream)
+    uu = torch.randn(nu, dtype=torch.float64, device="cuda")
+    bb = torch.randn(nu, dtype=torch.float64, device="cuda")
+    rr = torch.empty(nu, dtype=torch.float64, device="cuda")
+    yy = torch.empty(nu, dtype=torch.float64, device="cuda")
+    t_res = kernel_time_us(torch, lambda: sdg.sdg_residual_viscous(h, bb, uu, rr), args.kernel_reps)
+    t_app = kernel_time_us(torch, lambda: sdg.sdg_apply_viscous(h, uu, yy), args.kernel_reps)
+    sdg.sdg_problem_destroy(h)
+    bytes_res = nel * (3 * nb * 8 + 8)  # read b, u, eta; write r
+    bytes_app = nel * (2 * nb * 8 + 8)
+    gbs = bytes_res / (t_res * 1e-6) / 1e9
+    log(f"[bench] sip residual {t_res:.2f} us ({gbs:.0f} GB/s), apply {t_app:.2f} us")
+
+    out = {
+        "metric": "SIP viscous DoF/s + Stokes solves/s at 1e-8 resid; p50/p99 solve latency",
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "stokes-inclusion-64x64-Q4Q3-eta1e4-rtol1e-8",
+                   "nx": N, "ny": N, "k": K, "eta_contrast": ETA_IN, "rtol": RTOL,
+                   "inner_rtol": 1e-3, "velocity_dofs": nu, "pressure_dofs": npr,
+                   "setup_in_step": True},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "viscous_dof_per_s": nu * args.steps / elapsed,
+        "sip_apply_dof_per_s": nu / (t_app * 1e-6),
+        "solver": {"outer_its": st["outer_its"], "inner_its_total": st["inner_its_total"],
+                   "inner_its_max": st["inner_its_max"], "rel_residual": st["rel_residual"],
+                   "oracle_rel_residual": oracle_res, "setup_ms": st["setup_ms"],
+                   "solve_ms": st["solve_ms"]},
+        "roofline": {"bound": "hbm", "kernel": "sip_tile_kernel<K1=5,residual,f64>",
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_res, "us_per_launch": t_res},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(P0, st["outer_its"])
+        log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.3e} solves/s")
+    sdg.sdg_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * sdg.h -- C ABI of the MI355X library for the nested viscous-block solve of
+ * the block-preconditioned SIP discontinuous Galerkin Stokes solver
+ * (Charrier, May & Schnepp, "Symmetric interior penalty discontinuous
+ * Galerkin discretisations and block preconditioning for heterogeneous Stokes
+ * flow").
+ *
+ * Problem statement (Sections 2-4): find u in Q_k^2 (discontinuous) and
+ * p in Q_{k-1} on a regular Cartesian grid of the rectangle
+ * [0, lx] x [0, ly] with element-wise constant viscosity eta_K > 0 and body
+ * force f, such that A u + B p = F, B^T u = G (eq. discretestokes), with the
+ * SIP form A_h (eq. stiffness_form) and divergence form B_h
+ * (eq. divergence_form).  Boundary sides carry Navier (free slip), Neumann
+ * or Dirichlet conditions; Dirichlet sides use the symmetric Nitsche/SIP
+ * boundary terms with the Navier-face penalty (an addition to the paper, for
+ * manufactured solutions).
+ *
+ * Coefficient layouts (all arrays are dense, row-major, FP64 unless stated):
+ *   element e = iy*nx + ix;  basis psi_ij = (2/sqrt(hx hy)) lhat_i(xi)
+ *   lhat_j(eta) with lhat_i = sqrt((2i+1)/2) L_i, i.e. L2(K)-orthonormal
+ *   tensor Legendre modes (Section 5: orthogonal Legendre basis, orthonormal
+ *   pressure basis).
+ *   u, f  : [nel][2][k+1][k+1]   (component d, y-mode j, x-mode i)
+ *   p     : [nel][k][k]
+ *   eta   : [nel]
+ *   g     : [2 ny + 2 nx][2][k+1] Dirichlet data per boundary face in the
+ *           face-orthonormal basis sqrt(2/|e|) lhat_m; faces ordered left
+ *           side (iy = 0..ny-1), right side, bottom side (ix = 0..nx-1), top.
+ *   Coarse (continuous Q_1) nodal vectors: [(ny+1)(nx+1)][2], node
+ *   jy*(nx+1) + jx, the two velocity components interleaved.
+ *
+ * Ownership: the caller owns every pointer it passes; the library copies
+ * what it keeps.  "_dev" pointers are device (HBM) pointers valid on the
+ * problem's stream; the others are host pointers.
+ *
+ * Errors: functions return SDG_OK (0), a negative error code, or a positive
+ * soft outcome (SDG_NOT_CONVERGED: the output holds the last iterate).  No
+ * exception crosses this ABI.  sdg_last_error() describes the last failure
+ * of the calling thread.
+ *
+ * Threads: a context and the problems created from it may be used by one
+ * thread at a time.
+ */
+#ifndef SDG_H
+#define SDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SDG_OK 0
+#define SDG_ERR_INVALID (-1)     /* bad argument: eta <= 0 or non-finite, k out of range, NULL, n < 1 */
+#define SDG_ERR_NOMEM (-2)       /* device allocation failed or over the context's memory budget */
+#define SDG_ERR_DEVICE (-3)      /* HIP runtime error */
+#define SDG_ERR_UNSUPPORTED (-4) /* e.g. singular all-Neumann viscous problem */
+#define SDG_NOT_CONVERGED 1      /* iteration limit reached; last iterate returned */
+#define SDG_BREAKDOWN 2          /* Krylov breakdown; last iterate returned */
+
+/* boundary side types, sides ordered left, right, bottom, top */
+#define SDG_NAVIER 0
+#define SDG_NEUMANN 1
+#define SDG_DIRICHLET 2
+
+/* arithmetic of the smoother (block inverses) and the operator apply inside
+ * the multigrid cycle */
+#define SDG_FP64 0
+#define SDG_FP32 1
+#define SDG_BF16 2
+
+#define SDG_KMAX 6
+
+typedef struct sdg_mesh {
+  int32_t nx, ny;  /* elements per direction, >= 1 */
+  double lx, ly;   /* domain size, > 0 */
+  int32_t k;       /* velocity order, 1..SDG_KMAX; pressure order k-1 */
+  int32_t bc[4];   /* SDG_NAVIER / SDG_NEUMANN / SDG_DIRICHLET per side */
+} sdg_mesh;
+
+typedef struct sdg_options {
+  double rtol;            /* outer relative residual (2-norm, x0 = 0) */
+  double inner_rtol;      /* inner CG tolerance of the Stokes preconditioner (Section 8.1: 1e-3) */
+  int32_t max_it;         /* outer iteration limit */
+  int32_t inner_max_it;   /* inner iteration limit */
+  int32_t restart;        /* FGMRES restart length */
+  int32_t smooth_dg;      /* Chebyshev steps before and after on the DG level (Section 8: 2) */
+  int32_t smooth_h;       /* Chebyshev steps on each h-level (Section 8: 3) */
+  int32_t coarsest_n;     /* h-coarsening stops at <= this many elements per direction */
+  int32_t eig_steps;      /* Arnoldi steps for lambda* (Section 6: 10) */
+  double cheb_lo, cheb_hi;/* Chebyshev bounds as fractions of lambda* (Section 6: 0.1, 1.1) */
+  int32_t prec_smoother;  /* SDG_FP64 / SDG_FP32 / SDG_BF16 storage of block inverses */
+  int32_t prec_apply;     /* SDG_FP64 / SDG_FP32: operator apply inside the cycle */
+  int32_t viscous_krylov; /* 0: CG (paper); 1: FGMRES (needed when the cycle is not exactly linear) */
+  int32_t dedup;          /* 1: share block inverses between elements with equal normalised blocks */
+  uint64_t seed;          /* stream of the SplitMix64 start vectors of the eigen-estimates */
+} sdg_options;
+
+typedef struct sdg_stats {
+  int32_t status;          /* return code of the solve */
+  int32_t outer_its;       /* FGMRES (Stokes) or Krylov (viscous) iterations */
+  int32_t inner_its_total; /* inner CG iterations summed (Stokes) */
+  int32_t inner_its_max;
+  double rel_residual;     /* final true relative residual ||b - K x|| / ||b|| in FP64 */
+  double setup_ms, solve_ms;
+} sdg_stats;
+
+typedef struct sdg_ctx sdg_ctx;
+typedef struct sdg_problem sdg_problem;
+
+/* ---- context -------------------------------------------------------------
+ * sdg_create: bind the calling thread to HIP device `device` and create a
+ * context.  mem_budget (bytes) caps the device memory of all problems of the
+ * context (0 = no cap).  */
+int sdg_create(int device, size_t mem_budget, sdg_ctx** out);
+/* Releases the context; if problems created from it are still alive, the
+ * release happens when the last of them is destroyed. */
+void sdg_destroy(sdg_ctx* ctx);
+/* Message describing the last error on the calling thread ("" if none). */
+const char* sdg_last_error(void);
+/* Default options: rtol 1e-8, inner_rtol 1e-3 (Section 8.1), restart 30,
+ * smooth_dg 2, smooth_h 3 (Section 8), coarsest_n 8, eig_steps 10,
+ * cheb 0.1/1.1 (Section 6), FP64 everywhere, CG, dedup on, seed 0. */
+void sdg_options_default(sdg_options* opts);
+/* Device bytes a problem of this size needs (deterministic; used for
+ * admission).  stokes != 0 adds the pressure and FGMRES workspaces. */
+size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes);
+
+/* ---- problem setup (Sections 4 and 6) ---------------------------------------
+ * Copies eta (device pointer, nel values) and performs the setup of the
+ * hp-multilevel preconditioner on the device: face penalties
+ * (eq. eta_face, eq. const_trace_face, eq. sipg_penalty at its lower bound),
+ * element-block Jacobi inverses (eq. smoother; diagonal blocks of A), the
+ * Galerkin coarse operators A_1 and A_{1,c} = P_cd^T A_1 P_cd
+ * (Section 6.1.2), the Galerkin h-hierarchy, the coarsest dense factor and
+ * the Chebyshev bounds (Section 6).  stream is a hipStream_t (NULL = the
+ * null stream); every later call on the problem is ordered on it. */
+int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
+                       const double* eta_dev, void* stream, sdg_problem** out);
+void sdg_problem_destroy(sdg_problem* prob);
+/* Number of multigrid levels (1 DG level + CG-Q_1 h-levels) and the
+ * Chebyshev bounds [lambda_0, lambda_1] per smoothed level (2 doubles per
+ * level; the coarsest CG level is solved directly and has none). */
+int sdg_problem_levels(const sdg_problem* prob, int* nlevels);
+int sdg_get_bounds(const sdg_problem* prob, double* bounds);
+int sdg_set_bounds(sdg_problem* prob, const double* bounds);
+/* Largest Ritz value lambda* of eig_steps Arnoldi steps on M^{-1} A at
+ * level `level` (0 = DG level), started from the SplitMix64 vector of
+ * stream seed + level*2^32 (Section 6: ten GMRES iterations with a random
+ * right-hand side).  Also writes the (steps+1) x steps Hessenberg matrix
+ * column-major into hess (may be NULL). */
+int sdg_eig_estimate(sdg_problem* prob, int level, double* lambda_out, double* hess);
+
+/* ---- operators on device vectors (for parity and composition) -------------
+ * y = A u, A the SIP matrix of eq. (stiffness_form) (FP64). */
+int sdg_apply_viscous(sdg_problem* prob, const double* u_dev, double* y_dev);
+/* r = b - A u (fused residual). */
+int sdg_residual_viscous(sdg_problem* prob, const double* b_dev, const double* u_dev,
+                         double* r_dev);
+/* y = A u with the FP32 kernel used inside the multigrid cycle (float in/out). */
+int sdg_apply_viscous_f32(sdg_problem* prob, const float* u_dev, float* y_dev);
+/* q = B^T u (discrete divergence, eq. divergence_form), q: [nel][k][k]. */
+int sdg_apply_div(sdg_problem* prob, const double* u_dev, double* q_dev);
+/* v = B p (discrete gradient), v: velocity layout. */
+int sdg_apply_grad(sdg_problem* prob, const double* p_dev, double* v_dev);
+/* z = M_k^{-1} r, M_k the element-block Jacobi operator (eq. smoother),
+ * in the precision chosen by opts.prec_smoother (FP64 in/out). */
+int sdg_apply_blockjacobi(sdg_problem* prob, const double* r_dev, double* z_dev);
+/* Dense diagonal blocks of A: blocks [nel][nb][nb], nb = 2(k+1)^2, row =
+ * test mode, column = trial mode (FP64, before inversion). */
+int sdg_get_blocks(sdg_problem* prob, double* blocks_dev);
+/* rc = P_cd^T R_k^1 r (Section 6: truncation to Q_1 modes, then the
+ * transpose of the element-wise nodal-to-modal map, Section 6.1.2). */
+int sdg_p_restrict(sdg_problem* prob, const double* r_dev, double* rc_dev);
+/* u += P_k^1 P_cd ec (prolongation, P = R^T). */
+int sdg_p_prolong_add(sdg_problem* prob, const double* ec_dev, double* u_dev);
+/* Stencil of the coarse operator at h-level `level` (0 = A_{1,c} on the
+ * finest CG grid): [36][nodes] as [(dy+1)*3+(dx+1)][d][c][node] with
+ * (A x)_{node,d} = sum_{dx,dy,c} S[..][d][c][node] x_{node+(dx,dy),c}. */
+int sdg_get_coarse_stencil(sdg_problem* prob, int level, double* stencil_dev,
+                           int* nx_out, int* ny_out);
+/* One application of the hp-multilevel preconditioner (Algorithm 1 with
+ * zero initial guess, the h-cycle as coarse solve): x = B_mg b. */
+int sdg_vcycle(sdg_problem* prob, const double* b_dev, double* x_dev);
+/* Right-hand sides: F = f + Dirichlet lift, G = int q (g.n) on Dirichlet
+ * sides (eq. rhs_f plus the Nitsche terms).  g_dev may be NULL. */
+int sdg_assemble_rhs(sdg_problem* prob, const double* f_dev, const double* g_dev,
+                     double* F_dev, double* G_dev);
+
+/* ---- solves on device arrays ------------------------------------------------
+ * Viscous block: u = A^{-1} F with F assembled from f (and g) by the
+ * hp-multilevel preconditioned Krylov method of Sections 6 and 8, to
+ * opts.rtol.  Blocks the calling thread until done. */
+int sdg_solve_viscous_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
+                          double* u_dev, sdg_stats* stats);
+/* Stokes: right-preconditioned FGMRES on eq. (discretestokes) with the
+ * upper block-triangular preconditioner of eq. (discretestokespc),
+ * S* = diag(1/eta_K) (Section 5) and the inner viscous solve to
+ * opts.inner_rtol; the constant-pressure null space is projected out when
+ * no side is Neumann and p is returned with zero mean. */
+int sdg_solve_stokes_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
+                         double* u_dev, double* p_dev, sdg_stats* stats);
+
+/* ---- one-shot solves on host arrays (copy in, setup, solve, copy out) ------ */
+int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
+                      const double* eta, const double* f, const double* g, double* u,
+                      sdg_stats* stats);
+int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
+                     const double* eta, const double* f, const double* g, double* u,
+                     double* p, sdg_stats* stats);
+
+/* ---- SplitMix64 (counter form) on the device, for parity of start vectors --
+ * out[i] = 2 * (z_i >> 11) * 2^-53 - 1, z_i the i-th SplitMix64 output of
+ * state `seed` (Steele, Lea & Flood 2014). */
+int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDG_H */

@@ -1,0 +1,381 @@
+// p-transfer to the Q_1 coarse space and the continuous-Q_1 h-hierarchy
+// (Section 6 and Section 6.1.2).
+//
+// * R_k^1 keeps the hierarchical modes i, j <= 1; P_k^1 = (R_k^1)^T.
+// * P_cd maps nodal values of the continuous bilinear field at the four
+//   vertices of an element to its Q_1 modes: with the orthonormal scaling
+//   psi_ij = c_ij L_i L_j, c_ij = sqrt((2i+1)(2j+1)/(hx hy)), the vertex
+//   (a, b) hat function has mode (i, j) coefficient s_a^i s_b^j / (4 c_ij),
+//   s_0 = -1, s_1 = +1.  R_dc = P_cd^T (gather over the <= 4 elements that
+//   share a node).
+// * A_{1,c} = P_cd^T A_1 P_cd: on continuous bilinear fields the jumps vanish,
+//   so every interior-face term of A_1 drops out and A_{1,c} assembles from
+//   element-local volume + boundary-face matrices (computed by the SIP tile
+//   kernel on the hat functions).  Stored as a 9-point stencil of 2x2 blocks:
+//   st[s][d][c][node], s = (dy+1)*3 + (dx+1).
+// * h-levels: vertex-centred bilinear interpolation P_h, R_h = P_h^T,
+//   A_H = P_h^T A_h P_h computed stencil-wise.
+#include "sdg_common.h"
+#include "sdg_kernels.h"
+
+namespace sdg {
+
+__device__ __forceinline__ double pcd_coef(int i, int j, int va, int vb, double hx, double hy) {
+  const double cij = sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (hx * hy));
+  const double si = (i == 0) ? 1.0 : (va ? 1.0 : -1.0);
+  const double sj = (j == 0) ? 1.0 : (vb ? 1.0 : -1.0);
+  return 0.25 * si * sj / cij;
+}
+
+// rc[pb][node][c] = sum over adjacent elements of P_cd^T (Q1 modes of r)
+template <typename TV>
+__global__ void p_restrict_kernel(int nx, int ny, int k1, double hx, double hy, int nbatch,
+                                  const TV* __restrict__ r, double* __restrict__ rc) {
+  const int nn = (nx + 1) * (ny + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nn * 2) return;
+  const int c = (int)(g & 1);
+  const int64_t gn = g >> 1;
+  const int64_t pb = gn / nn;
+  const int node = (int)(gn - pb * nn);
+  const int jx = node % (nx + 1), jy = node / (nx + 1);
+  const int KK = k1 * k1, NB = 2 * KK;
+  double s = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const int ex = jx - a, ey = jy - b;  // element whose vertex (a, b) is this node
+      if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
+      const TV* re = r + ((pb * ny + ey) * (int64_t)nx + ex) * NB + c * KK;
+      for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) s += pcd_coef(i, j, a, b, hx, hy) * double(re[j * k1 + i]);
+    }
+  rc[g] = s;
+}
+
+// u[pb][e][c][j][i] += sum_vertices P_cd ec, i, j <= 1
+template <typename TV>
+__global__ void p_prolong_kernel(int nx, int ny, int k1, double hx, double hy, int nbatch,
+                                 const double* __restrict__ ec, TV* __restrict__ u) {
+  const int nel = nx * ny;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nel * 8) return;
+  const int mode = (int)(g & 3), c = (int)((g >> 2) & 1);
+  const int64_t ge = g >> 3;
+  const int64_t pb = ge / nel;
+  const int e = (int)(ge - pb * nel);
+  const int ex = e % nx, ey = e / nx;
+  const int i = mode & 1, j = mode >> 1;
+  const int nn = (nx + 1) * (ny + 1);
+  double s = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const int node = (ey + b) * (nx + 1) + ex + a;
+      s += pcd_coef(i, j, a, b, hx, hy) * ec[(pb * nn + node) * 2 + c];
+    }
+  const int KK = k1 * k1;
+  TV* ue = u + ge * 2 * KK + c * KK + j * k1 + i;
+  *ue = TV(double(*ue) + s);
+}
+
+int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (M.nx + 1) * (M.ny + 1) * 2;
+  hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
+                     k + 1, M.hx, M.hy, nbatch, r, rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (M.nx + 1) * (M.ny + 1) * 2;
+  hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
+                     k + 1, M.hx, M.hy, nbatch, r, rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int p_prolong_add(const MeshDev& M, int k, int nbatch, const double* ec, double* u, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * M.nx * M.ny * 8;
+  hipLaunchKernelGGL(p_prolong_kernel<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
+                     k + 1, M.hx, M.hy, nbatch, ec, u);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int p_prolong_add_f32(const MeshDev& M, int k, int nbatch, const double* ec, float* u, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * M.nx * M.ny * 8;
+  hipLaunchKernelGGL(p_prolong_kernel<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
+                     k + 1, M.hx, M.hy, nbatch, ec, u);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// A_{1,c} stencil from element-local 8x8 matrices (rows/cols vertex*2 + comp)
+// ---------------------------------------------------------------------------
+__global__ void stencil_from_local_kernel(int nx, int ny, int nbatch, const double* __restrict__ cl,
+                                          double* __restrict__ st) {
+  const int nn = (nx + 1) * (ny + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nn) return;
+  const int64_t pb = g / nn;
+  const int node = (int)(g - pb * nn);
+  const int jx = node % (nx + 1), jy = node / (nx + 1);
+  const int64_t NNB = (int64_t)nbatch * nn;
+  double out[36];
+  for (int z = 0; z < 36; ++z) out[z] = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const int ex = jx - a, ey = jy - b;
+      if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
+      const double* L = cl + ((pb * ny + ey) * (int64_t)nx + ex) * 64;
+      const int vr = b * 2 + a;
+      for (int vb = 0; vb < 2; ++vb)
+        for (int va = 0; va < 2; ++va) {
+          const int vc = vb * 2 + va;
+          const int dx = va - a, dy = vb - b;
+          const int sidx = (dy + 1) * 3 + (dx + 1);
+          for (int d = 0; d < 2; ++d)
+            for (int c = 0; c < 2; ++c) out[sidx * 4 + d * 2 + c] += L[(vr * 2 + d) * 8 + vc * 2 + c];
+        }
+    }
+  for (int z = 0; z < 36; ++z) st[z * NNB + g] = out[z];
+}
+
+int coarse_stencil_from_local(int nx, int ny, int nbatch, const double* clocal, double* st,
+                              hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(stencil_from_local_kernel, dim3(ceil_div(n, 128)), dim3(128), 0, s, nx, ny, nbatch,
+                     clocal, st);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarsening A_H = P_h^T A_h P_h on 9-point block stencils
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double w1(int o) { return o == 0 ? 1.0 : 0.5; }
+
+__global__ void galerkin_kernel(int nfx, int nfy, int nbatch, const double* __restrict__ stf,
+                                double* __restrict__ stc) {
+  const int ncx = nfx / 2, ncy = nfy / 2;
+  const int nnc = (ncx + 1) * (ncy + 1), nnf = (nfx + 1) * (nfy + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nnc) return;
+  const int64_t pb = g / nnc;
+  const int cn = (int)(g - pb * nnc);
+  const int cx = cn % (ncx + 1), cy = cn / (ncx + 1);
+  const int64_t NF = (int64_t)nbatch * nnf, NC = (int64_t)nbatch * nnc;
+  double out[36];
+  for (int z = 0; z < 36; ++z) out[z] = 0.0;
+  for (int oy = -1; oy <= 1; ++oy)
+    for (int ox = -1; ox <= 1; ++ox) {
+      const int fx = 2 * cx + ox, fy = 2 * cy + oy;  // fine node in the support of the coarse node
+      if (fx < 0 || fx > nfx || fy < 0 || fy > nfy) continue;
+      const double wi = w1(ox) * w1(oy);
+      const int64_t fi = pb * nnf + (int64_t)fy * (nfx + 1) + fx;
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          const int gx = fx + sx, gy = fy + sy;  // fine neighbour j
+          if (gx < 0 || gx > nfx || gy < 0 || gy > nfy) continue;
+          const int sidx = (sy + 1) * 3 + (sx + 1);
+          double a[4];
+          for (int z = 0; z < 4; ++z) a[z] = stf[(sidx * 4 + z) * NF + fi];
+          // coarse parents of (gx, gy)
+          const int px0 = gx >> 1, px1 = (gx + 1) >> 1;
+          const int py0 = gy >> 1, py1 = (gy + 1) >> 1;
+          for (int py = py0; py <= py1; ++py)
+            for (int px = px0; px <= px1; ++px) {
+              const double wj = ((gx & 1) ? 0.5 : 1.0) * ((gy & 1) ? 0.5 : 1.0);
+              const int ddx = px - cx, ddy = py - cy;
+              const int cidx = (ddy + 1) * 3 + (ddx + 1);
+              for (int z = 0; z < 4; ++z) out[cidx * 4 + z] += wi * wj * a[z];
+            }
+        }
+    }
+  for (int z = 0; z < 36; ++z) stc[z * NC + g] = out[z];
+}
+
+int galerkin_coarsen(int nfx, int nfy, int nbatch, const double* stf, double* stc, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nfx / 2 + 1) * (nfy / 2 + 1);
+  hipLaunchKernelGGL(galerkin_kernel, dim3(ceil_div(n, 128)), dim3(128), 0, s, nfx, nfy, nbatch, stf,
+                     stc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stencil operators
+// ---------------------------------------------------------------------------
+template <bool RESID>
+__global__ void stencil_kernel(int nx, int ny, int nbatch, const double* __restrict__ st,
+                               const double* __restrict__ b, const double* __restrict__ x,
+                               double* __restrict__ y) {
+  const int nn = (nx + 1) * (ny + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nn) return;
+  const int64_t pb = g / nn;
+  const int node = (int)(g - pb * nn);
+  const int jx = node % (nx + 1), jy = node / (nx + 1);
+  const int64_t NN = (int64_t)nbatch * nn;
+  double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+  for (int sy = -1; sy <= 1; ++sy)
+#pragma unroll
+    for (int sx = -1; sx <= 1; ++sx) {
+      const int gx = jx + sx, gy = jy + sy;
+      if (gx < 0 || gx > nx || gy < 0 || gy > ny) continue;
+      const int sidx = (sy + 1) * 3 + (sx + 1);
+      const int64_t nb = pb * nn + (int64_t)gy * (nx + 1) + gx;
+      const double x0 = x[nb * 2], x1 = x[nb * 2 + 1];
+      y0 += st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
+      y1 += st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+    }
+  if (RESID) {
+    y[g * 2] = b[g * 2] - y0;
+    y[g * 2 + 1] = b[g * 2 + 1] - y1;
+  } else {
+    y[g * 2] = y0;
+    y[g * 2 + 1] = y1;
+  }
+}
+
+int stencil_apply(int nx, int ny, int nbatch, const double* st, const double* x, double* y,
+                  hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(stencil_kernel<false>, dim3(ceil_div(n, 256)), dim3(256), 0, s, nx, ny, nbatch, st,
+                     nullptr, x, y);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int stencil_residual(int nx, int ny, int nbatch, const double* st, const double* b, const double* x,
+                     double* r, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(stencil_kernel<true>, dim3(ceil_div(n, 256)), dim3(256), 0, s, nx, ny, nbatch, st,
+                     b, x, r);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+__global__ void diag_inv_kernel(int64_t NN, const double* __restrict__ st, double* __restrict__ dinv) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= NN) return;
+  dinv[g * 2] = 1.0 / st[(4 * 4 + 0) * NN + g];
+  dinv[g * 2 + 1] = 1.0 / st[(4 * 4 + 3) * NN + g];
+}
+int stencil_diag_inv(int nx, int ny, int nbatch, const double* st, double* dinv, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(diag_inv_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, st, dinv);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// rc[I] = sum_{i in supp(I)} w_I(i) rf[i]
+__global__ void h_restrict_kernel(int ncx, int ncy, int nbatch, const double* __restrict__ rf,
+                                  double* __restrict__ rc) {
+  const int nfx = 2 * ncx, nfy = 2 * ncy;
+  const int nnc = (ncx + 1) * (ncy + 1), nnf = (nfx + 1) * (nfy + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nnc * 2) return;
+  const int c = (int)(g & 1);
+  const int64_t gn = g >> 1;
+  const int64_t pb = gn / nnc;
+  const int cn = (int)(gn - pb * nnc);
+  const int cx = cn % (ncx + 1), cy = cn / (ncx + 1);
+  double s = 0.0;
+  for (int oy = -1; oy <= 1; ++oy)
+    for (int ox = -1; ox <= 1; ++ox) {
+      const int fx = 2 * cx + ox, fy = 2 * cy + oy;
+      if (fx < 0 || fx > nfx || fy < 0 || fy > nfy) continue;
+      s += w1(ox) * w1(oy) * rf[(pb * nnf + (int64_t)fy * (nfx + 1) + fx) * 2 + c];
+    }
+  rc[g] = s;
+}
+// xf[i] += sum_{parents J} w_J(i) ec[J]
+__global__ void h_prolong_kernel(int ncx, int ncy, int nbatch, const double* __restrict__ ec,
+                                 double* __restrict__ xf) {
+  const int nfx = 2 * ncx, nfy = 2 * ncy;
+  const int nnc = (ncx + 1) * (ncy + 1), nnf = (nfx + 1) * (nfy + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nnf * 2) return;
+  const int c = (int)(g & 1);
+  const int64_t gn = g >> 1;
+  const int64_t pb = gn / nnf;
+  const int fn = (int)(gn - pb * nnf);
+  const int fx = fn % (nfx + 1), fy = fn / (nfx + 1);
+  const double wx = (fx & 1) ? 0.5 : 1.0, wy = (fy & 1) ? 0.5 : 1.0;
+  double s = 0.0;
+  for (int py = fy >> 1; py <= (fy + 1) >> 1; ++py)
+    for (int px = fx >> 1; px <= (fx + 1) >> 1; ++px)
+      s += wx * wy * ec[(pb * nnc + (int64_t)py * (ncx + 1) + px) * 2 + c];
+  xf[g] += s;
+}
+int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (ncx + 1) * (ncy + 1) * 2;
+  hipLaunchKernelGGL(h_restrict_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, ncx, ncy, nbatch, rf,
+                     rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int h_prolong_add(int ncx, int ncy, int nbatch, const double* ec, double* xf, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (2 * ncx + 1) * (2 * ncy + 1) * 2;
+  hipLaunchKernelGGL(h_prolong_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, ncx, ncy, nbatch, ec,
+                     xf);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: dense matrix from the stencil; dense matvec with the inverse
+// ---------------------------------------------------------------------------
+__global__ void stencil_to_dense_kernel(int nx, int ny, int nbatch, const double* __restrict__ st,
+                                        double* __restrict__ dense) {
+  const int nn = (nx + 1) * (ny + 1), n2 = 2 * nn;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nn) return;
+  const int64_t pb = g / nn;
+  const int node = (int)(g - pb * nn);
+  const int jx = node % (nx + 1), jy = node / (nx + 1);
+  const int64_t NN = (int64_t)nbatch * nn;
+  double* D = dense + pb * (int64_t)n2 * n2;
+  for (int c = 0; c < n2; ++c) {
+    D[(int64_t)(node * 2) * n2 + c] = 0.0;
+    D[(int64_t)(node * 2 + 1) * n2 + c] = 0.0;
+  }
+  for (int sy = -1; sy <= 1; ++sy)
+    for (int sx = -1; sx <= 1; ++sx) {
+      const int gx = jx + sx, gy = jy + sy;
+      if (gx < 0 || gx > nx || gy < 0 || gy > ny) continue;
+      const int sidx = (sy + 1) * 3 + (sx + 1);
+      const int nb = gy * (nx + 1) + gx;
+      for (int d = 0; d < 2; ++d)
+        for (int c = 0; c < 2; ++c)
+          D[(int64_t)(node * 2 + d) * n2 + nb * 2 + c] = st[(sidx * 4 + d * 2 + c) * NN + g];
+    }
+}
+int stencil_to_dense(int nx, int ny, int nbatch, const double* st, double* dense, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(stencil_to_dense_kernel, dim3(ceil_div(n, 64)), dim3(64), 0, s, nx, ny, nbatch, st,
+                     dense);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// y[pb] = A[pb] x[pb], one workgroup per (problem, 64-row block), wave per row
+__global__ __launch_bounds__(256) void dense_matvec_kernel(int n, const double* __restrict__ A,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ y) {
+  const int pb = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* Ap = A + (int64_t)pb * n * n;
+  const double* xp = x + (int64_t)pb * n;
+  for (int row = blockIdx.x * 4 + wave; row < n; row += gridDim.x * 4) {
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += Ap[(int64_t)row * n + c] * xp[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) y[(int64_t)pb * n + row] = s;
+  }
+}
+int dense_matvec(int n, int nbatch, const double* A, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(dense_matvec_kernel, dim3(ceil_div(n, 4), nbatch), dim3(256), 0, s, n, A, x, y);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+}  // namespace sdg

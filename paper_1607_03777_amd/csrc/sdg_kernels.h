@@ -1,0 +1,94 @@
+// Host-side launchers of the device kernels (all enqueue on stream s).
+#pragma once
+
+#include "sdg_common.h"
+
+namespace sdg {
+
+// SIP operator (sip_kernels.hip).  Vectors are batched: nbatch problems of
+// the same mesh, consecutive in memory; eta is [nbatch][nel].
+int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
+              hipStream_t s);
+int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
+                 const double* u, double* r, hipStream_t s);
+int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
+                  hipStream_t s);
+int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
+                     const float* u, float* r, hipStream_t s);
+// Diagonal blocks A_KK of the listed elements (one workgroup per listed
+// element): blocks[i][a][b] for element elems[i] of problem elems_pb[i].
+int sip_block_list(const MeshDev& M, int k, const double* eta, const int* elems, int nlist,
+                   double* blocks, hipStream_t s);
+// Element-local continuous-Q1 matrices (volume and boundary faces only):
+// clocal[pb][e][r][c], r, c = vertex*2 + component.
+int sip_coarse_local(const MeshDev& M, int k, int nbatch, const double* eta, double* clocal,
+                     hipStream_t s);
+int div_apply(const MeshDev& M, int k, int nbatch, const double* u, double* q, hipStream_t s);
+int grad_apply(const MeshDev& M, int k, int nbatch, const double* p, double* v, hipStream_t s);
+int rhs_assemble(const MeshDev& M, int k, const double* eta, const double* f, const double* g,
+                 double* F, double* G, hipStream_t s);
+
+// Block Jacobi (block_kernels.hip)
+// In-place inverse of nmat symmetric positive definite n x n matrices
+// (Cholesky, triangular inverse, L^-T L^-1).  status[i] = 0 ok, 1 not SPD.
+int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s);
+// z = scale_e * Binv[id_e] r_e, FP64 inverses.
+int blockjacobi_apply_f64(int nb, int64_t nel_total, const int* ids, const double* scale,
+                          const double* binv, const double* r, double* z, hipStream_t s);
+int blockjacobi_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale,
+                          const float* binv, const float* r, float* z, hipStream_t s);
+// Convert FP64 inverses to FP32 / BF16 storage.
+int convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s);
+int blockjacobi_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale,
+                           const uint16_t* binv, const float* r, float* z, hipStream_t s);
+
+// Transfers and coarse levels (coarse_kernels.hip)
+int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s);
+int p_prolong_add(const MeshDev& M, int k, int nbatch, const double* ec, double* u, hipStream_t s);
+int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s);
+int p_prolong_add_f32(const MeshDev& M, int k, int nbatch, const double* ec, float* u, hipStream_t s);
+int coarse_stencil_from_local(int nx, int ny, int nbatch, const double* clocal, double* st,
+                              hipStream_t s);
+int galerkin_coarsen(int nfx, int nfy, int nbatch, const double* stf, double* stc, hipStream_t s);
+int stencil_apply(int nx, int ny, int nbatch, const double* st, const double* x, double* y,
+                  hipStream_t s);
+int stencil_residual(int nx, int ny, int nbatch, const double* st, const double* b,
+                     const double* x, double* r, hipStream_t s);
+int stencil_diag_inv(int nx, int ny, int nbatch, const double* st, double* dinv, hipStream_t s);
+int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s);
+int h_prolong_add(int ncx, int ncy, int nbatch, const double* ec, double* xf, hipStream_t s);
+int stencil_to_dense(int nx, int ny, int nbatch, const double* st, double* dense, hipStream_t s);
+int dense_matvec(int n, int nbatch, const double* A, const double* x, double* y, hipStream_t s);
+
+// Vector kernels (vec_kernels.hip)
+int vec_copy(int64_t n, const double* x, double* y, hipStream_t s);
+int vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y = a x
+int vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);        // y += a x
+int vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);  // y = a x + b y
+int vec_mul(int64_t n, const double* d, const double* x, double* y, hipStream_t s);  // y = d .* x
+// Chebyshev update. mode 0: d = a d + b z, x += d; mode 1: d = b z, x = d;
+// mode 2: d = b z, x += d.
+int cheb_update(int64_t n, double a, const double* z, double b, double* d, double* x, int mode,
+                hipStream_t s);
+int cheb_update_f32(int64_t n, double a, const float* z, double b, float* d, float* x, int mode,
+                    hipStream_t s);
+// out[j] = <V_j, w> for j < m, V row-major [m][n]; result in device memory
+int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,
+              double* scratch, hipStream_t s);
+// w -= sum_j h[j] V_j (h in device memory)
+int multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w,
+               hipStream_t s);
+// y = sum_j h[j] V_j + beta y (h in device memory)
+int multi_combine(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* y,
+                  hipStream_t s);
+int dot(int64_t n, const double* x, const double* y, double* out, double* scratch, hipStream_t s);
+int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s);
+int d2f(int64_t n, const double* x, float* y, hipStream_t s);
+int f2d(int64_t n, const float* x, double* y, hipStream_t s);
+int pressure_project(int64_t nel, int np, double* p, double* scratch, hipStream_t s);
+// Largest real part of the eigenvalues of the m x m upper Hessenberg matrix
+// (column-major, leading dimension ld) -> out[0]; one thread.
+int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t s);
+
+}  // namespace sdg

@@ -1,0 +1,889 @@
+// SIP viscous operator A (eq. stiffness_form) on the hierarchical Legendre
+// basis, matrix-free, plus the divergence/gradient operators B^T, B
+// (eq. divergence_form) and the right-hand-side assembly.
+//
+// Modal closed forms used here (orthonormal basis, c = 2/sqrt(hx hy)):
+//  * volume: with D the 1D derivative matrix and S = D^T D,
+//      y0 = eta [2(2/hx)^2 S_x u0 + (2/hy)^2 S_y u0 + (2/hx)(2/hy) D_y^T D_x u1]
+//      y1 = eta [2(2/hy)^2 S_y u1 + (2/hx)^2 S_x u1 + (2/hx)(2/hy) D_x^T D_y u0]
+//    (the strain terms 2 eta eps(u):eps(v) are Euclidean products of modal
+//    derivative coefficients because the mass matrix is the identity);
+//  * faces: every face function is a 1D Legendre series; a face with normal
+//    direction n (hn = h_n, ht = the other) contributes to the adjacent
+//    element y_d[..] += a_d e_end(.) + b_d d_end(.), where (a, b) come from
+//    the traces t (values) and g (normal derivatives) of both sides:
+//      J = t^- - t^+, sigma = {2 eta eps(u)} n^-, Q = -sigma + alpha J,
+//    alpha = gamma_F C_F with gamma_F = 4 eta_F (interior, eta_F = max of
+//    the neighbours, eq. eta_face) or 8 eta_K (Navier/Dirichlet), and
+//    C_F = (k+1)^2/hn (discrete trace lemma).  Navier faces keep only the
+//    normal component; a Dirichlet face is an interior face whose outer
+//    trace is zero and whose inner viscosity counts twice (full, not
+//    averaged, flux).
+//
+// The tile kernel stages a TX x TY block of elements in LDS, computes face
+// traces from row/column pencils (halo neighbours read from HBM/L2), turns
+// each face into coefficients with one thread per face, then applies the
+// volume and face terms in a row pass and a column pass; all mode loops are
+// unrolled over K1 = k+1 so the Legendre constants are immediates.
+#include "sdg_common.h"
+#include "sdg_kernels.h"
+
+namespace sdg {
+
+template <int K1> struct Tile;
+template <> struct Tile<2> { static constexpr int TX = 16, TY = 8; };
+template <> struct Tile<3> { static constexpr int TX = 8, TY = 8; };
+template <> struct Tile<4> { static constexpr int TX = 8, TY = 4; };
+template <> struct Tile<5> { static constexpr int TX = 8, TY = 4; };
+template <> struct Tile<6> { static constexpr int TX = 4, TY = 4; };
+template <> struct Tile<7> { static constexpr int TX = 4, TY = 4; };
+
+constexpr int NT = 256;  // threads per tile workgroup
+
+// ---------------------------------------------------------------------------
+// face coefficients from traces
+// tr layout per face: [side s][comp d][w][m], w = 0 trace value, 1 normal
+// derivative; the output uses the same slots with w = 0 -> a, 1 -> b.
+// ---------------------------------------------------------------------------
+template <int K1, int DIR, typename T>
+__device__ __forceinline__ void interior_coefs(const T (&tm)[2][K1], const T (&gm)[2][K1],
+                                               const T (&tp)[2][K1], const T (&gp)[2][K1],
+                                               T etam, T etap, T alpha, T hn, T ht,
+                                               T (&a)[2][2][K1], T (&b)[2][2][K1]) {
+  constexpr int N = DIR, TT = 1 - DIR;
+  const T c2n = T(2) / hn, c2t = T(2) / ht;
+#pragma unroll
+  for (int m = 0; m < K1; ++m) {
+    T dtm = 0, dtp = 0, dtj = 0;
+#pragma unroll
+    for (int j = 0; j < K1; ++j) {
+      if (d_nz(m, j)) {
+        dtm += T(d_val(m, j)) * tm[N][j];
+        dtp += T(d_val(m, j)) * tp[N][j];
+      }
+      if (d_nz(j, m)) dtj += T(d_val(j, m)) * (tm[TT][j] - tp[TT][j]);
+    }
+    const T jn = tm[N][m] - tp[N][m];
+    const T jt = tm[TT][m] - tp[TT][m];
+    const T sn = c2n * (etam * gm[N][m] + etap * gp[N][m]);
+    const T st = T(0.5) * (c2t * (etam * dtm + etap * dtp) + c2n * (etam * gm[TT][m] + etap * gp[TT][m]));
+    const T qn = -sn + alpha * jn;
+    const T qt = -st + alpha * jt;
+    a[0][N][m] = c2n * (qn - etam / ht * dtj);
+    b[0][N][m] = -c2n * c2n * etam * jn;
+    a[0][TT][m] = c2n * qt;
+    b[0][TT][m] = -c2n / hn * etam * jt;
+    a[1][N][m] = -c2n * (qn + etap / ht * dtj);
+    b[1][N][m] = -c2n * c2n * etap * jn;
+    a[1][TT][m] = -c2n * qt;
+    b[1][TT][m] = -c2n / hn * etap * jt;
+  }
+}
+
+// kind: F_INTERIOR, or the boundary kind with `side` the present side.
+// isolate: each side sees a zero neighbour (diagonal blocks).
+// skip_interior: interior faces contribute nothing (continuous Q1 fields).
+template <int K1, int DIR, typename T>
+__device__ void face_coefs(T* f, int kind, int side, T etam, T etap, T hn, T ht, bool isolate,
+                           bool skip_interior) {
+  T tm[2][K1], gm[2][K1], tp[2][K1], gp[2][K1];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int m = 0; m < K1; ++m) {
+      tm[d][m] = f[((0 * 2 + d) * 2 + 0) * K1 + m];
+      gm[d][m] = f[((0 * 2 + d) * 2 + 1) * K1 + m];
+      tp[d][m] = f[((1 * 2 + d) * 2 + 0) * K1 + m];
+      gp[d][m] = f[((1 * 2 + d) * 2 + 1) * K1 + m];
+    }
+  T a[2][2][K1], b[2][2][K1];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int m = 0; m < K1; ++m) a[s][d][m] = b[s][d][m] = T(0);
+  const T kk = T(K1 * K1);
+  if (kind == F_INTERIOR) {
+    if (!skip_interior) {
+      const T alpha = T(4) * (etam > etap ? etam : etap) * kk / hn;
+      if (!isolate) {
+        interior_coefs<K1, DIR, T>(tm, gm, tp, gp, etam, etap, alpha, hn, ht, a, b);
+      } else {
+        T z[2][K1], am[2][2][K1], bm[2][2][K1];
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+          for (int m = 0; m < K1; ++m) z[d][m] = T(0);
+        interior_coefs<K1, DIR, T>(tm, gm, z, z, etam, etap, alpha, hn, ht, am, bm);
+        interior_coefs<K1, DIR, T>(z, z, tp, gp, etam, etap, alpha, hn, ht, a, b);
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+          for (int m = 0; m < K1; ++m) {
+            a[0][d][m] = am[0][d][m];
+            b[0][d][m] = bm[0][d][m];
+          }
+      }
+    }
+  } else if (kind == F_NAVIER) {
+    constexpr int N = DIR;
+    const T eta = side == 0 ? etam : etap;
+    const T alpha = T(8) * eta * kk / hn;
+    const T sgn = side == 0 ? T(1) : T(-1);
+    const T c2n = T(2) / hn;
+    const T w = T(4) * eta / hn;
+#pragma unroll
+    for (int m = 0; m < K1; ++m) {
+      const T t = side == 0 ? tm[N][m] : tp[N][m];
+      const T g = side == 0 ? gm[N][m] : gp[N][m];
+      const T av = c2n * (alpha * t - sgn * w * g);
+      const T bv = -c2n * sgn * w * t;
+      if (side == 0) {
+        a[0][N][m] = av;
+        b[0][N][m] = bv;
+      } else {
+        a[1][N][m] = av;
+        b[1][N][m] = bv;
+      }
+    }
+  } else if (kind == F_DIRICHLET) {
+    T z[2][K1];
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int m = 0; m < K1; ++m) z[d][m] = T(0);
+    const T eta2 = T(2) * (side == 0 ? etam : etap);
+    const T alpha = T(4) * eta2 * kk / hn;
+    if (side == 0)
+      interior_coefs<K1, DIR, T>(tm, gm, z, z, eta2, T(0), alpha, hn, ht, a, b);
+    else
+      interior_coefs<K1, DIR, T>(z, z, tp, gp, T(0), eta2, alpha, hn, ht, a, b);
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int m = 0; m < K1; ++m) {
+        f[((s * 2 + d) * 2 + 0) * K1 + m] = a[s][d][m];
+        f[((s * 2 + d) * 2 + 1) * K1 + m] = b[s][d][m];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// tile kernel
+// ---------------------------------------------------------------------------
+enum ApplyMode { M_APPLY = 0, M_RESID = 1, M_BLOCKCOL = 2, M_COARSECOL = 3 };
+
+// MODE M_APPLY / M_RESID: tile grid over the mesh (blockIdx.y = problem).
+// MODE M_BLOCKCOL: TX = TY = 1, blockIdx.x indexes `elems` (global element
+//   ids pb*nel + e); loops over the NB unit columns, writes out_mat[list][a][col].
+// MODE M_COARSECOL: tile grid; loops over the 8 hat columns, writes
+//   out_mat[pb*nel + e][r][col].
+template <int K1, int MODE, typename T, int TX, int TY>
+__global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __restrict__ u,
+                                                      const T* __restrict__ bvec, T* __restrict__ y,
+                                                      const double* __restrict__ eta_all,
+                                                      double* __restrict__ out_mat,
+                                                      const int* __restrict__ elems,
+                                                      int64_t vec_stride) {
+  constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY;
+  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1);
+  constexpr int FW = 8 * K1;
+  constexpr int EW = TX + 2;
+  __shared__ T su[E * NB];
+  __shared__ T sxy[E * NB];  // [el][0] = D_y u0 (columns), [el][1] = D_x u1 (rows)
+  __shared__ T sy[E * NB];
+  __shared__ T sf[(NFV + NFH) * FW];
+  __shared__ T seta[(TY + 2) * EW];
+
+  const int tid = threadIdx.x;
+  const int nx = M.nx, ny = M.ny;
+  int ix0, iy0;
+  int64_t pb;
+  if (MODE == M_BLOCKCOL) {
+    const int g = elems[blockIdx.x];
+    pb = g / (nx * ny);
+    const int e = g - (int)pb * nx * ny;
+    ix0 = e % nx;
+    iy0 = e / nx;
+  } else {
+    const int ntx = (nx + TX - 1) / TX;
+    ix0 = (blockIdx.x % ntx) * TX;
+    iy0 = (blockIdx.x / ntx) * TY;
+    pb = blockIdx.y;
+  }
+  const double* eta = eta_all + pb * (int64_t)nx * ny;
+  if (MODE == M_APPLY || MODE == M_RESID) {
+    u += pb * vec_stride;
+    y += pb * vec_stride;
+    if (MODE == M_RESID) bvec += pb * vec_stride;
+  }
+  const T hx = T(M.hx), hy = T(M.hy);
+
+  // ---- S0: load viscosity (tile + halo ring) and the tile's coefficients
+  for (int q = tid; q < (TY + 2) * EW; q += NT) {
+    const int ix = ix0 - 1 + q % EW, iy = iy0 - 1 + q / EW;
+    seta[q] = (ix >= 0 && ix < nx && iy >= 0 && iy < ny) ? T(eta[(int64_t)iy * nx + ix]) : T(0);
+  }
+  constexpr int NCOLS = (MODE == M_BLOCKCOL) ? NB : (MODE == M_COARSECOL ? 8 : 1);
+  for (int col = 0; col < NCOLS; ++col) {
+  for (int q = tid; q < E * NB; q += NT) {
+    const int ty = q / (TX * NB), rem = q - ty * TX * NB, tx = rem / NB, a = rem - tx * NB;
+    const int ix = ix0 + tx, iy = iy0 + ty;
+    T v = T(0);
+    if (ix < nx && iy < ny) {
+      if (MODE == M_APPLY || MODE == M_RESID) {
+        v = u[((int64_t)iy * nx + ix0) * NB + rem];
+      } else if (MODE == M_BLOCKCOL) {
+        v = (a == col) ? T(1) : T(0);
+      } else {  // hat function (vertex va, vb; component cc) as modal Q1 coefficients
+        const int vtx = col >> 1, cc = col & 1, va = vtx & 1, vb = vtx >> 1;
+        const int d = a / KK, j = (a % KK) / K1, i = a % K1;
+        if (d == cc && i <= 1 && j <= 1) {
+          const double cij = sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (M.hx * M.hy));
+          const double si = (i == 0) ? 1.0 : (va ? 1.0 : -1.0);
+          const double sj = (j == 0) ? 1.0 : (vb ? 1.0 : -1.0);
+          v = T(0.25 * si * sj / cij);
+        }
+      }
+    }
+    su[q] = v;
+  }
+  __syncthreads();
+
+  // ---- S1: traces of rows (x-faces) and columns (y-faces), derivatives for
+  // the mixed terms.  Row items: tx in [-1, TX], ty in [0, TY), d, j.
+  {
+    constexpr int NROW = (TX + 2) * TY * 2 * K1;
+    constexpr int NCOL = TX * (TY + 2) * 2 * K1;
+    const bool halo_ok = (MODE == M_APPLY || MODE == M_RESID);
+    for (int q = tid; q < NROW + NCOL; q += NT) {
+      if (q < NROW) {
+        const int j = q % K1, d = (q / K1) & 1, r = q / (2 * K1);
+        const int tx = r % (TX + 2) - 1, ty = r / (TX + 2);
+        const int ix = ix0 + tx, iy = iy0 + ty;
+        T row[K1];
+        const bool inside = (tx >= 0 && tx < TX);
+        const bool exists = (ix >= 0 && ix < nx && iy < ny);
+        if (inside) {
+          const T* p = su + (ty * TX + tx) * NB + d * KK + j * K1;
+#pragma unroll
+          for (int i = 0; i < K1; ++i) row[i] = p[i];
+        } else if (exists && halo_ok) {
+          const T* p = u + ((int64_t)iy * nx + ix) * NB + d * KK + j * K1;
+#pragma unroll
+          for (int i = 0; i < K1; ++i) row[i] = p[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < K1; ++i) row[i] = T(0);
+        }
+        T tl = 0, gl = 0, tr = 0, gr = 0;
+#pragma unroll
+        for (int i = 0; i < K1; ++i) {
+          tl += T(e_end(i, 0)) * row[i];
+          gl += T(d_end(i, 0)) * row[i];
+          tr += T(e_end(i, 1)) * row[i];
+          gr += T(d_end(i, 1)) * row[i];
+        }
+        // left end belongs to face fx = tx (plus side), right end to fx = tx+1 (minus side)
+        if (tx >= 0) {
+          T* f = sf + (ty * (TX + 1) + tx) * FW;
+          f[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
+          f[((1 * 2 + d) * 2 + 1) * K1 + j] = gl;
+        }
+        if (tx < TX) {
+          T* f = sf + (ty * (TX + 1) + tx + 1) * FW;
+          f[((0 * 2 + d) * 2 + 0) * K1 + j] = tr;
+          f[((0 * 2 + d) * 2 + 1) * K1 + j] = gr;
+        }
+        if (inside && d == 1) {  // D_x u1, row j
+          T* o = sxy + (ty * TX + tx) * NB + KK + j * K1;
+#pragma unroll
+          for (int i = 0; i < K1; ++i) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < K1; ++l)
+              if (d_nz(i, l)) s += T(d_val(i, l)) * row[l];
+            o[i] = s;
+          }
+        }
+      } else {
+        const int qq = q - NROW;
+        const int i = qq % K1, d = (qq / K1) & 1, r = qq / (2 * K1);
+        const int tx = r % TX, ty = r / TX - 1;
+        const int ix = ix0 + tx, iy = iy0 + ty;
+        T cl[K1];
+        const bool inside = (ty >= 0 && ty < TY);
+        const bool exists = (iy >= 0 && iy < ny && ix < nx);
+        if (inside) {
+          const T* p = su + (ty * TX + tx) * NB + d * KK + i;
+#pragma unroll
+          for (int jj = 0; jj < K1; ++jj) cl[jj] = p[jj * K1];
+        } else if (exists && halo_ok) {
+          const T* p = u + ((int64_t)iy * nx + ix) * NB + d * KK + i;
+#pragma unroll
+          for (int jj = 0; jj < K1; ++jj) cl[jj] = p[jj * K1];
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < K1; ++jj) cl[jj] = T(0);
+        }
+        T tb = 0, gb = 0, tt = 0, gt = 0;
+#pragma unroll
+        for (int jj = 0; jj < K1; ++jj) {
+          tb += T(e_end(jj, 0)) * cl[jj];
+          gb += T(d_end(jj, 0)) * cl[jj];
+          tt += T(e_end(jj, 1)) * cl[jj];
+          gt += T(d_end(jj, 1)) * cl[jj];
+        }
+        if (ty >= 0) {
+          T* f = sf + (NFV + ty * TX + tx) * FW;
+          f[((1 * 2 + d) * 2 + 0) * K1 + i] = tb;
+          f[((1 * 2 + d) * 2 + 1) * K1 + i] = gb;
+        }
+        if (ty < TY) {
+          T* f = sf + (NFV + (ty + 1) * TX + tx) * FW;
+          f[((0 * 2 + d) * 2 + 0) * K1 + i] = tt;
+          f[((0 * 2 + d) * 2 + 1) * K1 + i] = gt;
+        }
+        if (inside && d == 0) {  // D_y u0, column i
+          T* o = sxy + (ty * TX + tx) * NB + i;
+#pragma unroll
+          for (int jj = 0; jj < K1; ++jj) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < K1; ++l)
+              if (d_nz(jj, l)) s += T(d_val(jj, l)) * cl[l];
+            o[jj * K1] = s;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- S2: one thread per face: traces -> coefficients (in place)
+  for (int q = tid; q < NFV + NFH; q += NT) {
+    T* f = sf + q * FW;
+    if (q < NFV) {
+      const int ty = q / (TX + 1), fx = q % (TX + 1);
+      const int iy = iy0 + ty, ixm = ix0 + fx - 1, ixp = ix0 + fx;
+      const bool pm = (ixm >= 0 && ixm < nx), pp = (ixp < nx);
+      int kind = -1, side = 0;
+      if (iy < ny) {
+        if (pm && pp) kind = F_INTERIOR;
+        else if (!pm && pp) { kind = M.bc[0]; side = 1; }
+        else if (pm && ixp == nx) { kind = M.bc[1]; side = 0; }
+      }
+      if (kind < 0) {
+        for (int z = 0; z < FW; ++z) f[z] = T(0);
+        continue;
+      }
+      const T em = seta[(ty + 1) * EW + fx], ep = seta[(ty + 1) * EW + fx + 1];
+      face_coefs<K1, 0, T>(f, kind, side, em, ep, hx, hy, MODE == M_BLOCKCOL, MODE == M_COARSECOL);
+    } else {
+      const int qq = q - NFV;
+      const int fy = qq / TX, tx = qq % TX;
+      const int ix = ix0 + tx, iym = iy0 + fy - 1, iyp = iy0 + fy;
+      const bool pm = (iym >= 0 && iym < ny), pp = (iyp < ny);
+      int kind = -1, side = 0;
+      if (ix < nx) {
+        if (pm && pp) kind = F_INTERIOR;
+        else if (!pm && pp) { kind = M.bc[2]; side = 1; }
+        else if (pm && iyp == ny) { kind = M.bc[3]; side = 0; }
+      }
+      if (kind < 0) {
+        for (int z = 0; z < FW; ++z) f[z] = T(0);
+        continue;
+      }
+      const T em = seta[fy * EW + tx + 1], ep = seta[(fy + 1) * EW + tx + 1];
+      face_coefs<K1, 1, T>(f, kind, side, em, ep, hy, hx, MODE == M_BLOCKCOL, MODE == M_COARSECOL);
+    }
+  }
+  __syncthreads();
+
+  // ---- S3: row pass (x-direction volume terms, x-faces, mixed term of y1)
+  const T cxx = T(4) / (hx * hx), cyy = T(4) / (hy * hy), cxy = T(4) / (hx * hy);
+  for (int q = tid; q < E * 2 * K1; q += NT) {
+    const int j = q % K1, d = (q / K1) & 1, el = q / (2 * K1);
+    const int tx = el % TX, ty = el / TX;
+    const T et = seta[(ty + 1) * EW + tx + 1];
+    const T* rp = su + el * NB + d * KK + j * K1;
+    T row[K1], out[K1];
+#pragma unroll
+    for (int i = 0; i < K1; ++i) row[i] = rp[i];
+    const T cx = (d == 0 ? T(2) : T(1)) * et * cxx;
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < K1; ++l)
+        if (s_nz(i, l)) s += T(s_val(i, l)) * row[l];
+      out[i] = cx * s;
+    }
+    if (d == 1) {  // D_x^T (D_y u0), row j
+      const T* yp = sxy + el * NB + j * K1;
+      T r0[K1];
+#pragma unroll
+      for (int m = 0; m < K1; ++m) r0[m] = yp[m];
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < K1; ++m)
+          if (d_nz(m, i)) s += T(d_val(m, i)) * r0[m];
+        out[i] += et * cxy * s;
+      }
+    }
+    const T* fl = sf + (ty * (TX + 1) + tx) * FW;      // plus side of left face
+    const T* fr = sf + (ty * (TX + 1) + tx + 1) * FW;  // minus side of right face
+    const T al = fl[((1 * 2 + d) * 2 + 0) * K1 + j], bl = fl[((1 * 2 + d) * 2 + 1) * K1 + j];
+    const T ar = fr[((0 * 2 + d) * 2 + 0) * K1 + j], br = fr[((0 * 2 + d) * 2 + 1) * K1 + j];
+    T* op = sy + el * NB + d * KK + j * K1;
+#pragma unroll
+    for (int i = 0; i < K1; ++i)
+      op[i] = out[i] + al * T(e_end(i, 0)) + bl * T(d_end(i, 0)) + ar * T(e_end(i, 1)) +
+              br * T(d_end(i, 1));
+  }
+  __syncthreads();
+
+  // ---- S4: column pass (y-direction volume terms, y-faces, mixed term of y0)
+  for (int q = tid; q < E * 2 * K1; q += NT) {
+    const int i = q % K1, d = (q / K1) & 1, el = q / (2 * K1);
+    const int tx = el % TX, ty = el / TX;
+    const T et = seta[(ty + 1) * EW + tx + 1];
+    T* cp = su + el * NB + d * KK + i;
+    T cl[K1], out[K1];
+#pragma unroll
+    for (int jj = 0; jj < K1; ++jj) cl[jj] = cp[jj * K1];
+    const T cy = (d == 1 ? T(2) : T(1)) * et * cyy;
+#pragma unroll
+    for (int jj = 0; jj < K1; ++jj) {
+      T s = 0;
+#pragma unroll
+      for (int l = 0; l < K1; ++l)
+        if (s_nz(jj, l)) s += T(s_val(jj, l)) * cl[l];
+      out[jj] = cy * s;
+    }
+    if (d == 0) {  // D_y^T (D_x u1), column i
+      const T* xp = sxy + el * NB + KK + i;
+      T c1[K1];
+#pragma unroll
+      for (int m = 0; m < K1; ++m) c1[m] = xp[m * K1];
+#pragma unroll
+      for (int jj = 0; jj < K1; ++jj) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < K1; ++m)
+          if (d_nz(m, jj)) s += T(d_val(m, jj)) * c1[m];
+        out[jj] += et * cxy * s;
+      }
+    }
+    const T* fb = sf + (NFV + ty * TX + tx) * FW;        // plus side of bottom face
+    const T* ft = sf + (NFV + (ty + 1) * TX + tx) * FW;  // minus side of top face
+    const T ab = fb[((1 * 2 + d) * 2 + 0) * K1 + i], bb = fb[((1 * 2 + d) * 2 + 1) * K1 + i];
+    const T at = ft[((0 * 2 + d) * 2 + 0) * K1 + i], bt = ft[((0 * 2 + d) * 2 + 1) * K1 + i];
+    const T* sp = sy + el * NB + d * KK + i;
+#pragma unroll
+    for (int jj = 0; jj < K1; ++jj)
+      cp[jj * K1] = sp[jj * K1] + out[jj] + ab * T(e_end(jj, 0)) + bb * T(d_end(jj, 0)) +
+                    at * T(e_end(jj, 1)) + bt * T(d_end(jj, 1));
+  }
+  __syncthreads();
+
+  // ---- S5: write out
+  if (MODE == M_APPLY || MODE == M_RESID) {
+    for (int q = tid; q < E * NB; q += NT) {
+      const int ty = q / (TX * NB), rem = q - ty * TX * NB, tx = rem / NB;
+      const int ix = ix0 + tx, iy = iy0 + ty;
+      if (ix < nx && iy < ny) {
+        const int64_t g = ((int64_t)iy * nx + ix0) * NB + rem;
+        y[g] = (MODE == M_RESID) ? bvec[g] - su[q] : su[q];
+      }
+    }
+  } else if (MODE == M_BLOCKCOL) {
+    for (int a = tid; a < NB; a += NT) out_mat[((int64_t)blockIdx.x * NB + a) * NB + col] = double(su[a]);
+  } else {  // M_COARSECOL: project the Q1 modes with P_cd^T -> local nodal row (vtx', comp')
+    for (int q = tid; q < E * 8; q += NT) {
+      const int el = q / 8, r = q % 8, vtx = r >> 1, cc = r & 1, va = vtx & 1, vb = vtx >> 1;
+      const int tx = el % TX, ty = el / TX;
+      const int ix = ix0 + tx, iy = iy0 + ty;
+      if (ix < nx && iy < ny) {
+        double s = 0;
+        for (int j = 0; j < 2; ++j)
+          for (int i = 0; i < 2; ++i) {
+            const double cij = sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (M.hx * M.hy));
+            const double si = (i == 0) ? 1.0 : (va ? 1.0 : -1.0);
+            const double sj = (j == 0) ? 1.0 : (vb ? 1.0 : -1.0);
+            s += 0.25 * si * sj / cij * double(su[el * NB + cc * KK + j * K1 + i]);
+          }
+        const int64_t e = (int64_t)iy * nx + ix + pb * (int64_t)nx * ny;
+        out_mat[(e * 8 + r) * 8 + col] = s;
+      }
+    }
+  }
+  __syncthreads();
+  }  // column loop
+}
+
+// ---------------------------------------------------------------------------
+// B^T u (divergence) and B p (gradient): one thread per element (and
+// component for B p); neighbour traces are read directly.
+// ---------------------------------------------------------------------------
+template <int K1>
+__device__ __forceinline__ double trace_row(const double* ue, int d, int j, int plus) {
+  // value trace of component d at mode j on the x-face (plus: xi = +1)
+  double s = 0;
+  const double* p = ue + d * K1 * K1 + j * K1;
+#pragma unroll
+  for (int i = 0; i < K1; ++i) s += e_end(i, plus) * p[i];
+  return s;
+}
+template <int K1>
+__device__ __forceinline__ double trace_col(const double* ue, int d, int i, int plus) {
+  double s = 0;
+  const double* p = ue + d * K1 * K1 + i;
+#pragma unroll
+  for (int j = 0; j < K1; ++j) s += e_end(j, plus) * p[j * K1];
+  return s;
+}
+
+template <int K1>
+__global__ __launch_bounds__(256) void div_kernel(MeshDev M, const double* __restrict__ u,
+                                                  double* __restrict__ q, int64_t nel_total) {
+  constexpr int K = K1 - 1, KK = K1 * K1, NB = 2 * KK;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nel_total) return;
+  const int nel = M.nx * M.ny;
+  const int64_t pb = g / nel;
+  const int e = (int)(g - pb * nel);
+  const int ix = e % M.nx, iy = e / M.nx;
+  const double* ue = u + g * NB;
+  const double hx = M.hx, hy = M.hy;
+  double out[K][K];
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < K1; ++i)
+        if (d_nz(a, i)) s += d_val(a, i) * ue[0 * KK + b * K1 + i];
+      double s2 = 0;
+#pragma unroll
+      for (int j = 0; j < K1; ++j)
+        if (d_nz(b, j)) s2 += d_val(b, j) * ue[1 * KK + j * K1 + a];
+      out[b][a] = -(2.0 / hx) * s - (2.0 / hy) * s2;
+    }
+  // x-faces: mode b along the face
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {  // 0 left face (element = plus side), 1 right face (minus side)
+    const int nbx = side == 0 ? ix - 1 : ix + 1;
+    const bool interior = nbx >= 0 && nbx < M.nx;
+    const int kind = interior ? F_INTERIOR : M.bc[side];
+    if (kind == F_NEUMANN) continue;
+    const double* un = ue + (int64_t)(nbx - ix) * NB;
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      const double tself = trace_row<K1>(ue, 0, b, side == 1);
+      double c;
+      if (interior) {
+        const double tn = trace_row<K1>(un, 0, b, side == 0);
+        const double jm = side == 1 ? tself - tn : tn - tself;  // t^- - t^+
+        c = (1.0 / hx) * jm;
+      } else {
+        c = (side == 1 ? 1.0 : -1.0) * (2.0 / hx) * tself;
+      }
+#pragma unroll
+      for (int a = 0; a < K; ++a) out[b][a] += c * e_end(a, side == 1);
+    }
+  }
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {  // 0 bottom, 1 top
+    const int nby = side == 0 ? iy - 1 : iy + 1;
+    const bool interior = nby >= 0 && nby < M.ny;
+    const int kind = interior ? F_INTERIOR : M.bc[2 + side];
+    if (kind == F_NEUMANN) continue;
+    const double* un = ue + (int64_t)(nby - iy) * M.nx * NB;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      const double tself = trace_col<K1>(ue, 1, a, side == 1);
+      double c;
+      if (interior) {
+        const double tn = trace_col<K1>(un, 1, a, side == 0);
+        const double jm = side == 1 ? tself - tn : tn - tself;
+        c = (1.0 / hy) * jm;
+      } else {
+        c = (side == 1 ? 1.0 : -1.0) * (2.0 / hy) * tself;
+      }
+#pragma unroll
+      for (int b = 0; b < K; ++b) out[b][a] += c * e_end(b, side == 1);
+    }
+  }
+  double* qe = q + g * (K * K);
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+#pragma unroll
+    for (int a = 0; a < K; ++a) qe[b * K + a] = out[b][a];
+}
+
+template <int K1>
+__device__ __forceinline__ double ptrace_x(const double* qe, int j, int plus) {
+  constexpr int K = K1 - 1;
+  double s = 0;
+#pragma unroll
+  for (int a = 0; a < K; ++a) s += e_end(a, plus) * qe[j * K + a];
+  return s;
+}
+template <int K1>
+__device__ __forceinline__ double ptrace_y(const double* qe, int i, int plus) {
+  constexpr int K = K1 - 1;
+  double s = 0;
+#pragma unroll
+  for (int b = 0; b < K; ++b) s += e_end(b, plus) * qe[b * K + i];
+  return s;
+}
+
+template <int K1>
+__global__ __launch_bounds__(256) void grad_kernel(MeshDev M, const double* __restrict__ p,
+                                                   double* __restrict__ v, int64_t nel_total) {
+  constexpr int K = K1 - 1, KK = K1 * K1, NB = 2 * KK, NP = K * K;
+  const int64_t g2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g2 >= 2 * nel_total) return;
+  const int64_t g = g2 >> 1;
+  const int d = (int)(g2 & 1);
+  const int nel = M.nx * M.ny;
+  const int64_t pb = g / nel;
+  const int e = (int)(g - pb * nel);
+  const int ix = e % M.nx, iy = e / M.nx;
+  const double* qe = p + g * NP;
+  const double hx = M.hx, hy = M.hy;
+  double out[K1][K1];
+  if (d == 0) {
+#pragma unroll
+    for (int j = 0; j < K1; ++j)
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        double s = 0;
+        if (j < K) {
+#pragma unroll
+          for (int m = 0; m < K; ++m)
+            if (d_nz(m, i)) s += d_val(m, i) * qe[j * K + m];
+        }
+        out[j][i] = -(2.0 / hx) * s;
+      }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int nbx = side == 0 ? ix - 1 : ix + 1;
+      const bool interior = nbx >= 0 && nbx < M.nx;
+      const int kind = interior ? F_INTERIOR : M.bc[side];
+      if (kind == F_NEUMANN) continue;
+      const double* qn = qe + (int64_t)(nbx - ix) * NP;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const double qs = ptrace_x<K1>(qe, j, side == 1);
+        double c;
+        if (interior) {
+          const double qa = 0.5 * (qs + ptrace_x<K1>(qn, j, side == 0));
+          c = (side == 1 ? 1.0 : -1.0) * (2.0 / hx) * qa;
+        } else {
+          c = (side == 1 ? 1.0 : -1.0) * (2.0 / hx) * qs;
+        }
+#pragma unroll
+        for (int i = 0; i < K1; ++i) out[j][i] += c * e_end(i, side == 1);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K1; ++j)
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        double s = 0;
+        if (i < K) {
+#pragma unroll
+          for (int m = 0; m < K; ++m)
+            if (d_nz(m, j)) s += d_val(m, j) * qe[m * K + i];
+        }
+        out[j][i] = -(2.0 / hy) * s;
+      }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int nby = side == 0 ? iy - 1 : iy + 1;
+      const bool interior = nby >= 0 && nby < M.ny;
+      const int kind = interior ? F_INTERIOR : M.bc[2 + side];
+      if (kind == F_NEUMANN) continue;
+      const double* qn = qe + (int64_t)(nby - iy) * M.nx * NP;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const double qs = ptrace_y<K1>(qe, i, side == 1);
+        double c;
+        if (interior) {
+          const double qa = 0.5 * (qs + ptrace_y<K1>(qn, i, side == 0));
+          c = (side == 1 ? 1.0 : -1.0) * (2.0 / hy) * qa;
+        } else {
+          c = (side == 1 ? 1.0 : -1.0) * (2.0 / hy) * qs;
+        }
+#pragma unroll
+        for (int j = 0; j < K1; ++j) out[j][i] += c * e_end(j, side == 1);
+      }
+    }
+  }
+  double* ve = v + g * NB + d * KK;
+#pragma unroll
+  for (int j = 0; j < K1; ++j)
+#pragma unroll
+    for (int i = 0; i < K1; ++i) ve[j * K1 + i] = out[j][i];
+}
+
+// ---------------------------------------------------------------------------
+// right-hand sides: F = f + Dirichlet lift, G = int q (g.n) on Dirichlet sides
+// ---------------------------------------------------------------------------
+template <int K1>
+__global__ __launch_bounds__(256) void rhs_kernel(MeshDev M, const double* __restrict__ eta,
+                                                  const double* __restrict__ f,
+                                                  const double* __restrict__ gdir,
+                                                  double* __restrict__ F, double* __restrict__ G) {
+  constexpr int K = K1 - 1, KK = K1 * K1, NB = 2 * KK;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nel = M.nx * M.ny;
+  if (e >= nel) return;
+  const int ix = e % M.nx, iy = e / M.nx;
+  double* Fe = F + (int64_t)e * NB;
+  for (int a = 0; a < NB; ++a) Fe[a] = f[(int64_t)e * NB + a];
+  double* Ge = G + (int64_t)e * K * K;
+  for (int a = 0; a < K * K; ++a) Ge[a] = 0.0;
+  if (gdir == nullptr) return;
+  // sides of this element on the boundary: 0 left, 1 right, 2 bottom, 3 top
+  for (int side = 0; side < 4; ++side) {
+    bool on = (side == 0 && ix == 0) || (side == 1 && ix == M.nx - 1) || (side == 2 && iy == 0) ||
+              (side == 3 && iy == M.ny - 1);
+    if (!on || M.bc[side] != F_DIRICHLET) continue;
+    const int fi = side == 0 ? iy : side == 1 ? M.ny + iy : side == 2 ? 2 * M.ny + ix : 2 * M.ny + M.nx + ix;
+    const int dir = side < 2 ? 0 : 1;
+    const double hn = dir == 0 ? M.hx : M.hy, ht = dir == 0 ? M.hy : M.hx;
+    const double sc = sqrt(hn / 2.0);
+    // face coefficients with the inner trace zero and the outer trace g
+    double tr[8 * K1];
+    for (int z = 0; z < 8 * K1; ++z) tr[z] = 0.0;
+    const int present = (side == 1 || side == 3) ? 0 : 1;  // right/top: element is minus side
+    const int absent = 1 - present;
+    for (int d = 0; d < 2; ++d)
+      for (int m = 0; m < K1; ++m) tr[((absent * 2 + d) * 2 + 0) * K1 + m] = sc * gdir[((int64_t)fi * 2 + d) * K1 + m];
+    const double e2 = 2.0 * eta[e];
+    if (dir == 0)
+      face_coefs<K1, 0, double>(tr, F_INTERIOR, 0, present == 0 ? e2 : 0.0, present == 1 ? e2 : 0.0, hn, ht, false, false);
+    else
+      face_coefs<K1, 1, double>(tr, F_INTERIOR, 0, present == 0 ? e2 : 0.0, present == 1 ? e2 : 0.0, hn, ht, false, false);
+    // face_coefs used alpha = 4 max(eta^-, eta^+) K1^2/hn = 8 eta K1^2 / hn
+    const int plus_end = present == 0;  // the element's end at this face
+    for (int d = 0; d < 2; ++d)
+      for (int m = 0; m < K1; ++m) {
+        const double av = tr[((present * 2 + d) * 2 + 0) * K1 + m];
+        const double bv = tr[((present * 2 + d) * 2 + 1) * K1 + m];
+        for (int o = 0; o < K1; ++o) {
+          const double add = av * e_end(o, plus_end) + bv * d_end(o, plus_end);
+          if (dir == 0) Fe[d * KK + m * K1 + o] -= add;  // mode m along y, o along x
+          else Fe[d * KK + o * K1 + m] -= add;           // mode m along x, o along y
+        }
+      }
+    // G: int q (g.n)
+    const double sgn = present == 0 ? 1.0 : -1.0;
+    const int dn = dir;  // normal component
+    for (int m = 0; m < K; ++m) {
+      const double gn = sc * gdir[((int64_t)fi * 2 + dn) * K1 + m];
+      for (int o = 0; o < K; ++o) {
+        const double add = sgn * (2.0 / hn) * e_end(o, plus_end) * gn;
+        if (dir == 0) Ge[m * K + o] += add;
+        else Ge[o * K + m] += add;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int K1, int MODE, typename T>
+static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
+                       double* out_mat, hipStream_t s) {
+  constexpr int TX = Tile<K1>::TX, TY = Tile<K1>::TY;
+  const int ntiles = ceil_div(M.nx, TX) * ceil_div(M.ny, TY);
+  const int64_t stride = (int64_t)M.nx * M.ny * 2 * K1 * K1;
+  hipLaunchKernelGGL((sip_tile_kernel<K1, MODE, T, TX, TY>), dim3(ntiles, nbatch), dim3(NT), 0, s,
+                     M, u, b, y, eta, out_mat, nullptr, stride);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+template <int K1>
+static int launch_block_list(const MeshDev& M, const double* eta, const int* elems, int nlist,
+                             double* blocks, hipStream_t s) {
+  if (nlist <= 0) return SDG_OK;
+  hipLaunchKernelGGL((sip_tile_kernel<K1, M_BLOCKCOL, double, 1, 1>), dim3(nlist, 1), dim3(NT), 0,
+                     s, M, nullptr, nullptr, nullptr, eta, blocks, elems, (int64_t)0);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+#define SDG_K1_SWITCH(k1, CALL)                 \
+  switch (k1) {                                 \
+    case 2: { constexpr int KK1 = 2; CALL; } break; \
+    case 3: { constexpr int KK1 = 3; CALL; } break; \
+    case 4: { constexpr int KK1 = 4; CALL; } break; \
+    case 5: { constexpr int KK1 = 5; CALL; } break; \
+    case 6: { constexpr int KK1 = 6; CALL; } break; \
+    case 7: { constexpr int KK1 = 7; CALL; } break; \
+    default: set_error("order k out of range"); return SDG_ERR_INVALID; \
+  }
+
+int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
+              hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, double>(M, nbatch, u, nullptr, y, eta, nullptr, s)));
+  return SDG_OK;
+}
+int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
+                 const double* u, double* r, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, double>(M, nbatch, u, b, r, eta, nullptr, s)));
+  return SDG_OK;
+}
+int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
+                  hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, float>(M, nbatch, u, nullptr, y, eta, nullptr, s)));
+  return SDG_OK;
+}
+int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
+                     const float* u, float* r, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, float>(M, nbatch, u, b, r, eta, nullptr, s)));
+  return SDG_OK;
+}
+int sip_block_list(const MeshDev& M, int k, const double* eta, const int* elems, int nlist,
+                   double* blocks, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_block_list<KK1>(M, eta, elems, nlist, blocks, s)));
+  return SDG_OK;
+}
+int sip_coarse_local(const MeshDev& M, int k, int nbatch, const double* eta, double* clocal,
+                     hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_COARSECOL, double>(M, nbatch, nullptr, nullptr, nullptr, eta, clocal, s)));
+  return SDG_OK;
+}
+int div_apply(const MeshDev& M, int k, int nbatch, const double* u, double* q, hipStream_t s) {
+  const int64_t n = (int64_t)M.nx * M.ny * nbatch;
+  SDG_K1_SWITCH(k + 1, hipLaunchKernelGGL((div_kernel<KK1>), dim3(ceil_div(n, 256)), dim3(256), 0, s, M, u, q, n));
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int grad_apply(const MeshDev& M, int k, int nbatch, const double* p, double* v, hipStream_t s) {
+  const int64_t n = (int64_t)M.nx * M.ny * nbatch;
+  SDG_K1_SWITCH(k + 1, hipLaunchKernelGGL((grad_kernel<KK1>), dim3(ceil_div(2 * n, 256)), dim3(256), 0, s, M, p, v, n));
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int rhs_assemble(const MeshDev& M, int k, const double* eta, const double* f, const double* g,
+                 double* F, double* G, hipStream_t s) {
+  const int nel = M.nx * M.ny;
+  SDG_K1_SWITCH(k + 1, hipLaunchKernelGGL((rhs_kernel<KK1>), dim3(ceil_div(nel, 256)), dim3(256), 0, s, M, eta, f, g, F, G));
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+}  // namespace sdg

@@ -1,0 +1,339 @@
+// Vector updates, deterministic two-stage reductions, the SplitMix64 start
+// vectors and the small Hessenberg eigenvalue solve behind the Chebyshev
+// bounds (Section 6: lambda* from ten GMRES/Arnoldi steps).
+#include "sdg_common.h"
+#include "sdg_kernels.h"
+
+namespace sdg {
+
+constexpr int VT = 256;
+constexpr int RED_BLOCKS = 512;  // fixed partial count: reductions are deterministic
+
+__global__ void copy_kernel(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = x[g];
+}
+__global__ void scale_copy_kernel(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = a * x[g];
+}
+__global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] += a * x[g];
+}
+__global__ void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = a * x[g] + b * y[g];
+}
+__global__ void mul_kernel(int64_t n, const double* __restrict__ d, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = d[g] * x[g];
+}
+// mode 0: d = a d + b z, x += d;  mode 1: d = b z, x = d;  mode 2: d = b z, x += d
+template <typename T>
+__global__ void cheb_kernel(int64_t n, double a, const T* __restrict__ z, double b, T* __restrict__ d,
+                            T* __restrict__ x, int mode) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    const T dv = mode == 0 ? T(a * double(d[g]) + b * double(z[g])) : T(b * double(z[g]));
+    d[g] = dv;
+    x[g] = mode == 1 ? dv : T(x[g] + dv);
+  }
+}
+__global__ void d2f_kernel(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = (float)x[g];
+}
+__global__ void f2d_kernel(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) y[g] = (double)x[g];
+}
+
+static inline int grid_for(int64_t n) {
+  int64_t b = (n + VT - 1) / VT;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+#define VLAUNCH(kern, n, ...)                                                         \
+  do {                                                                               \
+    if ((n) > 0) hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(VT), 0, s, n, __VA_ARGS__); \
+    SDG_CHECK_LAUNCH();                                                              \
+  } while (0)
+
+int vec_copy(int64_t n, const double* x, double* y, hipStream_t s) { VLAUNCH(copy_kernel, n, x, y); return SDG_OK; }
+int vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) { VLAUNCH(scale_copy_kernel, n, a, x, y); return SDG_OK; }
+int vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) { VLAUNCH(axpy_kernel, n, a, x, y); return SDG_OK; }
+int vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) { VLAUNCH(axpby_kernel, n, a, x, b, y); return SDG_OK; }
+int vec_mul(int64_t n, const double* d, const double* x, double* y, hipStream_t s) { VLAUNCH(mul_kernel, n, d, x, y); return SDG_OK; }
+int cheb_update(int64_t n, double a, const double* z, double b, double* d, double* x, int mode, hipStream_t s) {
+  VLAUNCH(cheb_kernel<double>, n, a, z, b, d, x, mode);
+  return SDG_OK;
+}
+int cheb_update_f32(int64_t n, double a, const float* z, double b, float* d, float* x, int mode, hipStream_t s) {
+  VLAUNCH(cheb_kernel<float>, n, a, z, b, d, x, mode);
+  return SDG_OK;
+}
+int d2f(int64_t n, const double* x, float* y, hipStream_t s) { VLAUNCH(d2f_kernel, n, x, y); return SDG_OK; }
+int f2d(int64_t n, const float* x, double* y, hipStream_t s) { VLAUNCH(f2d_kernel, n, x, y); return SDG_OK; }
+
+// ---------------------------------------------------------------------------
+// reductions: stage 1 writes RED_BLOCKS partials per output, stage 2 sums
+// them in a fixed order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[VT / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < VT / 64; ++i) t += red[i];
+  return t;
+}
+
+// partial[j][blk] = sum over the block's slice of V_j . w
+__global__ __launch_bounds__(VT) void multidot_stage1(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w, double* __restrict__ part) {
+  const int j = blockIdx.y;
+  const double* v = V + j * ldv;
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) s += v[g] * w[g];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+}
+__global__ __launch_bounds__(VT) void reduce_stage2(int nparts, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += VT) s += part[(int64_t)j * nparts + i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+static inline int red_blocks(int64_t n) {
+  int64_t b = (n + VT - 1) / VT;
+  return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
+}
+
+int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,
+              double* scratch, hipStream_t s) {
+  if (m <= 0) return SDG_OK;
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(multidot_stage1, dim3(nb, m), dim3(VT), 0, s, n, V, ldv, w, scratch);
+  SDG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_stage2, dim3(m), dim3(VT), 0, s, nb, scratch, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int dot(int64_t n, const double* x, const double* y, double* out, double* scratch, hipStream_t s) {
+  return multi_dot(n, 1, x, 0, y, out, scratch, s);
+}
+
+// w -= sum_j h[j] V_j
+__global__ void multi_axpy_kernel(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
+                                  const double* __restrict__ h, double* __restrict__ w) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    double s = w[g];
+    for (int j = 0; j < m; ++j) s -= h[j] * V[j * ldv + g];
+    w[g] = s;
+  }
+}
+// y += sum_j h[j] V_j
+__global__ void multi_combine_kernel(int64_t n, int m, const double* __restrict__ V, int64_t ldv,
+                                     const double* __restrict__ h, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    double s = y[g];
+    for (int j = 0; j < m; ++j) s += h[j] * V[j * ldv + g];
+    y[g] = s;
+  }
+}
+int multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s) {
+  VLAUNCH(multi_axpy_kernel, n, m, V, ldv, h, w);
+  return SDG_OK;
+}
+int multi_combine(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* y, hipStream_t s) {
+  VLAUNCH(multi_combine_kernel, n, m, V, ldv, h, y);
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 in counter form: z_i = mix(seed + (i+1) * 0x9E3779B97F4A7C15)
+// ---------------------------------------------------------------------------
+__global__ void splitmix_kernel(int64_t n, uint64_t seed, double* __restrict__ out) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    uint64_t z = seed + (uint64_t)(g + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    out[g] = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+  }
+}
+int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s) {
+  VLAUNCH(splitmix_kernel, n, seed, out);
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pressure mean removal: subtract the mean of the constant modes (uniform
+// elements, so c = sqrt|K| on every constant mode)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(VT) void pmean_stage1(int64_t nel, int np, const double* __restrict__ p,
+                                                   double* __restrict__ part) {
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < nel; g += (int64_t)gridDim.x * VT) s += p[g * np];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ void pmean_sub(int64_t nel, int np, const double* __restrict__ sum, double* __restrict__ p) {
+  const double m = sum[0] / (double)nel;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < nel; g += (int64_t)gridDim.x * VT) p[g * np] -= m;
+}
+int pressure_project(int64_t nel, int np, double* p, double* scratch, hipStream_t s) {
+  const int nb = red_blocks(nel);
+  hipLaunchKernelGGL(pmean_stage1, dim3(nb), dim3(VT), 0, s, nel, np, p, scratch);
+  SDG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(VT), 0, s, nb, scratch, scratch + RED_BLOCKS);
+  SDG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(pmean_sub, dim3(grid_for(nel)), dim3(VT), 0, s, nel, np, scratch + RED_BLOCKS, p);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// eigenvalues of a small upper Hessenberg matrix: Francis double-shift QR
+// with deflation on the active window (Golub & Van Loan, Matrix
+// Computations, Sections 7.5.2-7.5.6); returns the largest real part.
+// ---------------------------------------------------------------------------
+constexpr int HMAX = 32;
+
+__device__ void house3(double x, double y, double z, double* v, double* beta) {
+  const double nrm = sqrt(x * x + y * y + z * z);
+  if (nrm == 0.0) {
+    v[0] = 1.0; v[1] = v[2] = 0.0; *beta = 0.0;
+    return;
+  }
+  const double alpha = x >= 0.0 ? -nrm : nrm;
+  v[0] = x - alpha; v[1] = y; v[2] = z;
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  *beta = vv > 0.0 ? 2.0 / vv : 0.0;
+}
+
+__global__ void hess_eig_kernel(const double* __restrict__ Hin, int m, int ld, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double H[HMAX][HMAX];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) H[i][j] = (i <= j + 1) ? Hin[(int64_t)j * ld + i] : 0.0;
+  double wr[HMAX];
+  double gersh = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < m; ++j) r += fabs(H[i][j]);
+    gersh = r > gersh ? r : gersh;
+  }
+  const double eps = 2.220446049250313e-16;
+  int p = m - 1;
+  int its = 0;
+  bool ok = true;
+  while (p >= 0) {
+    // deflation: find the start l of the unreduced active block ending at p
+    int l = p;
+    while (l > 0) {
+      double sc = fabs(H[l - 1][l - 1]) + fabs(H[l][l]);
+      if (sc == 0.0) sc = gersh;
+      if (fabs(H[l][l - 1]) <= eps * sc) {
+        H[l][l - 1] = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == p) {
+      wr[p] = H[p][p];
+      --p;
+      its = 0;
+      continue;
+    }
+    if (l == p - 1) {
+      const double a = H[p - 1][p - 1], b = H[p - 1][p], c = H[p][p - 1], d = H[p][p];
+      const double half = 0.5 * (a - d), disc = half * half + b * c;
+      const double mid = 0.5 * (a + d);
+      if (disc >= 0.0) {
+        const double r = sqrt(disc);
+        wr[p - 1] = mid + r;
+        wr[p] = mid - r;
+      } else {
+        wr[p - 1] = wr[p] = mid;
+      }
+      p -= 2;
+      its = 0;
+      continue;
+    }
+    if (++its > 200) {
+      ok = false;
+      break;
+    }
+    // shifts: eigenvalues of the trailing 2x2 (exceptional shift every 11 steps)
+    double sh, tt;
+    if (its % 11 == 10) {
+      const double w = fabs(H[p][p - 1]) + fabs(H[p - 1][p - 2]);
+      sh = H[p][p] + 1.5 * w;
+      tt = sh * sh / 4.0 + w * w;
+    } else {
+      sh = H[p - 1][p - 1] + H[p][p];
+      tt = H[p - 1][p - 1] * H[p][p] - H[p - 1][p] * H[p][p - 1];
+    }
+    double x = H[l][l] * H[l][l] + H[l][l + 1] * H[l + 1][l] - sh * H[l][l] + tt;
+    double y = H[l + 1][l] * (H[l][l] + H[l + 1][l + 1] - sh);
+    double z = H[l + 1][l] * H[l + 2][l + 1];
+    for (int k = l; k <= p - 2; ++k) {
+      double v[3], beta;
+      house3(x, y, z, v, &beta);
+      const int c0 = k > l ? k - 1 : l;
+      for (int c = c0; c <= p; ++c) {
+        const double w = beta * (v[0] * H[k][c] + v[1] * H[k + 1][c] + v[2] * H[k + 2][c]);
+        H[k][c] -= w * v[0];
+        H[k + 1][c] -= w * v[1];
+        H[k + 2][c] -= w * v[2];
+      }
+      const int r1 = (k + 3 < p) ? k + 3 : p;
+      for (int r = l; r <= r1; ++r) {
+        const double w = beta * (H[r][k] * v[0] + H[r][k + 1] * v[1] + H[r][k + 2] * v[2]);
+        H[r][k] -= w * v[0];
+        H[r][k + 1] -= w * v[1];
+        H[r][k + 2] -= w * v[2];
+      }
+      x = H[k + 1][k];
+      y = H[k + 2][k];
+      if (k < p - 2) z = H[k + 3][k];
+    }
+    // final Givens rotation on rows/cols p-1, p
+    const double rr = sqrt(x * x + y * y);
+    if (rr > 0.0) {
+      const double cg = x / rr, sg = y / rr;
+      for (int c = p - 2; c <= p; ++c) {
+        const double a1 = H[p - 1][c], a2 = H[p][c];
+        H[p - 1][c] = cg * a1 + sg * a2;
+        H[p][c] = -sg * a1 + cg * a2;
+      }
+      for (int r = l; r <= p; ++r) {
+        const double a1 = H[r][p - 1], a2 = H[r][p];
+        H[r][p - 1] = cg * a1 + sg * a2;
+        H[r][p] = -sg * a1 + cg * a2;
+      }
+    }
+  }
+  double best = -1e300;
+  if (ok) {
+    for (int i = 0; i < m; ++i) best = wr[i] > best ? wr[i] : best;
+  } else {
+    best = gersh;
+  }
+  out[0] = best;
+}
+
+int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t s) {
+  if (m < 1 || m > HMAX) {
+    set_error("hessenberg size out of range");
+    return SDG_ERR_INVALID;
+  }
+  hipLaunchKernelGGL(hess_eig_kernel, dim3(1), dim3(64), 0, s, H, m, ld, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+}  // namespace sdg

@@ -1,0 +1,337 @@
+"""ctypes binding of libsdg.so (the C ABI declared in include/sdg.h).
+
+Argument marshalling only: every function forwards to the library entry
+point of the same name.  Device arrays are torch tensors on the GPU (their
+data_ptr() is passed); host arrays are numpy arrays.  The library is
+required: importing this module on a machine where it is not built raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libsdg.so")
+
+NAVIER, NEUMANN, DIRICHLET = 0, 1, 2
+FP64, FP32, BF16 = 0, 1, 2
+OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+NOT_CONVERGED, BREAKDOWN = 1, 2
+
+
+class sdg_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("k", ctypes.c_int32), ("bc", ctypes.c_int32 * 4)]
+
+
+class sdg_options(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("max_it", ctypes.c_int32), ("inner_max_it", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("smooth_dg", ctypes.c_int32),
+                ("smooth_h", ctypes.c_int32), ("coarsest_n", ctypes.c_int32),
+                ("eig_steps", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
+                ("cheb_hi", ctypes.c_double), ("prec_smoother", ctypes.c_int32),
+                ("prec_apply", ctypes.c_int32), ("viscous_krylov", ctypes.c_int32),
+                ("dedup", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class sdg_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_its", ctypes.c_int32),
+                ("inner_its_total", ctypes.c_int32), ("inner_its_max", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+I = ctypes.c_int
+MESH = ctypes.POINTER(sdg_mesh)
+OPTS = ctypes.POINTER(sdg_options)
+STATS = ctypes.POINTER(sdg_stats)
+
+# name -> (restype, argtypes); every symbol declared in include/sdg.h
+PROTOTYPES = {
+    "sdg_create": (I, [I, ctypes.c_size_t, PP]),
+    "sdg_destroy": (None, [P]),
+    "sdg_last_error": (ctypes.c_char_p, []),
+    "sdg_options_default": (None, [OPTS]),
+    "sdg_required_bytes": (ctypes.c_size_t, [MESH, OPTS, I]),
+    "sdg_problem_create": (I, [P, MESH, OPTS, P, P, PP]),
+    "sdg_problem_destroy": (None, [P]),
+    "sdg_problem_levels": (I, [P, ctypes.POINTER(ctypes.c_int)]),
+    "sdg_get_bounds": (I, [P, ctypes.POINTER(ctypes.c_double)]),
+    "sdg_set_bounds": (I, [P, ctypes.POINTER(ctypes.c_double)]),
+    "sdg_eig_estimate": (I, [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "sdg_apply_viscous": (I, [P, P, P]),
+    "sdg_residual_viscous": (I, [P, P, P, P]),
+    "sdg_apply_viscous_f32": (I, [P, P, P]),
+    "sdg_apply_div": (I, [P, P, P]),
+    "sdg_apply_grad": (I, [P, P, P]),
+    "sdg_apply_blockjacobi": (I, [P, P, P]),
+    "sdg_get_blocks": (I, [P, P]),
+    "sdg_p_restrict": (I, [P, P, P]),
+    "sdg_p_prolong_add": (I, [P, P, P]),
+    "sdg_get_coarse_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "sdg_vcycle": (I, [P, P, P]),
+    "sdg_assemble_rhs": (I, [P, P, P, P, P]),
+    "sdg_solve_viscous_dev": (I, [P, P, P, P, STATS]),
+    "sdg_solve_stokes_dev": (I, [P, P, P, P, P, STATS]),
+    "sdg_solve_viscous": (I, [P, MESH, OPTS, P, P, P, P, STATS]),
+    "sdg_solve_stokes": (I, [P, MESH, OPTS, P, P, P, P, P, STATS]),
+    "sdg_uniform_pm1": (I, [P, ctypes.c_uint64, ctypes.c_int64, P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run paper_1607_03777_amd.build.build()")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in PROTOTYPES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SDGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sdg error {code}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc < 0:
+        raise SDGError(rc, lib().sdg_last_error().decode())
+    return rc
+
+
+def ptr(t):
+    """Device or host pointer of a torch tensor / numpy array (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags["C_CONTIGUOUS"]
+        return t.ctypes.data
+    assert t.is_contiguous()
+    return t.data_ptr()
+
+
+def make_mesh(nx, ny, k, bc=(NAVIER,) * 4, lx=1.0, ly=1.0):
+    m = sdg_mesh()
+    m.nx, m.ny, m.lx, m.ly, m.k = nx, ny, lx, ly, k
+    for i in range(4):
+        m.bc[i] = bc[i]
+    return m
+
+
+def make_options(**kw):
+    o = sdg_options()
+    lib().sdg_options_default(ctypes.byref(o))
+    for key, v in kw.items():
+        if not hasattr(o, key):
+            raise KeyError(key)
+        setattr(o, key, v)
+    return o
+
+
+def current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---- thin wrappers with the C names ---------------------------------------
+def sdg_create(device=0, mem_budget=0):
+    out = ctypes.c_void_p()
+    check(lib().sdg_create(device, mem_budget, ctypes.byref(out)))
+    return out
+
+
+def sdg_destroy(ctx):
+    lib().sdg_destroy(ctx)
+
+
+def sdg_required_bytes(mesh, opts, stokes):
+    return lib().sdg_required_bytes(ctypes.byref(mesh), ctypes.byref(opts), int(stokes))
+
+
+def sdg_problem_create(ctx, mesh, opts, eta_dev, stream=None):
+    out = ctypes.c_void_p()
+    check(lib().sdg_problem_create(ctx, ctypes.byref(mesh), ctypes.byref(opts), ptr(eta_dev),
+                                   stream, ctypes.byref(out)))
+    return out
+
+
+def sdg_problem_destroy(prob):
+    lib().sdg_problem_destroy(prob)
+
+
+def sdg_problem_levels(prob):
+    n = ctypes.c_int()
+    check(lib().sdg_problem_levels(prob, ctypes.byref(n)))
+    return n.value
+
+
+def sdg_get_bounds(prob):
+    n = sdg_problem_levels(prob)
+    b = (ctypes.c_double * (2 * n))()
+    check(lib().sdg_get_bounds(prob, b))
+    return np.array(b[:]).reshape(n, 2)
+
+
+def sdg_set_bounds(prob, bounds):
+    b = np.ascontiguousarray(bounds, dtype=np.float64).ravel()
+    check(lib().sdg_set_bounds(prob, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
+def sdg_eig_estimate(prob, level, steps=10):
+    lam = ctypes.c_double()
+    H = np.zeros((steps, steps + 1))  # column-major (steps+1) x steps
+    check(lib().sdg_eig_estimate(prob, level, ctypes.byref(lam),
+                                 H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return lam.value, H.T.copy()
+
+
+def _op(name):
+    fn = getattr(lib(), name)
+
+    def call(prob, *arrays):
+        return check(fn(prob, *[ptr(a) for a in arrays]))
+    call.__name__ = name
+    return call
+
+
+def sdg_apply_viscous(prob, u, y):
+    return _op("sdg_apply_viscous")(prob, u, y)
+
+
+def sdg_residual_viscous(prob, b, u, r):
+    return _op("sdg_residual_viscous")(prob, b, u, r)
+
+
+def sdg_apply_viscous_f32(prob, u, y):
+    return _op("sdg_apply_viscous_f32")(prob, u, y)
+
+
+def sdg_apply_div(prob, u, q):
+    return _op("sdg_apply_div")(prob, u, q)
+
+
+def sdg_apply_grad(prob, p, v):
+    return _op("sdg_apply_grad")(prob, p, v)
+
+
+def sdg_apply_blockjacobi(prob, r, z):
+    return _op("sdg_apply_blockjacobi")(prob, r, z)
+
+
+def sdg_get_blocks(prob, blocks):
+    return _op("sdg_get_blocks")(prob, blocks)
+
+
+def sdg_p_restrict(prob, r, rc):
+    return _op("sdg_p_restrict")(prob, r, rc)
+
+
+def sdg_p_prolong_add(prob, ec, u):
+    return _op("sdg_p_prolong_add")(prob, ec, u)
+
+
+def sdg_get_coarse_stencil(prob, level, st):
+    nx, ny = ctypes.c_int(), ctypes.c_int()
+    check(lib().sdg_get_coarse_stencil(prob, level, ptr(st), ctypes.byref(nx), ctypes.byref(ny)))
+    return nx.value, ny.value
+
+
+def sdg_vcycle(prob, b, x):
+    return _op("sdg_vcycle")(prob, b, x)
+
+
+def sdg_assemble_rhs(prob, f, g, F, G):
+    return check(lib().sdg_assemble_rhs(prob, ptr(f), ptr(g), ptr(F), ptr(G)))
+
+
+def sdg_solve_viscous_dev(prob, f, g, u):
+    st = sdg_stats()
+    rc = check(lib().sdg_solve_viscous_dev(prob, ptr(f), ptr(g), ptr(u), ctypes.byref(st)))
+    return rc, st.as_dict()
+
+
+def sdg_solve_stokes_dev(prob, f, g, u, p):
+    st = sdg_stats()
+    rc = check(lib().sdg_solve_stokes_dev(prob, ptr(f), ptr(g), ptr(u), ptr(p), ctypes.byref(st)))
+    return rc, st.as_dict()
+
+
+def sdg_solve_viscous(ctx, mesh, opts, eta, f, g, u):
+    st = sdg_stats()
+    rc = check(lib().sdg_solve_viscous(ctx, ctypes.byref(mesh), ctypes.byref(opts), ptr(eta), ptr(f),
+                                       ptr(g), ptr(u), ctypes.byref(st)))
+    return rc, st.as_dict()
+
+
+def sdg_solve_stokes(ctx, mesh, opts, eta, f, g, u, p):
+    st = sdg_stats()
+    rc = check(lib().sdg_solve_stokes(ctx, ctypes.byref(mesh), ctypes.byref(opts), ptr(eta), ptr(f),
+                                      ptr(g), ptr(u), ptr(p), ctypes.byref(st)))
+    return rc, st.as_dict()
+
+
+def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
+    return check(lib().sdg_uniform_pm1(ctx, ctypes.c_uint64(seed), n, ptr(out), stream))
+
+
+# ---- convenience object ------------------------------------------------------
+class Problem:
+    """A set-up problem on the current torch stream (device tensors in/out)."""
+
+    def __init__(self, ctx, nx, ny, k, eta, bc=(NAVIER,) * 4, lx=1.0, ly=1.0, **options):
+        import torch
+        self.torch = torch
+        self.mesh = make_mesh(nx, ny, k, bc, lx, ly)
+        self.opts = make_options(**options)
+        self.nx, self.ny, self.k = nx, ny, k
+        self.nel = nx * ny
+        self.nb = 2 * (k + 1) ** 2
+        self.nu = self.nel * self.nb
+        self.np = self.nel * k * k
+        self.eta = torch.as_tensor(eta, dtype=torch.float64, device="cuda").contiguous()
+        self.ctx = ctx
+        self.h = sdg_problem_create(ctx, self.mesh, self.opts, self.eta, current_stream())
+
+    def close(self):
+        if self.h:
+            sdg_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros(self, n, dtype=None):
+        return self.torch.zeros(n, dtype=dtype or self.torch.float64, device="cuda")
+
+    def apply(self, u):
+        y = self.zeros(self.nu)
+        sdg_apply_viscous(self.h, u, y)
+        return y
+
+    def solve_viscous(self, f, g=None):
+        u = self.zeros(self.nu)
+        rc, st = sdg_solve_viscous_dev(self.h, f, g, u)
+        return u, st
+
+    def solve_stokes(self, f, g=None):
+        u = self.zeros(self.nu)
+        p = self.zeros(max(self.np, 1))
+        rc, st = sdg_solve_stokes_dev(self.h, f, g, u, p)
+        return u, p[: self.np], st

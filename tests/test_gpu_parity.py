@@ -1,0 +1,329 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances are derived from the arithmetic: a matrix-vector product in FP64
+is compared componentwise against gamma |A| |u| (the standard rounding bound,
+gamma well above n_row * eps with n_row <= 500); solves are compared against
+the oracle's direct solution at a residual tolerance tight enough for the
+stated bound.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import assemble as asm
+from oracle.direct import solve_stokes, solve_viscous
+from oracle.mesh import DIRICHLET, NAVIER, NEUMANN, Mesh
+from oracle.multigrid import (BlockJacobi, Hierarchy, arnoldi_lambda_max,
+                              p_cd, p_prolongation)
+from oracle.rng import splitmix64, uniform_pm1
+from paper_1607_03777_amd import inputs as gen
+
+from gpu_helpers import (abs_bound, assert_close_componentwise, dev, host,
+                          stencil_to_matrix)
+
+pytestmark = pytest.mark.gpu
+
+# tile shapes of the apply kernel per k+1: (TX, TY); meshes below span
+# several tiles plus a ragged tail in each direction
+RAGGED = {1: (35, 10), 2: (19, 11), 3: (19, 9), 4: (13, 9), 5: (9, 6), 6: (7, 6)}
+BCS = [(NAVIER,) * 4, (NAVIER, NEUMANN, DIRICHLET, NAVIER), (DIRICHLET, NAVIER, NEUMANN, DIRICHLET)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sdg(torch):
+    from paper_1607_03777_amd import sdg as s
+    s.lib()
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(sdg):
+    c = sdg.sdg_create(0, 0)
+    yield c
+    sdg.sdg_destroy(c)
+
+
+def make_problem(sdg, ctx, nx, ny, k, eta, bc=(NAVIER,) * 4, **opts):
+    print(f"[case] problem nx={nx} ny={ny} k={k} bc={bc} opts={opts}", flush=True)
+    return sdg.Problem(ctx, nx, ny, k, eta, bc=bc, **opts)
+
+
+def rand_eta(n, seed, decades):
+    rng = np.random.default_rng(seed)
+    return 10.0 ** rng.uniform(0, decades, n)
+
+
+# ----------------------------------------------------------------------------
+def test_splitmix64_bit_exact(sdg, ctx, torch):
+    for seed in (0, 12345, (7 << 32) + 3):
+        out = torch.empty(1000, dtype=torch.float64, device="cuda")
+        sdg.sdg_uniform_pm1(ctx, seed, 1000, out, sdg.current_stream())
+        torch.cuda.synchronize()
+        ref = uniform_pm1(seed, 1000)
+        assert np.array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("bci", [0, 1, 2])
+def test_apply_parity(sdg, ctx, torch, k, bci):
+    nx, ny = RAGGED[k]
+    bc = BCS[bci]
+    eta = rand_eta(nx * ny, 100 * k + bci, 8)
+    m = Mesh(nx, ny, k, bc=bc)
+    A = asm.assemble_A(m, eta).tocsr()
+    rng = np.random.default_rng(k)
+    u = rng.normal(size=m.nu)
+    P = make_problem(sdg, ctx, nx, ny, k, eta, bc)
+    y = P.zeros(m.nu)
+    sdg.sdg_apply_viscous(P.h, dev(u), y)
+    torch.cuda.synchronize()
+    assert_close_componentwise(host(y), A @ u, abs_bound(A, u), 1e-13 * 64)
+    # fused residual
+    b = rng.normal(size=m.nu)
+    r = P.zeros(m.nu)
+    sdg.sdg_residual_viscous(P.h, dev(b), dev(u), r)
+    torch.cuda.synchronize()
+    assert_close_componentwise(host(r), b - A @ u, abs_bound(A, u) + np.abs(b), 1e-13 * 64)
+    # FP32 apply (same kernel in single precision)
+    y32 = P.zeros(m.nu, torch.float32)
+    sdg.sdg_apply_viscous_f32(P.h, dev(u.astype(np.float32)), y32)
+    torch.cuda.synchronize()
+    u32 = u.astype(np.float32).astype(np.float64)
+    assert_close_componentwise(host(y32).astype(np.float64), A @ u32, abs_bound(A, u32), 6e-7 * 64)
+    P.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_div_grad_parity(sdg, ctx, torch, k):
+    nx, ny = RAGGED[k]
+    for bc in BCS:
+        m = Mesh(nx, ny, k, bc=bc)
+        B = asm.assemble_B(m).tocsr()
+        rng = np.random.default_rng(7 + k)
+        u = rng.normal(size=m.nu)
+        p = rng.normal(size=m.np_)
+        P = make_problem(sdg, ctx, nx, ny, k, np.ones(m.nel), bc)
+        q = P.zeros(m.np_)
+        v = P.zeros(m.nu)
+        sdg.sdg_apply_div(P.h, dev(u), q)
+        sdg.sdg_apply_grad(P.h, dev(p), v)
+        torch.cuda.synchronize()
+        assert_close_componentwise(host(q), B.T @ u, abs(B.T) @ np.abs(u), 1e-12)
+        assert_close_componentwise(host(v), B @ p, abs(B) @ np.abs(p), 1e-12)
+        P.close()
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+@pytest.mark.parametrize("dedup", [0, 1])
+def test_blocks_and_blockjacobi(sdg, ctx, torch, k, dedup):
+    nx, ny = 6, 5
+    bc = (NAVIER, NEUMANN, DIRICHLET, NAVIER)
+    # a two-phase field so that dedup actually shares blocks
+    eta = np.where(np.arange(nx * ny) % 3 == 0, 1e4, 1.0)
+    m = Mesh(nx, ny, k, bc=bc)
+    Ad = asm.assemble_A(m, eta)
+    BJ = BlockJacobi(Ad, m.nbu)
+    P = make_problem(sdg, ctx, nx, ny, k, eta, bc, dedup=dedup)
+    blocks = P.zeros(m.nel * m.nbu * m.nbu)
+    sdg.sdg_get_blocks(P.h, blocks)
+    torch.cuda.synchronize()
+    G = host(blocks).reshape(m.nel, m.nbu, m.nbu)
+    scale = np.abs(BJ.blocks).max(axis=(1, 2))
+    assert np.max(np.abs(G - BJ.blocks).max(axis=(1, 2)) / scale) <= 1e-13
+    rng = np.random.default_rng(3)
+    r = rng.normal(size=m.nu)
+    z = P.zeros(m.nu)
+    sdg.sdg_apply_blockjacobi(P.h, dev(r), z)
+    torch.cuda.synchronize()
+    zr = BJ(r)
+    # inverse applied: error bounded by cond(block) * eps; blocks here have
+    # cond <= ~1e7, so compare at 1e-8 relative per element
+    Z, ZR = host(z).reshape(m.nel, -1), zr.reshape(m.nel, -1)
+    assert np.max(np.linalg.norm(Z - ZR, axis=1) / np.linalg.norm(ZR, axis=1)) <= 1e-8
+    P.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_p_transfer_parity(sdg, ctx, torch, k):
+    nx, ny = 9, 6
+    m = Mesh(nx, ny, k)
+    Pf = (p_prolongation(m) @ p_cd(m)).tocsr()
+    P = make_problem(sdg, ctx, nx, ny, k, np.ones(m.nel))
+    rng = np.random.default_rng(11)
+    r = rng.normal(size=m.nu)
+    nn2 = 2 * (nx + 1) * (ny + 1)
+    rc = P.zeros(nn2)
+    sdg.sdg_p_restrict(P.h, dev(r), rc)
+    ec = rng.normal(size=nn2)
+    u0 = rng.normal(size=m.nu)
+    u = dev(u0)
+    sdg.sdg_p_prolong_add(P.h, dev(ec), u)
+    torch.cuda.synchronize()
+    assert np.allclose(host(rc), Pf.T @ r, rtol=1e-13, atol=1e-13 * np.abs(r).max())
+    assert np.allclose(host(u), u0 + Pf @ ec, rtol=1e-13, atol=1e-13 * np.abs(ec).max())
+    P.close()
+
+
+@pytest.mark.parametrize("k,bc", [(2, (NAVIER,) * 4), (3, (NAVIER, NEUMANN, DIRICHLET, NAVIER))])
+def test_coarse_operators_parity(sdg, ctx, torch, k, bc):
+    nx, ny = 32, 16
+    eta = rand_eta(nx * ny, 5, 4)
+    m = Mesh(nx, ny, k, bc=bc)
+    H = Hierarchy(m, eta, coarsest_n=4)
+    P = make_problem(sdg, ctx, nx, ny, k, eta, bc, coarsest_n=4)
+    nlev = sdg.sdg_problem_levels(P.h)
+    assert nlev - 1 == len(H.levels)
+    for li, lev in enumerate(H.levels):
+        nn = (lev.nx + 1) * (lev.ny + 1)
+        st = P.zeros(36 * nn)
+        gx, gy = sdg.sdg_get_coarse_stencil(P.h, li, st)
+        torch.cuda.synchronize()
+        assert (gx, gy) == (lev.nx, lev.ny)
+        G = stencil_to_matrix(host(st), gx, gy)
+        R = lev.A.toarray()
+        assert np.abs(G - R).max() <= 1e-12 * np.abs(R).max(), li
+    P.close()
+
+
+def test_eig_estimates_parity(sdg, ctx, torch):
+    nx = ny = 16
+    k = 2
+    eta = rand_eta(nx * ny, 9, 3)
+    m = Mesh(nx, ny, k)
+    H = Hierarchy(m, eta, coarsest_n=4, seed=77)
+    P = make_problem(sdg, ctx, nx, ny, k, eta, coarsest_n=4, seed=77)
+    gb = sdg.sdg_get_bounds(P.h)
+    for li, (lo, hi) in enumerate(H.bounds):
+        assert gb[li, 1] == pytest.approx(hi, rel=1e-9), li
+        assert gb[li, 0] == pytest.approx(lo, rel=1e-9), li
+    P.close()
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_vcycle_parity(sdg, ctx, torch, k):
+    nx = ny = 16
+    P0 = gen.single_inclusion(nx, k, eta_in=1e4)
+    m = Mesh(nx, ny, k)
+    H = Hierarchy(m, P0.eta, coarsest_n=4)
+    P = make_problem(sdg, ctx, nx, ny, k, P0.eta, coarsest_n=4)
+    b = np.zeros((len(H.bounds) + 1, 2))
+    b[: len(H.bounds)] = H.bounds
+    sdg.sdg_set_bounds(P.h, b)
+    rng = np.random.default_rng(2)
+    r = rng.normal(size=m.nu)
+    x = P.zeros(m.nu)
+    sdg.sdg_vcycle(P.h, dev(r), x)
+    torch.cuda.synchronize()
+    xr = H.vcycle(r)
+    # the coarsest solve differs in rounding (explicit inverse vs Cholesky
+    # solves): allow cond(A_coarsest) * eps amplification
+    kc = np.linalg.cond(H.levels[-1].A.toarray())
+    tol = max(1e-11, 50.0 * kc * 2.2e-16)
+    assert np.linalg.norm(host(x) - xr) <= tol * np.linalg.norm(xr), (tol, kc)
+    P.close()
+
+
+@pytest.mark.parametrize("n,k,contrast,bc,tol", [
+    (16, 2, 1e4, (NAVIER,) * 4, 1e-9),
+    (12, 3, 1e4, (NAVIER, NEUMANN, NAVIER, NAVIER), 1e-9),
+    (8, 5, 1e2, (DIRICHLET,) * 4, 1e-9),
+    (5, 4, 1e3, (NAVIER,) * 4, 1e-9),
+    # random element viscosity over six decades: the direct solution itself
+    # carries cond(A) * eps ~ 1e-8 relative error, so the bar is 1e-7 here
+    (12, 3, 1e6, (NAVIER,) * 4, 1e-7),
+])
+def test_viscous_solve_parity(sdg, ctx, torch, n, k, contrast, bc, tol):
+    P0 = gen.random_problem(n, k, 4, contrast=contrast, bc=bc)
+    m = Mesh(n, n, k, bc=bc)
+    ud = solve_viscous(m, P0.eta, P0.f)
+    P = make_problem(sdg, ctx, n, n, k, P0.eta, bc, rtol=1e-13, max_it=3000, coarsest_n=4)
+    u, st = P.solve_viscous(dev(P0.f.reshape(-1)))
+    assert st["status"] == 0, st
+    assert np.linalg.norm(host(u) - ud) <= tol * np.linalg.norm(ud), st
+    P.close()
+
+
+def test_stokes_manufactured(sdg, ctx, torch):
+    """Exact polynomial Stokes solution with Dirichlet data (velocity Q_2,
+    pressure Q_1): the discrete solution is the exact one."""
+    P0 = gen.manufactured_stokes(8, 2)
+    P = make_problem(sdg, ctx, 8, 8, 2, P0.eta, P0.bc, rtol=1e-12, inner_rtol=1e-6,
+                     coarsest_n=4, max_it=400)
+    u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)), dev(P0.g.reshape(-1)))
+    assert st["status"] == 0, st
+    ue, pe = P0.meta["u_exact"], P0.meta["p_exact"]
+    assert np.linalg.norm(host(u) - ue) <= 1e-8 * np.linalg.norm(ue), st
+    assert np.linalg.norm(host(p) - pe) <= 1e-6 * np.linalg.norm(pe), st
+    P.close()
+
+
+# rtol: the smallest true residual FGMRES reaches in FP64 on each case (the
+# Neumann case stagnates near 3e-12)
+@pytest.mark.parametrize("n,k,ein,bc,rtol", [(8, 2, 1e2, (NAVIER,) * 4, 1e-12),
+                                            (6, 3, 1e3, (NAVIER, NAVIER, NAVIER, NEUMANN), 1e-11)])
+def test_stokes_solve_parity(sdg, ctx, torch, n, k, ein, bc, rtol):
+    P0 = gen.single_inclusion(n, k, eta_in=ein)
+    m = Mesh(n, n, k, bc=bc)
+    ud, pd = solve_stokes(m, P0.eta, P0.f)
+    P = make_problem(sdg, ctx, n, n, k, P0.eta, bc, rtol=rtol, inner_rtol=1e-6, coarsest_n=4,
+                     max_it=600)
+    u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)))
+    assert st["status"] == 0, st
+    assert np.linalg.norm(host(u) - ud) <= 1e-9 * np.linalg.norm(ud), st
+    assert np.linalg.norm(host(p) - pd) <= 1e-7 * np.linalg.norm(pd), st
+    P.close()
+
+
+def test_error_paths(sdg, ctx, torch):
+    import ctypes
+    L = sdg.lib()
+    eta = dev(np.ones(16))
+    for mesh, e, code in [
+        (sdg.make_mesh(4, 4, 7), eta, sdg.ERR_INVALID),            # k out of range
+        (sdg.make_mesh(0, 4, 2), eta, sdg.ERR_INVALID),            # empty mesh
+        (sdg.make_mesh(4, 4, 2, bc=(NEUMANN,) * 4), eta, sdg.ERR_UNSUPPORTED),
+        (sdg.make_mesh(4, 4, 2), dev(-np.ones(16)), sdg.ERR_INVALID),
+        (sdg.make_mesh(4, 4, 2), dev(np.full(16, np.nan)), sdg.ERR_INVALID),
+    ]:
+        out = ctypes.c_void_p()
+        rc = L.sdg_problem_create(ctx, ctypes.byref(mesh), ctypes.byref(sdg.make_options()),
+                                  sdg.ptr(e), None, ctypes.byref(out))
+        assert rc == code, (rc, sdg.lib().sdg_last_error())
+    # memory budget too small
+    small = sdg.sdg_create(0, 1024)
+    out = ctypes.c_void_p()
+    rc = L.sdg_problem_create(small, ctypes.byref(sdg.make_mesh(4, 4, 2)),
+                              ctypes.byref(sdg.make_options()), sdg.ptr(eta), None, ctypes.byref(out))
+    assert rc == sdg.ERR_NOMEM
+    sdg.sdg_destroy(small)
+    # iteration limit reached -> soft outcome with the last iterate
+    P0 = gen.random_problem(8, 2, 1, contrast=1e3)
+    P = make_problem(sdg, ctx, 8, 8, 2, P0.eta, max_it=1, rtol=1e-12)
+    u, st = P.solve_viscous(dev(P0.f.reshape(-1)))
+    assert st["status"] == sdg.NOT_CONVERGED and st["outer_its"] == 1
+    P.close()
+
+
+def test_single_element_meshes(sdg, ctx, torch):
+    """Degenerate grids: one element per direction (all faces on the
+    boundary) and a 1 x n strip."""
+    for nx, ny, k in [(1, 1, 3), (1, 5, 2), (7, 1, 4)]:
+        bc = (NAVIER, DIRICHLET, NAVIER, DIRICHLET)
+        m = Mesh(nx, ny, k, bc=bc)
+        eta = rand_eta(nx * ny, 1, 3)
+        A = asm.assemble_A(m, eta).tocsr()
+        u = np.random.default_rng(0).normal(size=m.nu)
+        P = make_problem(sdg, ctx, nx, ny, k, eta, bc)
+        y = P.zeros(m.nu)
+        sdg.sdg_apply_viscous(P.h, dev(u), y)
+        torch.cuda.synchronize()
+        assert_close_componentwise(host(y), A @ u, abs_bound(A, u), 1e-13 * 64)
+        P.close()
