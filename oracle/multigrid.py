@@ -19,7 +19,8 @@ Components (Sections 5, 6, 8):
   * CG on A preconditioned by one cycle (Section 8: the preconditioner is
     linear, so CG is admissible) and right-preconditioned FGMRES on the
     Stokes system with the upper block-triangular preconditioner of eq.
-    (discretestokespc) and S* = diag(1/eta_K) (Section 5).
+    (discretestokespc) and S = -diag(1/eta_K), the viscosity-scaled pressure
+    mass matrix standing in for the Schur complement -B^T A^{-1} B (Section 5).
 
 Readings where the paper is silent (listed in the design notes too):
   * 2 Chebyshev steps before and 2 after on the DG level, 3 and 3 on every
@@ -383,8 +384,18 @@ class ViscousSolver:
 
 
 class StokesSolver:
-    """Right-preconditioned FGMRES on [A B; B^T 0] with
-    P^{-1} x: y_p = S*^{-1} x_p, y_u = (inner CG, rtol_inner)(x_u - B y_p)."""
+    """Right-preconditioned FGMRES on [A B; B^T 0] with the upper
+    block-triangular preconditioner [A B; 0 S] of eq. (discretestokespc):
+    P^{-1} x: y_p = S^{-1} x_p, y_u = (inner CG, rtol_inner)(x_u - B y_p).
+
+    S approximates the pressure Schur complement of the saddle matrix,
+    0 - B^T A^{-1} B, which is negative definite; the approximation of
+    Section 5 (pressure mass matrix scaled by 1/eta_K, diagonal in the
+    orthonormal basis) therefore enters as S = -diag(1/eta_K).  The text
+    writes the Schur complement without the minus sign; with exact blocks
+    either sign converges in two iterations, but with the inexact inner solve
+    only the negative one keeps the preconditioned spectrum on one side of
+    the origin."""
 
     def __init__(self, mesh: Mesh, eta, inner_rtol=1e-3, inner_maxit=200, **kw):
         self.mesh = mesh
@@ -413,7 +424,7 @@ class StokesSolver:
     def prec(self, x):
         nu = self.mesh.nu
         xu, xp = x[:nu], x[nu:]
-        yp = self.sinv * xp
+        yp = -self.sinv * xp
         yu, it, _ = pcg(self.h.Acsr, xu - self.B @ yp, self.h.vcycle,
                         self.inner_rtol, self.inner_maxit)
         self.inner_its.append(it)

@@ -719,10 +719,13 @@ int stokes_matvec(sdg_problem* P, const double* x, double* y) {
   return SDG_OK;
 }
 
-// upper block-triangular preconditioner: z_p = S*^{-1} v_p = eta v_p,
-// z_u = (inner CG)(v_u - B z_p)
+// upper block-triangular preconditioner [A B; 0 S] (eq. discretestokespc)
+// with S = -diag(1/eta_K), the viscosity-scaled pressure mass matrix taken
+// as an approximation of the (negative definite) Schur complement
+// -B^T A^{-1} B:  z_p = S^{-1} v_p = -eta v_p, z_u = (inner CG)(v_u - B z_p)
 int stokes_prec(sdg_problem* P, const double* v, double* z) {
   SDG_TRY(vec_mul(P->np, P->etap, v + P->nu, z + P->nu, P->s));
+  SDG_TRY(vec_scale_copy(P->np, -1.0, z + P->nu, z + P->nu, P->s));
   SDG_TRY(grad_apply(P->M, P->k, 1, z + P->nu, P->gt, P->s));
   SDG_TRY(vec_axpby(P->nu, 1.0, v, -1.0, P->gt, P->s));
   int its = 0;
