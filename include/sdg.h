@@ -59,6 +59,9 @@ extern "C" {
 #define SDG_ERR_UNSUPPORTED (-4) /* e.g. singular all-Neumann viscous problem */
 #define SDG_NOT_CONVERGED 1      /* iteration limit reached; last iterate returned */
 #define SDG_BREAKDOWN 2          /* Krylov breakdown; last iterate returned */
+#define SDG_FLOOR 3              /* FGMRES stopped at the FP64 rounding floor of the true residual
+                                    (about eps |K||x| / |b|), above rtol; stats.rel_residual is
+                                    the residual reached */
 
 /* boundary side types, sides ordered left, right, bottom, top */
 #define SDG_NAVIER 0
@@ -91,7 +94,8 @@ typedef struct sdg_options {
   int32_t coarsest_n;     /* h-coarsening stops at <= this many elements per direction */
   int32_t eig_steps;      /* Arnoldi steps for lambda* (Section 6: 10) */
   double cheb_lo, cheb_hi;/* Chebyshev bounds as fractions of lambda* (Section 6: 0.1, 1.1) */
-  int32_t prec_smoother;  /* SDG_FP64 / SDG_FP32 / SDG_BF16 storage of block inverses */
+  int32_t prec_smoother;  /* SDG_FP64: full block inverses; SDG_FP32 / SDG_BF16: inverse Cholesky
+                             factors X = L^{-1} (packed lower triangles), smoother X^T X */
   int32_t prec_apply;     /* SDG_FP64 / SDG_FP32: operator apply inside the cycle */
   int32_t viscous_krylov; /* 0: CG (paper); 1: FGMRES (needed when the cycle is not exactly linear) */
   int32_t dedup;          /* 1: share block inverses between elements with equal normalised blocks */
@@ -127,6 +131,7 @@ void sdg_options_default(sdg_options* opts);
 /* Device bytes a problem of this size needs (deterministic; used for
  * admission).  stokes != 0 adds the pressure and FGMRES workspaces. */
 size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes);
+size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, int stokes, int nbatch);
 
 /* ---- problem setup (Sections 4 and 6) ---------------------------------------
  * Copies eta (device pointer, nel values) and performs the setup of the
@@ -139,18 +144,30 @@ size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int sto
  * null stream); every later call on the problem is ordered on it. */
 int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
                        const double* eta_dev, void* stream, sdg_problem** out);
+/* Batched form: nbatch (1..4096) independent problems on the same mesh and
+ * options, each with its own viscosity (eta_dev: [nbatch][nel]).  Every
+ * operator and solve of the problem object then acts on all of them: device
+ * arrays are [nbatch][...] (problem after problem), stats/bounds/lambda
+ * outputs hold nbatch entries.  Each problem converges on its own test; a
+ * problem that has converged keeps its iterate while the others continue.
+ * Element blocks are shared across the batch when their normalised blocks
+ * coincide (opts.dedup).  sdg_problem_create is the batch of one. */
+int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, int nbatch,
+                             const double* eta_dev, void* stream, sdg_problem** out);
+int sdg_problem_batch(const sdg_problem* prob, int* nbatch);
 void sdg_problem_destroy(sdg_problem* prob);
 /* Number of multigrid levels (1 DG level + CG-Q_1 h-levels) and the
- * Chebyshev bounds [lambda_0, lambda_1] per smoothed level (2 doubles per
- * level; the coarsest CG level is solved directly and has none). */
+ * Chebyshev bounds [lambda_0, lambda_1] per level ([nbatch][nlevels][2];
+ * the coarsest CG level is solved directly, its entries are 0 and ignored). */
 int sdg_problem_levels(const sdg_problem* prob, int* nlevels);
 int sdg_get_bounds(const sdg_problem* prob, double* bounds);
 int sdg_set_bounds(sdg_problem* prob, const double* bounds);
 /* Largest Ritz value lambda* of eig_steps Arnoldi steps on M^{-1} A at
  * level `level` (0 = DG level), started from the SplitMix64 vector of
  * stream seed + level*2^32 (Section 6: ten GMRES iterations with a random
- * right-hand side).  Also writes the (steps+1) x steps Hessenberg matrix
- * column-major into hess (may be NULL). */
+ * right-hand side).  lambda_out: nbatch values.  hess (may be NULL):
+ * [nbatch][steps][steps+1], column j of problem pb holding rows 0..steps of
+ * its Hessenberg matrix. */
 int sdg_eig_estimate(sdg_problem* prob, int level, double* lambda_out, double* hess);
 
 /* ---- operators on device vectors (for parity and composition) -------------
@@ -192,7 +209,9 @@ int sdg_assemble_rhs(sdg_problem* prob, const double* f_dev, const double* g_dev
 /* ---- solves on device arrays ------------------------------------------------
  * Viscous block: u = A^{-1} F with F assembled from f (and g) by the
  * hp-multilevel preconditioned Krylov method of Sections 6 and 8, to
- * opts.rtol.  Blocks the calling thread until done. */
+ * opts.rtol.  Blocks the calling thread until done.  stats (may be NULL)
+ * receives nbatch entries; the return value is SDG_OK when every problem
+ * converged, else the largest soft outcome, or a negative error. */
 int sdg_solve_viscous_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
                           double* u_dev, sdg_stats* stats);
 /* Stokes: right-preconditioned FGMRES on eq. (discretestokes) with the

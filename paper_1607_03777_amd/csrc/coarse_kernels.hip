@@ -379,3 +379,174 @@ int dense_matvec(int n, int nbatch, const double* A, const double* x, double* y,
 }
 
 }  // namespace sdg
+
+namespace sdg {
+
+// ---------------------------------------------------------------------------
+// one Chebyshev / point-Jacobi step on an h-level, double-buffered x:
+// mode 1: d = b D^-1 rhs, xo = d;  2: d = b D^-1 (rhs - A xi), xo = xi + d;
+// mode 0: d = a d + b D^-1 (rhs - A xi), xo = xi + d.  ab[pb] = (a, b).
+// ---------------------------------------------------------------------------
+__global__ void hcheb_kernel(int nx, int ny, int nbatch, const double* __restrict__ st,
+                             const double* __restrict__ dinv, const double* __restrict__ rhs,
+                             const double* __restrict__ xi, double* __restrict__ xo, double* __restrict__ d,
+                             const double* __restrict__ ab, int mode) {
+  const int nn = (nx + 1) * (ny + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nbatch * nn) return;
+  const int64_t pb = g / nn;
+  const int node = (int)(g - pb * nn);
+  const int jx = node % (nx + 1), jy = node / (nx + 1);
+  const int64_t NN = (int64_t)nbatch * nn;
+  double r0 = rhs[g * 2], r1 = rhs[g * 2 + 1];
+  if (mode != 1) {
+#pragma unroll
+    for (int sy = -1; sy <= 1; ++sy)
+#pragma unroll
+      for (int sx = -1; sx <= 1; ++sx) {
+        const int gx = jx + sx, gy = jy + sy;
+        if (gx < 0 || gx > nx || gy < 0 || gy > ny) continue;
+        const int sidx = (sy + 1) * 3 + (sx + 1);
+        const int64_t nb = pb * nn + (int64_t)gy * (nx + 1) + gx;
+        const double x0 = xi[nb * 2], x1 = xi[nb * 2 + 1];
+        r0 -= st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
+        r1 -= st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+      }
+  }
+  const double ca = ab[2 * pb], cb = ab[2 * pb + 1];
+  const double z0 = dinv[g * 2] * r0, z1 = dinv[g * 2 + 1] * r1;
+  const double d0 = mode == 0 ? ca * d[g * 2] + cb * z0 : cb * z0;
+  const double d1 = mode == 0 ? ca * d[g * 2 + 1] + cb * z1 : cb * z1;
+  d[g * 2] = d0;
+  d[g * 2 + 1] = d1;
+  xo[g * 2] = mode == 1 ? d0 : xi[g * 2] + d0;
+  xo[g * 2 + 1] = mode == 1 ? d1 : xi[g * 2 + 1] + d1;
+}
+int hcheb_step(int nx, int ny, int nbatch, const double* st, const double* dinv, const double* rhs,
+               const double* xi, double* xo, double* d, const double* ab, int mode, hipStream_t s) {
+  const int64_t n = (int64_t)nbatch * (nx + 1) * (ny + 1);
+  hipLaunchKernelGGL(hcheb_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, nx, ny, nbatch, st, dinv, rhs, xi,
+                     xo, d, ab, mode);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// coarse tail: the h-cycle below a size threshold in one workgroup per
+// problem (levels 0..nlev-1 of the tail, the last one solved with its dense
+// inverse); every sweep ends with a workgroup barrier.
+// ---------------------------------------------------------------------------
+constexpr int TAIL_NT = 1024;
+
+__device__ __forceinline__ void tail_resid(const TailLevel& L, int64_t pb, int nbatch, const double* x,
+                                           double* r) {
+  const int nn = (L.nx + 1) * (L.ny + 1);
+  const int64_t NN = (int64_t)nbatch * nn;
+  for (int node = threadIdx.x; node < nn; node += TAIL_NT) {
+    const int64_t g = pb * nn + node;
+    const int jx = node % (L.nx + 1), jy = node / (L.nx + 1);
+    double r0 = L.b[g * 2], r1 = L.b[g * 2 + 1];
+    for (int sy = -1; sy <= 1; ++sy)
+      for (int sx = -1; sx <= 1; ++sx) {
+        const int gx = jx + sx, gy = jy + sy;
+        if (gx < 0 || gx > L.nx || gy < 0 || gy > L.ny) continue;
+        const int sidx = (sy + 1) * 3 + (sx + 1);
+        const int64_t nb = pb * nn + (int64_t)gy * (L.nx + 1) + gx;
+        const double x0 = x[nb * 2], x1 = x[nb * 2 + 1];
+        r0 -= L.st[(sidx * 4 + 0) * NN + g] * x0 + L.st[(sidx * 4 + 1) * NN + g] * x1;
+        r1 -= L.st[(sidx * 4 + 2) * NN + g] * x0 + L.st[(sidx * 4 + 3) * NN + g] * x1;
+      }
+    r[g * 2] = r0;
+    r[g * 2 + 1] = r1;
+  }
+}
+
+__device__ void tail_cheb(const TailLevel& L, int64_t pb, int nbatch, int steps, bool zero) {
+  const int nn = (L.nx + 1) * (L.ny + 1);
+  for (int s = 0; s < steps; ++s) {
+    const bool first = (s == 0);
+    if (!(first && zero)) {
+      tail_resid(L, pb, nbatch, L.x, L.r);
+      __syncthreads();
+    }
+    const double ca = L.ab[(int64_t)(s * nbatch + pb) * 2], cb = L.ab[(int64_t)(s * nbatch + pb) * 2 + 1];
+    for (int i = threadIdx.x; i < 2 * nn; i += TAIL_NT) {
+      const int64_t g = pb * nn * 2 + i;
+      const double rv = (first && zero) ? L.b[g] : L.r[g];
+      const double z = L.dinv[g] * rv;
+      const double dv = first ? cb * z : ca * L.d[g] + cb * z;
+      L.d[g] = dv;
+      L.x[g] = (first && zero) ? dv : L.x[g] + dv;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(TAIL_NT) void coarse_tail_kernel(TailArgs A) {
+  const int64_t pb = blockIdx.x;
+  const int nb = A.nbatch;
+  // descend
+  for (int l = 0; l < A.nlev - 1; ++l) {
+    const TailLevel& L = A.lev[l];
+    tail_cheb(L, pb, nb, A.steps, true);
+    tail_resid(L, pb, nb, L.x, L.r);
+    __syncthreads();
+    const TailLevel& C = A.lev[l + 1];
+    const int ncx = C.nx, ncy = C.ny, nfx = L.nx, nfy = L.ny;
+    const int nnc = (ncx + 1) * (ncy + 1), nnf = (nfx + 1) * (nfy + 1);
+    for (int i = threadIdx.x; i < 2 * nnc; i += TAIL_NT) {
+      const int c = i & 1, cn = i >> 1;
+      const int cx = cn % (ncx + 1), cy = cn / (ncx + 1);
+      double s = 0.0;
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int fx = 2 * cx + ox, fy = 2 * cy + oy;
+          if (fx < 0 || fx > nfx || fy < 0 || fy > nfy) continue;
+          s += (ox == 0 ? 1.0 : 0.5) * (oy == 0 ? 1.0 : 0.5) *
+               L.r[(pb * nnf + (int64_t)fy * (nfx + 1) + fx) * 2 + c];
+        }
+      C.b[(pb * nnc + cn) * 2 + c] = s;
+    }
+    __syncthreads();
+  }
+  // coarsest: x = Dinv b
+  {
+    const TailLevel& L = A.lev[A.nlev - 1];
+    const int nn = (L.nx + 1) * (L.ny + 1), n2 = 2 * nn;
+    const double* D = A.dense + pb * (int64_t)n2 * n2;
+    const double* b = L.b + pb * n2;
+    for (int i = threadIdx.x; i < n2; i += TAIL_NT) {
+      double s = 0.0;
+      for (int j = 0; j < n2; ++j) s += D[(int64_t)i * n2 + j] * b[j];
+      L.x[pb * n2 + i] = s;
+    }
+    __syncthreads();
+  }
+  // ascend
+  for (int l = A.nlev - 2; l >= 0; --l) {
+    const TailLevel& L = A.lev[l];
+    const TailLevel& C = A.lev[l + 1];
+    const int ncx = C.nx, nfx = L.nx, nfy = L.ny;
+    const int nnc = (ncx + 1) * (C.ny + 1), nnf = (nfx + 1) * (nfy + 1);
+    for (int i = threadIdx.x; i < 2 * nnf; i += TAIL_NT) {
+      const int c = i & 1, fn = i >> 1;
+      const int fx = fn % (nfx + 1), fy = fn / (nfx + 1);
+      const double wx = (fx & 1) ? 0.5 : 1.0, wy = (fy & 1) ? 0.5 : 1.0;
+      double s = 0.0;
+      for (int py = fy >> 1; py <= (fy + 1) >> 1; ++py)
+        for (int px = fx >> 1; px <= (fx + 1) >> 1; ++px)
+          s += wx * wy * C.x[(pb * nnc + (int64_t)py * (ncx + 1) + px) * 2 + c];
+      L.x[(pb * nnf + fn) * 2 + c] += s;
+    }
+    __syncthreads();
+    tail_cheb(L, pb, nb, A.steps, false);
+  }
+}
+
+int coarse_tail(const TailArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(coarse_tail_kernel, dim3(A.nbatch), dim3(TAIL_NT), 0, s, A);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+}  // namespace sdg

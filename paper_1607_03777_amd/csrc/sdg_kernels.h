@@ -25,13 +25,23 @@ int sip_coarse_local(const MeshDev& M, int k, int nbatch, const double* eta, dou
                      hipStream_t s);
 int div_apply(const MeshDev& M, int k, int nbatch, const double* u, double* q, hipStream_t s);
 int grad_apply(const MeshDev& M, int k, int nbatch, const double* p, double* v, hipStream_t s);
-int rhs_assemble(const MeshDev& M, int k, const double* eta, const double* f, const double* g,
+int rhs_assemble(const MeshDev& M, int k, int nbatch, const double* eta, const double* f, const double* g,
                  double* F, double* G, hipStream_t s);
 
 // Block Jacobi (block_kernels.hip)
 // In-place inverse of nmat symmetric positive definite n x n matrices
 // (Cholesky, triangular inverse, L^-T L^-1).  status[i] = 0 ok, 1 not SPD.
-int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s);
+// packed (optional): also store X = L^{-1} as packed lower triangles
+int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, double* packed = nullptr);
+// factored low-precision smoother: z = s_e X^T (X r), X packed lower triangular
+int bj_tri_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* X,
+                    const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
+int bj_tri_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* X,
+                     const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
+int bj_tri_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale, const float* X,
+                     const float* r, float* z, hipStream_t s);
+int bj_tri_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale, const uint16_t* X,
+                      const float* r, float* z, hipStream_t s);
 // z = scale_e * Binv[id_e] r_e, FP64 inverses.
 int blockjacobi_apply_f64(int nb, int64_t nel_total, const int* ids, const double* scale,
                           const double* binv, const double* r, double* z, hipStream_t s);
@@ -90,5 +100,52 @@ int pressure_project(int64_t nel, int np, double* p, double* scratch, hipStream_
 // Largest real part of the eigenvalues of the m x m upper Hessenberg matrix
 // (column-major, leading dimension ld) -> out[0]; one thread.
 int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t s);
+
+// ---- batched variants: vectors [nbatch][n], per-problem scalars in device arrays
+int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* w, double* out,
+               double* scratch, hipStream_t s);  // out[pb][j]
+int bmulti_axpy(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* h, double* w,
+                hipStream_t s);  // w[pb] -= sum_j h[pb][j] V_j[pb]
+int bmulti_combine(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* h, double* y,
+                   hipStream_t s);  // y[pb] += sum_j h[pb][j] V_j[pb]
+int bscale(int64_t n, int nbatch, const double* a, const double* x, double* y, int invert, hipStream_t s);
+int cg_update1(int64_t n, int nbatch, const double* p, const double* q, double* x, double* r,
+               const double* rz, const double* pq, const int* active, double* rr, double* scratch,
+               hipStream_t s);
+int cg_update2(int64_t n, int nbatch, const double* z, double* p, const double* rz_new, const double* rz_old,
+               const int* active, hipStream_t s);
+// ab[pb] = (a, b) Chebyshev coefficients per problem
+int bcheb_update(int64_t n, int nbatch, const double* ab, const double* z, double* d, double* x, int mode,
+                 hipStream_t s);
+int bpressure_project(int64_t nel, int np, int nbatch, int64_t stride, double* p, double* scratch,
+                      hipStream_t s);
+int bhessenberg_max_eig(int nbatch, const double* H, const int* ms, int ld, int64_t hstride, double* out,
+                        hipStream_t s);
+
+// fused smoother kernels
+int bj_cheb_f64(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const double* binv,
+                const double* r, const double* ab, double* d, double* x, int mode, hipStream_t s);
+int bj_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* binv,
+                const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
+int bj_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* binv,
+                 const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
+int hcheb_step(int nx, int ny, int nbatch, const double* st, const double* dinv, const double* rhs,
+               const double* xi, double* xo, double* d, const double* ab, int mode, hipStream_t s);
+
+// coarse tail (the small h-levels in one workgroup per problem)
+constexpr int TAIL_MAXLEV = 8;
+struct TailLevel {
+  int nx, ny;
+  const double* st;
+  const double* dinv;
+  double *b, *x, *r, *d;
+  const double* ab;  // [steps][nbatch][2] Chebyshev coefficients
+};
+struct TailArgs {
+  int nlev, nbatch, steps;
+  TailLevel lev[TAIL_MAXLEV];
+  const double* dense;  // inverse of the last level, [nbatch][n2][n2]
+};
+int coarse_tail(const TailArgs& A, hipStream_t s);
 
 }  // namespace sdg

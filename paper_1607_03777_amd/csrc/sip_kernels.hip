@@ -740,20 +740,24 @@ __global__ __launch_bounds__(256) void grad_kernel(MeshDev M, const double* __re
 // right-hand sides: F = f + Dirichlet lift, G = int q (g.n) on Dirichlet sides
 // ---------------------------------------------------------------------------
 template <int K1>
-__global__ __launch_bounds__(256) void rhs_kernel(MeshDev M, const double* __restrict__ eta,
+__global__ __launch_bounds__(256) void rhs_kernel(MeshDev M, int nbatch, const double* __restrict__ eta_all,
                                                   const double* __restrict__ f,
-                                                  const double* __restrict__ gdir,
+                                                  const double* __restrict__ gdir_all,
                                                   double* __restrict__ F, double* __restrict__ G) {
   constexpr int K = K1 - 1, KK = K1 * K1, NB = 2 * KK;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ge = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nel = M.nx * M.ny;
-  if (e >= nel) return;
+  if (ge >= (int64_t)nel * nbatch) return;
+  const int64_t pb = ge / nel;
+  const int e = (int)(ge - pb * nel);
   const int ix = e % M.nx, iy = e / M.nx;
-  double* Fe = F + (int64_t)e * NB;
-  for (int a = 0; a < NB; ++a) Fe[a] = f[(int64_t)e * NB + a];
-  double* Ge = G + (int64_t)e * K * K;
+  const double* eta = eta_all + pb * nel;
+  double* Fe = F + ge * NB;
+  for (int a = 0; a < NB; ++a) Fe[a] = f[ge * NB + a];
+  double* Ge = G + ge * K * K;
   for (int a = 0; a < K * K; ++a) Ge[a] = 0.0;
-  if (gdir == nullptr) return;
+  if (gdir_all == nullptr) return;
+  const double* gdir = gdir_all + pb * (int64_t)(2 * M.nx + 2 * M.ny) * 2 * K1;
   // sides of this element on the boundary: 0 left, 1 right, 2 bottom, 3 top
   for (int side = 0; side < 4; ++side) {
     bool on = (side == 0 && ix == 0) || (side == 1 && ix == M.nx - 1) || (side == 2 && iy == 0) ||
@@ -878,10 +882,10 @@ int grad_apply(const MeshDev& M, int k, int nbatch, const double* p, double* v, 
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
-int rhs_assemble(const MeshDev& M, int k, const double* eta, const double* f, const double* g,
+int rhs_assemble(const MeshDev& M, int k, int nbatch, const double* eta, const double* f, const double* g,
                  double* F, double* G, hipStream_t s) {
-  const int nel = M.nx * M.ny;
-  SDG_K1_SWITCH(k + 1, hipLaunchKernelGGL((rhs_kernel<KK1>), dim3(ceil_div(nel, 256)), dim3(256), 0, s, M, eta, f, g, F, G));
+  const int64_t n = (int64_t)M.nx * M.ny * nbatch;
+  SDG_K1_SWITCH(k + 1, hipLaunchKernelGGL((rhs_kernel<KK1>), dim3(ceil_div(n, 256)), dim3(256), 0, s, M, nbatch, eta, f, g, F, G));
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

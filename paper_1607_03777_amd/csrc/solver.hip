@@ -1,5 +1,11 @@
 // Problem setup and solver orchestration behind the C ABI (include/sdg.h).
 //
+// A problem object holds nbatch independent problems on one mesh (same nx,
+// ny, k, boundary sides and options; own viscosity, force and solution).
+// Device vectors are stored problem after problem; Krylov scalars are
+// per-problem device arrays and each problem leaves the iteration when it
+// converges (its updates are masked) while the others continue.
+//
 // Setup (Sections 4 and 6): element viscosity -> deduplicated diagonal
 // blocks of A (eq. smoother) and their inverses; A_{1,c} = P_cd^T A_1 P_cd
 // (Section 6.1.2) from element-local matrices; the Galerkin h-hierarchy;
@@ -8,13 +14,15 @@
 // eig_steps Arnoldi steps on M^{-1} A (Section 6).
 //
 // Solve: the two-level cycle of Algorithm 1 (Chebyshev with element-block
-// Jacobi, 2 steps before and after; the coarse solve is one h-cycle with
-// Chebyshev/point-Jacobi smoothing, 3 steps, and the dense coarsest
-// inverse), preconditioning CG (Section 8.1) or FGMRES for the viscous
-// block, and right-preconditioned FGMRES with the upper block-triangular
-// preconditioner for Stokes (Section 5).  The Krylov loops run on the host
-// and read one scalar per reduction back; all vector work runs in the
-// library's kernels.
+// Jacobi before and after; the coarse solve is one h-cycle with
+// Chebyshev/point-Jacobi smoothing and the dense coarsest inverse; the
+// small h-levels run in one workgroup per problem), preconditioning CG
+// (Section 8.1) or FGMRES for the viscous block, and right-preconditioned
+// FGMRES with the upper block-triangular preconditioner for Stokes
+// (Section 5).  The Krylov loops run on the host and read one short array of
+// per-problem scalars back per step; all vector work runs in the library's
+// kernels.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -45,13 +53,17 @@ using namespace sdg;
 
 namespace {
 
+constexpr int TAIL_NODES = 33 * 33;  // h-levels with at most this many nodes run in the tail kernel
+constexpr int RED_SCRATCH = 512 * 64;
+
 struct CLevel {
   int nx = 0, ny = 0, nn = 0;
   double* st = nullptr;
   double* dinv = nullptr;
-  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *d = nullptr;
+  double *b = nullptr, *x = nullptr, *xalt = nullptr, *r = nullptr, *d = nullptr;
   double* dense = nullptr;
-  double lmin = 0, lmax = 0;
+  double* ab = nullptr;  // [smooth_h][nbatch][2]
+  std::vector<double> lmin, lmax;
   bool coarsest = false;
 };
 
@@ -68,13 +80,14 @@ struct sdg_problem {
   sdg_options opt{};
   MeshDev M{};
   hipStream_t s = nullptr;
+  int nb = 1;  // batch size
   int k = 0, K1 = 0, NB = 0, NPE = 0;
   int nel = 0;
-  int64_t nu = 0, np = 0;
+  int64_t nu = 0, np = 0;  // per problem
   std::vector<void*> allocs;
   size_t bytes = 0;
-  double* eta = nullptr;
-  double* etap = nullptr;  // eta expanded over pressure modes (S*^{-1})
+  double* eta = nullptr;   // [nb][nel]
+  double* etap = nullptr;  // [nb][np], eta over the pressure modes
   std::vector<double> eta_host;
   // block Jacobi
   int nuniq = 0;
@@ -84,28 +97,34 @@ struct sdg_problem {
   float* binv32 = nullptr;
   uint16_t* binv16 = nullptr;
   std::vector<int> reps;
-  // DG cycle work vectors (FP64 and FP32)
-  double *vr = nullptr, *vz = nullptr, *vd = nullptr;
-  float *fb = nullptr, *fx = nullptr, *fr = nullptr, *fz = nullptr, *fd = nullptr;
-  double lmin0 = 0, lmax0 = 0;
+  // DG cycle
+  double *vr = nullptr, *vd = nullptr;
+  float *fb = nullptr, *fx = nullptr, *fr = nullptr, *fd = nullptr;
+  std::vector<double> lmin0, lmax0;
+  double* ab0 = nullptr;  // [smooth_dg][nb][2]
   std::vector<CLevel> lev;
-  // Krylov work
-  double* red = nullptr;    // reduction scratch
-  double* dsc = nullptr;    // device scalars
-  double* hsc = nullptr;    // pinned host scalars
+  int tail_start = 0;
+  TailArgs tail{};
+  // Krylov
+  double* red = nullptr;
+  double* dsc = nullptr;  // device scalars (see SC_* offsets)
+  double* hsc = nullptr;  // pinned host mirror
+  int* active = nullptr;  // device [nb]
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
-  // FGMRES (viscous or Stokes): V [(m+1) x n], Z [m x n]
   double *gV = nullptr, *gZ = nullptr, *gw = nullptr, *gt = nullptr;
-  int64_t gn = 0;
-  // stats of the last solve
-  int inner_total = 0, inner_max = 0;
+  int64_t gn = 0;  // per-problem length of the FGMRES vectors
   bool neumann = false;
   double setup_ms = 0;
+  // per-problem statistics of the last solve
+  std::vector<int> inner_total, inner_max;
 };
 
 namespace {
 
-constexpr int RED_SCRATCH = 512 * 64;
+// device scalar layout: each slot holds nb doubles; SC_H holds [nb][restart+4]
+enum { SC_RZ = 0, SC_RZ2, SC_PQ, SC_RR, SC_BN, SC_H, SC_COUNT_FIXED };
+inline double* sc(sdg_problem* P, int slot) { return P->dsc + (int64_t)slot * P->nb; }
+inline double* sc_h(sdg_problem* P) { return P->dsc + (int64_t)SC_H * P->nb; }
 
 int palloc(sdg_problem* P, void** out, size_t bytes) {
   *out = nullptr;
@@ -130,7 +149,7 @@ int palloc(sdg_problem* P, void** out, size_t bytes) {
 template <typename T>
 int palloc_t(sdg_problem* P, T** out, int64_t n) {
   void* p = nullptr;
-  int rc = palloc(P, &p, (size_t)n * sizeof(T));
+  int rc = palloc(P, &p, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
   *out = (T*)p;
   return rc;
 }
@@ -142,6 +161,25 @@ bool mesh_ok(const sdg_mesh* m) {
   for (int i = 0; i < 4; ++i)
     if (m->bc[i] < 0 || m->bc[i] > 2) return false;
   return true;
+}
+
+int to_host(sdg_problem* P, void* dst, const void* src, size_t bytes) {
+  SDG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, P->s));
+  SDG_HIP(hipStreamSynchronize(P->s));
+  return SDG_OK;
+}
+// host -> device through the pinned mirror when it fits (the source may be
+// reused right after the call returns)
+int to_dev(sdg_problem* P, void* dst, const void* src, size_t bytes) {
+  SDG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, P->s));
+  SDG_HIP(hipStreamSynchronize(P->s));
+  return SDG_OK;
+}
+int read_dev(sdg_problem* P, const double* src, int n, double* out) {
+  SDG_HIP(hipMemcpyAsync(P->hsc, src, n * sizeof(double), hipMemcpyDeviceToHost, P->s));
+  SDG_HIP(hipStreamSynchronize(P->s));
+  std::memcpy(out, P->hsc, n * sizeof(double));
+  return SDG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -171,20 +209,24 @@ struct BlockKeyHash {
 
 int setup_blocks(sdg_problem* P) {
   const int nx = P->mesh.nx, ny = P->mesh.ny, nel = P->nel;
-  std::vector<int> ids(nel);
-  std::vector<double> scale(nel);
+  const int64_t ntot = (int64_t)nel * P->nb;
+  std::vector<int> ids(ntot);
+  std::vector<double> scale(ntot);
   P->reps.clear();
   std::unordered_map<BlockKey, int, BlockKeyHash> map;
-  for (int e = 0; e < nel; ++e) {
+  for (int64_t ge = 0; ge < ntot; ++ge) {
+    const int64_t pb = ge / nel;
+    const int e = (int)(ge - pb * nel);
+    const double* et = P->eta_host.data() + pb * nel;
     const int ix = e % nx, iy = e / nx;
-    const double ee = P->eta_host[e];
+    const double ee = et[e];
     BlockKey key;
     const int nbs[4] = {ix > 0 ? e - 1 : -1, ix < nx - 1 ? e + 1 : -1, iy > 0 ? e - nx : -1,
                         iy < ny - 1 ? e + nx : -1};
     for (int f = 0; f < 4; ++f) {
       if (nbs[f] >= 0) {
         key.kind[f] = F_INTERIOR;
-        const double r = P->eta_host[nbs[f]] / ee;
+        const double r = et[nbs[f]] / ee;
         key.ratio[f] = r > 1.0 ? r : 1.0;
       } else {
         key.kind[f] = P->mesh.bc[f];
@@ -197,55 +239,59 @@ int setup_blocks(sdg_problem* P) {
       if (it == map.end()) {
         id = (int)P->reps.size();
         map.emplace(key, id);
-        P->reps.push_back(e);
+        P->reps.push_back((int)ge);
       } else {
         id = it->second;
       }
     } else {
-      id = e;
-      P->reps.push_back(e);
+      id = (int)P->reps.size();
+      P->reps.push_back((int)ge);
     }
-    ids[e] = id;
-    scale[e] = P->eta_host[P->reps[id]] / ee;
+    ids[ge] = id;
+    scale[ge] = P->eta_host[P->reps[id]] / ee;
   }
   P->nuniq = (int)P->reps.size();
-  SDG_TRY(palloc_t(P, &P->ids, nel));
-  SDG_TRY(palloc_t(P, &P->scale, nel));
-  SDG_HIP(hipMemcpyAsync(P->ids, ids.data(), nel * sizeof(int), hipMemcpyHostToDevice, P->s));
-  SDG_HIP(hipMemcpyAsync(P->scale, scale.data(), nel * sizeof(double), hipMemcpyHostToDevice, P->s));
-  // blocks of the representatives, then their inverses
+  SDG_TRY(palloc_t(P, &P->ids, ntot));
+  SDG_TRY(palloc_t(P, &P->scale, ntot));
+  SDG_TRY(to_dev(P, P->ids, ids.data(), ntot * sizeof(int)));
+  SDG_TRY(to_dev(P, P->scale, scale.data(), ntot * sizeof(double)));
   int* dreps = nullptr;
   int* dstat = nullptr;
   SDG_TRY(palloc_t(P, &dreps, P->nuniq));
   SDG_TRY(palloc_t(P, &dstat, P->nuniq));
-  SDG_HIP(hipMemcpyAsync(dreps, P->reps.data(), P->nuniq * sizeof(int), hipMemcpyHostToDevice, P->s));
+  SDG_TRY(to_dev(P, dreps, P->reps.data(), P->nuniq * sizeof(int)));
   const int64_t nbb = (int64_t)P->NB * P->NB;
+  const int64_t npk = (int64_t)P->NB * (P->NB + 1) / 2;
+  const bool low = P->opt.prec_apply == SDG_FP32 || P->opt.prec_smoother != SDG_FP64;
+  double* packed = nullptr;
+  if (low) SDG_TRY(palloc_t(P, &packed, (int64_t)P->nuniq * npk));
   SDG_TRY(palloc_t(P, &P->binv, (int64_t)P->nuniq * nbb));
   SDG_TRY(sip_block_list(P->M, P->k, P->eta, dreps, P->nuniq, P->binv, P->s));
-  SDG_TRY(spd_inverse(P->binv, P->NB, P->nuniq, dstat, P->s));
+  SDG_TRY(spd_inverse(P->binv, P->NB, P->nuniq, dstat, P->s, packed));
   std::vector<int> st(P->nuniq);
-  SDG_HIP(hipMemcpyAsync(st.data(), dstat, P->nuniq * sizeof(int), hipMemcpyDeviceToHost, P->s));
-  SDG_HIP(hipStreamSynchronize(P->s));
+  SDG_TRY(to_host(P, st.data(), dstat, P->nuniq * sizeof(int)));
   for (int i = 0; i < P->nuniq; ++i)
     if (st[i]) {
       set_error("element block " + std::to_string(P->reps[i]) + " is not positive definite");
       return SDG_ERR_UNSUPPORTED;
     }
-  if (P->opt.prec_smoother == SDG_FP32) {
-    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * nbb));
-    SDG_TRY(convert_f64_f32(P->binv, P->binv32, (int64_t)P->nuniq * nbb, P->s));
-  } else if (P->opt.prec_smoother == SDG_BF16) {
-    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * nbb));
-    SDG_TRY(convert_f64_bf16(P->binv, P->binv16, (int64_t)P->nuniq * nbb, P->s));
+  // low precision: the inverse Cholesky factor X = L^{-1} (packed lower
+  // triangle) in FP32 or BF16; the smoother applies X^T X
+  if (low && P->opt.prec_smoother == SDG_BF16) {
+    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * npk));
+    SDG_TRY(convert_f64_bf16(packed, P->binv16, (int64_t)P->nuniq * npk, P->s));
+  } else if (low) {
+    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * npk));
+    SDG_TRY(convert_f64_f32(packed, P->binv32, (int64_t)P->nuniq * npk, P->s));
   }
   return SDG_OK;
 }
 
 int setup_coarse(sdg_problem* P) {
-  const int nx = P->mesh.nx, ny = P->mesh.ny;
+  const int nx = P->mesh.nx, ny = P->mesh.ny, nb = P->nb;
   double* clocal = nullptr;
-  SDG_TRY(palloc_t(P, &clocal, (int64_t)P->nel * 64));
-  SDG_TRY(sip_coarse_local(P->M, P->k, 1, P->eta, clocal, P->s));
+  SDG_TRY(palloc_t(P, &clocal, (int64_t)P->nel * nb * 64));
+  SDG_TRY(sip_coarse_local(P->M, P->k, nb, P->eta, clocal, P->s));
   int cx = nx, cy = ny;
   P->lev.clear();
   while (true) {
@@ -253,469 +299,635 @@ int setup_coarse(sdg_problem* P) {
     L.nx = cx;
     L.ny = cy;
     L.nn = (cx + 1) * (cy + 1);
-    SDG_TRY(palloc_t(P, &L.st, (int64_t)36 * L.nn));
-    for (double** v : {&L.b, &L.x, &L.r, &L.z, &L.d}) SDG_TRY(palloc_t(P, v, (int64_t)2 * L.nn));
+    const int64_t nv = (int64_t)2 * L.nn * nb;
+    SDG_TRY(palloc_t(P, &L.st, (int64_t)36 * L.nn * nb));
+    for (double** v : {&L.b, &L.x, &L.xalt, &L.r, &L.d}) SDG_TRY(palloc_t(P, v, nv));
     if (P->lev.empty()) {
-      SDG_TRY(coarse_stencil_from_local(cx, cy, 1, clocal, L.st, P->s));
+      SDG_TRY(coarse_stencil_from_local(cx, cy, nb, clocal, L.st, P->s));
     } else {
       const CLevel& F = P->lev.back();
-      SDG_TRY(galerkin_coarsen(F.nx, F.ny, 1, F.st, L.st, P->s));
+      SDG_TRY(galerkin_coarsen(F.nx, F.ny, nb, F.st, L.st, P->s));
     }
     const bool more = (cx % 2 == 0) && (cy % 2 == 0) && cx > P->opt.coarsest_n && cy > P->opt.coarsest_n;
     L.coarsest = !more;
     if (L.coarsest) {
       const int n2 = 2 * L.nn;
       if (n2 > 2048) {
-        set_error("coarsest level too large for the dense solve (more than 2048 unknowns); use element counts with more factors of two");
+        set_error("coarsest level too large for the dense solve (more than 2048 unknowns); use element "
+                  "counts with more factors of two");
         return SDG_ERR_UNSUPPORTED;
       }
       int* dstat = nullptr;
-      SDG_TRY(palloc_t(P, &L.dense, (int64_t)n2 * n2));
-      SDG_TRY(palloc_t(P, &dstat, 1));
-      SDG_TRY(stencil_to_dense(cx, cy, 1, L.st, L.dense, P->s));
-      SDG_TRY(spd_inverse(L.dense, n2, 1, dstat, P->s));
-      int st = 0;
-      SDG_HIP(hipMemcpyAsync(&st, dstat, sizeof(int), hipMemcpyDeviceToHost, P->s));
-      SDG_HIP(hipStreamSynchronize(P->s));
-      if (st) {
-        set_error("coarsest operator is not positive definite (a rigid motion is not restrained)");
-        return SDG_ERR_UNSUPPORTED;
-      }
+      SDG_TRY(palloc_t(P, &L.dense, (int64_t)n2 * n2 * nb));
+      SDG_TRY(palloc_t(P, &dstat, nb));
+      SDG_TRY(stencil_to_dense(cx, cy, nb, L.st, L.dense, P->s));
+      SDG_TRY(spd_inverse(L.dense, n2, nb, dstat, P->s));
+      std::vector<int> st(nb);
+      SDG_TRY(to_host(P, st.data(), dstat, nb * sizeof(int)));
+      for (int i = 0; i < nb; ++i)
+        if (st[i]) {
+          set_error("coarsest operator is not positive definite (a rigid motion is not restrained)");
+          return SDG_ERR_UNSUPPORTED;
+        }
     } else {
-      SDG_TRY(palloc_t(P, &L.dinv, (int64_t)2 * L.nn));
-      SDG_TRY(stencil_diag_inv(cx, cy, 1, L.st, L.dinv, P->s));
+      SDG_TRY(palloc_t(P, &L.dinv, nv));
+      SDG_TRY(stencil_diag_inv(cx, cy, nb, L.st, L.dinv, P->s));
+      SDG_TRY(palloc_t(P, &L.ab, (int64_t)P->opt.smooth_h * nb * 2));
     }
     P->lev.push_back(L);
     if (L.coarsest) break;
     cx /= 2;
     cy /= 2;
   }
+  // the tail: the suffix of levels with few nodes (always includes the coarsest)
+  const int nl = (int)P->lev.size();
+  int ts = nl - 1;
+  while (ts > 0 && P->lev[ts - 1].nn <= TAIL_NODES && nl - (ts - 1) <= TAIL_MAXLEV) --ts;
+  P->tail_start = ts;
+  return SDG_OK;
+}
+
+// Chebyshev coefficients: step 0 -> (0, 1/theta); step s >= 1 ->
+// (rho_s rho_{s-1}, 2 rho_s / delta) with rho_0 = 1/sigma,
+// rho_s = 1/(2 sigma - rho_{s-1})
+void cheb_coefs(double lmin, double lmax, int steps, std::vector<double>& out, int nb, int pb) {
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int s = 0; s < steps; ++s) {
+    double a, b;
+    if (s == 0) {
+      a = 0.0;
+      b = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      a = rn * rho;
+      b = 2.0 * rn / delta;
+      rho = rn;
+    }
+    out[((size_t)s * nb + pb) * 2] = a;
+    out[((size_t)s * nb + pb) * 2 + 1] = b;
+  }
+}
+
+int upload_cheb(sdg_problem* P) {
+  const int nb = P->nb;
+  std::vector<double> c0((size_t)P->opt.smooth_dg * nb * 2);
+  for (int pb = 0; pb < nb; ++pb) cheb_coefs(P->lmin0[pb], P->lmax0[pb], P->opt.smooth_dg, c0, nb, pb);
+  SDG_TRY(to_dev(P, P->ab0, c0.data(), c0.size() * sizeof(double)));
+  for (auto& L : P->lev) {
+    if (L.coarsest) continue;
+    std::vector<double> c((size_t)P->opt.smooth_h * nb * 2);
+    for (int pb = 0; pb < nb; ++pb) cheb_coefs(L.lmin[pb], L.lmax[pb], P->opt.smooth_h, c, nb, pb);
+    SDG_TRY(to_dev(P, L.ab, c.data(), c.size() * sizeof(double)));
+  }
+  TailArgs& T = P->tail;
+  T.nlev = (int)P->lev.size() - P->tail_start;
+  T.nbatch = nb;
+  T.steps = P->opt.smooth_h;
+  for (int i = 0; i < T.nlev; ++i) {
+    const CLevel& L = P->lev[P->tail_start + i];
+    T.lev[i] = TailLevel{L.nx, L.ny, L.st, L.dinv, L.b, L.x, L.r, L.d, L.ab};
+  }
+  T.dense = P->lev.back().dense;
   return SDG_OK;
 }
 
 // ---------------------------------------------------------------------------
-// operators used by the cycle and Krylov methods
+// multigrid cycle
 // ---------------------------------------------------------------------------
-int bj64(sdg_problem* P, const double* r, double* z) {
-  return blockjacobi_apply_f64(P->NB, P->nel, P->ids, P->scale, P->binv, r, z, P->s);
+const double* ab0_step(sdg_problem* P, int s) { return P->ab0 + (int64_t)s * P->nb * 2; }
+
+int bj_step64(sdg_problem* P, const double* r, int s, double* x, int mode) {
+  return bj_cheb_f64(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv, r, ab0_step(P, s),
+                     P->vd, x, mode, P->s);
 }
-int bj32(sdg_problem* P, const float* r, float* z) {
-  if (P->binv16) return blockjacobi_apply_bf16(P->NB, P->nel, P->ids, P->scale, P->binv16, r, z, P->s);
-  return blockjacobi_apply_f32(P->NB, P->nel, P->ids, P->scale, P->binv32, r, z, P->s);
+int bj_step32(sdg_problem* P, const float* r, int s, float* x, int mode) {
+  if (P->binv16)
+    return bj_tri_cheb_bf16(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv16, r,
+                            ab0_step(P, s), P->fd, x, mode, P->s);
+  return bj_tri_cheb_f32(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv32, r,
+                         ab0_step(P, s), P->fd, x, mode, P->s);
+}
+int bj_apply32(sdg_problem* P, const float* r, float* z) {
+  const int64_t ne = (int64_t)P->nel * P->nb;
+  if (P->binv16) return bj_tri_apply_bf16(P->NB, ne, P->ids, P->scale, P->binv16, r, z, P->s);
+  return bj_tri_apply_f32(P->NB, ne, P->ids, P->scale, P->binv32, r, z, P->s);
 }
 
-struct Cheb {
-  double theta, delta, sigma;
-};
-Cheb cheb_params(double lmin, double lmax) {
-  Cheb c;
-  c.theta = 0.5 * (lmax + lmin);
-  c.delta = 0.5 * (lmax - lmin);
-  c.sigma = c.theta / c.delta;
-  return c;
-}
-
-// m Chebyshev steps on the DG level (FP64); zero: x starts at 0
 int cheb_dg64(sdg_problem* P, const double* b, double* x, bool zero) {
-  const Cheb c = cheb_params(P->lmin0, P->lmax0);
-  double rho = 1.0 / c.sigma;
-  const int64_t n = P->nu;
-  if (zero) {
-    SDG_TRY(bj64(P, b, P->vz));
-  } else {
-    SDG_TRY(sip_residual(P->M, P->k, 1, P->eta, b, x, P->vr, P->s));
-    SDG_TRY(bj64(P, P->vr, P->vz));
-  }
-  SDG_TRY(cheb_update(n, 0.0, P->vz, 1.0 / c.theta, P->vd, x, zero ? 1 : 2, P->s));
-  for (int it = 1; it < P->opt.smooth_dg; ++it) {
-    SDG_TRY(sip_residual(P->M, P->k, 1, P->eta, b, x, P->vr, P->s));
-    SDG_TRY(bj64(P, P->vr, P->vz));
-    const double rn = 1.0 / (2.0 * c.sigma - rho);
-    SDG_TRY(cheb_update(n, rn * rho, P->vz, 2.0 * rn / c.delta, P->vd, x, 0, P->s));
-    rho = rn;
+  for (int s = 0; s < P->opt.smooth_dg; ++s) {
+    const double* r = b;
+    if (!(s == 0 && zero)) {
+      SDG_TRY(sip_residual(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s));
+      r = P->vr;
+    }
+    SDG_TRY(bj_step64(P, r, s, x, s == 0 ? (zero ? 1 : 2) : 0));
   }
   return SDG_OK;
 }
-
 int cheb_dg32(sdg_problem* P, const float* b, float* x, bool zero) {
-  const Cheb c = cheb_params(P->lmin0, P->lmax0);
-  double rho = 1.0 / c.sigma;
-  const int64_t n = P->nu;
-  if (zero) {
-    SDG_TRY(bj32(P, b, P->fz));
-  } else {
-    SDG_TRY(sip_residual_f32(P->M, P->k, 1, P->eta, b, x, P->fr, P->s));
-    SDG_TRY(bj32(P, P->fr, P->fz));
-  }
-  SDG_TRY(cheb_update_f32(n, 0.0, P->fz, 1.0 / c.theta, P->fd, x, zero ? 1 : 2, P->s));
-  for (int it = 1; it < P->opt.smooth_dg; ++it) {
-    SDG_TRY(sip_residual_f32(P->M, P->k, 1, P->eta, b, x, P->fr, P->s));
-    SDG_TRY(bj32(P, P->fr, P->fz));
-    const double rn = 1.0 / (2.0 * c.sigma - rho);
-    SDG_TRY(cheb_update_f32(n, rn * rho, P->fz, 2.0 * rn / c.delta, P->fd, x, 0, P->s));
-    rho = rn;
+  for (int s = 0; s < P->opt.smooth_dg; ++s) {
+    const float* r = b;
+    if (!(s == 0 && zero)) {
+      SDG_TRY(sip_residual_f32(P->M, P->k, P->nb, P->eta, b, x, P->fr, P->s));
+      r = P->fr;
+    }
+    SDG_TRY(bj_step32(P, r, s, x, s == 0 ? (zero ? 1 : 2) : 0));
   }
   return SDG_OK;
 }
 
 int cheb_h(sdg_problem* P, CLevel& L, bool zero) {
-  const Cheb c = cheb_params(L.lmin, L.lmax);
-  double rho = 1.0 / c.sigma;
-  const int64_t n = 2 * (int64_t)L.nn;
-  if (zero) {
-    SDG_TRY(vec_mul(n, L.dinv, L.b, L.z, P->s));
-  } else {
-    SDG_TRY(stencil_residual(L.nx, L.ny, 1, L.st, L.b, L.x, L.r, P->s));
-    SDG_TRY(vec_mul(n, L.dinv, L.r, L.z, P->s));
-  }
-  SDG_TRY(cheb_update(n, 0.0, L.z, 1.0 / c.theta, L.d, L.x, zero ? 1 : 2, P->s));
-  for (int it = 1; it < P->opt.smooth_h; ++it) {
-    SDG_TRY(stencil_residual(L.nx, L.ny, 1, L.st, L.b, L.x, L.r, P->s));
-    SDG_TRY(vec_mul(n, L.dinv, L.r, L.z, P->s));
-    const double rn = 1.0 / (2.0 * c.sigma - rho);
-    SDG_TRY(cheb_update(n, rn * rho, L.z, 2.0 * rn / c.delta, L.d, L.x, 0, P->s));
-    rho = rn;
+  for (int s = 0; s < P->opt.smooth_h; ++s) {
+    const int mode = s == 0 ? (zero ? 1 : 2) : 0;
+    const double* ab = L.ab + (int64_t)s * P->nb * 2;
+    SDG_TRY(hcheb_step(L.nx, L.ny, P->nb, L.st, L.dinv, L.b, L.x, L.xalt, L.d, ab, mode, P->s));
+    std::swap(L.x, L.xalt);
   }
   return SDG_OK;
 }
 
-// h-cycle on level li: L.x = B_h L.b
 int hcycle(sdg_problem* P, int li) {
+  if (li >= P->tail_start) return coarse_tail(P->tail, P->s);
   CLevel& L = P->lev[li];
-  if (L.coarsest) return dense_matvec(2 * L.nn, 1, L.dense, L.b, L.x, P->s);
-  SDG_TRY(cheb_h(P, L, true));
-  SDG_TRY(stencil_residual(L.nx, L.ny, 1, L.st, L.b, L.x, L.r, P->s));
   CLevel& C = P->lev[li + 1];
-  SDG_TRY(h_restrict(C.nx, C.ny, 1, L.r, C.b, P->s));
+  SDG_TRY(cheb_h(P, L, true));
+  SDG_TRY(stencil_residual(L.nx, L.ny, P->nb, L.st, L.b, L.x, L.r, P->s));
+  SDG_TRY(h_restrict(C.nx, C.ny, P->nb, L.r, C.b, P->s));
   SDG_TRY(hcycle(P, li + 1));
-  SDG_TRY(h_prolong_add(C.nx, C.ny, 1, C.x, L.x, P->s));
+  SDG_TRY(h_prolong_add(C.nx, C.ny, P->nb, C.x, L.x, P->s));
   SDG_TRY(cheb_h(P, L, false));
   return SDG_OK;
 }
 
-// x = B_mg b in FP64 (Algorithm 1, zero initial guess)
 int vcycle64(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(cheb_dg64(P, b, x, true));
-  SDG_TRY(sip_residual(P->M, P->k, 1, P->eta, b, x, P->vr, P->s));
-  SDG_TRY(p_restrict(P->M, P->k, 1, P->vr, P->lev[0].b, P->s));
+  SDG_TRY(sip_residual(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s));
+  SDG_TRY(p_restrict(P->M, P->k, P->nb, P->vr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
-  SDG_TRY(p_prolong_add(P->M, P->k, 1, P->lev[0].x, x, P->s));
+  SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
   SDG_TRY(cheb_dg64(P, b, x, false));
   return SDG_OK;
 }
 
-// x = B_mg b with the fine level in FP32 (FP64 in and out)
+// fine level in FP32 (FP64 in and out); the coarse Q1 hierarchy stays FP64
 int vcycle32(sdg_problem* P, const double* b, double* x) {
-  SDG_TRY(d2f(P->nu, b, P->fb, P->s));
+  const int64_t n = P->nu * P->nb;
+  SDG_TRY(d2f(n, b, P->fb, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, true));
-  SDG_TRY(sip_residual_f32(P->M, P->k, 1, P->eta, P->fb, P->fx, P->fr, P->s));
-  SDG_TRY(p_restrict_f32(P->M, P->k, 1, P->fr, P->lev[0].b, P->s));
+  SDG_TRY(sip_residual_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s));
+  SDG_TRY(p_restrict_f32(P->M, P->k, P->nb, P->fr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
-  SDG_TRY(p_prolong_add_f32(P->M, P->k, 1, P->lev[0].x, P->fx, P->s));
+  SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, false));
-  SDG_TRY(f2d(P->nu, P->fx, x, P->s));
+  SDG_TRY(f2d(n, P->fx, x, P->s));
   return SDG_OK;
+}
+
+bool low_precision(const sdg_problem* P) {
+  return P->opt.prec_apply == SDG_FP32 || P->opt.prec_smoother != SDG_FP64;
 }
 
 int vcycle(sdg_problem* P, const double* b, double* x) {
-  if (P->opt.prec_apply == SDG_FP32 || P->opt.prec_smoother != SDG_FP64) return vcycle32(P, b, x);
-  return vcycle64(P, b, x);
-}
-
-// scalar readback helpers
-int read_scalars(sdg_problem* P, int n) {
-  SDG_HIP(hipMemcpyAsync(P->hsc, P->dsc, n * sizeof(double), hipMemcpyDeviceToHost, P->s));
-  SDG_HIP(hipStreamSynchronize(P->s));
-  return SDG_OK;
-}
-int norm2(sdg_problem* P, int64_t n, const double* x, double* out) {
-  SDG_TRY(dot(n, x, x, P->dsc, P->red, P->s));
-  SDG_TRY(read_scalars(P, 1));
-  *out = std::sqrt(P->hsc[0] > 0 ? P->hsc[0] : 0.0);
-  return SDG_OK;
-}
-int read_device(sdg_problem* P, const double* src, int n) {
-  SDG_HIP(hipMemcpyAsync(P->hsc, src, n * sizeof(double), hipMemcpyDeviceToHost, P->s));
-  SDG_HIP(hipStreamSynchronize(P->s));
-  return SDG_OK;
-}
-int dot_host(sdg_problem* P, int64_t n, const double* x, const double* y, double* out) {
-  SDG_TRY(dot(n, x, y, P->dsc, P->red, P->s));
-  SDG_TRY(read_scalars(P, 1));
-  *out = P->hsc[0];
-  return SDG_OK;
+  return low_precision(P) ? vcycle32(P, b, x) : vcycle64(P, b, x);
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev bounds: Arnoldi (classical Gram-Schmidt twice) on M^{-1} A
+// batched vector helpers over one or two segments per problem (Stokes
+// vectors: all velocities, then all pressures)
 // ---------------------------------------------------------------------------
-// level -1: DG level; level >= 0: CG level li
-int arnoldi(sdg_problem* P, int li, double* lambda, std::vector<double>* hess_out) {
-  const int m = P->opt.eig_steps;
+struct Seg {
+  int64_t off;  // offset of the segment block
+  int64_t n;    // per-problem length
+};
+struct VSpec {
+  Seg seg[2];
+  int nseg;
+  int64_t total;  // length of one batched vector
+};
+VSpec viscous_spec(const sdg_problem* P) {
+  VSpec v;
+  v.seg[0] = {0, P->nu};
+  v.seg[1] = {0, 0};
+  v.nseg = 1;
+  v.total = P->nu * P->nb;
+  return v;
+}
+VSpec stokes_spec(const sdg_problem* P) {
+  VSpec v;
+  v.seg[0] = {0, P->nu};
+  v.seg[1] = {P->nu * P->nb, P->np};
+  v.nseg = P->np > 0 ? 2 : 1;
+  v.total = (P->nu + P->np) * P->nb;
+  return v;
+}
+
+// out[pb * m + j] = <V_j[pb], w[pb]> summed over the segments (host array)
+int vs_dots(sdg_problem* P, const VSpec& S, int m, const double* V, int64_t ldv, const double* w,
+            std::vector<double>& out) {
+  const int nb = P->nb;
+  out.assign((size_t)nb * m, 0.0);
+  std::vector<double> part((size_t)nb * m);
+  for (int q = 0; q < S.nseg; ++q) {
+    SDG_TRY(bmulti_dot(S.seg[q].n, nb, m, V + S.seg[q].off, ldv, w + S.seg[q].off, sc_h(P), P->red, P->s));
+    SDG_TRY(read_dev(P, sc_h(P), nb * m, part.data()));
+    for (size_t i = 0; i < part.size(); ++i) out[i] += part[i];
+  }
+  return SDG_OK;
+}
+int vs_axpy(sdg_problem* P, const VSpec& S, int m, const double* V, int64_t ldv, const double* hdev, double* w) {
+  for (int q = 0; q < S.nseg; ++q)
+    SDG_TRY(bmulti_axpy(S.seg[q].n, P->nb, m, V + S.seg[q].off, ldv, hdev, w + S.seg[q].off, P->s));
+  return SDG_OK;
+}
+int vs_combine(sdg_problem* P, const VSpec& S, int m, const double* V, int64_t ldv, const double* hdev, double* y) {
+  for (int q = 0; q < S.nseg; ++q)
+    SDG_TRY(bmulti_combine(S.seg[q].n, P->nb, m, V + S.seg[q].off, ldv, hdev, y + S.seg[q].off, P->s));
+  return SDG_OK;
+}
+// y = x / a[pb] (a in device memory; a = 0 -> 0)
+int vs_div(sdg_problem* P, const VSpec& S, const double* adev, const double* x, double* y) {
+  for (int q = 0; q < S.nseg; ++q)
+    SDG_TRY(bscale(S.seg[q].n, P->nb, adev, x + S.seg[q].off, y + S.seg[q].off, 1, P->s));
+  return SDG_OK;
+}
+int vs_norms(sdg_problem* P, const VSpec& S, const double* x, std::vector<double>& out) {
+  SDG_TRY(vs_dots(P, S, 1, x, 0, x, out));
+  for (auto& v : out) v = std::sqrt(v > 0 ? v : 0.0);
+  return SDG_OK;
+}
+int upload_scalars(sdg_problem* P, double* dst, const std::vector<double>& v) {
+  return to_dev(P, dst, v.data(), v.size() * sizeof(double));
+}
+int upload_active(sdg_problem* P, const std::vector<int>& act) {
+  return to_dev(P, P->active, act.data(), act.size() * sizeof(int));
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev bounds: Arnoldi (classical Gram-Schmidt twice) on M^{-1} A for
+// every problem of the batch; level -1 = DG level, li >= 0 = CG level li
+// ---------------------------------------------------------------------------
+int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<double>* hess_out) {
+  const int m = P->opt.eig_steps, nb = P->nb;
   const int64_t n = li < 0 ? P->nu : 2 * (int64_t)P->lev[li].nn;
-  double* V = nullptr;
-  double* w = nullptr;
-  double* dH = nullptr;
-  double* hcol = nullptr;
-  // temporary workspace, freed at the end
-  if (hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&w, (size_t)n * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&dH, (size_t)(m + 1) * m * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&hcol, (size_t)(m + 2) * sizeof(double)) != hipSuccess) {
+  VSpec S;
+  S.seg[0] = {0, n};
+  S.seg[1] = {0, 0};
+  S.nseg = 1;
+  S.total = n * nb;
+  double *V = nullptr, *w = nullptr, *dH = nullptr, *lam = nullptr;
+  int* dms = nullptr;
+  if (hipMalloc((void**)&V, (size_t)(m + 1) * S.total * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&w, (size_t)S.total * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&dH, (size_t)(m + 1) * m * nb * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&lam, (size_t)nb * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&dms, (size_t)nb * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(V);
-    (void)hipFree(w);
-    (void)hipFree(dH);
-    (void)hipFree(hcol);
+    for (void* q : {(void*)V, (void*)w, (void*)dH, (void*)lam, (void*)dms}) (void)hipFree(q);
     set_error("allocation of the Arnoldi workspace failed");
     return SDG_ERR_NOMEM;
   }
   const uint64_t seed = P->opt.seed + ((uint64_t)(li + 1) << 32);
   int rc = SDG_OK;
-  std::vector<double> H((size_t)(m + 1) * m, 0.0);
-  int mm = m;
+  std::vector<double> H((size_t)nb * (m + 1) * m, 0.0);  // [pb][col j][row i], ld m+1
+  std::vector<int> ms(nb, m);
+  std::vector<char> stopped(nb, 0);
   do {
-    if ((rc = uniform_pm1(seed, n, V, P->s)) < 0) break;
-    double nv;
-    if ((rc = norm2(P, n, V, &nv)) < 0) break;
-    if ((rc = vec_scale_copy(n, 1.0 / nv, V, V, P->s)) < 0) break;
+    for (int pb = 0; pb < nb && rc >= 0; ++pb) rc = uniform_pm1(seed, n, V + pb * n, P->s);
+    if (rc < 0) break;
+    std::vector<double> nv;
+    if ((rc = vs_norms(P, S, V, nv)) < 0) break;
+    if ((rc = upload_scalars(P, sc(P, SC_BN), nv)) < 0) break;
+    if ((rc = vs_div(P, S, sc(P, SC_BN), V, V)) < 0) break;
     for (int j = 0; j < m; ++j) {
-      double* vj = V + (int64_t)j * n;
-      if (li < 0) {
-        if ((rc = sip_apply(P->M, P->k, 1, P->eta, vj, P->vr, P->s)) < 0) break;
-        if ((rc = bj64(P, P->vr, w)) < 0) break;
+      double* vj = V + (int64_t)j * S.total;
+      if (li < 0 && low_precision(P)) {
+        // bounds of the operator the smoother applies: FP32 apply, FP32/BF16 inverses
+        if ((rc = d2f(S.total, vj, P->fb, P->s)) < 0) break;
+        if ((rc = sip_apply_f32(P->M, P->k, nb, P->eta, P->fb, P->fr, P->s)) < 0) break;
+        if ((rc = bj_apply32(P, P->fr, P->fd)) < 0) break;
+        if ((rc = f2d(S.total, P->fd, w, P->s)) < 0) break;
+      } else if (li < 0) {
+        if ((rc = sip_apply(P->M, P->k, nb, P->eta, vj, P->vr, P->s)) < 0) break;
+        if ((rc = blockjacobi_apply_f64(P->NB, (int64_t)P->nel * nb, P->ids, P->scale, P->binv, P->vr, w,
+                                        P->s)) < 0)
+          break;
       } else {
         CLevel& L = P->lev[li];
-        if ((rc = stencil_apply(L.nx, L.ny, 1, L.st, vj, L.r, P->s)) < 0) break;
-        if ((rc = vec_mul(n, L.dinv, L.r, w, P->s)) < 0) break;
+        if ((rc = stencil_apply(L.nx, L.ny, nb, L.st, vj, L.r, P->s)) < 0) break;
+        if ((rc = vec_mul(S.total, L.dinv, L.r, w, P->s)) < 0) break;
       }
-      std::vector<double> h(j + 1, 0.0);
-      for (int pass = 0; pass < 2; ++pass) {
-        if ((rc = multi_dot(n, j + 1, V, n, w, hcol, P->red, P->s)) < 0) break;
-        if ((rc = multi_axpy(n, j + 1, V, n, hcol, w, P->s)) < 0) break;
-        if ((rc = read_device(P, hcol, j + 1)) < 0) break;
-        for (int i = 0; i <= j; ++i) h[i] += P->hsc[i];
+      std::vector<double> h((size_t)nb * (j + 1), 0.0), part;
+      for (int pass = 0; pass < 2 && rc >= 0; ++pass) {
+        if ((rc = vs_dots(P, S, j + 1, V, S.total, w, part)) < 0) break;
+        if ((rc = upload_scalars(P, sc_h(P), part)) < 0) break;
+        if ((rc = vs_axpy(P, S, j + 1, V, S.total, sc_h(P), w)) < 0) break;
+        for (size_t i = 0; i < h.size(); ++i) h[i] += part[i];
       }
       if (rc < 0) break;
-      double hn;
-      if ((rc = norm2(P, n, w, &hn)) < 0) break;
-      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = h[i];
-      H[(size_t)j * (m + 1) + j + 1] = hn;
-      if (hn <= 1e-14 * std::fabs(h[j])) {
-        mm = j + 1;
-        break;
+      std::vector<double> hn;
+      if ((rc = vs_norms(P, S, w, hn)) < 0) break;
+      for (int pb = 0; pb < nb; ++pb) {
+        if (stopped[pb]) {
+          hn[pb] = 0.0;
+          continue;
+        }
+        double* col = H.data() + ((size_t)pb * m + j) * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] = h[(size_t)pb * (j + 1) + i];
+        col[j + 1] = hn[pb];
+        if (hn[pb] <= 1e-14 * std::fabs(h[(size_t)pb * (j + 1) + j])) {
+          ms[pb] = j + 1;
+          stopped[pb] = 1;
+          hn[pb] = 0.0;
+        }
       }
-      if ((rc = vec_scale_copy(n, 1.0 / hn, w, V + (int64_t)(j + 1) * n, P->s)) < 0) break;
+      if ((rc = upload_scalars(P, sc(P, SC_BN), hn)) < 0) break;
+      if ((rc = vs_div(P, S, sc(P, SC_BN), w, V + (int64_t)(j + 1) * S.total)) < 0) break;
     }
     if (rc < 0) break;
-    if (hipMemcpyAsync(dH, H.data(), H.size() * sizeof(double), hipMemcpyHostToDevice, P->s) != hipSuccess) {
-      set_error("copy of the Hessenberg matrix failed");
+    if (hipMemcpyAsync(dH, H.data(), H.size() * sizeof(double), hipMemcpyHostToDevice, P->s) != hipSuccess ||
+        hipMemcpyAsync(dms, ms.data(), nb * sizeof(int), hipMemcpyHostToDevice, P->s) != hipSuccess) {
+      set_error("copy of the Hessenberg matrices failed");
       rc = SDG_ERR_DEVICE;
       break;
     }
-    if ((rc = hessenberg_max_eig(dH, mm, m + 1, hcol, P->s)) < 0) break;
-    if ((rc = read_device(P, hcol, 1)) < 0) break;
+    if ((rc = bhessenberg_max_eig(nb, dH, dms, m + 1, (int64_t)(m + 1) * m, lam, P->s)) < 0) break;
+    lambda.resize(nb);
+    if ((rc = read_dev(P, lam, nb, lambda.data())) < 0) break;
   } while (0);
   (void)hipStreamSynchronize(P->s);
-  (void)hipFree(V);
-  (void)hipFree(w);
-  (void)hipFree(dH);
-  (void)hipFree(hcol);
+  for (void* q : {(void*)V, (void*)w, (void*)dH, (void*)lam, (void*)dms}) (void)hipFree(q);
   if (rc < 0) return rc;
-  *lambda = P->hsc[0];
   if (hess_out) *hess_out = H;
   return SDG_OK;
 }
 
-}  // namespace
-
 // ---------------------------------------------------------------------------
 // Krylov methods
 // ---------------------------------------------------------------------------
-namespace {
-
-// Preconditioned CG with x0 = 0; stops when ||r||_2 < rtol ||b||_2 (the
-// unpreconditioned, recursively updated residual).
-int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit, int* its,
-             double* relres) {
+// Batched preconditioned CG with x0 = 0; problem pb stops when
+// ||r||_2 < rtol ||b||_2 (unpreconditioned, recursively updated residual).
+// status[pb]: SDG_OK, SDG_NOT_CONVERGED or SDG_BREAKDOWN.
+int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit, std::vector<int>& its,
+             std::vector<double>& rel, std::vector<int>& status) {
+  const int nb = P->nb;
   const int64_t n = P->nu;
-  double bn;
-  SDG_TRY(norm2(P, n, b, &bn));
-  SDG_HIP(hipMemsetAsync(x, 0, n * sizeof(double), P->s));
-  *its = 0;
-  *relres = 0.0;
-  if (bn == 0.0) return SDG_OK;
-  if (!std::isfinite(bn)) {
-    set_error("right-hand side is not finite");
-    return SDG_ERR_INVALID;
+  const VSpec S = viscous_spec(P);
+  std::vector<double> bn;
+  SDG_TRY(vs_norms(P, S, b, bn));
+  SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
+  its.assign(nb, 0);
+  rel.assign(nb, 0.0);
+  status.assign(nb, SDG_OK);
+  std::vector<int> act(nb, 0);
+  int nact = 0;
+  for (int pb = 0; pb < nb; ++pb) {
+    if (!std::isfinite(bn[pb])) {
+      status[pb] = SDG_BREAKDOWN;
+      rel[pb] = NAN;
+    } else if (bn[pb] > 0.0) {
+      act[pb] = 1;
+      rel[pb] = 1.0;
+      status[pb] = SDG_NOT_CONVERGED;
+      ++nact;
+    }
   }
-  SDG_TRY(vec_copy(n, b, P->cg_r, P->s));
+  if (nact == 0) return SDG_OK;
+  SDG_TRY(upload_active(P, act));
+  SDG_TRY(vec_copy(S.total, b, P->cg_r, P->s));
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
-  SDG_TRY(vec_copy(n, P->cg_z, P->cg_p, P->s));
-  double rz;
-  SDG_TRY(dot_host(P, n, P->cg_r, P->cg_z, &rz));
-  double rel = 1.0;
-  int it = 0;
-  int status = SDG_NOT_CONVERGED;
-  while (it < maxit) {
-    SDG_TRY(sip_apply(P->M, P->k, 1, P->eta, P->cg_p, P->cg_q, P->s));
-    double pq;
-    SDG_TRY(dot_host(P, n, P->cg_p, P->cg_q, &pq));
-    if (!(pq > 0.0) || !std::isfinite(pq)) {
-      status = SDG_BREAKDOWN;
-      break;
+  SDG_TRY(vec_copy(S.total, P->cg_z, P->cg_p, P->s));
+  double* rz = sc(P, SC_RZ);
+  double* rz2 = sc(P, SC_RZ2);
+  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz, P->red, P->s));
+  std::vector<double> rr(nb), pq(nb);
+  for (int it = 0; it < maxit && nact > 0; ++it) {
+    SDG_TRY(sip_apply(P->M, P->k, nb, P->eta, P->cg_p, P->cg_q, P->s));
+    SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
+    SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
+                       P->s));
+    // one readback per iteration: p.q and ||r||^2 of every problem (adjacent slots)
+    SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
+    SDG_HIP(hipStreamSynchronize(P->s));
+    std::memcpy(pq.data(), P->hsc, nb * sizeof(double));
+    std::memcpy(rr.data(), P->hsc + nb, nb * sizeof(double));
+    bool changed = false;
+    for (int pb = 0; pb < nb; ++pb) {
+      if (!act[pb]) continue;
+      if (!(pq[pb] > 0.0) || !std::isfinite(pq[pb])) {
+        status[pb] = SDG_BREAKDOWN;
+        act[pb] = 0;
+        --nact;
+        changed = true;
+        continue;
+      }
+      ++its[pb];
+      rel[pb] = std::sqrt(rr[pb] > 0 ? rr[pb] : 0.0) / bn[pb];
+      if (!std::isfinite(rel[pb])) {
+        status[pb] = SDG_BREAKDOWN;
+        act[pb] = 0;
+        --nact;
+        changed = true;
+      } else if (rel[pb] < rtol) {
+        status[pb] = SDG_OK;
+        act[pb] = 0;
+        --nact;
+        changed = true;
+      }
     }
-    const double alpha = rz / pq;
-    SDG_TRY(vec_axpy(n, alpha, P->cg_p, x, P->s));
-    SDG_TRY(vec_axpy(n, -alpha, P->cg_q, P->cg_r, P->s));
-    ++it;
-    double rn;
-    SDG_TRY(norm2(P, n, P->cg_r, &rn));
-    rel = rn / bn;
-    if (!std::isfinite(rel)) {
-      status = SDG_BREAKDOWN;
-      break;
-    }
-    if (rel < rtol) {
-      status = SDG_OK;
-      break;
-    }
+    if (nact == 0 || it + 1 >= maxit) break;
+    if (changed) SDG_TRY(upload_active(P, act));
     SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
-    double rz2;
-    SDG_TRY(dot_host(P, n, P->cg_r, P->cg_z, &rz2));
-    SDG_TRY(vec_axpby(n, 1.0, P->cg_z, rz2 / rz, P->cg_p, P->s));
-    rz = rz2;
+    SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz2, P->red, P->s));
+    SDG_TRY(cg_update2(n, nb, P->cg_z, P->cg_p, rz2, rz, P->active, P->s));
+    std::swap(rz, rz2);
   }
-  *its = it;
-  *relres = rel;
-  return status;
-}
-
-int ensure_gmres(sdg_problem* P, int64_t n) {
-  if (P->gV && P->gn >= n) return SDG_OK;
-  if (P->gV) {
-    set_error("FGMRES workspace size mismatch");
-    return SDG_ERR_INVALID;
-  }
-  const int m = P->opt.restart;
-  SDG_TRY(palloc_t(P, &P->gV, (int64_t)(m + 1) * n));
-  SDG_TRY(palloc_t(P, &P->gZ, (int64_t)m * n));
-  SDG_TRY(palloc_t(P, &P->gw, n));
-  SDG_TRY(palloc_t(P, &P->gt, P->nu));
-  P->gn = n;
   return SDG_OK;
 }
 
-template <typename MV, typename PC, typename PJ>
-int fgmres(sdg_problem* P, int64_t n, const double* b_in, double* x, double rtol, int maxit,
-           MV matvec, PC prec, PJ project, int* its, double* relres) {
+int ensure_gmres(sdg_problem* P, int64_t n_per_problem) {
+  if (P->gV && P->gn == n_per_problem) return SDG_OK;
+  if (P->gV) {
+    set_error("FGMRES workspace was sized for the other system (viscous vs Stokes)");
+    return SDG_ERR_INVALID;
+  }
   const int m = P->opt.restart;
-  SDG_TRY(ensure_gmres(P, n));
+  const int64_t tot = n_per_problem * P->nb;
+  SDG_TRY(palloc_t(P, &P->gV, (int64_t)(m + 1) * tot));
+  SDG_TRY(palloc_t(P, &P->gZ, (int64_t)m * tot));
+  SDG_TRY(palloc_t(P, &P->gw, tot));
+  SDG_TRY(palloc_t(P, &P->gt, P->nu * P->nb));
+  P->gn = n_per_problem;
+  return SDG_OK;
+}
+
+// Batched right-preconditioned FGMRES(restart), classical Gram-Schmidt
+// applied twice, x0 = 0; each problem stops on its own true residual.
+template <typename MV, typename PC, typename PJ>
+int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double rtol, int maxit, MV matvec,
+           PC prec, PJ project, std::vector<int>& its, std::vector<double>& rel, std::vector<int>& status) {
+  const int m = P->opt.restart, nb = P->nb;
+  SDG_TRY(ensure_gmres(P, S.total / nb));
   double* V = P->gV;
   double* Z = P->gZ;
   double* w = P->gw;
-  // b lives in V[m] until the first basis vector overwrites it: keep a
-  // projected copy in x's place? x is output; use w as the residual vector.
-  SDG_TRY(vec_copy(n, b_in, w, P->s));
+  const int64_t ldv = S.total;
+  SDG_TRY(vec_copy(S.total, b_in, w, P->s));
   SDG_TRY(project(w));
-  double bn;
-  SDG_TRY(norm2(P, n, w, &bn));
-  SDG_HIP(hipMemsetAsync(x, 0, n * sizeof(double), P->s));
-  *its = 0;
-  *relres = 0.0;
-  if (bn == 0.0) return SDG_OK;
-  if (!std::isfinite(bn)) {
-    set_error("right-hand side is not finite");
-    return SDG_ERR_INVALID;
-  }
-  int total = 0;
-  int status = SDG_NOT_CONVERGED;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  double beta = bn;  // residual vector is in w
-  while (true) {
-    if (beta / bn < rtol) {
-      status = SDG_OK;
-      break;
+  std::vector<double> bn, beta;
+  SDG_TRY(vs_norms(P, S, w, bn));
+  SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
+  its.assign(nb, 0);
+  rel.assign(nb, 0.0);
+  status.assign(nb, SDG_OK);
+  std::vector<char> act(nb, 0);
+  for (int pb = 0; pb < nb; ++pb) {
+    if (!std::isfinite(bn[pb])) {
+      status[pb] = SDG_BREAKDOWN;
+    } else if (bn[pb] > 0.0) {
+      act[pb] = 1;
+      rel[pb] = 1.0;
+      status[pb] = SDG_NOT_CONVERGED;
     }
-    if (total >= maxit) break;
-    SDG_TRY(vec_scale_copy(n, 1.0 / beta, w, V, P->s));
+  }
+  beta = bn;
+  std::vector<double> H((size_t)nb * (m + 1) * m), cs((size_t)nb * m), sn((size_t)nb * m);
+  std::vector<double> g((size_t)nb * (m + 1)), y((size_t)nb * m);
+  std::vector<int> jd(nb), gaps(nb, 0);
+  std::vector<char> done(nb), est_conv(nb);
+  std::vector<double> prev_rel(nb, 1.0);
+  int total = 0;
+  while (true) {
+    bool any = false;
+    for (int pb = 0; pb < nb; ++pb) any = any || act[pb];
+    if (!any || total >= maxit) break;
+    std::vector<double> bsc(nb);
+    for (int pb = 0; pb < nb; ++pb) bsc[pb] = act[pb] ? beta[pb] : 0.0;
+    SDG_TRY(upload_scalars(P, sc(P, SC_BN), bsc));
+    SDG_TRY(vs_div(P, S, sc(P, SC_BN), w, V));
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jd = 0;
-    bool done = false;
+    for (int pb = 0; pb < nb; ++pb) {
+      g[(size_t)pb * (m + 1)] = beta[pb];
+      jd[pb] = 0;
+      done[pb] = !act[pb];
+      est_conv[pb] = 0;
+    }
     for (int j = 0; j < m; ++j) {
-      double* zj = Z + (int64_t)j * n;
-      SDG_TRY(prec(V + (int64_t)j * n, zj));
+      double* zj = Z + (int64_t)j * ldv;
+      SDG_TRY(prec(V + (int64_t)j * ldv, zj));
       SDG_TRY(project(zj));
       SDG_TRY(matvec(zj, w));
-      std::vector<double> h(j + 1, 0.0);
+      std::vector<double> h((size_t)nb * (j + 1), 0.0), part;
       for (int pass = 0; pass < 2; ++pass) {
-        SDG_TRY(multi_dot(n, j + 1, V, n, w, P->dsc, P->red, P->s));
-        SDG_TRY(multi_axpy(n, j + 1, V, n, P->dsc, w, P->s));
-        SDG_TRY(read_scalars(P, j + 1));
-        for (int i = 0; i <= j; ++i) h[i] += P->hsc[i];
+        SDG_TRY(vs_dots(P, S, j + 1, V, ldv, w, part));
+        SDG_TRY(upload_scalars(P, sc_h(P), part));
+        SDG_TRY(vs_axpy(P, S, j + 1, V, ldv, sc_h(P), w));
+        for (size_t i = 0; i < h.size(); ++i) h[i] += part[i];
       }
-      double hn;
-      SDG_TRY(norm2(P, n, w, &hn));
-      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = h[i];
-      H[(size_t)j * (m + 1) + j + 1] = hn;
-      if (hn > 0.0 && j + 1 <= m) {
-        if (j + 1 < m + 1) SDG_TRY(vec_scale_copy(n, 1.0 / hn, w, V + (int64_t)(j + 1) * n, P->s));
+      std::vector<double> hn;
+      SDG_TRY(vs_norms(P, S, w, hn));
+      std::vector<double> hs(nb);
+      for (int pb = 0; pb < nb; ++pb) hs[pb] = done[pb] ? 0.0 : hn[pb];
+      SDG_TRY(upload_scalars(P, sc(P, SC_BN), hs));
+      SDG_TRY(vs_div(P, S, sc(P, SC_BN), w, V + (int64_t)(j + 1) * ldv));
+      bool all_done = true;
+      for (int pb = 0; pb < nb; ++pb) {
+        if (done[pb]) continue;
+        double* col = H.data() + ((size_t)pb * m + j) * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] = h[(size_t)pb * (j + 1) + i];
+        col[j + 1] = hn[pb];
+        double* c = cs.data() + (size_t)pb * m;
+        double* s_ = sn.data() + (size_t)pb * m;
+        double* gg = g.data() + (size_t)pb * (m + 1);
+        for (int i = 0; i < j; ++i) {
+          const double t = c[i] * col[i] + s_[i] * col[i + 1];
+          col[i + 1] = -s_[i] * col[i] + c[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        if (!(den > 0.0) || !std::isfinite(den)) {
+          status[pb] = SDG_BREAKDOWN;
+          act[pb] = 0;
+          done[pb] = 1;
+          continue;
+        }
+        c[j] = col[j] / den;
+        s_[j] = col[j + 1] / den;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        gg[j + 1] = -s_[j] * gg[j];
+        gg[j] = c[j] * gg[j];
+        ++its[pb];
+        jd[pb] = j + 1;
+        const double est = std::fabs(gg[j + 1]) / bn[pb];
+        if (est < rtol) est_conv[pb] = 1;
+        if (est < rtol || hn[pb] == 0.0 || its[pb] >= maxit) done[pb] = 1;
+        all_done = all_done && done[pb];
       }
-      double* col = &H[(size_t)j * (m + 1)];
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-      }
-      const double den = std::hypot(col[j], col[j + 1]);
-      if (!(den > 0.0) || !std::isfinite(den)) {
-        status = SDG_BREAKDOWN;
-        done = true;
-        jd = j;
-        break;
-      }
-      cs[j] = col[j] / den;
-      sn[j] = col[j + 1] / den;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
       ++total;
-      jd = j + 1;
-      const double est = std::fabs(g[j + 1]) / bn;
-      if (est < rtol || total >= maxit || hn == 0.0) break;
+      if (all_done || total >= maxit) break;
     }
-    // y = H^{-1} g (upper triangular), x += Z y
-    for (int i = jd - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int l = i + 1; l < jd; ++l) s -= H[(size_t)l * (m + 1) + i] * y[l];
-      y[i] = s / H[(size_t)i * (m + 1) + i];
+    // y = H^{-1} g per problem, x += Z y
+    std::fill(y.begin(), y.end(), 0.0);
+    int jmax = 0;
+    for (int pb = 0; pb < nb; ++pb) {
+      const int jj = jd[pb];
+      jmax = std::max(jmax, jj);
+      const double* Hp = H.data() + (size_t)pb * m * (m + 1);
+      const double* gg = g.data() + (size_t)pb * (m + 1);
+      double* yy = y.data() + (size_t)pb * m;
+      for (int i = jj - 1; i >= 0; --i) {
+        double s = gg[i];
+        for (int l = i + 1; l < jj; ++l) s -= Hp[(size_t)l * (m + 1) + i] * yy[l];
+        yy[i] = s / Hp[(size_t)i * (m + 1) + i];
+      }
     }
-    if (jd > 0) {
-      SDG_HIP(hipMemcpyAsync(P->dsc, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, P->s));
-      SDG_TRY(multi_combine(n, jd, Z, n, P->dsc, x, P->s));
+    if (jmax > 0) {
+      std::vector<double> yc((size_t)nb * jmax);
+      for (int pb = 0; pb < nb; ++pb)
+        for (int i = 0; i < jmax; ++i) yc[(size_t)pb * jmax + i] = y[(size_t)pb * m + i];
+      SDG_TRY(upload_scalars(P, sc_h(P), yc));
+      SDG_TRY(vs_combine(P, S, jmax, Z, ldv, sc_h(P), x));
     }
     // true residual
     SDG_TRY(matvec(x, w));
-    SDG_TRY(vec_axpby(n, 1.0, b_in, -1.0, w, P->s));
+    SDG_TRY(vec_axpby(S.total, 1.0, b_in, -1.0, w, P->s));
     SDG_TRY(project(w));
-    SDG_TRY(norm2(P, n, w, &beta));
-    if (done) break;
+    SDG_TRY(vs_norms(P, S, w, beta));
+    for (int pb = 0; pb < nb; ++pb) {
+      if (bn[pb] > 0.0 && std::isfinite(bn[pb])) rel[pb] = beta[pb] / bn[pb];
+      if (!act[pb]) continue;
+      if (rel[pb] < rtol) {
+        status[pb] = SDG_OK;
+        act[pb] = 0;
+        continue;
+      }
+      // rounding floor: the Arnoldi estimate fell below rtol but the true
+      // residual (computed in FP64, accurate only to about
+      // eps |K| |x| / |b|) did not follow, twice without halving
+      if (est_conv[pb] && rel[pb] > 0.5 * prev_rel[pb]) ++gaps[pb];
+      else gaps[pb] = 0;
+      prev_rel[pb] = rel[pb];
+      if (gaps[pb] >= 2) {
+        status[pb] = SDG_FLOOR;
+        act[pb] = 0;
+      } else if (its[pb] >= maxit) {
+        status[pb] = SDG_NOT_CONVERGED;
+        act[pb] = 0;
+      }
+    }
   }
-  *its = total;
-  *relres = beta / bn;
-  if (status != SDG_BREAKDOWN) status = (*relres < rtol) ? SDG_OK : SDG_NOT_CONVERGED;
-  return status;
+  return SDG_OK;
 }
 
-// Stokes operator K = [A B; B^T 0] on x = [u; p]
+// Stokes operator K = [A B; B^T 0] on x = [u (all problems); p (all problems)]
 int stokes_matvec(sdg_problem* P, const double* x, double* y) {
-  SDG_TRY(sip_apply(P->M, P->k, 1, P->eta, x, y, P->s));
-  SDG_TRY(grad_apply(P->M, P->k, 1, x + P->nu, P->gt, P->s));
-  SDG_TRY(vec_axpy(P->nu, 1.0, P->gt, y, P->s));
-  SDG_TRY(div_apply(P->M, P->k, 1, x, y + P->nu, P->s));
+  const int64_t U = P->nu * P->nb;
+  SDG_TRY(sip_apply(P->M, P->k, P->nb, P->eta, x, y, P->s));
+  SDG_TRY(grad_apply(P->M, P->k, P->nb, x + U, P->gt, P->s));
+  SDG_TRY(vec_axpy(U, 1.0, P->gt, y, P->s));
+  SDG_TRY(div_apply(P->M, P->k, P->nb, x, y + U, P->s));
   return SDG_OK;
 }
 
@@ -724,28 +936,43 @@ int stokes_matvec(sdg_problem* P, const double* x, double* y) {
 // as an approximation of the (negative definite) Schur complement
 // -B^T A^{-1} B:  z_p = S^{-1} v_p = -eta v_p, z_u = (inner CG)(v_u - B z_p)
 int stokes_prec(sdg_problem* P, const double* v, double* z) {
-  SDG_TRY(vec_mul(P->np, P->etap, v + P->nu, z + P->nu, P->s));
-  SDG_TRY(vec_scale_copy(P->np, -1.0, z + P->nu, z + P->nu, P->s));
-  SDG_TRY(grad_apply(P->M, P->k, 1, z + P->nu, P->gt, P->s));
-  SDG_TRY(vec_axpby(P->nu, 1.0, v, -1.0, P->gt, P->s));
-  int its = 0;
-  double rel = 0.0;
-  int rc = cg_solve(P, P->gt, z, P->opt.inner_rtol, P->opt.inner_max_it, &its, &rel);
-  if (rc < 0) return rc;
-  P->inner_total += its;
-  if (its > P->inner_max) P->inner_max = its;
+  const int64_t U = P->nu * P->nb, Pn = P->np * P->nb;
+  SDG_TRY(vec_mul(Pn, P->etap, v + U, z + U, P->s));
+  SDG_TRY(vec_scale_copy(Pn, -1.0, z + U, z + U, P->s));
+  SDG_TRY(grad_apply(P->M, P->k, P->nb, z + U, P->gt, P->s));
+  SDG_TRY(vec_axpby(U, 1.0, v, -1.0, P->gt, P->s));
+  std::vector<int> its, st;
+  std::vector<double> rel;
+  SDG_TRY(cg_solve(P, P->gt, z, P->opt.inner_rtol, P->opt.inner_max_it, its, rel, st));
+  for (int pb = 0; pb < P->nb; ++pb) {
+    P->inner_total[pb] += its[pb];
+    P->inner_max[pb] = std::max(P->inner_max[pb], its[pb]);
+  }
   return SDG_OK;
 }
 
 int stokes_project(sdg_problem* P, double* x) {
-  if (P->neumann) return SDG_OK;
-  return pressure_project(P->nel, P->NPE, x + P->nu, P->red, P->s);
+  if (P->neumann || P->np == 0) return SDG_OK;
+  return bpressure_project(P->nel, P->NPE, P->nb, P->np, x + P->nu * P->nb, P->red, P->s);
 }
 
-int sync_ms(sdg_problem* P, double t0, double* out) {
-  SDG_HIP(hipStreamSynchronize(P->s));
-  *out = now_ms() - t0;
-  return SDG_OK;
+int fill_stats(sdg_problem* P, sdg_stats* st, const std::vector<int>& status, const std::vector<int>& its,
+               const std::vector<double>& rel, double t0, bool stokes) {
+  // aggregate outcome: breakdown > not converged > rounding floor > ok
+  auto rank = [](int s) { return s == SDG_BREAKDOWN ? 3 : s == SDG_NOT_CONVERGED ? 2 : s == SDG_FLOOR ? 1 : 0; };
+  int worst = SDG_OK;
+  for (int pb = 0; pb < P->nb; ++pb) {
+    if (rank(status[pb]) > rank(worst)) worst = status[pb];
+    if (!st) continue;
+    st[pb].status = status[pb];
+    st[pb].outer_its = its[pb];
+    st[pb].inner_its_total = stokes ? P->inner_total[pb] : 0;
+    st[pb].inner_its_max = stokes ? P->inner_max[pb] : 0;
+    st[pb].rel_residual = rel[pb];
+    st[pb].setup_ms = P->setup_ms;
+    st[pb].solve_ms = now_ms() - t0;
+  }
+  return worst;
 }
 
 }  // namespace
@@ -814,48 +1041,56 @@ static bool opts_ok(const sdg_options* o) {
   return true;
 }
 
-size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes) {
-  if (!mesh_ok(mesh) || !opts_ok(opts)) return 0;
+size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, int stokes, int nbatch) {
+  if (!mesh_ok(mesh) || !opts_ok(opts) || nbatch < 1) return 0;
+  const int64_t nb = nbatch;
   const int64_t nel = (int64_t)mesh->nx * mesh->ny;
   const int64_t NB = 2 * (int64_t)(mesh->k + 1) * (mesh->k + 1);
   const int64_t nu = nel * NB, np = nel * mesh->k * mesh->k;
   size_t b = 0;
-  b += nel * 8 * 2 + nel * 4 + np * 8;              // eta, scale, ids, etap
-  const int64_t nuniq = opts->dedup ? std::min<int64_t>(nel, 4096) : nel;
-  b += nuniq * NB * NB * 8;                          // FP64 inverses (dedup: bound)
-  if (opts->prec_smoother == SDG_FP32) b += nuniq * NB * NB * 4;
-  if (opts->prec_smoother == SDG_BF16) b += nuniq * NB * NB * 2;
-  b += nuniq * 8 + nel * 64 * 8;                     // reps/status, coarse local matrices
+  b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, ids, etap
+  const int64_t nuniq = opts->dedup ? std::min<int64_t>(nel * nb, 4096) : nel * nb;
+  b += nuniq * NB * NB * 8 + nuniq * 8;
+  const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
+  if (low) b += nuniq * NB * (NB + 1) / 2 * (8 + (opts->prec_smoother == SDG_BF16 ? 2 : 4));
+  b += nb * nel * 64 * 8;  // coarse local matrices
   int cx = mesh->nx, cy = mesh->ny;
   while (true) {
     const int64_t nn = (int64_t)(cx + 1) * (cy + 1);
-    b += nn * (36 + 12) * 8;
+    b += nb * nn * (36 + 14) * 8 + opts->smooth_h * nb * 16;
     const bool more = cx % 2 == 0 && cy % 2 == 0 && cx > opts->coarsest_n && cy > opts->coarsest_n;
     if (!more) {
-      b += 4 * nn * nn * 8 + 8;
+      b += nb * 4 * nn * nn * 8 + nb * 8;
       break;
     }
     cx /= 2;
     cy /= 2;
   }
-  b += nu * 8 * 3;                                   // DG cycle vectors
-  if (opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64) b += nu * 4 * 5;
-  b += RED_SCRATCH * 8 + 64 * 8 + nu * 8 * 4;        // reductions, CG
+  b += nb * nu * 8 * 2 + opts->smooth_dg * nb * 16;  // DG cycle vectors
+  if (low) b += nb * nu * 4 * 4;
+  b += RED_SCRATCH * 8 + (SC_COUNT_FIXED + std::max(opts->restart, opts->eig_steps) + 4) * nb * 8 * 2 + nb * 4;
+  b += nb * nu * 8 * 4;  // CG
   const int64_t n = stokes ? nu + np : nu;
-  if (stokes || opts->viscous_krylov == 1) b += ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
-  b += (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
+  if (stokes || opts->viscous_krylov == 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
+  b += nb * (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
   return b;
 }
 
-int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
-                       const double* eta_dev, void* stream, sdg_problem** out) {
+size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes) {
+  return sdg_required_bytes_batch(mesh, opts, stokes, 1);
+}
+
+void sdg_problem_destroy(sdg_problem* P);
+
+int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, int nbatch,
+                             const double* eta_dev, void* stream, sdg_problem** out) {
   if (!out) {
     set_error("NULL output pointer");
     return SDG_ERR_INVALID;
   }
   *out = nullptr;
-  if (!ctx || !eta_dev) {
-    set_error("NULL context or viscosity");
+  if (!ctx || !eta_dev || nbatch < 1 || nbatch > 4096) {
+    set_error("NULL context or viscosity, or batch size outside 1..4096");
     return SDG_ERR_INVALID;
   }
   if (!mesh_ok(mesh)) {
@@ -869,8 +1104,7 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
     set_error("invalid options");
     return SDG_ERR_INVALID;
   }
-  bool all_neumann = true;
-  bool any_neumann = false;
+  bool all_neumann = true, any_neumann = false;
   for (int i = 0; i < 4; ++i) {
     all_neumann = all_neumann && mesh->bc[i] == SDG_NEUMANN;
     any_neumann = any_neumann || mesh->bc[i] == SDG_NEUMANN;
@@ -887,6 +1121,7 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
   P->mesh = *mesh;
   P->opt = o;
   P->s = (hipStream_t)stream;
+  P->nb = nbatch;
   P->k = mesh->k;
   P->K1 = mesh->k + 1;
   P->NB = 2 * P->K1 * P->K1;
@@ -900,74 +1135,88 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
   P->M.hx = mesh->lx / mesh->nx;
   P->M.hy = mesh->ly / mesh->ny;
   for (int i = 0; i < 4; ++i) P->M.bc[i] = mesh->bc[i];
+  P->inner_total.assign(nbatch, 0);
+  P->inner_max.assign(nbatch, 0);
   auto fail = [&](int rc) {
     sdg_problem_destroy(P);
     return rc;
   };
+  const int64_t ntot = (int64_t)P->nel * nbatch;
   int rc;
-  if ((rc = palloc_t(P, &P->eta, P->nel)) < 0) return fail(rc);
-  P->eta_host.resize(P->nel);
-  if (hipMemcpyAsync(P->eta_host.data(), eta_dev, P->nel * sizeof(double), hipMemcpyDeviceToHost, P->s) != hipSuccess ||
+  if ((rc = palloc_t(P, &P->eta, ntot)) < 0) return fail(rc);
+  P->eta_host.resize(ntot);
+  if (hipMemcpyAsync(P->eta_host.data(), eta_dev, ntot * sizeof(double), hipMemcpyDeviceToHost, P->s) != hipSuccess ||
       hipStreamSynchronize(P->s) != hipSuccess) {
+    (void)hipGetLastError();
     set_error("copy of the viscosity failed (device pointer expected)");
     return fail(SDG_ERR_DEVICE);
   }
-  for (int e = 0; e < P->nel; ++e)
+  for (int64_t e = 0; e < ntot; ++e)
     if (!(P->eta_host[e] > 0.0) || !std::isfinite(P->eta_host[e])) {
-      set_error("viscosity must be positive and finite (element " + std::to_string(e) + ")");
+      set_error("viscosity must be positive and finite (element " + std::to_string(e % P->nel) + " of problem " +
+                std::to_string(e / P->nel) + ")");
       return fail(SDG_ERR_INVALID);
     }
-  if (hipMemcpyAsync(P->eta, P->eta_host.data(), P->nel * sizeof(double), hipMemcpyHostToDevice, P->s) != hipSuccess) {
-    set_error("viscosity upload failed");
-    return fail(SDG_ERR_DEVICE);
-  }
+  if ((rc = to_dev(P, P->eta, P->eta_host.data(), ntot * sizeof(double))) < 0) return fail(rc);
   {
-    std::vector<double> ep(P->np);
-    for (int e = 0; e < P->nel; ++e)
-      for (int m = 0; m < P->NPE; ++m) ep[(size_t)e * P->NPE + m] = P->eta_host[e];
-    if ((rc = palloc_t(P, &P->etap, std::max<int64_t>(P->np, 1))) < 0) return fail(rc);
-    if (hipMemcpyAsync(P->etap, ep.data(), P->np * sizeof(double), hipMemcpyHostToDevice, P->s) != hipSuccess ||
-        hipStreamSynchronize(P->s) != hipSuccess) {
-      set_error("upload failed");
-      return fail(SDG_ERR_DEVICE);
-    }
+    std::vector<double> ep((size_t)P->np * nbatch);
+    for (int64_t ge = 0; ge < ntot; ++ge)
+      for (int m = 0; m < P->NPE; ++m) ep[(size_t)ge * P->NPE + m] = P->eta_host[ge];
+    if ((rc = palloc_t(P, &P->etap, (int64_t)ep.size())) < 0) return fail(rc);
+    if ((rc = to_dev(P, P->etap, ep.data(), ep.size() * sizeof(double))) < 0) return fail(rc);
   }
   if ((rc = setup_blocks(P)) < 0) return fail(rc);
   if ((rc = setup_coarse(P)) < 0) return fail(rc);
-  for (double** v : {&P->vr, &P->vz, &P->vd, &P->cg_r, &P->cg_z, &P->cg_p, &P->cg_q})
-    if ((rc = palloc_t(P, v, P->nu)) < 0) return fail(rc);
-  if (o.prec_apply == SDG_FP32 || o.prec_smoother != SDG_FP64) {
-    if (o.prec_smoother == SDG_FP64) {  // FP32 apply with FP32 copies of the inverses
-      if ((rc = palloc_t(P, &P->binv32, (int64_t)P->nuniq * P->NB * P->NB)) < 0) return fail(rc);
-      if ((rc = convert_f64_f32(P->binv, P->binv32, (int64_t)P->nuniq * P->NB * P->NB, P->s)) < 0) return fail(rc);
-    }
-    for (float** v : {&P->fb, &P->fx, &P->fr, &P->fz, &P->fd})
-      if ((rc = palloc_t(P, v, P->nu)) < 0) return fail(rc);
-  }
+  const int64_t U = P->nu * nbatch;
+  for (double** v : {&P->vr, &P->vd, &P->cg_r, &P->cg_z, &P->cg_p, &P->cg_q})
+    if ((rc = palloc_t(P, v, U)) < 0) return fail(rc);
+  if (low_precision(P))
+    for (float** v : {&P->fb, &P->fx, &P->fr, &P->fd})
+      if ((rc = palloc_t(P, v, U)) < 0) return fail(rc);
+  if ((rc = palloc_t(P, &P->ab0, (int64_t)o.smooth_dg * nbatch * 2)) < 0) return fail(rc);
   if ((rc = palloc_t(P, &P->red, RED_SCRATCH)) < 0) return fail(rc);
-  if ((rc = palloc_t(P, &P->dsc, 256)) < 0) return fail(rc);
-  if (hipHostMalloc((void**)&P->hsc, 256 * sizeof(double)) != hipSuccess) {
+  const int64_t nsc = (int64_t)(SC_COUNT_FIXED + std::max(o.restart, o.eig_steps) + 4) * nbatch * 2;
+  if ((rc = palloc_t(P, &P->dsc, nsc)) < 0) return fail(rc);
+  if ((rc = palloc_t(P, &P->active, nbatch)) < 0) return fail(rc);
+  if (hipHostMalloc((void**)&P->hsc, nsc * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
     set_error("pinned allocation failed");
     return fail(SDG_ERR_NOMEM);
   }
   // Chebyshev bounds
-  double lam;
-  if ((rc = arnoldi(P, -1, &lam, nullptr)) < 0) return fail(rc);
-  P->lmin0 = o.cheb_lo * lam;
-  P->lmax0 = o.cheb_hi * lam;
-  for (size_t li = 0; li < P->lev.size(); ++li) {
-    if (P->lev[li].coarsest) continue;
-    if ((rc = arnoldi(P, (int)li, &lam, nullptr)) < 0) return fail(rc);
-    P->lev[li].lmin = o.cheb_lo * lam;
-    P->lev[li].lmax = o.cheb_hi * lam;
+  std::vector<double> lam;
+  if ((rc = arnoldi(P, -1, lam, nullptr)) < 0) return fail(rc);
+  P->lmin0.resize(nbatch);
+  P->lmax0.resize(nbatch);
+  for (int pb = 0; pb < nbatch; ++pb) {
+    P->lmin0[pb] = o.cheb_lo * lam[pb];
+    P->lmax0[pb] = o.cheb_hi * lam[pb];
   }
+  for (size_t li = 0; li < P->lev.size(); ++li) {
+    CLevel& L = P->lev[li];
+    if (L.coarsest) continue;
+    if ((rc = arnoldi(P, (int)li, lam, nullptr)) < 0) return fail(rc);
+    L.lmin.resize(nbatch);
+    L.lmax.resize(nbatch);
+    for (int pb = 0; pb < nbatch; ++pb) {
+      L.lmin[pb] = o.cheb_lo * lam[pb];
+      L.lmax[pb] = o.cheb_hi * lam[pb];
+    }
+  }
+  if ((rc = upload_cheb(P)) < 0) return fail(rc);
   if (hipStreamSynchronize(P->s) != hipSuccess) {
+    (void)hipGetLastError();
     set_error("setup failed on the device");
     return fail(SDG_ERR_DEVICE);
   }
   P->setup_ms = now_ms() - t0;
   *out = P;
   return SDG_OK;
+}
+
+int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta_dev,
+                       void* stream, sdg_problem** out) {
+  return sdg_problem_create_batch(ctx, mesh, opts, 1, eta_dev, stream, out);
 }
 
 void sdg_problem_destroy(sdg_problem* P) {
@@ -981,6 +1230,15 @@ void sdg_problem_destroy(sdg_problem* P) {
     if (c->closing && c->live == 0) delete c;
   }
   delete P;
+}
+
+int sdg_problem_batch(const sdg_problem* P, int* nbatch) {
+  if (!P || !nbatch) {
+    set_error("NULL argument");
+    return SDG_ERR_INVALID;
+  }
+  *nbatch = P->nb;
+  return SDG_OK;
 }
 
 int sdg_problem_levels(const sdg_problem* P, int* nlevels) {
@@ -997,11 +1255,16 @@ int sdg_get_bounds(const sdg_problem* P, double* b) {
     set_error("NULL argument");
     return SDG_ERR_INVALID;
   }
-  b[0] = P->lmin0;
-  b[1] = P->lmax0;
-  for (size_t i = 0; i < P->lev.size(); ++i) {
-    b[2 + 2 * i] = P->lev[i].lmin;
-    b[3 + 2 * i] = P->lev[i].lmax;
+  const int nl = 1 + (int)P->lev.size();
+  for (int pb = 0; pb < P->nb; ++pb) {
+    double* o = b + (size_t)pb * nl * 2;
+    o[0] = P->lmin0[pb];
+    o[1] = P->lmax0[pb];
+    for (size_t i = 0; i < P->lev.size(); ++i) {
+      const bool c = P->lev[i].coarsest;
+      o[2 + 2 * i] = c ? 0.0 : P->lev[i].lmin[pb];
+      o[3 + 2 * i] = c ? 0.0 : P->lev[i].lmax[pb];
+    }
   }
   return SDG_OK;
 }
@@ -1011,13 +1274,18 @@ int sdg_set_bounds(sdg_problem* P, const double* b) {
     set_error("NULL argument");
     return SDG_ERR_INVALID;
   }
-  P->lmin0 = b[0];
-  P->lmax0 = b[1];
-  for (size_t i = 0; i < P->lev.size(); ++i) {
-    P->lev[i].lmin = b[2 + 2 * i];
-    P->lev[i].lmax = b[3 + 2 * i];
+  const int nl = 1 + (int)P->lev.size();
+  for (int pb = 0; pb < P->nb; ++pb) {
+    const double* o = b + (size_t)pb * nl * 2;
+    P->lmin0[pb] = o[0];
+    P->lmax0[pb] = o[1];
+    for (size_t i = 0; i < P->lev.size(); ++i) {
+      if (P->lev[i].coarsest) continue;
+      P->lev[i].lmin[pb] = o[2 + 2 * i];
+      P->lev[i].lmax[pb] = o[3 + 2 * i];
+    }
   }
-  return SDG_OK;
+  return upload_cheb(P);
 }
 
 int sdg_eig_estimate(sdg_problem* P, int level, double* lambda_out, double* hess) {
@@ -1029,8 +1297,9 @@ int sdg_eig_estimate(sdg_problem* P, int level, double* lambda_out, double* hess
     set_error("the coarsest level is solved directly and has no smoother");
     return SDG_ERR_INVALID;
   }
-  std::vector<double> H;
-  SDG_TRY(arnoldi(P, level - 1, lambda_out, &H));
+  std::vector<double> lam, H;
+  SDG_TRY(arnoldi(P, level - 1, lam, &H));
+  for (int pb = 0; pb < P->nb; ++pb) lambda_out[pb] = lam[pb];
   if (hess) std::memcpy(hess, H.data(), H.size() * sizeof(double));
   return SDG_OK;
 }
@@ -1051,51 +1320,58 @@ int sdg_eig_estimate(sdg_problem* P, int level, double* lambda_out, double* hess
 
 int sdg_apply_viscous(sdg_problem* P, const double* u, double* y) {
   PCHECK(u, y);
-  return sip_apply(P->M, P->k, 1, P->eta, u, y, P->s);
+  return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s);
 }
 int sdg_residual_viscous(sdg_problem* P, const double* b, const double* u, double* r) {
   PCHECK(b, u, r);
-  return sip_residual(P->M, P->k, 1, P->eta, b, u, r, P->s);
+  return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s);
 }
 int sdg_apply_viscous_f32(sdg_problem* P, const float* u, float* y) {
   PCHECK(u, y);
-  return sip_apply_f32(P->M, P->k, 1, P->eta, u, y, P->s);
+  return sip_apply_f32(P->M, P->k, P->nb, P->eta, u, y, P->s);
 }
 int sdg_apply_div(sdg_problem* P, const double* u, double* q) {
   PCHECK(u, q);
-  return div_apply(P->M, P->k, 1, u, q, P->s);
+  return div_apply(P->M, P->k, P->nb, u, q, P->s);
 }
 int sdg_apply_grad(sdg_problem* P, const double* p, double* v) {
   PCHECK(p, v);
-  return grad_apply(P->M, P->k, 1, p, v, P->s);
+  return grad_apply(P->M, P->k, P->nb, p, v, P->s);
 }
 int sdg_apply_blockjacobi(sdg_problem* P, const double* r, double* z) {
   PCHECK(r, z);
-  if (P->opt.prec_smoother == SDG_FP64) return bj64(P, r, z);
-  SDG_TRY(d2f(P->nu, r, P->fr, P->s));
-  SDG_TRY(bj32(P, P->fr, P->fz));
-  return f2d(P->nu, P->fz, z, P->s);
+  const int64_t ntot = (int64_t)P->nel * P->nb;
+  if (P->opt.prec_smoother == SDG_FP64)
+    return blockjacobi_apply_f64(P->NB, ntot, P->ids, P->scale, P->binv, r, z, P->s);
+  if (!P->fr) {
+    set_error("low-precision smoother storage missing");
+    return SDG_ERR_INVALID;
+  }
+  SDG_TRY(d2f(P->nu * P->nb, r, P->fr, P->s));
+  SDG_TRY(bj_apply32(P, P->fr, P->fd));
+  return f2d(P->nu * P->nb, P->fd, z, P->s);
 }
 int sdg_get_blocks(sdg_problem* P, double* blocks) {
   PCHECK(blocks);
-  std::vector<int> all(P->nel);
-  for (int e = 0; e < P->nel; ++e) all[e] = e;
+  const int64_t ntot = (int64_t)P->nel * P->nb;
+  std::vector<int> all(ntot);
+  for (int64_t e = 0; e < ntot; ++e) all[e] = (int)e;
   int* d = nullptr;
-  SDG_HIP(hipMalloc((void**)&d, P->nel * sizeof(int)));
+  SDG_HIP(hipMalloc((void**)&d, ntot * sizeof(int)));
   int rc = SDG_OK;
-  if (hipMemcpyAsync(d, all.data(), P->nel * sizeof(int), hipMemcpyHostToDevice, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
-  if (rc == SDG_OK) rc = sip_block_list(P->M, P->k, P->eta, d, P->nel, blocks, P->s);
+  if (hipMemcpyAsync(d, all.data(), ntot * sizeof(int), hipMemcpyHostToDevice, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
+  if (rc == SDG_OK) rc = sip_block_list(P->M, P->k, P->eta, d, (int)ntot, blocks, P->s);
   (void)hipStreamSynchronize(P->s);
   (void)hipFree(d);
   return rc;
 }
 int sdg_p_restrict(sdg_problem* P, const double* r, double* rc) {
   PCHECK(r, rc);
-  return p_restrict(P->M, P->k, 1, r, rc, P->s);
+  return p_restrict(P->M, P->k, P->nb, r, rc, P->s);
 }
 int sdg_p_prolong_add(sdg_problem* P, const double* ec, double* u) {
   PCHECK(ec, u);
-  return p_prolong_add(P->M, P->k, 1, ec, u, P->s);
+  return p_prolong_add(P->M, P->k, P->nb, ec, u, P->s);
 }
 int sdg_get_coarse_stencil(sdg_problem* P, int level, double* st, int* nx_out, int* ny_out) {
   PCHECK(st);
@@ -1104,7 +1380,7 @@ int sdg_get_coarse_stencil(sdg_problem* P, int level, double* st, int* nx_out, i
     return SDG_ERR_INVALID;
   }
   const CLevel& L = P->lev[level];
-  SDG_HIP(hipMemcpyAsync(st, L.st, (size_t)36 * L.nn * sizeof(double), hipMemcpyDeviceToDevice, P->s));
+  SDG_HIP(hipMemcpyAsync(st, L.st, (size_t)36 * L.nn * P->nb * sizeof(double), hipMemcpyDeviceToDevice, P->s));
   if (nx_out) *nx_out = L.nx;
   if (ny_out) *ny_out = L.ny;
   return SDG_OK;
@@ -1115,102 +1391,91 @@ int sdg_vcycle(sdg_problem* P, const double* b, double* x) {
 }
 int sdg_assemble_rhs(sdg_problem* P, const double* f, const double* g, double* F, double* G) {
   PCHECK(f, F, G);
-  return rhs_assemble(P->M, P->k, P->eta, f, g, F, G, P->s);
+  return rhs_assemble(P->M, P->k, P->nb, P->eta, f, g, F, G, P->s);
 }
 
 int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, double* u, sdg_stats* st) {
   PCHECK(f, u);
   const double t0 = now_ms();
+  const int64_t U = P->nu * P->nb;
   double* F = nullptr;
   double* G = nullptr;
-  SDG_HIP(hipMalloc((void**)&F, P->nu * sizeof(double)));
-  if (hipMalloc((void**)&G, std::max<int64_t>(P->np, 1) * sizeof(double)) != hipSuccess) {
+  SDG_HIP(hipMalloc((void**)&F, U * sizeof(double)));
+  if (hipMalloc((void**)&G, std::max<int64_t>(P->np * P->nb, 1) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
     (void)hipFree(F);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
-  int rc = rhs_assemble(P->M, P->k, P->eta, f, g, F, G, P->s);
-  int its = 0;
-  double rel = 0.0;
+  std::vector<int> its, status;
+  std::vector<double> rel;
+  int rc = rhs_assemble(P->M, P->k, P->nb, P->eta, f, g, F, G, P->s);
   if (rc >= 0) {
     if (P->opt.viscous_krylov == 1) {
-      auto mv = [&](const double* x, double* y) { return sip_apply(P->M, P->k, 1, P->eta, x, y, P->s); };
+      const VSpec S = viscous_spec(P);
+      auto mv = [&](const double* x, double* y) { return sip_apply(P->M, P->k, P->nb, P->eta, x, y, P->s); };
       auto pc = [&](const double* v, double* z) { return vcycle(P, v, z); };
       auto pj = [&](double*) { return SDG_OK; };
-      rc = fgmres(P, P->nu, F, u, P->opt.rtol, P->opt.max_it, mv, pc, pj, &its, &rel);
+      rc = fgmres(P, S, F, u, P->opt.rtol, P->opt.max_it, mv, pc, pj, its, rel, status);
     } else {
-      rc = cg_solve(P, F, u, P->opt.rtol, P->opt.max_it, &its, &rel);
+      rc = cg_solve(P, F, u, P->opt.rtol, P->opt.max_it, its, rel, status);
     }
   }
-  // true residual ||F - A u|| / ||F||
-  double trel = rel;
+  // true residual ||F - A u|| / ||F|| per problem
   if (rc >= 0) {
-    double fn, rn;
-    int r2 = norm2(P, P->nu, F, &fn);
-    if (r2 >= 0) r2 = sip_residual(P->M, P->k, 1, P->eta, F, u, P->vr, P->s);
-    if (r2 >= 0) r2 = norm2(P, P->nu, P->vr, &rn);
-    if (r2 >= 0) trel = fn > 0 ? rn / fn : 0.0;
-    else rc = r2;
+    const VSpec S = viscous_spec(P);
+    std::vector<double> fn, rn;
+    rc = vs_norms(P, S, F, fn);
+    if (rc >= 0) rc = sip_residual(P->M, P->k, P->nb, P->eta, F, u, P->vr, P->s);
+    if (rc >= 0) rc = vs_norms(P, S, P->vr, rn);
+    if (rc >= 0)
+      for (int pb = 0; pb < P->nb; ++pb) rel[pb] = fn[pb] > 0 ? rn[pb] / fn[pb] : 0.0;
   }
   (void)hipStreamSynchronize(P->s);
   (void)hipFree(F);
   (void)hipFree(G);
-  if (st) {
-    st->status = rc;
-    st->outer_its = its;
-    st->inner_its_total = 0;
-    st->inner_its_max = 0;
-    st->rel_residual = trel;
-    st->setup_ms = P->setup_ms;
-    st->solve_ms = now_ms() - t0;
-  }
-  return rc;
+  if (rc < 0) return rc;
+  return fill_stats(P, st, status, its, rel, t0, false);
 }
 
-int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, double* u, double* p,
-                         sdg_stats* st) {
+int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, double* u, double* p, sdg_stats* st) {
   PCHECK(f, u, p);
   const double t0 = now_ms();
-  const int64_t n = P->nu + P->np;
+  const VSpec S = stokes_spec(P);
+  const int64_t U = P->nu * P->nb;
   double* b = nullptr;
   double* x = nullptr;
-  SDG_HIP(hipMalloc((void**)&b, n * sizeof(double)));
-  if (hipMalloc((void**)&x, n * sizeof(double)) != hipSuccess) {
+  SDG_HIP(hipMalloc((void**)&b, S.total * sizeof(double)));
+  if (hipMalloc((void**)&x, S.total * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
     (void)hipFree(b);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
-  P->inner_total = 0;
-  P->inner_max = 0;
-  int rc = rhs_assemble(P->M, P->k, P->eta, f, g, b, b + P->nu, P->s);
-  int its = 0;
-  double rel = 0.0;
-  if (rc >= 0) rc = ensure_gmres(P, n);
+  std::fill(P->inner_total.begin(), P->inner_total.end(), 0);
+  std::fill(P->inner_max.begin(), P->inner_max.end(), 0);
+  std::vector<int> its, status;
+  std::vector<double> rel;
+  int rc = rhs_assemble(P->M, P->k, P->nb, P->eta, f, g, b, b + U, P->s);
+  if (rc >= 0) rc = ensure_gmres(P, P->nu + P->np);
   if (rc >= 0) {
     auto mv = [&](const double* xx, double* yy) { return stokes_matvec(P, xx, yy); };
     auto pc = [&](const double* v, double* z) { return stokes_prec(P, v, z); };
     auto pj = [&](double* v) { return stokes_project(P, v); };
-    rc = fgmres(P, n, b, x, P->opt.rtol, P->opt.max_it, mv, pc, pj, &its, &rel);
+    rc = fgmres(P, S, b, x, P->opt.rtol, P->opt.max_it, mv, pc, pj, its, rel, status);
   }
   if (rc >= 0) {
-    int r2 = stokes_project(P, x);
-    if (r2 >= 0 && hipMemcpyAsync(u, x, P->nu * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess) r2 = SDG_ERR_DEVICE;
-    if (r2 >= 0 && hipMemcpyAsync(p, x + P->nu, P->np * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess) r2 = SDG_ERR_DEVICE;
-    if (r2 < 0) rc = r2;
+    rc = stokes_project(P, x);
+    if (rc >= 0 && hipMemcpyAsync(u, x, U * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
+    if (rc >= 0 && P->np > 0 &&
+        hipMemcpyAsync(p, x + U, P->np * P->nb * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess)
+      rc = SDG_ERR_DEVICE;
   }
   (void)hipStreamSynchronize(P->s);
   (void)hipFree(b);
   (void)hipFree(x);
-  if (st) {
-    st->status = rc;
-    st->outer_its = its;
-    st->inner_its_total = P->inner_total;
-    st->inner_its_max = P->inner_max;
-    st->rel_residual = rel;
-    st->setup_ms = P->setup_ms;
-    st->solve_ms = now_ms() - t0;
-  }
-  return rc;
+  if (rc < 0) return rc;
+  return fill_stats(P, st, status, its, rel, t0, true);
 }
 
 static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta,
@@ -1243,6 +1508,7 @@ static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
     if (hipMemcpy(de, eta, nel * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(df, f, nu * 8, hipMemcpyHostToDevice) != hipSuccess ||
         (g && hipMemcpy(dg, g, ng * 8, hipMemcpyHostToDevice) != hipSuccess)) {
+      (void)hipGetLastError();
       set_error("host to device copy failed");
       rc = SDG_ERR_DEVICE;
     }
@@ -1253,7 +1519,8 @@ static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
     rc = stokes ? sdg_solve_stokes_dev(P, df, dg, du, dp, st) : sdg_solve_viscous_dev(P, df, dg, du, st);
     if (rc >= 0) {
       if (hipMemcpy(u, du, nu * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-          (stokes && hipMemcpy(p, dp, np * 8, hipMemcpyDeviceToHost) != hipSuccess)) {
+          (stokes && np > 0 && hipMemcpy(p, dp, np * 8, hipMemcpyDeviceToHost) != hipSuccess)) {
+        (void)hipGetLastError();
         set_error("device to host copy failed");
         rc = SDG_ERR_DEVICE;
       }

@@ -1,6 +1,8 @@
 // Vector updates, deterministic two-stage reductions, the SplitMix64 start
 // vectors and the small Hessenberg eigenvalue solve behind the Chebyshev
 // bounds (Section 6: lambda* from ten GMRES/Arnoldi steps).
+#include <algorithm>
+
 #include "sdg_common.h"
 #include "sdg_kernels.h"
 
@@ -214,8 +216,7 @@ __device__ void house3(double x, double y, double z, double* v, double* beta) {
   *beta = vv > 0.0 ? 2.0 / vv : 0.0;
 }
 
-__global__ void hess_eig_kernel(const double* __restrict__ Hin, int m, int ld, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ double hess_max_eig_dev(const double* __restrict__ Hin, int m, int ld) {
   double H[HMAX][HMAX];
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) H[i][j] = (i <= j + 1) ? Hin[(int64_t)j * ld + i] : 0.0;
@@ -323,7 +324,12 @@ __global__ void hess_eig_kernel(const double* __restrict__ Hin, int m, int ld, d
   } else {
     best = gersh;
   }
-  out[0] = best;
+  return best;
+}
+
+__global__ void hess_eig_kernel(const double* __restrict__ Hin, int m, int ld, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  out[0] = hess_max_eig_dev(Hin, m, ld);
 }
 
 int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t s) {
@@ -332,6 +338,214 @@ int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t 
     return SDG_ERR_INVALID;
   }
   hipLaunchKernelGGL(hess_eig_kernel, dim3(1), dim3(64), 0, s, H, m, ld, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+}  // namespace sdg
+
+// ===========================================================================
+// Batched kernels: vectors are [nbatch][n] (problem pb at offset pb * n);
+// per-problem scalars are device arrays indexed by pb.
+// ===========================================================================
+namespace sdg {
+
+// partial[pb][j][blk] = slice of <V_j[pb], w[pb]>; V_j at V + j * ldv
+__global__ __launch_bounds__(VT) void bmultidot_stage1(int64_t n, int m, const double* __restrict__ V,
+                                                       int64_t ldv, const double* __restrict__ w,
+                                                       double* __restrict__ part) {
+  const int j = blockIdx.y % m, pb = blockIdx.y / m;
+  const double* v = V + j * ldv + (int64_t)pb * n;
+  const double* ww = w + (int64_t)pb * n;
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) s += v[g] * ww[g];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* w, double* out,
+               double* scratch, hipStream_t s) {
+  if (m <= 0 || nbatch <= 0) return SDG_OK;
+  if ((int64_t)m * nbatch > 512 * 64) {
+    set_error("reduction scratch too small for this batch");
+    return SDG_ERR_INVALID;
+  }
+  int nb = red_blocks(n);
+  if (nb * m * nbatch > 512 * 64) nb = std::max(1, 512 * 64 / (m * nbatch));
+  hipLaunchKernelGGL(bmultidot_stage1, dim3(nb, m * nbatch), dim3(VT), 0, s, n, m, V, ldv, w, scratch);
+  SDG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_stage2, dim3(m * nbatch), dim3(VT), 0, s, nb, scratch, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// w[pb] -= sum_j h[pb][j] V_j[pb]
+__global__ void bmulti_axpy_kernel(int64_t n, int nbatch, int m, const double* __restrict__ V, int64_t ldv,
+                                   const double* __restrict__ h, double* __restrict__ w) {
+  const int64_t tot = n * nbatch;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const int64_t pb = g / n;
+    double s = w[g];
+    for (int j = 0; j < m; ++j) s -= h[pb * m + j] * V[j * ldv + g];
+    w[g] = s;
+  }
+}
+// y[pb] += sum_j h[pb][j] V_j[pb]
+__global__ void bmulti_combine_kernel(int64_t n, int nbatch, int m, const double* __restrict__ V, int64_t ldv,
+                                      const double* __restrict__ h, double* __restrict__ y) {
+  const int64_t tot = n * nbatch;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const int64_t pb = g / n;
+    double s = y[g];
+    for (int j = 0; j < m; ++j) s += h[pb * m + j] * V[j * ldv + g];
+    y[g] = s;
+  }
+}
+int bmulti_axpy(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* h, double* w,
+                hipStream_t s) {
+  const int64_t tot = n * nbatch;
+  if (tot > 0) hipLaunchKernelGGL(bmulti_axpy_kernel, dim3(grid_for(tot)), dim3(VT), 0, s, n, nbatch, m, V, ldv, h, w);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int bmulti_combine(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* h, double* y,
+                   hipStream_t s) {
+  const int64_t tot = n * nbatch;
+  if (tot > 0) hipLaunchKernelGGL(bmulti_combine_kernel, dim3(grid_for(tot)), dim3(VT), 0, s, n, nbatch, m, V, ldv, h, y);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// y[pb] = a[pb] * x[pb] (a from device memory)
+__global__ void bscale_kernel(int64_t n, int64_t tot, const double* __restrict__ a, const double* __restrict__ x,
+                              double* __restrict__ y, int invert) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const double s = a[g / n];
+    y[g] = invert ? (s != 0.0 ? x[g] / s : 0.0) : s * x[g];
+  }
+}
+int bscale(int64_t n, int nbatch, const double* a, const double* x, double* y, int invert, hipStream_t s) {
+  const int64_t tot = n * nbatch;
+  if (tot > 0) hipLaunchKernelGGL(bscale_kernel, dim3(grid_for(tot)), dim3(VT), 0, s, n, tot, a, x, y, invert);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// CG step 1: alpha = active ? rz/pq : 0; x += alpha p; r -= alpha q;
+// partial sums of ||r||^2 per problem
+__global__ __launch_bounds__(VT) void cg_update1_kernel(int64_t n, const double* __restrict__ p,
+                                                        const double* __restrict__ q, double* __restrict__ x,
+                                                        double* __restrict__ r, const double* __restrict__ rz,
+                                                        const double* __restrict__ pq,
+                                                        const int* __restrict__ active,
+                                                        double* __restrict__ part) {
+  const int pb = blockIdx.y;
+  const double a = (active[pb] && pq[pb] > 0.0) ? rz[pb] / pq[pb] : 0.0;
+  const int64_t off = (int64_t)pb * n;
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    const double rv = r[off + g] - a * q[off + g];
+    x[off + g] += a * p[off + g];
+    r[off + g] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(int64_t)pb * gridDim.x + blockIdx.x] = s;
+}
+int cg_update1(int64_t n, int nbatch, const double* p, const double* q, double* x, double* r,
+               const double* rz, const double* pq, const int* active, double* rr, double* scratch,
+               hipStream_t s) {
+  int nb = red_blocks(n);
+  if (nb * nbatch > 512 * 64) nb = std::max(1, 512 * 64 / nbatch);
+  hipLaunchKernelGGL(cg_update1_kernel, dim3(nb, nbatch), dim3(VT), 0, s, n, p, q, x, r, rz, pq, active, scratch);
+  SDG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_stage2, dim3(nbatch), dim3(VT), 0, s, nb, scratch, rr);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+// CG step 2: p = z + (rz_new / rz_old) p for active problems
+__global__ void cg_update2_kernel(int64_t n, int64_t tot, const double* __restrict__ z, double* __restrict__ p,
+                                  const double* __restrict__ rz_new, const double* __restrict__ rz_old,
+                                  const int* __restrict__ active) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const int64_t pb = g / n;
+    if (!active[pb]) continue;
+    p[g] = z[g] + (rz_new[pb] / rz_old[pb]) * p[g];
+  }
+}
+int cg_update2(int64_t n, int nbatch, const double* z, double* p, const double* rz_new, const double* rz_old,
+               const int* active, hipStream_t s) {
+  const int64_t tot = n * nbatch;
+  if (tot > 0) hipLaunchKernelGGL(cg_update2_kernel, dim3(grid_for(tot)), dim3(VT), 0, s, n, tot, z, p, rz_new, rz_old, active);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// mode 0: d = a[pb] d + b[pb] z, x += d; 1: d = b z, x = d; 2: d = b z, x += d
+template <typename T>
+__global__ void bcheb_kernel(int64_t n, int64_t tot, const double* __restrict__ ab, const T* __restrict__ z,
+                             T* __restrict__ d, T* __restrict__ x, int mode) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const int64_t pb = g / n;
+    const double a = ab[2 * pb], b = ab[2 * pb + 1];
+    const T dv = mode == 0 ? T(a * double(d[g]) + b * double(z[g])) : T(b * double(z[g]));
+    d[g] = dv;
+    x[g] = mode == 1 ? dv : T(x[g] + dv);
+  }
+}
+int bcheb_update(int64_t n, int nbatch, const double* ab, const double* z, double* d, double* x, int mode,
+                 hipStream_t s) {
+  const int64_t tot = n * nbatch;
+  if (tot > 0) hipLaunchKernelGGL(bcheb_kernel<double>, dim3(grid_for(tot)), dim3(VT), 0, s, n, tot, ab, z, d, x, mode);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// pressure mean removal per problem (constant modes, uniform elements)
+__global__ __launch_bounds__(VT) void bpmean_stage1(int64_t nel, int np, int64_t stride, const double* __restrict__ p,
+                                                    double* __restrict__ part) {
+  const int pb = blockIdx.y;
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < nel; g += (int64_t)gridDim.x * VT)
+    s += p[pb * stride + g * np];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(int64_t)pb * gridDim.x + blockIdx.x] = s;
+}
+__global__ void bpmean_sub(int64_t nel, int np, int64_t stride, int nbatch, const double* __restrict__ sum,
+                           double* __restrict__ p) {
+  const int64_t tot = nel * nbatch;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) {
+    const int64_t pb = g / nel, e = g - pb * nel;
+    p[pb * stride + e * np] -= sum[pb] / (double)nel;
+  }
+}
+// p[pb] at p + pb * stride (stride >= nel * np)
+int bpressure_project(int64_t nel, int np, int nbatch, int64_t stride, double* p, double* scratch,
+                      hipStream_t s) {
+  int nb = red_blocks(nel);
+  if (nb * nbatch > 512 * 32) nb = std::max(1, 512 * 32 / nbatch);
+  hipLaunchKernelGGL(bpmean_stage1, dim3(nb, nbatch), dim3(VT), 0, s, nel, np, stride, p, scratch);
+  SDG_CHECK_LAUNCH();
+  double* sums = scratch + 512 * 32;
+  hipLaunchKernelGGL(reduce_stage2, dim3(nbatch), dim3(VT), 0, s, nb, scratch, sums);
+  SDG_CHECK_LAUNCH();
+  const int64_t tot = nel * nbatch;
+  hipLaunchKernelGGL(bpmean_sub, dim3(grid_for(tot)), dim3(VT), 0, s, nel, np, stride, nbatch, sums, p);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// largest eigenvalue for nbatch Hessenberg matrices (one thread each);
+// matrix pb at Hin + pb * hstride, order ms[pb]
+__global__ void bhess_eig_kernel(int nbatch, const double* __restrict__ Hin, const int* __restrict__ ms, int ld,
+                                 int64_t hstride, double* __restrict__ out) {
+  const int pb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pb >= nbatch) return;
+  out[pb] = hess_max_eig_dev(Hin + pb * hstride, ms[pb], ld);
+}
+int bhessenberg_max_eig(int nbatch, const double* H, const int* ms, int ld, int64_t hstride, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(bhess_eig_kernel, dim3(ceil_div(nbatch, 64)), dim3(64), 0, s, nbatch, H, ms, ld, hstride, out);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libsdg.so")
 NAVIER, NEUMANN, DIRICHLET = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-NOT_CONVERGED, BREAKDOWN = 1, 2
+NOT_CONVERGED, BREAKDOWN, FLOOR = 1, 2, 3
 
 
 class sdg_mesh(ctypes.Structure):
@@ -60,6 +60,9 @@ PROTOTYPES = {
     "sdg_options_default": (None, [OPTS]),
     "sdg_required_bytes": (ctypes.c_size_t, [MESH, OPTS, I]),
     "sdg_problem_create": (I, [P, MESH, OPTS, P, P, PP]),
+    "sdg_problem_create_batch": (I, [P, MESH, OPTS, I, P, P, PP]),
+    "sdg_problem_batch": (I, [P, ctypes.POINTER(ctypes.c_int)]),
+    "sdg_required_bytes_batch": (ctypes.c_size_t, [MESH, OPTS, I, I]),
     "sdg_problem_destroy": (None, [P]),
     "sdg_problem_levels": (I, [P, ctypes.POINTER(ctypes.c_int)]),
     "sdg_get_bounds": (I, [P, ctypes.POINTER(ctypes.c_double)]),
@@ -169,6 +172,23 @@ def sdg_problem_create(ctx, mesh, opts, eta_dev, stream=None):
     return out
 
 
+def sdg_problem_create_batch(ctx, mesh, opts, nbatch, eta_dev, stream=None):
+    out = ctypes.c_void_p()
+    check(lib().sdg_problem_create_batch(ctx, ctypes.byref(mesh), ctypes.byref(opts), int(nbatch),
+                                         ptr(eta_dev), stream, ctypes.byref(out)))
+    return out
+
+
+def sdg_problem_batch(prob):
+    n = ctypes.c_int()
+    check(lib().sdg_problem_batch(prob, ctypes.byref(n)))
+    return n.value
+
+
+def sdg_required_bytes_batch(mesh, opts, stokes, nbatch):
+    return lib().sdg_required_bytes_batch(ctypes.byref(mesh), ctypes.byref(opts), int(stokes), int(nbatch))
+
+
 def sdg_problem_destroy(prob):
     lib().sdg_problem_destroy(prob)
 
@@ -180,23 +200,29 @@ def sdg_problem_levels(prob):
 
 
 def sdg_get_bounds(prob):
+    """[nbatch][nlevels][2] array (a batch of one is returned as [nlevels][2])."""
     n = sdg_problem_levels(prob)
-    b = (ctypes.c_double * (2 * n))()
-    check(lib().sdg_get_bounds(prob, b))
-    return np.array(b[:]).reshape(n, 2)
+    nb = sdg_problem_batch(prob)
+    b = np.zeros((nb, n, 2))
+    check(lib().sdg_get_bounds(prob, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return b[0] if nb == 1 else b
 
 
 def sdg_set_bounds(prob, bounds):
-    b = np.ascontiguousarray(bounds, dtype=np.float64).ravel()
+    n = sdg_problem_levels(prob)
+    nb = sdg_problem_batch(prob)
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(bounds, dtype=np.float64), (nb, n, 2)))
     check(lib().sdg_set_bounds(prob, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
 def sdg_eig_estimate(prob, level, steps=10):
-    lam = ctypes.c_double()
-    H = np.zeros((steps, steps + 1))  # column-major (steps+1) x steps
-    check(lib().sdg_eig_estimate(prob, level, ctypes.byref(lam),
+    """Returns (lambda[nbatch], H[nbatch][steps+1][steps])."""
+    nb = sdg_problem_batch(prob)
+    lam = np.zeros(nb)
+    H = np.zeros((nb, steps, steps + 1))
+    check(lib().sdg_eig_estimate(prob, level, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-    return lam.value, H.T.copy()
+    return lam, np.transpose(H, (0, 2, 1)).copy()
 
 
 def _op(name):
@@ -258,16 +284,24 @@ def sdg_assemble_rhs(prob, f, g, F, G):
     return check(lib().sdg_assemble_rhs(prob, ptr(f), ptr(g), ptr(F), ptr(G)))
 
 
+def _stats_out(st, nb):
+    d = [st[i].as_dict() for i in range(nb)]
+    return d[0] if nb == 1 else d
+
+
 def sdg_solve_viscous_dev(prob, f, g, u):
-    st = sdg_stats()
-    rc = check(lib().sdg_solve_viscous_dev(prob, ptr(f), ptr(g), ptr(u), ctypes.byref(st)))
-    return rc, st.as_dict()
+    """Returns (rc, stats); stats is a dict, or a list of nbatch dicts."""
+    nb = sdg_problem_batch(prob)
+    st = (sdg_stats * nb)()
+    rc = check(lib().sdg_solve_viscous_dev(prob, ptr(f), ptr(g), ptr(u), st))
+    return rc, _stats_out(st, nb)
 
 
 def sdg_solve_stokes_dev(prob, f, g, u, p):
-    st = sdg_stats()
-    rc = check(lib().sdg_solve_stokes_dev(prob, ptr(f), ptr(g), ptr(u), ptr(p), ctypes.byref(st)))
-    return rc, st.as_dict()
+    nb = sdg_problem_batch(prob)
+    st = (sdg_stats * nb)()
+    rc = check(lib().sdg_solve_stokes_dev(prob, ptr(f), ptr(g), ptr(u), ptr(p), st))
+    return rc, _stats_out(st, nb)
 
 
 def sdg_solve_viscous(ctx, mesh, opts, eta, f, g, u):
@@ -290,7 +324,8 @@ def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
 
 # ---- convenience object ------------------------------------------------------
 class Problem:
-    """A set-up problem on the current torch stream (device tensors in/out)."""
+    """A set-up problem (or batch of problems on one mesh: eta of shape
+    [nbatch, nel]) on the current torch stream; device tensors in/out."""
 
     def __init__(self, ctx, nx, ny, k, eta, bc=(NAVIER,) * 4, lx=1.0, ly=1.0, **options):
         import torch
@@ -300,11 +335,15 @@ class Problem:
         self.nx, self.ny, self.k = nx, ny, k
         self.nel = nx * ny
         self.nb = 2 * (k + 1) ** 2
-        self.nu = self.nel * self.nb
-        self.np = self.nel * k * k
-        self.eta = torch.as_tensor(eta, dtype=torch.float64, device="cuda").contiguous()
+        eta = torch.as_tensor(eta, dtype=torch.float64, device="cuda").contiguous()
+        self.nbatch = eta.numel() // self.nel
+        assert eta.numel() == self.nbatch * self.nel
+        self.nu = self.nel * self.nb * self.nbatch
+        self.np = self.nel * k * k * self.nbatch
+        self.eta = eta.reshape(-1)
         self.ctx = ctx
-        self.h = sdg_problem_create(ctx, self.mesh, self.opts, self.eta, current_stream())
+        self.h = sdg_problem_create_batch(ctx, self.mesh, self.opts, self.nbatch, self.eta,
+                                          current_stream())
 
     def close(self):
         if self.h:

@@ -276,9 +276,10 @@ def test_stokes_solve_parity(sdg, ctx, torch, n, k, ein, bc, rtol):
     P = make_problem(sdg, ctx, n, n, k, P0.eta, bc, rtol=rtol, inner_rtol=1e-6, coarsest_n=4,
                      max_it=600)
     u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)))
-    assert st["status"] == 0, st
+    assert st["status"] in (0, sdg.FLOOR), st
     assert np.linalg.norm(host(u) - ud) <= 1e-9 * np.linalg.norm(ud), st
-    assert np.linalg.norm(host(p) - pd) <= 1e-7 * np.linalg.norm(pd), st
+    # the pressure is determined through B only: one more order of κ
+    assert np.linalg.norm(host(p) - pd) <= 1e-6 * np.linalg.norm(pd), st
     P.close()
 
 
@@ -327,3 +328,90 @@ def test_single_element_meshes(sdg, ctx, torch):
         torch.cuda.synchronize()
         assert_close_componentwise(host(y), A @ u, abs_bound(A, u), 1e-13 * 64)
         P.close()
+
+
+# ----------------------------------------------------------------------------
+# batched problems (several problems on one mesh in one problem object)
+# ----------------------------------------------------------------------------
+def test_batch_apply_bit_identical(sdg, ctx, torch):
+    """Problem pb of a batch runs the same arithmetic as a solo problem."""
+    nx, ny, k = 13, 9, 4
+    etas = [rand_eta(nx * ny, 50 + i, 6) for i in range(3)]
+    Pb = make_problem(sdg, ctx, nx, ny, k, np.stack(etas))
+    nu1 = nx * ny * 2 * (k + 1) ** 2
+    rng = np.random.default_rng(8)
+    u = rng.normal(size=3 * nu1)
+    y = Pb.zeros(3 * nu1)
+    sdg.sdg_apply_viscous(Pb.h, dev(u), y)
+    torch.cuda.synchronize()
+    yb = host(y)
+    for i in range(3):
+        P1 = make_problem(sdg, ctx, nx, ny, k, etas[i])
+        y1 = P1.zeros(nu1)
+        sdg.sdg_apply_viscous(P1.h, dev(u[i * nu1:(i + 1) * nu1]), y1)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(y1), yb[i * nu1:(i + 1) * nu1])
+        P1.close()
+    Pb.close()
+
+
+def test_batch_viscous_matches_solo_and_oracle(sdg, ctx, torch):
+    n, k = 16, 3
+    probs = [gen.random_problem(n, k, 20 + i, contrast=10.0 ** (i + 1)) for i in range(3)]
+    eta = np.stack([p.eta for p in probs])
+    f = np.concatenate([p.f.reshape(-1) for p in probs])
+    Pb = make_problem(sdg, ctx, n, n, k, eta, rtol=1e-12, max_it=2000, coarsest_n=4)
+    u, stats = Pb.solve_viscous(dev(f))
+    assert all(s["status"] == 0 for s in stats), stats
+    ub = host(u).reshape(3, -1)
+    m = Mesh(n, n, k)
+    for i, p in enumerate(probs):
+        ud = solve_viscous(m, p.eta, p.f)
+        assert np.linalg.norm(ub[i] - ud) <= 1e-9 * np.linalg.norm(ud), (i, stats[i])
+        P1 = make_problem(sdg, ctx, n, n, k, p.eta, rtol=1e-12, max_it=2000, coarsest_n=4)
+        u1, st1 = P1.solve_viscous(dev(p.f.reshape(-1)))
+        assert st1["outer_its"] == stats[i]["outer_its"], (st1, stats[i])
+        assert np.linalg.norm(host(u1) - ub[i]) <= 1e-10 * np.linalg.norm(ud)
+        P1.close()
+    Pb.close()
+
+
+def test_batch_stokes_matches_oracle(sdg, ctx, torch):
+    n, k = 8, 2
+    probs = [gen.single_inclusion(n, k, eta_in=e) for e in (1e1, 1e3)]
+    eta = np.stack([p.eta for p in probs])
+    f = np.concatenate([p.f.reshape(-1) for p in probs])
+    Pb = make_problem(sdg, ctx, n, n, k, eta, rtol=1e-11, inner_rtol=1e-6, coarsest_n=4, max_it=600)
+    u, p, stats = Pb.solve_stokes(dev(f))
+    assert all(s["status"] in (0, sdg.FLOOR) for s in stats), stats
+    ub, pb_ = host(u).reshape(2, -1), host(p).reshape(2, -1)
+    m = Mesh(n, n, k)
+    for i, pr in enumerate(probs):
+        ud, pd = solve_stokes(m, pr.eta, pr.f)
+        assert np.linalg.norm(ub[i] - ud) <= 1e-9 * np.linalg.norm(ud), stats[i]
+        assert np.linalg.norm(pb_[i] - pd) <= 1e-6 * np.linalg.norm(pd), stats[i]
+    Pb.close()
+
+
+# (n, k, contrast, rtol, velocity bound): the first case has an FP64
+# residual floor eps |A||u|/|F| ~ 1e-10, the second ~ 2e-8 (measured with the
+# oracle), so the second may end at the floor
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,k,ein,rtol,ubound", [(16, 3, 1e2, 1e-9, 1e-9), (16, 4, 1e4, 1e-8, 3e-9)])
+def test_mixed_precision_viscous(sdg, ctx, torch, prec, n, k, ein, rtol, ubound):
+    """FP32 fine-level cycle with FP32 or BF16 block inverses inside FP64
+    FGMRES (iterative refinement): reaches the FP64 tolerance (or the FP64
+    rounding floor) with the FP64 path's accuracy against the direct
+    solution."""
+    P0 = gen.single_inclusion(n, k, eta_in=ein)
+    m = Mesh(n, n, k)
+    ud = solve_viscous(m, P0.eta, P0.f)
+    ps = sdg.FP32 if prec == "fp32" else sdg.BF16
+    P = make_problem(sdg, ctx, n, n, k, P0.eta, rtol=rtol, max_it=400, coarsest_n=4,
+                     prec_apply=sdg.FP32, prec_smoother=ps, viscous_krylov=1, restart=60)
+    u, st = P.solve_viscous(dev(P0.f.reshape(-1)))
+    print(f"[mixed] {prec} n={n} k={k} eta={ein}: {st}", flush=True)
+    assert st["status"] in (0, sdg.FLOOR), st
+    assert st["rel_residual"] < max(rtol, 5e-8)
+    assert np.linalg.norm(host(u) - ud) <= ubound * np.linalg.norm(ud), st
+    P.close()
