@@ -219,8 +219,8 @@ def main():
                    "nx": N, "ny": N, "k": K, "eta_contrast": ETA_IN, "rtol": RTOL,
                    "inner_rtol": 1e-3, "velocity_dofs": nu, "pressure_dofs": npr,
                    "batch_per_step": B, "setup_in_step": True, "cycle_precision": args.prec},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "samples": len(lat), "kind": "single-problem setup+solve"},
+        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "samples": len(lat), "kind": "single-problem setup+solve"} if lat else None),
         "batch_ms": ms_per_step,
         "viscous_dof_per_s": B * nu * args.steps / elapsed,
         "sip_apply_dof_per_s": B * nu / (t_app * 1e-6),

@@ -9,7 +9,10 @@
 // The apply is z_e = s_e * Binv[id_e] r_e, where id_e is the element's
 // unique block and s_e = eta_rep / eta_e rescales a shared block to the
 // element (blocks with equal face kinds and neighbour viscosity ratios are
-// equal up to the factor eta_K).
+// equal up to the factor eta_K).  Elements are grouped by id_e, so the apply
+// is a small dense product Binv * [r_e1 ... r_eG] per group: one workgroup
+// stages the block and G residual columns in LDS and each thread holds a
+// 4 x 4 register tile of the result.
 #include "sdg_common.h"
 #include "sdg_kernels.h"
 
@@ -95,67 +98,6 @@ int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, doubl
   return SDG_OK;
 }
 
-// ---------------------------------------------------------------------------
-// apply
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float bf16_to_f32(uint16_t v) {
-  return __uint_as_float(((uint32_t)v) << 16);
-}
-
-template <typename TM, typename TV>
-__global__ __launch_bounds__(256) void bj_apply_kernel(int nb, int64_t nel_total,
-                                                       const int* __restrict__ ids,
-                                                       const double* __restrict__ scale,
-                                                       const TM* __restrict__ binv,
-                                                       const TV* __restrict__ r, TV* __restrict__ z) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nel_total * nb) return;
-  const int64_t e = g / nb;
-  const int a = (int)(g - e * nb);
-  const TM* row = binv + ((int64_t)ids[e] * nb + a) * nb;
-  const TV* re = r + e * nb;
-  if constexpr (sizeof(TM) == 8) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += row[b] * double(re[b]);
-    z[g] = TV(acc * scale[e]);
-  } else if constexpr (sizeof(TM) == 4) {
-    float acc = 0.f;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += row[b] * float(re[b]);
-    z[g] = TV(acc * float(scale[e]));
-  } else {
-    float acc = 0.f;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += bf16_to_f32(row[b]) * float(re[b]);
-    z[g] = TV(acc * float(scale[e]));
-  }
-}
-
-int blockjacobi_apply_f64(int nb, int64_t nel_total, const int* ids, const double* scale,
-                          const double* binv, const double* r, double* z, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_apply_kernel<double, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s,
-                     nb, nel_total, ids, scale, binv, r, z);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
-int blockjacobi_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale,
-                          const float* binv, const float* r, float* z, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_apply_kernel<float, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, nb,
-                     nel_total, ids, scale, binv, r, z);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
-int blockjacobi_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale,
-                           const uint16_t* binv, const float* r, float* z, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_apply_kernel<uint16_t, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s,
-                     nb, nel_total, ids, scale, binv, r, z);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
 
 __global__ void f64_to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,166 +125,315 @@ int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s) 
   return SDG_OK;
 }
 
-}  // namespace sdg
 
-namespace sdg {
-
-// Fused smoother step on the DG level: z_e = s_e Binv[id_e] r_e, then the
-// Chebyshev recurrence with per-problem coefficients ab[pb] = (a, b):
-// mode 0: d = a d + b z, x += d;  1: d = b z, x = d;  2: d = b z, x += d.
+// ---------------------------------------------------------------------------
+// grouped apply
+//
+// Work item w = (uid, start, count): elements perm[start .. start+count) all
+// use block uid.  The kernel is specialised on K1 = k + 1, so the block size
+// NB = 2 K1^2, the padded row length NBP (NB rounded up to 4) and the
+// largest group GMAX are compile-time constants and every staging loop
+// unrolls into independent loads.  LDS holds the matrix as [b][a] rows
+// (FP64 inverse: Binv, symmetric; factored: X^T and X, zero outside the
+// triangle) and the residual columns as R[b][e].  Thread t owns rows
+// a0 .. a0+3 (a0 = 4 (t mod NAG)) of elements e0 .. e0+3 (e0 = 4 (t div NAG)).
+// The operands of the Chebyshev update are fetched before the product, so
+// their latency hides behind it.
+//
+// Update (z = s_e Binv r_e, per-problem coefficients ab[pb] = (a, b)):
+// d' = b z + a d_old, x' = x + d', where d_old is d (BJ_READ_D) or x itself
+// (BJ_FOLD: the step after a start from zero, whose direction equals x);
+// without BJ_READ_X the old x is zero; d' is stored only with BJ_WRITE_D;
+// BJ_APPLY stores z in x instead.
+// ---------------------------------------------------------------------------
 template <typename TM, typename TV>
-__global__ __launch_bounds__(256) void bj_cheb_kernel(int nb, int64_t nel_total, int nel,
-                                                      const int* __restrict__ ids,
-                                                      const double* __restrict__ scale,
-                                                      const TM* __restrict__ binv,
-                                                      const TV* __restrict__ r,
-                                                      const double* __restrict__ ab,
-                                                      TV* __restrict__ d, TV* __restrict__ x, int mode) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nel_total * nb) return;
-  const int64_t e = g / nb;
-  const int a = (int)(g - e * nb);
-  const int64_t pb = e / nel;
-  const TM* row = binv + ((int64_t)ids[e] * nb + a) * nb;
-  const TV* re = r + e * nb;
-  double z;
-  if constexpr (sizeof(TM) == 8) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += row[b] * double(re[b]);
-    z = acc * scale[e];
-  } else if constexpr (sizeof(TM) == 4) {
-    float acc = 0.f;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += row[b] * float(re[b]);
-    z = double(acc * float(scale[e]));
-  } else {
-    float acc = 0.f;
-#pragma unroll 4
-    for (int b = 0; b < nb; ++b) acc += bf16_to_f32(row[b]) * float(re[b]);
-    z = double(acc * float(scale[e]));
-  }
-  const double ca = ab[2 * pb], cb = ab[2 * pb + 1];
-  const double dv = mode == 0 ? ca * double(d[g]) + cb * z : cb * z;
-  d[g] = TV(dv);
-  x[g] = mode == 1 ? TV(dv) : TV(double(x[g]) + dv);
-}
+struct BjArgs {
+  int G, nel;
+  const int* perm;
+  const int* work;
+  const double* scale;
+  const TM* mat;
+  const TV* r;
+  const double* ab;
+  TV* d;
+  TV* x;
+  int flags;
+};
 
-int bj_cheb_f64(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const double* binv,
-                const double* r, const double* ab, double* d, double* x, int mode, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_cheb_kernel<double, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, nb,
-                     nel_total, nel, ids, scale, binv, r, ab, d, x, mode);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
-int bj_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* binv,
-                const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_cheb_kernel<float, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, nb,
-                     nel_total, nel, ids, scale, binv, r, ab, d, x, mode);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
-int bj_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* binv,
-                 const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s) {
-  const int64_t n = nel_total * nb;
-  hipLaunchKernelGGL((bj_cheb_kernel<uint16_t, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, nb,
-                     nel_total, nel, ids, scale, binv, r, ab, d, x, mode);
-  SDG_CHECK_LAUNCH();
-  return SDG_OK;
-}
-
-}  // namespace sdg
-
-namespace sdg {
-
-// ---------------------------------------------------------------------------
-// Low-precision smoother through the inverse Cholesky factor: with
-// A_KK = L L^T and X = L^{-1} stored as a packed lower triangle in FP32 or
-// BF16, z_e = s_e X^T (X r_e).  Rounding X keeps the smoother symmetric
-// positive definite (X^T X with X nonsingular), which rounding the entries of
-// the full inverse does not when the block is ill conditioned, and the
-// triangle is half the bytes.  One workgroup handles EPB = 256 / nb elements.
-// ---------------------------------------------------------------------------
 template <typename TM>
-__device__ __forceinline__ float ldx(const TM* p) {
-  if constexpr (sizeof(TM) == 2) return bf16_to_f32(*p);
+__device__ __forceinline__ float ld_f32(const TM* p) {
+  if constexpr (sizeof(TM) == 2) return __uint_as_float(((uint32_t)*p) << 16);
   else return float(*p);
 }
 
-template <typename TM, typename TV>
-__global__ __launch_bounds__(256) void bj_tri_kernel(int nb, int64_t nel_total, int nel,
-                                                     const int* __restrict__ ids,
-                                                     const double* __restrict__ scale,
-                                                     const TM* __restrict__ X, const TV* __restrict__ r,
-                                                     const double* __restrict__ ab, TV* __restrict__ d,
-                                                     TV* __restrict__ x, TV* __restrict__ z_out, int mode) {
-  __shared__ float sr[256];
-  __shared__ float sy[256];
-  const int epb = 256 / nb;
-  const int t = threadIdx.x;
-  const int le = t / nb, a = t - le * nb;
-  const int64_t e = (int64_t)blockIdx.x * epb + le;
-  const bool live = le < epb && e < nel_total;
-  const int64_t npk = (int64_t)nb * (nb + 1) / 2;
-  const TM* Xe = live ? X + (int64_t)ids[e] * npk : X;
-  if (live) sr[t] = float(r[e * nb + a]);
-  __syncthreads();
-  if (live) {
-    const TM* row = Xe + (int64_t)a * (a + 1) / 2;
-    const float* re = sr + le * nb;
-    float acc = 0.f;
-    for (int b = 0; b <= a; ++b) acc += ldx(row + b) * re[b];
-    sy[t] = acc;
+template <int K1>
+struct BjShape {
+  static constexpr int NB = 2 * K1 * K1;
+  static constexpr int NBP = (NB + 3) & ~3;
+  static constexpr int NAG = NBP / 4;
+  static constexpr int GMAX = 4 * (256 / NAG);
+};
+
+template <typename TC>
+__device__ __forceinline__ void tile_fma(TC (&acc)[4][4], const TC* __restrict__ mrow,
+                                         const TC* __restrict__ rrow) {
+  TC m[4], v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    m[i] = mrow[i];
+    v[i] = rrow[i];
   }
-  __syncthreads();
-  if (!live) return;
-  const float* ye = sy + le * nb;
-  float acc = 0.f;
-  for (int c = a; c < nb; ++c) acc += ldx(Xe + (int64_t)c * (c + 1) / 2 + a) * ye[c];
-  const double zv = double(acc) * scale[e];
-  const int64_t g = e * nb + a;
-  if (z_out) {
-    z_out[g] = TV(zv);
-    return;
-  }
-  const int64_t pb = e / nel;
-  const double ca = ab[2 * pb], cb = ab[2 * pb + 1];
-  const double dv = mode == 0 ? ca * double(d[g]) + cb * zv : cb * zv;
-  d[g] = TV(dv);
-  x[g] = mode == 1 ? TV(dv) : TV(double(x[g]) + dv);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = fma(m[i], v[j], acc[i][j]);
 }
 
-template <typename TM>
-static int launch_tri(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const TM* X,
-                      const float* r, const double* ab, float* d, float* x, float* z, int mode, hipStream_t s) {
-  if (nb > 256) {
-    set_error("element block larger than 256 for the factored smoother");
-    return SDG_ERR_UNSUPPORTED;
+template <typename TV>
+struct Pair {
+  TV v[2];
+};
+template <typename TV>
+__device__ __forceinline__ Pair<TV> ld2(const TV* p) {
+  if constexpr (sizeof(TV) == 8) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    return Pair<TV>{{q.x, q.y}};
+  } else {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    return Pair<TV>{{q.x, q.y}};
   }
-  const int epb = 256 / nb;
-  hipLaunchKernelGGL((bj_tri_kernel<TM, float>), dim3(ceil_div(nel_total, epb)), dim3(256), 0, s, nb, nel_total,
-                     nel, ids, scale, X, r, ab, d, x, z, mode);
+}
+template <typename TV>
+__device__ __forceinline__ void st2(TV* p, TV a, TV b) {
+  if constexpr (sizeof(TV) == 8) *reinterpret_cast<double2*>(p) = make_double2(a, b);
+  else *reinterpret_cast<float2*>(p) = make_float2(a, b);
+}
+
+template <int K1, typename TM, typename TV, bool TRI>
+__global__ __launch_bounds__(256) void bj_group_kernel(BjArgs<TM, TV> A) {
+  using TC = TV;  // FP64 vectors accumulate in FP64, FP32 vectors in FP32
+  using S = BjShape<K1>;
+  constexpr int NB = S::NB, NBP = S::NBP, NAG = S::NAG, GMAX = S::GMAX;
+  __shared__ __align__(16) TC M0[NB * NBP];
+  __shared__ __align__(16) TC M1[TRI ? NB * NBP : 4];
+  __shared__ __align__(16) TC R[NB * GMAX];
+  __shared__ __align__(16) TC Y[TRI ? NB * GMAX : 4];
+  __shared__ int sperm[GMAX];
+  const int G = A.G;
+  const int t = threadIdx.x;
+  const int uid = A.work[3 * blockIdx.x], start = A.work[3 * blockIdx.x + 1],
+            cnt = A.work[3 * blockIdx.x + 2];
+  for (int q = t; q < cnt; q += 256) sperm[q] = A.perm[start + q];
+
+  if constexpr (!TRI) {
+    const TM* B = A.mat + (int64_t)uid * NB * NB;
+#pragma unroll
+    for (int i0 = 0; i0 < NB * NBP; i0 += 256) {
+      const int i = i0 + t;
+      if (i < NB * NBP) {
+        const int b = i / NBP, a = i - b * NBP;
+        M0[i] = a < NB ? TC(B[b * NB + a]) : TC(0);
+      }
+    }
+  } else {
+    // packed lower triangle: X[a][b] (b <= a) at a(a+1)/2 + b
+    const TM* X = A.mat + (int64_t)uid * NB * (NB + 1) / 2;
+#pragma unroll
+    for (int i0 = 0; i0 < NB * NBP; i0 += 256) {
+      const int i = i0 + t;
+      if (i < NB * NBP) {
+        const int b = i / NBP, a = i - b * NBP;
+        M0[i] = (a < NB && b <= a) ? TC(ld_f32(X + a * (a + 1) / 2 + b)) : TC(0);  // X^T[b][a]
+        M1[i] = (a <= b) ? TC(ld_f32(X + b * (b + 1) / 2 + a)) : TC(0);            // X[b][a]
+      }
+    }
+  }
+  __syncthreads();  // sperm
+  {
+    constexpr int NLD = (NB * GMAX + 255) / 256;
+    TV v[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int i = q * 256 + t;
+      const int e = i / NB, b = i - e * NB;
+      v[q] = e < cnt ? A.r[(int64_t)sperm[e] * NB + b] : TV(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int i = q * 256 + t;
+      const int e = i / NB, b = i - e * NB;
+      if (e < G) R[b * G + e] = TC(v[q]);
+    }
+  }
+
+  const int ag = t % NAG, eg = t / NAG;
+  const int a0 = 4 * ag, e0 = 4 * eg;
+  const bool act = e0 < cnt;  // e0 < cnt <= G
+  const bool hi = a0 + 2 < NB;  // rows a0+2, a0+3 exist (NB is even)
+  const int flags = A.flags;
+  // operands of the update, fetched ahead of the product
+  int64_t ge[4];
+  TV xo[4][4], dold[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ge[j] = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xo[j][i] = dold[j][i] = TV(0);
+  }
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (e0 + j >= cnt) break;
+      ge[j] = sperm[e0 + j];
+      const TV* xx = A.x + ge[j] * NB + a0;
+      const TV* dd = A.d + ge[j] * NB + a0;
+      if (flags & BJ_READ_X) {
+        Pair<TV> p = ld2(xx);
+        xo[j][0] = p.v[0];
+        xo[j][1] = p.v[1];
+        if (hi) {
+          p = ld2(xx + 2);
+          xo[j][2] = p.v[0];
+          xo[j][3] = p.v[1];
+        }
+      }
+      if (flags & BJ_READ_D) {
+        Pair<TV> p = ld2(dd);
+        dold[j][0] = p.v[0];
+        dold[j][1] = p.v[1];
+        if (hi) {
+          p = ld2(dd + 2);
+          dold[j][2] = p.v[0];
+          dold[j][3] = p.v[1];
+        }
+      }
+    }
+  }
+  __syncthreads();  // R, M0, M1
+
+  TC acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
+  if constexpr (!TRI) {
+    if (act)
+#pragma unroll 2
+      for (int b = 0; b < NB; ++b) tile_fma(acc, M0 + b * NBP + a0, R + b * G + e0);
+  } else {
+    // y = X r (rows a0..a0+3 need b <= a0+3), then z = X^T y (c >= a0)
+    if (act) {
+      const int bend = min(a0 + 4, NB);
+      for (int b = 0; b < bend; ++b) tile_fma(acc, M0 + b * NBP + a0, R + b * G + e0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (a0 + i < NB)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Y[(a0 + i) * G + e0 + j] = acc[i][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
+    if (act)
+      for (int c = a0; c < NB; ++c) tile_fma(acc, M1 + c * NBP + a0, Y + c * G + e0);
+  }
+  if (!act) return;
+
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (ge[j] < 0) break;
+    const double sc = A.scale[ge[j]];
+    TV* xx = A.x + ge[j] * NB + a0;
+    TV* dd = A.d + ge[j] * NB + a0;
+    TV xn[4], dn[4];
+    if (flags & BJ_APPLY) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xn[i] = TV(double(acc[i][j]) * sc);
+    } else {
+      const int64_t pb = ge[j] / A.nel;
+      const double ca = A.ab[2 * pb], cb = A.ab[2 * pb + 1];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double z = double(acc[i][j]) * sc;
+        double dv = cb * z;
+        if (flags & BJ_READ_D) dv += ca * double(dold[j][i]);
+        if (flags & BJ_FOLD) dv += ca * double(xo[j][i]);
+        dn[i] = TV(dv);
+        xn[i] = TV((flags & BJ_READ_X) ? double(xo[j][i]) + dv : dv);
+      }
+      if (flags & BJ_WRITE_D) {
+        st2(dd, dn[0], dn[1]);
+        if (hi) st2(dd + 2, dn[2], dn[3]);
+      }
+    }
+    st2(xx, xn[0], xn[1]);
+    if (hi) st2(xx + 2, xn[2], xn[3]);
+  }
+}
+
+int bj_group_size(int nb) {
+  const int nag = ((nb + 3) & ~3) / 4;
+  return 4 * (256 / nag);
+}
+
+template <int K1, typename TM, typename TV, bool TRI>
+static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
+                     hipStream_t s) {
+  BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
+  hipLaunchKernelGGL((bj_group_kernel<K1, TM, TV, TRI>), dim3(P.nwork), dim3(256), 0, s, A);
+}
+
+template <typename TM, typename TV, bool TRI>
+static int launch_group(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
+                        hipStream_t s) {
+  if (P.nwork <= 0) return SDG_OK;
+  if (P.G < 4 || P.G % 4 || P.G > bj_group_size(P.nb)) {
+    set_error("block smoother: group size does not fit one workgroup");
+    return SDG_ERR_INVALID;
+  }
+  // the update moves pairs of values: x and d must be aligned to two values
+  const uintptr_t al = 2 * sizeof(TV);
+  if (reinterpret_cast<uintptr_t>(x) % al || reinterpret_cast<uintptr_t>(d) % al) {
+    set_error("block smoother: vectors must be aligned to two values");
+    return SDG_ERR_INVALID;
+  }
+  switch (P.nb) {
+    case 8: launch_k<2, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    case 18: launch_k<3, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    case 32: launch_k<4, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    case 50: launch_k<5, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    case 72: launch_k<6, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    case 98: launch_k<7, TM, TV, TRI>(P, mat, r, ab, d, x, flags, s); break;
+    default:
+      set_error("block smoother: unsupported element block size");
+      return SDG_ERR_UNSUPPORTED;
+  }
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
 
-int bj_tri_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* X,
-                    const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s) {
-  return launch_tri<float>(nb, nel_total, nel, ids, scale, X, r, ab, d, x, nullptr, mode, s);
+int bj_cheb_f64(const BjPlan& P, const double* binv, const double* r, const double* ab, double* d, double* x,
+                int flags, hipStream_t s) {
+  return launch_group<double, double, false>(P, binv, r, ab, d, x, flags, s);
 }
-int bj_tri_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* X,
-                     const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s) {
-  return launch_tri<uint16_t>(nb, nel_total, nel, ids, scale, X, r, ab, d, x, nullptr, mode, s);
+int bj_apply_f64(const BjPlan& P, const double* binv, const double* r, double* z, hipStream_t s) {
+  return launch_group<double, double, false>(P, binv, r, nullptr, nullptr, z, BJ_APPLY, s);
 }
-int bj_tri_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale, const float* X,
-                     const float* r, float* z, hipStream_t s) {
-  return launch_tri<float>(nb, nel_total, 1, ids, scale, X, r, nullptr, nullptr, nullptr, z, 0, s);
+int bj_tri_cheb_f32(const BjPlan& P, const float* X, const float* r, const double* ab, float* d, float* x,
+                    int flags, hipStream_t s) {
+  return launch_group<float, float, true>(P, X, r, ab, d, x, flags, s);
 }
-int bj_tri_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale, const uint16_t* X,
-                      const float* r, float* z, hipStream_t s) {
-  return launch_tri<uint16_t>(nb, nel_total, 1, ids, scale, X, r, nullptr, nullptr, nullptr, z, 0, s);
+int bj_tri_cheb_bf16(const BjPlan& P, const uint16_t* X, const float* r, const double* ab, float* d, float* x,
+                     int flags, hipStream_t s) {
+  return launch_group<uint16_t, float, true>(P, X, r, ab, d, x, flags, s);
+}
+int bj_tri_apply_f32(const BjPlan& P, const float* X, const float* r, float* z, hipStream_t s) {
+  return launch_group<float, float, true>(P, X, r, nullptr, nullptr, z, BJ_APPLY, s);
+}
+int bj_tri_apply_bf16(const BjPlan& P, const uint16_t* X, const float* r, float* z, hipStream_t s) {
+  return launch_group<uint16_t, float, true>(P, X, r, nullptr, nullptr, z, BJ_APPLY, s);
 }
 
 }  // namespace sdg

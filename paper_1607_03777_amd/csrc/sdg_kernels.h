@@ -33,25 +33,33 @@ int rhs_assemble(const MeshDev& M, int k, int nbatch, const double* eta, const d
 // (Cholesky, triangular inverse, L^-T L^-1).  status[i] = 0 ok, 1 not SPD.
 // packed (optional): also store X = L^{-1} as packed lower triangles
 int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, double* packed = nullptr);
+// Grouped block-Jacobi apply.  Elements perm[start .. start+count) of work
+// item w = work[3w .. 3w+2] = (uid, start, count) share block uid; G columns
+// per workgroup at most (bj_group_size).  scale[ge] = eta_rep / eta_ge;
+// ab[pb] = Chebyshev coefficients of problem pb = ge / nel.
+struct BjPlan {
+  int nb, G, nwork, nel;
+  const int* perm;
+  const int* work;
+  const double* scale;
+};
+// largest G for an element block of nb unknowns
+int bj_group_size(int nb);
+// update flags: d' = b z + a d_old, x' = x + d' (see block_kernels.hip)
+enum BjFlags { BJ_READ_X = 1, BJ_READ_D = 2, BJ_FOLD = 4, BJ_WRITE_D = 8, BJ_APPLY = 16 };
+int bj_cheb_f64(const BjPlan& P, const double* binv, const double* r, const double* ab, double* d, double* x,
+                int flags, hipStream_t s);
+int bj_apply_f64(const BjPlan& P, const double* binv, const double* r, double* z, hipStream_t s);
 // factored low-precision smoother: z = s_e X^T (X r), X packed lower triangular
-int bj_tri_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* X,
-                    const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
-int bj_tri_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* X,
-                     const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
-int bj_tri_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale, const float* X,
-                     const float* r, float* z, hipStream_t s);
-int bj_tri_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale, const uint16_t* X,
-                      const float* r, float* z, hipStream_t s);
-// z = scale_e * Binv[id_e] r_e, FP64 inverses.
-int blockjacobi_apply_f64(int nb, int64_t nel_total, const int* ids, const double* scale,
-                          const double* binv, const double* r, double* z, hipStream_t s);
-int blockjacobi_apply_f32(int nb, int64_t nel_total, const int* ids, const double* scale,
-                          const float* binv, const float* r, float* z, hipStream_t s);
+int bj_tri_cheb_f32(const BjPlan& P, const float* X, const float* r, const double* ab, float* d, float* x,
+                    int flags, hipStream_t s);
+int bj_tri_cheb_bf16(const BjPlan& P, const uint16_t* X, const float* r, const double* ab, float* d, float* x,
+                     int flags, hipStream_t s);
+int bj_tri_apply_f32(const BjPlan& P, const float* X, const float* r, float* z, hipStream_t s);
+int bj_tri_apply_bf16(const BjPlan& P, const uint16_t* X, const float* r, float* z, hipStream_t s);
 // Convert FP64 inverses to FP32 / BF16 storage.
 int convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s);
-int blockjacobi_apply_bf16(int nb, int64_t nel_total, const int* ids, const double* scale,
-                           const uint16_t* binv, const float* r, float* z, hipStream_t s);
 
 // Transfers and coarse levels (coarse_kernels.hip)
 int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s);
@@ -122,13 +130,6 @@ int bpressure_project(int64_t nel, int np, int nbatch, int64_t stride, double* p
 int bhessenberg_max_eig(int nbatch, const double* H, const int* ms, int ld, int64_t hstride, double* out,
                         hipStream_t s);
 
-// fused smoother kernels
-int bj_cheb_f64(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const double* binv,
-                const double* r, const double* ab, double* d, double* x, int mode, hipStream_t s);
-int bj_cheb_f32(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const float* binv,
-                const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
-int bj_cheb_bf16(int nb, int64_t nel_total, int nel, const int* ids, const double* scale, const uint16_t* binv,
-                 const float* r, const double* ab, float* d, float* x, int mode, hipStream_t s);
 int hcheb_step(int nx, int ny, int nbatch, const double* st, const double* dinv, const double* rhs,
                const double* xi, double* xo, double* d, const double* ab, int mode, hipStream_t s);
 

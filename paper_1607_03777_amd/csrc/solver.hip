@@ -91,7 +91,7 @@ struct sdg_problem {
   std::vector<double> eta_host;
   // block Jacobi
   int nuniq = 0;
-  int* ids = nullptr;
+  BjPlan bj{};  // elements grouped by unique block
   double* scale = nullptr;
   double* binv = nullptr;
   float* binv32 = nullptr;
@@ -251,10 +251,29 @@ int setup_blocks(sdg_problem* P) {
     scale[ge] = P->eta_host[P->reps[id]] / ee;
   }
   P->nuniq = (int)P->reps.size();
-  SDG_TRY(palloc_t(P, &P->ids, ntot));
+  // group the elements by block (counting sort, element order kept inside
+  // a group) and cut each group into work items of at most G elements
+  // at least ~512 work items where the batch allows it (one per CU pair)
+  const int G = std::max(16, std::min(bj_group_size(P->NB), 4 * (int)((ntot + 2047) / 2048)));
+  std::vector<int> first(P->nuniq + 1, 0);
+  for (int64_t ge = 0; ge < ntot; ++ge) ++first[ids[ge] + 1];
+  for (int u = 0; u < P->nuniq; ++u) first[u + 1] += first[u];
+  std::vector<int> perm(ntot), fill(first.begin(), first.end() - 1), work;
+  for (int64_t ge = 0; ge < ntot; ++ge) perm[fill[ids[ge]]++] = (int)ge;
+  for (int u = 0; u < P->nuniq; ++u)
+    for (int st = first[u]; st < first[u + 1]; st += G) {
+      work.push_back(u);
+      work.push_back(st);
+      work.push_back(std::min(G, first[u + 1] - st));
+    }
+  int *dperm = nullptr, *dwork = nullptr;
+  SDG_TRY(palloc_t(P, &dperm, ntot));
+  SDG_TRY(palloc_t(P, &dwork, (int64_t)work.size()));
   SDG_TRY(palloc_t(P, &P->scale, ntot));
-  SDG_TRY(to_dev(P, P->ids, ids.data(), ntot * sizeof(int)));
+  SDG_TRY(to_dev(P, dperm, perm.data(), ntot * sizeof(int)));
+  SDG_TRY(to_dev(P, dwork, work.data(), work.size() * sizeof(int)));
   SDG_TRY(to_dev(P, P->scale, scale.data(), ntot * sizeof(double)));
+  P->bj = BjPlan{P->NB, G, (int)(work.size() / 3), P->nel, dperm, dwork, P->scale};
   int* dreps = nullptr;
   int* dstat = nullptr;
   SDG_TRY(palloc_t(P, &dreps, P->nuniq));
@@ -397,21 +416,28 @@ int upload_cheb(sdg_problem* P) {
 // ---------------------------------------------------------------------------
 const double* ab0_step(sdg_problem* P, int s) { return P->ab0 + (int64_t)s * P->nb * 2; }
 
-int bj_step64(sdg_problem* P, const double* r, int s, double* x, int mode) {
-  return bj_cheb_f64(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv, r, ab0_step(P, s),
-                     P->vd, x, mode, P->s);
+// Update flags of Chebyshev step s of m on the DG level.  From a zero start
+// the first direction equals the first iterate, so step 1 takes it from x
+// (BJ_FOLD) and step 0 stores no direction; the last step stores none.
+int bj_flags(int s, int m, bool zero) {
+  int f = 0;
+  if (s > 0 || !zero) f |= BJ_READ_X;
+  if (s == 1 && zero) f |= BJ_FOLD;
+  else if (s > 0) f |= BJ_READ_D;
+  if (s < m - 1 && !(s == 0 && zero)) f |= BJ_WRITE_D;
+  return f;
 }
-int bj_step32(sdg_problem* P, const float* r, int s, float* x, int mode) {
-  if (P->binv16)
-    return bj_tri_cheb_bf16(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv16, r,
-                            ab0_step(P, s), P->fd, x, mode, P->s);
-  return bj_tri_cheb_f32(P->NB, (int64_t)P->nel * P->nb, P->nel, P->ids, P->scale, P->binv32, r,
-                         ab0_step(P, s), P->fd, x, mode, P->s);
+int bj_step64(sdg_problem* P, const double* r, int s, double* x, bool zero) {
+  return bj_cheb_f64(P->bj, P->binv, r, ab0_step(P, s), P->vd, x, bj_flags(s, P->opt.smooth_dg, zero), P->s);
+}
+int bj_step32(sdg_problem* P, const float* r, int s, float* x, bool zero) {
+  const int f = bj_flags(s, P->opt.smooth_dg, zero);
+  if (P->binv16) return bj_tri_cheb_bf16(P->bj, P->binv16, r, ab0_step(P, s), P->fd, x, f, P->s);
+  return bj_tri_cheb_f32(P->bj, P->binv32, r, ab0_step(P, s), P->fd, x, f, P->s);
 }
 int bj_apply32(sdg_problem* P, const float* r, float* z) {
-  const int64_t ne = (int64_t)P->nel * P->nb;
-  if (P->binv16) return bj_tri_apply_bf16(P->NB, ne, P->ids, P->scale, P->binv16, r, z, P->s);
-  return bj_tri_apply_f32(P->NB, ne, P->ids, P->scale, P->binv32, r, z, P->s);
+  if (P->binv16) return bj_tri_apply_bf16(P->bj, P->binv16, r, z, P->s);
+  return bj_tri_apply_f32(P->bj, P->binv32, r, z, P->s);
 }
 
 int cheb_dg64(sdg_problem* P, const double* b, double* x, bool zero) {
@@ -421,7 +447,7 @@ int cheb_dg64(sdg_problem* P, const double* b, double* x, bool zero) {
       SDG_TRY(sip_residual(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s));
       r = P->vr;
     }
-    SDG_TRY(bj_step64(P, r, s, x, s == 0 ? (zero ? 1 : 2) : 0));
+    SDG_TRY(bj_step64(P, r, s, x, zero));
   }
   return SDG_OK;
 }
@@ -432,7 +458,7 @@ int cheb_dg32(sdg_problem* P, const float* b, float* x, bool zero) {
       SDG_TRY(sip_residual_f32(P->M, P->k, P->nb, P->eta, b, x, P->fr, P->s));
       r = P->fr;
     }
-    SDG_TRY(bj_step32(P, r, s, x, s == 0 ? (zero ? 1 : 2) : 0));
+    SDG_TRY(bj_step32(P, r, s, x, zero));
   }
   return SDG_OK;
 }
@@ -609,9 +635,7 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
         if ((rc = f2d(S.total, P->fd, w, P->s)) < 0) break;
       } else if (li < 0) {
         if ((rc = sip_apply(P->M, P->k, nb, P->eta, vj, P->vr, P->s)) < 0) break;
-        if ((rc = blockjacobi_apply_f64(P->NB, (int64_t)P->nel * nb, P->ids, P->scale, P->binv, P->vr, w,
-                                        P->s)) < 0)
-          break;
+        if ((rc = bj_apply_f64(P->bj, P->binv, P->vr, w, P->s)) < 0) break;
       } else {
         CLevel& L = P->lev[li];
         if ((rc = stencil_apply(L.nx, L.ny, nb, L.st, vj, L.r, P->s)) < 0) break;
@@ -1048,9 +1072,10 @@ size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, i
   const int64_t NB = 2 * (int64_t)(mesh->k + 1) * (mesh->k + 1);
   const int64_t nu = nel * NB, np = nel * mesh->k * mesh->k;
   size_t b = 0;
-  b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, ids, etap
+  b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, element permutation, etap
   const int64_t nuniq = opts->dedup ? std::min<int64_t>(nel * nb, 4096) : nel * nb;
   b += nuniq * NB * NB * 8 + nuniq * 8;
+  b += 12 * (nel * nb / bj_group_size((int)NB) + nuniq + 1);  // smoother work list
   const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
   if (low) b += nuniq * NB * (NB + 1) / 2 * (8 + (opts->prec_smoother == SDG_BF16 ? 2 : 4));
   b += nb * nel * 64 * 8;  // coarse local matrices
@@ -1340,9 +1365,7 @@ int sdg_apply_grad(sdg_problem* P, const double* p, double* v) {
 }
 int sdg_apply_blockjacobi(sdg_problem* P, const double* r, double* z) {
   PCHECK(r, z);
-  const int64_t ntot = (int64_t)P->nel * P->nb;
-  if (P->opt.prec_smoother == SDG_FP64)
-    return blockjacobi_apply_f64(P->NB, ntot, P->ids, P->scale, P->binv, r, z, P->s);
+  if (P->opt.prec_smoother == SDG_FP64) return bj_apply_f64(P->bj, P->binv, r, z, P->s);
   if (!P->fr) {
     set_error("low-precision smoother storage missing");
     return SDG_ERR_INVALID;

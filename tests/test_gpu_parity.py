@@ -151,6 +151,49 @@ def test_blocks_and_blockjacobi(sdg, ctx, torch, k, dedup):
     P.close()
 
 
+@pytest.mark.parametrize("k", [2, 4, 6])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_blockjacobi_grouped(sdg, ctx, torch, k, prec):
+    """Grouped apply: one block shared by more elements than a workgroup
+    takes (several work items and a ragged last one), shared across the
+    problems of a batch.  FP64: the inverse applied to rounding accuracy.
+    FP32/BF16: z = s X~^T (X~ r~) with X = L^{-1} and r rounded to the
+    storage type; checked against the FP64 inverse within the bound that
+    rounding X and r by a unit u implies, |X~^T X~ - X^T X| <= (2u + u^2)
+    |X|^T |X|, plus FP32 accumulation."""
+    n, nbatch = 12, 2
+    m = Mesh(n, n, k)
+    eta1 = np.ones(m.nel)
+    eta1[::7] = 30.0  # a few elements with other blocks
+    etas = np.stack([eta1, 2.5 * eta1])
+    prec_s = {"fp64": sdg.FP64, "fp32": sdg.FP32, "bf16": sdg.BF16}[prec]
+    P = make_problem(sdg, ctx, n, n, k, etas, prec_smoother=prec_s,
+                     prec_apply=sdg.FP64 if prec == "fp64" else sdg.FP32)
+    rng = np.random.default_rng(11)
+    r = rng.normal(size=(nbatch, m.nu))
+    z = P.zeros(nbatch * m.nu)
+    sdg.sdg_apply_blockjacobi(P.h, dev(r.ravel()), z)
+    torch.cuda.synchronize()
+    Z = host(z).reshape(nbatch, m.nel, m.nbu)
+    for pb in range(nbatch):
+        BJ = BlockJacobi(asm.assemble_A(m, etas[pb]), m.nbu)
+        R = r[pb].reshape(m.nel, m.nbu)
+        ZR = np.einsum("eab,eb->ea", BJ.inv, R)
+        if prec == "fp64":
+            err = np.linalg.norm(Z[pb] - ZR, axis=1) / np.linalg.norm(ZR, axis=1)
+            assert err.max() <= 1e-10, err.max()
+            continue
+        u = 2.0 ** -24 if prec == "fp32" else 2.0 ** -8
+        X = np.linalg.inv(np.linalg.cholesky(BJ.blocks))
+        XA = np.abs(X)
+        bound = np.einsum("eca,ecb,eb->ea", XA, XA, np.abs(R))
+        bound *= (2 * u + u * u) + 2 * 2.0 ** -24 + 2 * m.nbu * 2.0 ** -24
+        err = np.abs(Z[pb] - ZR)
+        worst = np.max(err / bound)
+        assert worst <= 1.0, worst
+    P.close()
+
+
 @pytest.mark.parametrize("k", [1, 2, 4])
 def test_p_transfer_parity(sdg, ctx, torch, k):
     nx, ny = 9, 6
