@@ -97,6 +97,8 @@ def main():
                     help="arithmetic of the fine-level cycle (operator apply and block smoother); "
                          "the Krylov solvers, true residuals and the coarse Q1 hierarchy stay FP64")
     ap.add_argument("--latency-solves", type=int, default=5)
+    ap.add_argument("--no-trace", action="store_true",
+                    help="skip the traced step after the timed region (per-kernel breakdown)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver library runs each problem on a single "
@@ -159,6 +161,21 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
+    # one more step, outside the timed region, with every hot kernel
+    # bracketed by HIP events: per-kernel time and algorithmic bytes
+    traced = {}
+    if not args.no_trace:
+        sdg.sdg_trace_enable(ctx, 1)
+        step()
+        torch.cuda.synchronize()
+        sdg.sdg_trace_enable(ctx, 0)
+        for cls, name in sdg.TRACE_NAMES.items():
+            n, ms, by = sdg.sdg_trace_read(ctx, cls)
+            traced[name] = {"launches": n, "total_ms": ms, "us_per_launch": 1e3 * ms / max(n, 1),
+                            "bytes_per_launch": by / max(n, 1),
+                            "GB_per_s": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
+            log(f"[bench] traced {name}: {n} launches, {ms:.1f} ms total, "
+                f"{1e3 * ms / max(n, 1):.2f} us/launch")
     st = stats[-1][0]
     # converged to rtol, or to the FP64 rounding floor of the true residual
     # (eps |K||x| / |b|, a few 1e-8 at this size), which rtol 1e-8 is below
@@ -187,20 +204,37 @@ def main():
     oracle_res = float(np.linalg.norm(r) / np.linalg.norm(np.concatenate([F, G])))
     log(f"[bench] oracle true residual of the GPU solution: {oracle_res:.3e}")
 
-    # dominant kernel: the fused SIP residual r = b - A u (FP64, k = 4), as
-    # launched by the Chebyshev smoother; timed on the problem's stream
+    # roofline of the dominant kernel: the traced class with the largest
+    # time in the traced step, launched back to back at the step's shape
+    # (batch B) between two HIP events on the problem's stream
+    kernel_names = {"sip_apply": f"sip_tile_kernel<{K + 1},apply>",
+                    "sip_residual": f"sip_tile_kernel<{K + 1},residual>",
+                    "block_jacobi_smoother": f"bj_group_kernel<{K + 1}>"}
+    cand = {k: v for k, v in traced.items() if v["bytes_per_launch"] > 0}
+    dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else "sip_residual"
     h = sdg.sdg_problem_create_batch(ctx, mesh, opts, B, eta, stream)
     uu = torch.randn(B * nu, dtype=torch.float64, device="cuda")
     bb = torch.randn(B * nu, dtype=torch.float64, device="cuda")
-    rr = torch.empty(B * nu, dtype=torch.float64, device="cuda")
     yy = torch.empty(B * nu, dtype=torch.float64, device="cuda")
-    t_res = kernel_time_us(torch, lambda: sdg.sdg_residual_viscous(h, bb, uu, rr), args.kernel_reps)
-    t_app = kernel_time_us(torch, lambda: sdg.sdg_apply_viscous(h, uu, yy), args.kernel_reps)
+    t_app = kernel_time_us(torch, lambda: sdg.sdg_apply_viscous(h, uu, yy), max(args.kernel_reps, 20))
+    if dom == "sip_residual":
+        fn, nbytes = (lambda: sdg.sdg_residual_viscous(h, bb, uu, yy)), B * nel * (3 * nb * 8 + 8)
+        what = "r = b - A u: read b, u, eta; write r"
+    elif dom == "sip_apply":
+        fn, nbytes = (lambda: sdg.sdg_apply_viscous(h, uu, yy)), B * nel * (2 * nb * 8 + 8)
+        what = "y = A u: read u, eta; write y"
+    else:
+        fn, nbytes = (lambda: sdg.sdg_apply_blockjacobi(h, uu, yy)), B * nel * (2 * nb * 8 + 12)
+        what = "z = M^-1 r: read r, scale, permutation; write z (blocks cache-resident)"
+    t_dom = kernel_time_us(torch, fn, max(args.kernel_reps, 20))
     sdg.sdg_problem_destroy(h)
-    bytes_res = B * nel * (3 * nb * 8 + 8)  # read b, u, eta; write r
-    bytes_app = B * nel * (2 * nb * 8 + 8)
-    gbs = bytes_res / (t_res * 1e-6) / 1e9
-    log(f"[bench] sip residual {t_res:.2f} us ({gbs:.0f} GB/s), apply {t_app:.2f} us")
+    gbs = nbytes / (t_dom * 1e-6) / 1e9
+    log(f"[bench] dominant kernel {kernel_names[dom]}: {t_dom:.2f} us/launch, {gbs:.0f} GB/s; "
+        f"sip apply {t_app:.2f} us")
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_names[dom],
+            "algorithmic_bytes": what, "bytes_per_launch": nbytes, "us_per_launch": t_dom,
+            "launches_timed": max(args.kernel_reps, 20)}
 
     out = {
         "metric": "SIP viscous DoF/s + Stokes solves/s at 1e-8 resid; p50/p99 solve latency",
@@ -230,10 +264,8 @@ def main():
                    "oracle_rel_residual": oracle_res, "status": st["status"],
                    "stopped_at_fp64_floor": n_floor, "setup_ms": st["setup_ms"],
                    "solve_ms": st["solve_ms"]},
-        "roofline": {"bound": "hbm", "kernel": "sip_tile_kernel<K1=5,residual,f64>",
-                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_res, "us_per_launch": t_res},
+        "roofline": roof,
+        "kernels_traced_step": traced,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")

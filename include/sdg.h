@@ -235,6 +235,24 @@ int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts
  * state `seed` (Steele, Lea & Flood 2014). */
 int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, void* stream);
 
+/* ---- kernel tracing ---------------------------------------------------------
+ * While tracing is on, every launch of the traced kernel classes made by
+ * problems of this context is bracketed by two HIP events on the problem's
+ * stream, and its algorithmic HBM bytes are recorded (vectors read and
+ * written once, the viscosity, the smoother's scale and permutation; blocks
+ * and stencils that stay cache-resident are not counted).
+ * sdg_trace_enable(ctx, 1) clears the counters and starts; (ctx, 0) stops.
+ * sdg_trace_read waits for the recorded events and returns, for one class,
+ * the number of launches, their summed duration (ms) and summed bytes; any
+ * pointer may be NULL.  Tracing adds two event records per traced launch. */
+#define SDG_TRACE_SIP_APPLY 0    /* y = A u (FP64 or FP32) */
+#define SDG_TRACE_SIP_RESIDUAL 1 /* r = b - A u (FP64 or FP32) */
+#define SDG_TRACE_SMOOTHER 2     /* block-Jacobi apply / Chebyshev step */
+#define SDG_TRACE_COARSE_TAIL 3  /* small h-levels and coarsest solve (bytes not counted) */
+#define SDG_TRACE_CLASSES 4
+int sdg_trace_enable(sdg_ctx* ctx, int on);
+int sdg_trace_read(sdg_ctx* ctx, int kclass, int64_t* launches, double* total_ms, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

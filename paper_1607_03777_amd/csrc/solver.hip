@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -41,6 +42,26 @@ struct sdg_ctx {
   size_t used = 0;
   int live = 0;
   bool closing = false;
+  // kernel tracing
+  struct TraceRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool trace = false;
+  std::mutex trace_mu;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TraceRec> pending;
+  int64_t tr_n[SDG_TRACE_CLASSES] = {};
+  double tr_ms[SDG_TRACE_CLASSES] = {};
+  double tr_bytes[SDG_TRACE_CLASSES] = {};
+  ~sdg_ctx() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace sdg {
@@ -53,8 +74,38 @@ using namespace sdg;
 
 namespace {
 
-constexpr int TAIL_NODES = 33 * 33;  // h-levels with at most this many nodes run in the tail kernel
+constexpr int TAIL_NODES = 17 * 17;  // h-levels with at most this many nodes run in the tail kernel
 constexpr int RED_SCRATCH = 512 * 64;
+
+hipEvent_t trace_event(sdg_ctx* c) {
+  hipEvent_t e = nullptr;
+  {
+    std::lock_guard<std::mutex> g(c->trace_mu);
+    if (!c->ev_pool.empty()) {
+      e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+    }
+  }
+  if (!e && hipEventCreate(&e) != hipSuccess) e = nullptr;
+  return e;
+}
+
+// Runs launch() and, while tracing is on, brackets it with events.
+template <typename F>
+int traced(sdg_ctx* c, hipStream_t s, int cls, double bytes, F&& launch) {
+  if (!c->trace) return launch();
+  hipEvent_t a = trace_event(c), b = trace_event(c);
+  if (!a || !b) {
+    set_error("hipEventCreate failed while tracing");
+    return SDG_ERR_DEVICE;
+  }
+  SDG_HIP(hipEventRecord(a, s));
+  const int rc = launch();
+  SDG_HIP(hipEventRecord(b, s));
+  std::lock_guard<std::mutex> g(c->trace_mu);
+  c->pending.push_back(sdg_ctx::TraceRec{cls, a, b, bytes});
+  return rc;
+}
 
 struct CLevel {
   int nx = 0, ny = 0, nn = 0;
@@ -366,6 +417,30 @@ int setup_coarse(sdg_problem* P) {
   return SDG_OK;
 }
 
+// traced launches of the hot kernels (algorithmic bytes: vectors once each)
+double vec_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * P->NB * w; }
+double elem_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * w; }
+int run_sip_apply(sdg_problem* P, const double* u, double* y) {
+  return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8),
+                [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s); });
+}
+int run_sip_residual(sdg_problem* P, const double* b, const double* u, double* r) {
+  return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 8) + elem_bytes(P, 8),
+                [&] { return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s); });
+}
+int run_sip_apply_f32(sdg_problem* P, const float* u, float* y) {
+  return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 4) + elem_bytes(P, 8),
+                [&] { return sip_apply_f32(P->M, P->k, P->nb, P->eta, u, y, P->s); });
+}
+int run_sip_residual_f32(sdg_problem* P, const float* b, const float* u, float* r) {
+  return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 4) + elem_bytes(P, 8),
+                [&] { return sip_residual_f32(P->M, P->k, P->nb, P->eta, b, u, r, P->s); });
+}
+double smoother_bytes(const sdg_problem* P, int flags, int w) {
+  const int nvec = 2 + !!(flags & BJ_READ_X) + !!(flags & BJ_READ_D) + !!(flags & BJ_WRITE_D);
+  return nvec * vec_bytes(P, w) + elem_bytes(P, 12);  // + scale and permutation
+}
+
 // Chebyshev coefficients: step 0 -> (0, 1/theta); step s >= 1 ->
 // (rho_s rho_{s-1}, 2 rho_s / delta) with rho_0 = 1/sigma,
 // rho_s = 1/(2 sigma - rho_{s-1})
@@ -428,23 +503,33 @@ int bj_flags(int s, int m, bool zero) {
   return f;
 }
 int bj_step64(sdg_problem* P, const double* r, int s, double* x, bool zero) {
-  return bj_cheb_f64(P->bj, P->binv, r, ab0_step(P, s), P->vd, x, bj_flags(s, P->opt.smooth_dg, zero), P->s);
+  const int f = bj_flags(s, P->opt.smooth_dg, zero);
+  return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, f, 8),
+                [&] { return bj_cheb_f64(P->bj, P->binv, r, ab0_step(P, s), P->vd, x, f, P->s); });
 }
 int bj_step32(sdg_problem* P, const float* r, int s, float* x, bool zero) {
   const int f = bj_flags(s, P->opt.smooth_dg, zero);
-  if (P->binv16) return bj_tri_cheb_bf16(P->bj, P->binv16, r, ab0_step(P, s), P->fd, x, f, P->s);
-  return bj_tri_cheb_f32(P->bj, P->binv32, r, ab0_step(P, s), P->fd, x, f, P->s);
+  return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, f, 4), [&] {
+    if (P->binv16) return bj_tri_cheb_bf16(P->bj, P->binv16, r, ab0_step(P, s), P->fd, x, f, P->s);
+    return bj_tri_cheb_f32(P->bj, P->binv32, r, ab0_step(P, s), P->fd, x, f, P->s);
+  });
 }
 int bj_apply32(sdg_problem* P, const float* r, float* z) {
-  if (P->binv16) return bj_tri_apply_bf16(P->bj, P->binv16, r, z, P->s);
-  return bj_tri_apply_f32(P->bj, P->binv32, r, z, P->s);
+  return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, BJ_APPLY, 4), [&] {
+    if (P->binv16) return bj_tri_apply_bf16(P->bj, P->binv16, r, z, P->s);
+    return bj_tri_apply_f32(P->bj, P->binv32, r, z, P->s);
+  });
+}
+int bj_apply64(sdg_problem* P, const double* r, double* z) {
+  return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, BJ_APPLY, 8),
+                [&] { return bj_apply_f64(P->bj, P->binv, r, z, P->s); });
 }
 
 int cheb_dg64(sdg_problem* P, const double* b, double* x, bool zero) {
   for (int s = 0; s < P->opt.smooth_dg; ++s) {
     const double* r = b;
     if (!(s == 0 && zero)) {
-      SDG_TRY(sip_residual(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s));
+      SDG_TRY(run_sip_residual(P, b, x, P->vr));
       r = P->vr;
     }
     SDG_TRY(bj_step64(P, r, s, x, zero));
@@ -455,7 +540,7 @@ int cheb_dg32(sdg_problem* P, const float* b, float* x, bool zero) {
   for (int s = 0; s < P->opt.smooth_dg; ++s) {
     const float* r = b;
     if (!(s == 0 && zero)) {
-      SDG_TRY(sip_residual_f32(P->M, P->k, P->nb, P->eta, b, x, P->fr, P->s));
+      SDG_TRY(run_sip_residual_f32(P, b, x, P->fr));
       r = P->fr;
     }
     SDG_TRY(bj_step32(P, r, s, x, zero));
@@ -474,7 +559,8 @@ int cheb_h(sdg_problem* P, CLevel& L, bool zero) {
 }
 
 int hcycle(sdg_problem* P, int li) {
-  if (li >= P->tail_start) return coarse_tail(P->tail, P->s);
+  if (li >= P->tail_start)
+    return traced(P->ctx, P->s, SDG_TRACE_COARSE_TAIL, 0.0, [&] { return coarse_tail(P->tail, P->s); });
   CLevel& L = P->lev[li];
   CLevel& C = P->lev[li + 1];
   SDG_TRY(cheb_h(P, L, true));
@@ -488,7 +574,7 @@ int hcycle(sdg_problem* P, int li) {
 
 int vcycle64(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(cheb_dg64(P, b, x, true));
-  SDG_TRY(sip_residual(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s));
+  SDG_TRY(run_sip_residual(P, b, x, P->vr));
   SDG_TRY(p_restrict(P->M, P->k, P->nb, P->vr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
   SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
@@ -501,7 +587,7 @@ int vcycle32(sdg_problem* P, const double* b, double* x) {
   const int64_t n = P->nu * P->nb;
   SDG_TRY(d2f(n, b, P->fb, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, true));
-  SDG_TRY(sip_residual_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s));
+  SDG_TRY(run_sip_residual_f32(P, P->fb, P->fx, P->fr));
   SDG_TRY(p_restrict_f32(P->M, P->k, P->nb, P->fr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
   SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
@@ -630,12 +716,12 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
       if (li < 0 && low_precision(P)) {
         // bounds of the operator the smoother applies: FP32 apply, FP32/BF16 inverses
         if ((rc = d2f(S.total, vj, P->fb, P->s)) < 0) break;
-        if ((rc = sip_apply_f32(P->M, P->k, nb, P->eta, P->fb, P->fr, P->s)) < 0) break;
+        if ((rc = run_sip_apply_f32(P, P->fb, P->fr)) < 0) break;
         if ((rc = bj_apply32(P, P->fr, P->fd)) < 0) break;
         if ((rc = f2d(S.total, P->fd, w, P->s)) < 0) break;
       } else if (li < 0) {
-        if ((rc = sip_apply(P->M, P->k, nb, P->eta, vj, P->vr, P->s)) < 0) break;
-        if ((rc = bj_apply_f64(P->bj, P->binv, P->vr, w, P->s)) < 0) break;
+        if ((rc = run_sip_apply(P, vj, P->vr)) < 0) break;
+        if ((rc = bj_apply64(P, P->vr, w)) < 0) break;
       } else {
         CLevel& L = P->lev[li];
         if ((rc = stencil_apply(L.nx, L.ny, nb, L.st, vj, L.r, P->s)) < 0) break;
@@ -726,7 +812,7 @@ int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit,
   SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz, P->red, P->s));
   std::vector<double> rr(nb), pq(nb);
   for (int it = 0; it < maxit && nact > 0; ++it) {
-    SDG_TRY(sip_apply(P->M, P->k, nb, P->eta, P->cg_p, P->cg_q, P->s));
+    SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
     SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
     SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                        P->s));
@@ -948,7 +1034,7 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
 // Stokes operator K = [A B; B^T 0] on x = [u (all problems); p (all problems)]
 int stokes_matvec(sdg_problem* P, const double* x, double* y) {
   const int64_t U = P->nu * P->nb;
-  SDG_TRY(sip_apply(P->M, P->k, P->nb, P->eta, x, y, P->s));
+  SDG_TRY(run_sip_apply(P, x, y));
   SDG_TRY(grad_apply(P->M, P->k, P->nb, x + U, P->gt, P->s));
   SDG_TRY(vec_axpy(U, 1.0, P->gt, y, P->s));
   SDG_TRY(div_apply(P->M, P->k, P->nb, x, y + U, P->s));
@@ -1345,15 +1431,15 @@ int sdg_eig_estimate(sdg_problem* P, int level, double* lambda_out, double* hess
 
 int sdg_apply_viscous(sdg_problem* P, const double* u, double* y) {
   PCHECK(u, y);
-  return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s);
+  return run_sip_apply(P, u, y);
 }
 int sdg_residual_viscous(sdg_problem* P, const double* b, const double* u, double* r) {
   PCHECK(b, u, r);
-  return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s);
+  return run_sip_residual(P, b, u, r);
 }
 int sdg_apply_viscous_f32(sdg_problem* P, const float* u, float* y) {
   PCHECK(u, y);
-  return sip_apply_f32(P->M, P->k, P->nb, P->eta, u, y, P->s);
+  return run_sip_apply_f32(P, u, y);
 }
 int sdg_apply_div(sdg_problem* P, const double* u, double* q) {
   PCHECK(u, q);
@@ -1365,7 +1451,7 @@ int sdg_apply_grad(sdg_problem* P, const double* p, double* v) {
 }
 int sdg_apply_blockjacobi(sdg_problem* P, const double* r, double* z) {
   PCHECK(r, z);
-  if (P->opt.prec_smoother == SDG_FP64) return bj_apply_f64(P->bj, P->binv, r, z, P->s);
+  if (P->opt.prec_smoother == SDG_FP64) return bj_apply64(P, r, z);
   if (!P->fr) {
     set_error("low-precision smoother storage missing");
     return SDG_ERR_INVALID;
@@ -1436,7 +1522,7 @@ int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, doub
   if (rc >= 0) {
     if (P->opt.viscous_krylov == 1) {
       const VSpec S = viscous_spec(P);
-      auto mv = [&](const double* x, double* y) { return sip_apply(P->M, P->k, P->nb, P->eta, x, y, P->s); };
+      auto mv = [&](const double* x, double* y) { return run_sip_apply(P, x, y); };
       auto pc = [&](const double* v, double* z) { return vcycle(P, v, z); };
       auto pj = [&](double*) { return SDG_OK; };
       rc = fgmres(P, S, F, u, P->opt.rtol, P->opt.max_it, mv, pc, pj, its, rel, status);
@@ -1449,7 +1535,7 @@ int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, doub
     const VSpec S = viscous_spec(P);
     std::vector<double> fn, rn;
     rc = vs_norms(P, S, F, fn);
-    if (rc >= 0) rc = sip_residual(P->M, P->k, P->nb, P->eta, F, u, P->vr, P->s);
+    if (rc >= 0) rc = run_sip_residual(P, F, u, P->vr);
     if (rc >= 0) rc = vs_norms(P, S, P->vr, rn);
     if (rc >= 0)
       for (int pb = 0; pb < P->nb; ++pb) rel[pb] = fn[pb] > 0 ? rn[pb] / fn[pb] : 0.0;
@@ -1562,6 +1648,50 @@ int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
 int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta,
                      const double* f, const double* g, double* u, double* p, sdg_stats* st) {
   return host_solve(ctx, mesh, opts, eta, f, g, u, p, st, true);
+}
+
+int sdg_trace_enable(sdg_ctx* ctx, int on) {
+  if (!ctx) {
+    set_error("NULL context");
+    return SDG_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> g(ctx->trace_mu);
+  if (on) {
+    for (auto& r : ctx->pending) {
+      ctx->ev_pool.push_back(r.a);
+      ctx->ev_pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+    for (int c = 0; c < SDG_TRACE_CLASSES; ++c) {
+      ctx->tr_n[c] = 0;
+      ctx->tr_ms[c] = ctx->tr_bytes[c] = 0.0;
+    }
+  }
+  ctx->trace = on != 0;
+  return SDG_OK;
+}
+
+int sdg_trace_read(sdg_ctx* ctx, int kclass, int64_t* launches, double* total_ms, double* bytes) {
+  if (!ctx || kclass < 0 || kclass >= SDG_TRACE_CLASSES) {
+    set_error("invalid context or kernel class");
+    return SDG_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> g(ctx->trace_mu);
+  for (auto& r : ctx->pending) {
+    SDG_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    SDG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    ctx->tr_n[r.cls] += 1;
+    ctx->tr_ms[r.cls] += ms;
+    ctx->tr_bytes[r.cls] += r.bytes;
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  if (launches) *launches = ctx->tr_n[kclass];
+  if (total_ms) *total_ms = ctx->tr_ms[kclass];
+  if (bytes) *bytes = ctx->tr_bytes[kclass];
+  return SDG_OK;
 }
 
 int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out, void* stream) {

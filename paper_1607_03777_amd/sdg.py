@@ -85,6 +85,9 @@ PROTOTYPES = {
     "sdg_solve_viscous": (I, [P, MESH, OPTS, P, P, P, P, STATS]),
     "sdg_solve_stokes": (I, [P, MESH, OPTS, P, P, P, P, P, STATS]),
     "sdg_uniform_pm1": (I, [P, ctypes.c_uint64, ctypes.c_int64, P, P]),
+    "sdg_trace_enable": (I, [P, I]),
+    "sdg_trace_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -320,6 +323,24 @@ def sdg_solve_stokes(ctx, mesh, opts, eta, f, g, u, p):
 
 def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
     return check(lib().sdg_uniform_pm1(ctx, ctypes.c_uint64(seed), n, ptr(out), stream))
+
+
+TRACE_SIP_APPLY, TRACE_SIP_RESIDUAL, TRACE_SMOOTHER, TRACE_COARSE_TAIL = 0, 1, 2, 3
+TRACE_NAMES = {TRACE_SIP_APPLY: "sip_apply", TRACE_SIP_RESIDUAL: "sip_residual",
+               TRACE_SMOOTHER: "block_jacobi_smoother", TRACE_COARSE_TAIL: "coarse_tail"}
+
+
+def sdg_trace_enable(ctx, on):
+    return check(lib().sdg_trace_enable(ctx, int(on)))
+
+
+def sdg_trace_read(ctx, kclass):
+    """-> (launches, total_ms, bytes) of one traced kernel class."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    check(lib().sdg_trace_read(ctx, kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
 
 
 # ---- convenience object ------------------------------------------------------
