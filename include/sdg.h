@@ -235,6 +235,24 @@ int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts
  * state `seed` (Steele, Lea & Flood 2014). */
 int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, void* stream);
 
+/* ---- tile shapes of the SIP operator kernels and their autotuner -------------
+ * The SIP apply/residual kernels stage TX x TY element tiles in LDS; each
+ * order k has sdg_tile_variants() candidate shapes (variant 0 = default).
+ * sdg_set_tile picks one for a problem: kernel 0 = apply (y = A u),
+ * 1 = residual (r = b - A u); precision SDG_FP64 or SDG_FP32 (the fine-level
+ * cycle of the low-precision forms).  sdg_autotune times every candidate on
+ * the problem's own shape and stream (reps launches each, HIP events, the
+ * problem's Krylov scratch vectors overwritten), keeps the fastest, and
+ * records it for every problem later created in this process with the same
+ * (k, nx, ny, nbatch).  variants[4] and us[4] (optional) receive the choice
+ * and its time per launch for [apply FP64, apply FP32, residual FP64,
+ * residual FP32]; FP32 entries are -1 / 0 when the problem has no FP32
+ * cycle.  Results are identical up to rounding order for every shape. */
+int sdg_tile_variants(int k, int* count);
+int sdg_tile_shape(int k, int variant, int* tx, int* ty);
+int sdg_set_tile(sdg_problem* prob, int kernel, int precision, int variant);
+int sdg_autotune(sdg_problem* prob, int reps, int* variants, double* us);
+
 /* ---- kernel tracing ---------------------------------------------------------
  * While tracing is on, every launch of the traced kernel classes made by
  * problems of this context is bracketed by two HIP events on the problem's

@@ -7,14 +7,17 @@ namespace sdg {
 
 // SIP operator (sip_kernels.hip).  Vectors are batched: nbatch problems of
 // the same mesh, consecutive in memory; eta is [nbatch][nel].
+// var selects the tile shape (sip_tile_variants(k) candidates, 0 = default)
 int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
-              hipStream_t s);
+              hipStream_t s, int var = 0);
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
-                 const double* u, double* r, hipStream_t s);
+                 const double* u, double* r, hipStream_t s, int var = 0);
 int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
-                  hipStream_t s);
+                  hipStream_t s, int var = 0);
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
-                     const float* u, float* r, hipStream_t s);
+                     const float* u, float* r, hipStream_t s, int var = 0);
+int sip_tile_variants(int k);
+void sip_tile_shape(int k, int var, int* tx, int* ty);
 // Diagonal blocks A_KK of the listed elements (one workgroup per listed
 // element): blocks[i][a][b] for element elems[i] of problem elems_pb[i].
 int sip_block_list(const MeshDev& M, int k, const double* eta, const int* elems, int nlist,

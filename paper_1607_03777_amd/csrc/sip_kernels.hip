@@ -30,13 +30,16 @@
 
 namespace sdg {
 
-template <int K1> struct Tile;
-template <> struct Tile<2> { static constexpr int TX = 16, TY = 8; };
-template <> struct Tile<3> { static constexpr int TX = 8, TY = 8; };
-template <> struct Tile<4> { static constexpr int TX = 8, TY = 4; };
-template <> struct Tile<5> { static constexpr int TX = 8, TY = 4; };
-template <> struct Tile<6> { static constexpr int TX = 4, TY = 4; };
-template <> struct Tile<7> { static constexpr int TX = 4, TY = 4; };
+// Tile shapes (TX x TY elements per workgroup) per K1; variant 0 is the
+// default, the others are candidates for the autotuner.
+constexpr int TILE_NV[8] = {0, 0, 3, 3, 3, 4, 3, 3};
+constexpr int TILE_TX[8][4] = {{0}, {0}, {16, 8, 16, 0}, {8, 16, 8, 0}, {8, 8, 4, 0},
+                               {8, 4, 16, 8}, {4, 8, 4, 0}, {4, 4, 2, 0}};
+constexpr int TILE_TY[8][4] = {{0}, {0}, {8, 8, 4, 0}, {8, 4, 4, 0}, {4, 8, 4, 0},
+                               {4, 4, 2, 2}, {4, 2, 2, 0}, {4, 2, 2, 0}};
+template <int K1> struct Tile {
+  static constexpr int TX = TILE_TX[K1][0], TY = TILE_TY[K1][0];
+};
 
 constexpr int NT = 256;  // threads per tile workgroup
 
@@ -45,11 +48,13 @@ constexpr int NT = 256;  // threads per tile workgroup
 // tr layout per face: [side s][comp d][w][m], w = 0 trace value, 1 normal
 // derivative; the output uses the same slots with w = 0 -> a, 1 -> b.
 // ---------------------------------------------------------------------------
+// Coefficients of one interior face, stored mode by mode into the face
+// record f (sides in `sides`: bit 0 the minus side, bit 1 the plus side), so
+// that only the traces stay live in registers.
 template <int K1, int DIR, typename T>
 __device__ __forceinline__ void interior_coefs(const T (&tm)[2][K1], const T (&gm)[2][K1],
                                                const T (&tp)[2][K1], const T (&gp)[2][K1],
-                                               T etam, T etap, T alpha, T hn, T ht,
-                                               T (&a)[2][2][K1], T (&b)[2][2][K1]) {
+                                               T etam, T etap, T alpha, T hn, T ht, T* f, int sides) {
   constexpr int N = DIR, TT = 1 - DIR;
   const T c2n = T(2) / hn, c2t = T(2) / ht;
 #pragma unroll
@@ -69,17 +74,32 @@ __device__ __forceinline__ void interior_coefs(const T (&tm)[2][K1], const T (&g
     const T st = T(0.5) * (c2t * (etam * dtm + etap * dtp) + c2n * (etam * gm[TT][m] + etap * gp[TT][m]));
     const T qn = -sn + alpha * jn;
     const T qt = -st + alpha * jt;
-    a[0][N][m] = c2n * (qn - etam / ht * dtj);
-    b[0][N][m] = -c2n * c2n * etam * jn;
-    a[0][TT][m] = c2n * qt;
-    b[0][TT][m] = -c2n / hn * etam * jt;
-    a[1][N][m] = -c2n * (qn + etap / ht * dtj);
-    b[1][N][m] = -c2n * c2n * etap * jn;
-    a[1][TT][m] = -c2n * qt;
-    b[1][TT][m] = -c2n / hn * etap * jt;
+    if (sides & 1) {
+      f[((0 * 2 + N) * 2 + 0) * K1 + m] = c2n * (qn - etam / ht * dtj);
+      f[((0 * 2 + N) * 2 + 1) * K1 + m] = -c2n * c2n * etam * jn;
+      f[((0 * 2 + TT) * 2 + 0) * K1 + m] = c2n * qt;
+      f[((0 * 2 + TT) * 2 + 1) * K1 + m] = -c2n / hn * etam * jt;
+    }
+    if (sides & 2) {
+      f[((1 * 2 + N) * 2 + 0) * K1 + m] = -c2n * (qn + etap / ht * dtj);
+      f[((1 * 2 + N) * 2 + 1) * K1 + m] = -c2n * c2n * etap * jn;
+      f[((1 * 2 + TT) * 2 + 0) * K1 + m] = -c2n * qt;
+      f[((1 * 2 + TT) * 2 + 1) * K1 + m] = -c2n / hn * etap * jt;
+    }
   }
 }
 
+template <int K1, typename T>
+__device__ __forceinline__ void zero_sides(T* f, int sides) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+    if (sides & (1 << s))
+#pragma unroll
+      for (int z = 0; z < 4 * K1; ++z) f[s * 4 * K1 + z] = T(0);
+}
+
+// Turns the traces of face record f into its coefficients, in place (the
+// traces are read into registers first).
 // kind: F_INTERIOR, or the boundary kind with `side` the present side.
 // isolate: each side sees a zero neighbour (diagonal blocks).
 // skip_interior: interior faces contribute nothing (continuous Q1 fields).
@@ -96,34 +116,22 @@ __device__ void face_coefs(T* f, int kind, int side, T etam, T etap, T hn, T ht,
       tp[d][m] = f[((1 * 2 + d) * 2 + 0) * K1 + m];
       gp[d][m] = f[((1 * 2 + d) * 2 + 1) * K1 + m];
     }
-  T a[2][2][K1], b[2][2][K1];
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int d = 0; d < 2; ++d)
-#pragma unroll
-      for (int m = 0; m < K1; ++m) a[s][d][m] = b[s][d][m] = T(0);
   const T kk = T(K1 * K1);
   if (kind == F_INTERIOR) {
-    if (!skip_interior) {
+    if (skip_interior) {
+      zero_sides<K1, T>(f, 3);
+    } else {
       const T alpha = T(4) * (etam > etap ? etam : etap) * kk / hn;
       if (!isolate) {
-        interior_coefs<K1, DIR, T>(tm, gm, tp, gp, etam, etap, alpha, hn, ht, a, b);
+        interior_coefs<K1, DIR, T>(tm, gm, tp, gp, etam, etap, alpha, hn, ht, f, 3);
       } else {
-        T z[2][K1], am[2][2][K1], bm[2][2][K1];
+        T z[2][K1];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
 #pragma unroll
           for (int m = 0; m < K1; ++m) z[d][m] = T(0);
-        interior_coefs<K1, DIR, T>(tm, gm, z, z, etam, etap, alpha, hn, ht, am, bm);
-        interior_coefs<K1, DIR, T>(z, z, tp, gp, etam, etap, alpha, hn, ht, a, b);
-#pragma unroll
-        for (int d = 0; d < 2; ++d)
-#pragma unroll
-          for (int m = 0; m < K1; ++m) {
-            a[0][d][m] = am[0][d][m];
-            b[0][d][m] = bm[0][d][m];
-          }
+        interior_coefs<K1, DIR, T>(tm, gm, z, z, etam, etap, alpha, hn, ht, f, 1);
+        interior_coefs<K1, DIR, T>(z, z, tp, gp, etam, etap, alpha, hn, ht, f, 2);
       }
     }
   } else if (kind == F_NAVIER) {
@@ -133,19 +141,13 @@ __device__ void face_coefs(T* f, int kind, int side, T etam, T etap, T hn, T ht,
     const T sgn = side == 0 ? T(1) : T(-1);
     const T c2n = T(2) / hn;
     const T w = T(4) * eta / hn;
+    zero_sides<K1, T>(f, 3);
 #pragma unroll
     for (int m = 0; m < K1; ++m) {
       const T t = side == 0 ? tm[N][m] : tp[N][m];
       const T g = side == 0 ? gm[N][m] : gp[N][m];
-      const T av = c2n * (alpha * t - sgn * w * g);
-      const T bv = -c2n * sgn * w * t;
-      if (side == 0) {
-        a[0][N][m] = av;
-        b[0][N][m] = bv;
-      } else {
-        a[1][N][m] = av;
-        b[1][N][m] = bv;
-      }
+      f[((side * 2 + N) * 2 + 0) * K1 + m] = c2n * (alpha * t - sgn * w * g);
+      f[((side * 2 + N) * 2 + 1) * K1 + m] = -c2n * sgn * w * t;
     }
   } else if (kind == F_DIRICHLET) {
     T z[2][K1];
@@ -155,20 +157,14 @@ __device__ void face_coefs(T* f, int kind, int side, T etam, T etap, T hn, T ht,
       for (int m = 0; m < K1; ++m) z[d][m] = T(0);
     const T eta2 = T(2) * (side == 0 ? etam : etap);
     const T alpha = T(4) * eta2 * kk / hn;
+    zero_sides<K1, T>(f, side == 0 ? 2 : 1);
     if (side == 0)
-      interior_coefs<K1, DIR, T>(tm, gm, z, z, eta2, T(0), alpha, hn, ht, a, b);
+      interior_coefs<K1, DIR, T>(tm, gm, z, z, eta2, T(0), alpha, hn, ht, f, 1);
     else
-      interior_coefs<K1, DIR, T>(z, z, tp, gp, T(0), eta2, alpha, hn, ht, a, b);
+      interior_coefs<K1, DIR, T>(z, z, tp, gp, T(0), eta2, alpha, hn, ht, f, 2);
+  } else {
+    zero_sides<K1, T>(f, 3);
   }
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int d = 0; d < 2; ++d)
-#pragma unroll
-      for (int m = 0; m < K1; ++m) {
-        f[((s * 2 + d) * 2 + 0) * K1 + m] = a[s][d][m];
-        f[((s * 2 + d) * 2 + 1) * K1 + m] = b[s][d][m];
-      }
 }
 
 // ---------------------------------------------------------------------------
@@ -182,7 +178,7 @@ enum ApplyMode { M_APPLY = 0, M_RESID = 1, M_BLOCKCOL = 2, M_COARSECOL = 3 };
 // MODE M_COARSECOL: tile grid; loops over the 8 hat columns, writes
 //   out_mat[pb*nel + e][r][col].
 template <int K1, int MODE, typename T, int TX, int TY>
-__global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __restrict__ u,
+__global__ __launch_bounds__(NT, (K1 >= 7 ? 3 : 1)) void sip_tile_kernel(MeshDev M, const T* __restrict__ u,
                                                       const T* __restrict__ bvec, T* __restrict__ y,
                                                       const double* __restrict__ eta_all,
                                                       double* __restrict__ out_mat,
@@ -191,11 +187,12 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
   constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY;
   constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1);
   constexpr int FW = 8 * K1;
+  constexpr int FS = FW + 1;  // face record stride: odd, so one-thread-per-face access avoids bank conflicts
   constexpr int EW = TX + 2;
   __shared__ T su[E * NB];
-  __shared__ T sxy[E * NB];  // [el][0] = D_y u0 (columns), [el][1] = D_x u1 (rows)
+  __shared__ T sdm[K1 * K1];  // derivative matrix D(m, i) (zero off its pattern)
   __shared__ T sy[E * NB];
-  __shared__ T sf[(NFV + NFH) * FW];
+  __shared__ T sf[(NFV + NFH) * FS];
   __shared__ T seta[(TY + 2) * EW];
 
   const int tid = threadIdx.x;
@@ -226,6 +223,10 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
   for (int q = tid; q < (TY + 2) * EW; q += NT) {
     const int ix = ix0 - 1 + q % EW, iy = iy0 - 1 + q / EW;
     seta[q] = (ix >= 0 && ix < nx && iy >= 0 && iy < ny) ? T(eta[(int64_t)iy * nx + ix]) : T(0);
+  }
+  for (int q = tid; q < K1 * K1; q += NT) {
+    const int m = q / K1, i = q % K1;
+    sdm[q] = d_nz(m, i) ? T(d_val(m, i)) : T(0);
   }
   constexpr int NCOLS = (MODE == M_BLOCKCOL) ? NB : (MODE == M_COARSECOL ? 8 : 1);
   for (int col = 0; col < NCOLS; ++col) {
@@ -289,25 +290,14 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
         }
         // left end belongs to face fx = tx (plus side), right end to fx = tx+1 (minus side)
         if (tx >= 0) {
-          T* f = sf + (ty * (TX + 1) + tx) * FW;
+          T* f = sf + (ty * (TX + 1) + tx) * FS;
           f[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
           f[((1 * 2 + d) * 2 + 1) * K1 + j] = gl;
         }
         if (tx < TX) {
-          T* f = sf + (ty * (TX + 1) + tx + 1) * FW;
+          T* f = sf + (ty * (TX + 1) + tx + 1) * FS;
           f[((0 * 2 + d) * 2 + 0) * K1 + j] = tr;
           f[((0 * 2 + d) * 2 + 1) * K1 + j] = gr;
-        }
-        if (inside && d == 1) {  // D_x u1, row j
-          T* o = sxy + (ty * TX + tx) * NB + KK + j * K1;
-#pragma unroll
-          for (int i = 0; i < K1; ++i) {
-            T s = 0;
-#pragma unroll
-            for (int l = 0; l < K1; ++l)
-              if (d_nz(i, l)) s += T(d_val(i, l)) * row[l];
-            o[i] = s;
-          }
         }
       } else {
         const int qq = q - NROW;
@@ -338,25 +328,14 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
           gt += T(d_end(jj, 1)) * cl[jj];
         }
         if (ty >= 0) {
-          T* f = sf + (NFV + ty * TX + tx) * FW;
+          T* f = sf + (NFV + ty * TX + tx) * FS;
           f[((1 * 2 + d) * 2 + 0) * K1 + i] = tb;
           f[((1 * 2 + d) * 2 + 1) * K1 + i] = gb;
         }
         if (ty < TY) {
-          T* f = sf + (NFV + (ty + 1) * TX + tx) * FW;
+          T* f = sf + (NFV + (ty + 1) * TX + tx) * FS;
           f[((0 * 2 + d) * 2 + 0) * K1 + i] = tt;
           f[((0 * 2 + d) * 2 + 1) * K1 + i] = gt;
-        }
-        if (inside && d == 0) {  // D_y u0, column i
-          T* o = sxy + (ty * TX + tx) * NB + i;
-#pragma unroll
-          for (int jj = 0; jj < K1; ++jj) {
-            T s = 0;
-#pragma unroll
-            for (int l = 0; l < K1; ++l)
-              if (d_nz(jj, l)) s += T(d_val(jj, l)) * cl[l];
-            o[jj * K1] = s;
-          }
         }
       }
     }
@@ -365,7 +344,7 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
 
   // ---- S2: one thread per face: traces -> coefficients (in place)
   for (int q = tid; q < NFV + NFH; q += NT) {
-    T* f = sf + q * FW;
+    T* f = sf + q * FS;
     if (q < NFV) {
       const int ty = q / (TX + 1), fx = q % (TX + 1);
       const int iy = iy0 + ty, ixm = ix0 + fx - 1, ixp = ix0 + fx;
@@ -422,11 +401,16 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
         if (s_nz(i, l)) s += T(s_val(i, l)) * row[l];
       out[i] = cx * s;
     }
-    if (d == 1) {  // D_x^T (D_y u0), row j
-      const T* yp = sxy + el * NB + j * K1;
+    if (d == 1) {  // D_x^T (D_y u0), row j; (D_y u0)[j][m] = sum_{l > j} D(j, l) u0[l][m]
+      const T* u0 = su + el * NB;
       T r0[K1];
 #pragma unroll
-      for (int m = 0; m < K1; ++m) r0[m] = yp[m];
+      for (int m = 0; m < K1; ++m) r0[m] = T(0);
+      for (int l = j + 1; l < K1; l += 2) {
+        const T c = sdm[j * K1 + l];
+#pragma unroll
+        for (int m = 0; m < K1; ++m) r0[m] += c * u0[l * K1 + m];
+      }
 #pragma unroll
       for (int i = 0; i < K1; ++i) {
         T s = 0;
@@ -436,8 +420,8 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
         out[i] += et * cxy * s;
       }
     }
-    const T* fl = sf + (ty * (TX + 1) + tx) * FW;      // plus side of left face
-    const T* fr = sf + (ty * (TX + 1) + tx + 1) * FW;  // minus side of right face
+    const T* fl = sf + (ty * (TX + 1) + tx) * FS;      // plus side of left face
+    const T* fr = sf + (ty * (TX + 1) + tx + 1) * FS;  // minus side of right face
     const T al = fl[((1 * 2 + d) * 2 + 0) * K1 + j], bl = fl[((1 * 2 + d) * 2 + 1) * K1 + j];
     const T ar = fr[((0 * 2 + d) * 2 + 0) * K1 + j], br = fr[((0 * 2 + d) * 2 + 1) * K1 + j];
     T* op = sy + el * NB + d * KK + j * K1;
@@ -453,7 +437,7 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
     const int i = q % K1, d = (q / K1) & 1, el = q / (2 * K1);
     const int tx = el % TX, ty = el / TX;
     const T et = seta[(ty + 1) * EW + tx + 1];
-    T* cp = su + el * NB + d * KK + i;
+    const T* cp = su + el * NB + d * KK + i;
     T cl[K1], out[K1];
 #pragma unroll
     for (int jj = 0; jj < K1; ++jj) cl[jj] = cp[jj * K1];
@@ -466,11 +450,16 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
         if (s_nz(jj, l)) s += T(s_val(jj, l)) * cl[l];
       out[jj] = cy * s;
     }
-    if (d == 0) {  // D_y^T (D_x u1), column i
-      const T* xp = sxy + el * NB + KK + i;
+    if (d == 0) {  // D_y^T (D_x u1), column i; (D_x u1)[m][i] = sum_{l > i} D(i, l) u1[m][l]
+      const T* u1 = su + el * NB + KK;
       T c1[K1];
 #pragma unroll
-      for (int m = 0; m < K1; ++m) c1[m] = xp[m * K1];
+      for (int m = 0; m < K1; ++m) c1[m] = T(0);
+      for (int l = i + 1; l < K1; l += 2) {
+        const T c = sdm[i * K1 + l];
+#pragma unroll
+        for (int m = 0; m < K1; ++m) c1[m] += c * u1[m * K1 + l];
+      }
 #pragma unroll
       for (int jj = 0; jj < K1; ++jj) {
         T s = 0;
@@ -480,14 +469,16 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
         out[jj] += et * cxy * s;
       }
     }
-    const T* fb = sf + (NFV + ty * TX + tx) * FW;        // plus side of bottom face
-    const T* ft = sf + (NFV + (ty + 1) * TX + tx) * FW;  // minus side of top face
+    const T* fb = sf + (NFV + ty * TX + tx) * FS;        // plus side of bottom face
+    const T* ft = sf + (NFV + (ty + 1) * TX + tx) * FS;  // minus side of top face
     const T ab = fb[((1 * 2 + d) * 2 + 0) * K1 + i], bb = fb[((1 * 2 + d) * 2 + 1) * K1 + i];
     const T at = ft[((0 * 2 + d) * 2 + 0) * K1 + i], bt = ft[((0 * 2 + d) * 2 + 1) * K1 + i];
-    const T* sp = sy + el * NB + d * KK + i;
+    // the result goes to sy (this thread's own column): su stays intact for
+    // the other columns' mixed terms
+    T* sp = sy + el * NB + d * KK + i;
 #pragma unroll
     for (int jj = 0; jj < K1; ++jj)
-      cp[jj * K1] = sp[jj * K1] + out[jj] + ab * T(e_end(jj, 0)) + bb * T(d_end(jj, 0)) +
+      sp[jj * K1] = sp[jj * K1] + out[jj] + ab * T(e_end(jj, 0)) + bb * T(d_end(jj, 0)) +
                     at * T(e_end(jj, 1)) + bt * T(d_end(jj, 1));
   }
   __syncthreads();
@@ -499,11 +490,11 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
       const int ix = ix0 + tx, iy = iy0 + ty;
       if (ix < nx && iy < ny) {
         const int64_t g = ((int64_t)iy * nx + ix0) * NB + rem;
-        y[g] = (MODE == M_RESID) ? bvec[g] - su[q] : su[q];
+        y[g] = (MODE == M_RESID) ? bvec[g] - sy[q] : sy[q];
       }
     }
   } else if (MODE == M_BLOCKCOL) {
-    for (int a = tid; a < NB; a += NT) out_mat[((int64_t)blockIdx.x * NB + a) * NB + col] = double(su[a]);
+    for (int a = tid; a < NB; a += NT) out_mat[((int64_t)blockIdx.x * NB + a) * NB + col] = double(sy[a]);
   } else {  // M_COARSECOL: project the Q1 modes with P_cd^T -> local nodal row (vtx', comp')
     for (int q = tid; q < E * 8; q += NT) {
       const int el = q / 8, r = q % 8, vtx = r >> 1, cc = r & 1, va = vtx & 1, vb = vtx >> 1;
@@ -516,7 +507,7 @@ __global__ __launch_bounds__(NT) void sip_tile_kernel(MeshDev M, const T* __rest
             const double cij = sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (M.hx * M.hy));
             const double si = (i == 0) ? 1.0 : (va ? 1.0 : -1.0);
             const double sj = (j == 0) ? 1.0 : (vb ? 1.0 : -1.0);
-            s += 0.25 * si * sj / cij * double(su[el * NB + cc * KK + j * K1 + i]);
+            s += 0.25 * si * sj / cij * double(sy[el * NB + cc * KK + j * K1 + i]);
           }
         const int64_t e = (int64_t)iy * nx + ix + pb * (int64_t)nx * ny;
         out_mat[(e * 8 + r) * 8 + col] = s;
@@ -808,16 +799,44 @@ __global__ __launch_bounds__(256) void rhs_kernel(MeshDev M, int nbatch, const d
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int K1, int MODE, typename T>
-static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
+template <int K1, int MODE, typename T, int V>
+static void launch_var(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
                        double* out_mat, hipStream_t s) {
-  constexpr int TX = Tile<K1>::TX, TY = Tile<K1>::TY;
+  constexpr int TX = TILE_TX[K1][V], TY = TILE_TY[K1][V];
   const int ntiles = ceil_div(M.nx, TX) * ceil_div(M.ny, TY);
   const int64_t stride = (int64_t)M.nx * M.ny * 2 * K1 * K1;
   hipLaunchKernelGGL((sip_tile_kernel<K1, MODE, T, TX, TY>), dim3(ntiles, nbatch), dim3(NT), 0, s,
                      M, u, b, y, eta, out_mat, nullptr, stride);
+}
+
+template <int K1, int MODE, typename T>
+static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
+                       double* out_mat, hipStream_t s, int var = 0) {
+  if (var < 0 || var >= TILE_NV[K1]) {
+    set_error("tile variant out of range");
+    return SDG_ERR_INVALID;
+  }
+  if (MODE == M_APPLY || MODE == M_RESID) {
+    switch (var) {
+      case 0: launch_var<K1, MODE, T, 0>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      case 1: launch_var<K1, MODE, T, 1>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      case 2: launch_var<K1, MODE, T, 2>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      default:
+        if constexpr (TILE_NV[K1] > 3) launch_var<K1, MODE, T, 3>(M, nbatch, u, b, y, eta, out_mat, s);
+        break;
+    }
+  } else {
+    launch_var<K1, MODE, T, 0>(M, nbatch, u, b, y, eta, out_mat, s);
+  }
   SDG_CHECK_LAUNCH();
   return SDG_OK;
+}
+
+int sip_tile_variants(int k) { return (k >= 1 && k <= 6) ? TILE_NV[k + 1] : 0; }
+void sip_tile_shape(int k, int var, int* tx, int* ty) {
+  const bool ok = k >= 1 && k <= 6 && var >= 0 && var < TILE_NV[k + 1];
+  *tx = ok ? TILE_TX[k + 1][var] : 0;
+  *ty = ok ? TILE_TY[k + 1][var] : 0;
 }
 template <int K1>
 static int launch_block_list(const MeshDev& M, const double* eta, const int* elems, int nlist,
@@ -841,23 +860,23 @@ static int launch_block_list(const MeshDev& M, const double* eta, const int* ele
   }
 
 int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
-              hipStream_t s) {
-  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, double>(M, nbatch, u, nullptr, y, eta, nullptr, s)));
+              hipStream_t s, int var) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, double>(M, nbatch, u, nullptr, y, eta, nullptr, s, var)));
   return SDG_OK;
 }
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
-                 const double* u, double* r, hipStream_t s) {
-  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, double>(M, nbatch, u, b, r, eta, nullptr, s)));
+                 const double* u, double* r, hipStream_t s, int var) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, double>(M, nbatch, u, b, r, eta, nullptr, s, var)));
   return SDG_OK;
 }
 int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
-                  hipStream_t s) {
-  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, float>(M, nbatch, u, nullptr, y, eta, nullptr, s)));
+                  hipStream_t s, int var) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, float>(M, nbatch, u, nullptr, y, eta, nullptr, s, var)));
   return SDG_OK;
 }
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
-                     const float* u, float* r, hipStream_t s) {
-  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, float>(M, nbatch, u, b, r, eta, nullptr, s)));
+                     const float* u, float* r, hipStream_t s, int var) {
+  SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_RESID, float>(M, nbatch, u, b, r, eta, nullptr, s, var)));
   return SDG_OK;
 }
 int sip_block_list(const MeshDev& M, int k, const double* eta, const int* elems, int nlist,

@@ -25,7 +25,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <array>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -76,6 +78,11 @@ namespace {
 
 constexpr int TAIL_NODES = 17 * 17;  // h-levels with at most this many nodes run in the tail kernel
 constexpr int RED_SCRATCH = 512 * 64;
+
+// Tile shapes chosen by sdg_autotune, per (k, nx, ny, nbatch, kernel,
+// precision), shared by every later problem of that shape in the process.
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, int> g_tune;
 
 hipEvent_t trace_event(sdg_ctx* c) {
   hipEvent_t e = nullptr;
@@ -168,6 +175,8 @@ struct sdg_problem {
   double setup_ms = 0;
   // per-problem statistics of the last solve
   std::vector<int> inner_total, inner_max;
+  // tile shape of the SIP kernels: [apply, residual][FP64, FP32]
+  int tile[2][2] = {{0, 0}, {0, 0}};
 };
 
 namespace {
@@ -422,19 +431,22 @@ double vec_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * 
 double elem_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * w; }
 int run_sip_apply(sdg_problem* P, const double* u, double* y) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8),
-                [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s); });
+                [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s, P->tile[0][0]); });
 }
 int run_sip_residual(sdg_problem* P, const double* b, const double* u, double* r) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 8) + elem_bytes(P, 8),
-                [&] { return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s); });
+                [&] { return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s, P->tile[1][0]); });
 }
 int run_sip_apply_f32(sdg_problem* P, const float* u, float* y) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 4) + elem_bytes(P, 8),
-                [&] { return sip_apply_f32(P->M, P->k, P->nb, P->eta, u, y, P->s); });
+                [&] { return sip_apply_f32(P->M, P->k, P->nb, P->eta, u, y, P->s, P->tile[0][1]); });
 }
 int run_sip_residual_f32(sdg_problem* P, const float* b, const float* u, float* r) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 4) + elem_bytes(P, 8),
-                [&] { return sip_residual_f32(P->M, P->k, P->nb, P->eta, b, u, r, P->s); });
+                [&] { return sip_residual_f32(P->M, P->k, P->nb, P->eta, b, u, r, P->s, P->tile[1][1]); });
+}
+std::array<int, 6> tune_key(const sdg_problem* P, int kernel, int prec) {
+  return {P->k, P->mesh.nx, P->mesh.ny, P->nb, kernel, prec};
 }
 double smoother_bytes(const sdg_problem* P, int flags, int w) {
   const int nvec = 2 + !!(flags & BJ_READ_X) + !!(flags & BJ_READ_D) + !!(flags & BJ_WRITE_D);
@@ -1248,6 +1260,14 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   for (int i = 0; i < 4; ++i) P->M.bc[i] = mesh->bc[i];
   P->inner_total.assign(nbatch, 0);
   P->inner_max.assign(nbatch, 0);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (int kern = 0; kern < 2; ++kern)
+      for (int pr = 0; pr < 2; ++pr) {
+        auto it = g_tune.find(tune_key(P, kern, pr));
+        if (it != g_tune.end()) P->tile[kern][pr] = it->second;
+      }
+  }
   auto fail = [&](int rc) {
     sdg_problem_destroy(P);
     return rc;
@@ -1648,6 +1668,102 @@ int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
 int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta,
                      const double* f, const double* g, double* u, double* p, sdg_stats* st) {
   return host_solve(ctx, mesh, opts, eta, f, g, u, p, st, true);
+}
+
+int sdg_tile_variants(int k, int* count) {
+  if (!count || k < 1 || k > 6) {
+    set_error("NULL output or order k out of range");
+    return SDG_ERR_INVALID;
+  }
+  *count = sip_tile_variants(k);
+  return SDG_OK;
+}
+
+int sdg_tile_shape(int k, int variant, int* tx, int* ty) {
+  if (!tx || !ty || k < 1 || k > 6 || variant < 0 || variant >= sip_tile_variants(k)) {
+    set_error("NULL output, order k or tile variant out of range");
+    return SDG_ERR_INVALID;
+  }
+  sip_tile_shape(k, variant, tx, ty);
+  return SDG_OK;
+}
+
+int sdg_set_tile(sdg_problem* P, int kernel, int precision, int variant) {
+  if (!P || kernel < 0 || kernel > 1 || (precision != SDG_FP64 && precision != SDG_FP32) || variant < 0 ||
+      variant >= sip_tile_variants(P->k)) {
+    set_error("invalid problem, kernel, precision or tile variant");
+    return SDG_ERR_INVALID;
+  }
+  P->tile[kernel][precision == SDG_FP64 ? 0 : 1] = variant;
+  return SDG_OK;
+}
+
+int sdg_autotune(sdg_problem* P, int reps, int* variants, double* us) {
+  if (!P || reps < 1) {
+    set_error("invalid problem or repetition count");
+    return SDG_ERR_INVALID;
+  }
+  const int64_t U = P->nu * P->nb;
+  const int nv = sip_tile_variants(P->k);
+  SDG_TRY(uniform_pm1(P->opt.seed ^ 0x5eedull, U, P->cg_r, P->s));
+  SDG_TRY(uniform_pm1(P->opt.seed ^ 0xb0bull, U, P->cg_z, P->s));
+  const bool f32 = low_precision(P);
+  if (f32) {
+    SDG_TRY(d2f(U, P->cg_r, P->fx, P->s));
+    SDG_TRY(d2f(U, P->cg_z, P->fb, P->s));
+  }
+  hipEvent_t e0, e1;
+  SDG_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return SDG_ERR_DEVICE;
+  }
+  int rc = SDG_OK;
+  for (int kern = 0; kern < 2 && rc >= 0; ++kern)
+    for (int pr = 0; pr < (f32 ? 2 : 1) && rc >= 0; ++pr) {
+      double best = 1e300;
+      int bestv = 0;
+      for (int v = 0; v < nv && rc >= 0; ++v) {
+        auto launch = [&]() {
+          if (pr == 0)
+            return kern == 0 ? sip_apply(P->M, P->k, P->nb, P->eta, P->cg_r, P->cg_p, P->s, v)
+                             : sip_residual(P->M, P->k, P->nb, P->eta, P->cg_z, P->cg_r, P->cg_p, P->s, v);
+          return kern == 0 ? sip_apply_f32(P->M, P->k, P->nb, P->eta, P->fx, P->fr, P->s, v)
+                           : sip_residual_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s, v);
+        };
+        for (int w = 0; w < 2 && rc >= 0; ++w) rc = launch();
+        if (rc < 0) break;
+        if (hipEventRecord(e0, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
+        for (int r = 0; r < reps && rc >= 0; ++r) rc = launch();
+        if (rc < 0) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, P->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          set_error("event timing failed during autotuning");
+          rc = SDG_ERR_DEVICE;
+          break;
+        }
+        const double t = 1e3 * ms / reps;
+        if (t < best) {
+          best = t;
+          bestv = v;
+        }
+      }
+      if (rc < 0) break;
+      P->tile[kern][pr] = bestv;
+      if (variants) variants[kern * 2 + pr] = bestv;
+      if (us) us[kern * 2 + pr] = best;
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune[tune_key(P, kern, pr)] = bestv;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!f32 && rc >= 0) {
+    if (variants) variants[1] = variants[3] = -1;
+    if (us) us[1] = us[3] = 0.0;
+  }
+  return rc;
 }
 
 int sdg_trace_enable(sdg_ctx* ctx, int on) {

@@ -85,6 +85,10 @@ PROTOTYPES = {
     "sdg_solve_viscous": (I, [P, MESH, OPTS, P, P, P, P, STATS]),
     "sdg_solve_stokes": (I, [P, MESH, OPTS, P, P, P, P, P, STATS]),
     "sdg_uniform_pm1": (I, [P, ctypes.c_uint64, ctypes.c_int64, P, P]),
+    "sdg_tile_variants": (I, [I, ctypes.POINTER(I)]),
+    "sdg_tile_shape": (I, [I, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "sdg_set_tile": (I, [P, I, I, I]),
+    "sdg_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]),
     "sdg_trace_enable": (I, [P, I]),
     "sdg_trace_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
@@ -323,6 +327,36 @@ def sdg_solve_stokes(ctx, mesh, opts, eta, f, g, u, p):
 
 def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
     return check(lib().sdg_uniform_pm1(ctx, ctypes.c_uint64(seed), n, ptr(out), stream))
+
+
+TILE_APPLY, TILE_RESIDUAL = 0, 1
+
+
+def sdg_tile_variants(k):
+    n = I()
+    check(lib().sdg_tile_variants(k, ctypes.byref(n)))
+    return n.value
+
+
+def sdg_tile_shape(k, variant):
+    tx, ty = I(), I()
+    check(lib().sdg_tile_shape(k, variant, ctypes.byref(tx), ctypes.byref(ty)))
+    return tx.value, ty.value
+
+
+def sdg_set_tile(prob, kernel, precision, variant):
+    return check(lib().sdg_set_tile(prob, kernel, precision, variant))
+
+
+def sdg_autotune(prob, reps=20):
+    """-> ({(kernel, precision): variant}, {(kernel, precision): us}) for
+    kernel in (apply, residual) and precision in (FP64, FP32)."""
+    v = (I * 4)()
+    us = (ctypes.c_double * 4)()
+    check(lib().sdg_autotune(prob, reps, v, us))
+    keys = [(TILE_APPLY, FP64), (TILE_APPLY, FP32), (TILE_RESIDUAL, FP64), (TILE_RESIDUAL, FP32)]
+    return ({k: v[i] for i, k in enumerate(keys) if v[i] >= 0},
+            {k: us[i] for i, k in enumerate(keys) if v[i] >= 0})
 
 
 TRACE_SIP_APPLY, TRACE_SIP_RESIDUAL, TRACE_SMOOTHER, TRACE_COARSE_TAIL = 0, 1, 2, 3

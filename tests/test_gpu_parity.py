@@ -82,22 +82,37 @@ def test_apply_parity(sdg, ctx, torch, k, bci):
     rng = np.random.default_rng(k)
     u = rng.normal(size=m.nu)
     P = make_problem(sdg, ctx, nx, ny, k, eta, bc)
-    y = P.zeros(m.nu)
-    sdg.sdg_apply_viscous(P.h, dev(u), y)
-    torch.cuda.synchronize()
-    assert_close_componentwise(host(y), A @ u, abs_bound(A, u), 1e-13 * 64)
-    # fused residual
     b = rng.normal(size=m.nu)
-    r = P.zeros(m.nu)
-    sdg.sdg_residual_viscous(P.h, dev(b), dev(u), r)
-    torch.cuda.synchronize()
-    assert_close_componentwise(host(r), b - A @ u, abs_bound(A, u) + np.abs(b), 1e-13 * 64)
-    # FP32 apply (same kernel in single precision)
-    y32 = P.zeros(m.nu, torch.float32)
-    sdg.sdg_apply_viscous_f32(P.h, dev(u.astype(np.float32)), y32)
-    torch.cuda.synchronize()
-    u32 = u.astype(np.float32).astype(np.float64)
-    assert_close_componentwise(host(y32).astype(np.float64), A @ u32, abs_bound(A, u32), 6e-7 * 64)
+    first = None
+    # every tile shape of the kernels (the mesh leaves ragged tiles for each)
+    for var in range(sdg.sdg_tile_variants(k)):
+        print(f"[case] tile variant {var} {sdg.sdg_tile_shape(k, var)}", flush=True)
+        for kern in (sdg.TILE_APPLY, sdg.TILE_RESIDUAL):
+            for prec in (sdg.FP64, sdg.FP32):
+                sdg.sdg_set_tile(P.h, kern, prec, var)
+        y = P.zeros(m.nu)
+        sdg.sdg_apply_viscous(P.h, dev(u), y)
+        torch.cuda.synchronize()
+        assert_close_componentwise(host(y), A @ u, abs_bound(A, u), 1e-13 * 64)
+        # fused residual
+        r = P.zeros(m.nu)
+        sdg.sdg_residual_viscous(P.h, dev(b), dev(u), r)
+        torch.cuda.synchronize()
+        assert_close_componentwise(host(r), b - A @ u, abs_bound(A, u) + np.abs(b), 1e-13 * 64)
+        # FP32 apply (same kernel in single precision)
+        y32 = P.zeros(m.nu, torch.float32)
+        sdg.sdg_apply_viscous_f32(P.h, dev(u.astype(np.float32)), y32)
+        torch.cuda.synchronize()
+        u32 = u.astype(np.float32).astype(np.float64)
+        assert_close_componentwise(host(y32).astype(np.float64), A @ u32, abs_bound(A, u32), 6e-7 * 64)
+        # the tile shape changes which elements share a workgroup, not the
+        # arithmetic of any element: outputs are bit-identical
+        outs = (host(y), host(r), host(y32))
+        if first is None:
+            first = outs
+        else:
+            for a, c in zip(outs, first):
+                assert np.array_equal(a, c)
     P.close()
 
 

@@ -56,3 +56,31 @@ def test_trace_counts_launches_and_bytes(sdg, torch):
         prob.close()
     finally:
         sdg.sdg_destroy(ctx)
+
+
+def test_autotune_picks_valid_shapes_and_keeps_results(sdg, torch):
+    ctx = sdg.sdg_create(0, 0)
+    try:
+        n, k = 24, 4
+        P0 = gen.single_inclusion(n, k, eta_in=1e3)
+        print(f"[case] autotune n={n} k={k}", flush=True)
+        prob = sdg.Problem(ctx, n, n, k, P0.eta, prec_apply=sdg.FP32, prec_smoother=sdg.FP32)
+        f = torch.as_tensor(P0.f.reshape(-1), device="cuda")
+        u0, st0 = prob.solve_viscous(f)
+        var, us = sdg.sdg_autotune(prob.h, 5)
+        nv = sdg.sdg_tile_variants(k)
+        assert set(var) == {(sdg.TILE_APPLY, sdg.FP64), (sdg.TILE_APPLY, sdg.FP32),
+                            (sdg.TILE_RESIDUAL, sdg.FP64), (sdg.TILE_RESIDUAL, sdg.FP32)}
+        assert all(0 <= v < nv for v in var.values()) and all(t > 0 for t in us.values())
+        u1, st1 = prob.solve_viscous(f)
+        assert st1["status"] == st0["status"] == 0
+        # tile shapes do not change the arithmetic: the same iterates
+        assert torch.equal(u0, u1)
+        # a later problem of the same shape starts from the tuned shapes
+        prob2 = sdg.Problem(ctx, n, n, k, P0.eta, prec_apply=sdg.FP32, prec_smoother=sdg.FP32)
+        u2, _ = prob2.solve_viscous(f)
+        assert torch.equal(u0, u2)
+        prob2.close()
+        prob.close()
+    finally:
+        sdg.sdg_destroy(ctx)
