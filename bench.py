@@ -85,6 +85,74 @@ def cpu_baseline(prob_in, gpu_outer_its, budget_s=25.0):
     }
 
 
+def serving(sdg, ctx, nreq, rate, prec):
+    """Request-server form: a Poisson trace of Stokes requests (n in
+    {32, 48, 64}, k in 2..4, 1-16 disks with contrast 10^U[2,6], rtol 1e-8)
+    replayed in real time into the server (mixed-precision cycle, batching
+    by shape, 4 slots), and the same trace through a plain FP64 per-request
+    path (one-shot solves one after another, no batching).  Latency =
+    completion - arrival."""
+    from paper_1607_03777_amd import inputs as gen
+    trace = gen.serving_trace(nreq=nreq, rate=rate, seed=0, nmin=32, nmax=64, kmin=2, kmax=4)
+    probs = [gen.serving_problem(r) for r in trace]
+    prec_mix = {"fp64": (sdg.FP64, sdg.FP64), "fp32": (sdg.FP32, sdg.FP32), "bf16": (sdg.FP32, sdg.BF16)}[prec]
+    o_mix = sdg.make_options(rtol=RTOL, inner_rtol=1e-3, max_it=2000, prec_apply=prec_mix[0],
+                             prec_smoother=prec_mix[1])
+    o_64 = sdg.make_options(rtol=RTOL, inner_rtol=1e-3, max_it=2000)
+
+    def pct(x):
+        return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
+
+    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=16)
+    t0 = time.perf_counter()
+    hs = []
+    for r, pr in zip(trace, probs):
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        mesh = sdg.make_mesh(pr.nx, pr.ny, pr.k)
+        hs.append((sdg.sdg_submit(srv, mesh, o_mix, sdg.STOKES, pr.eta, pr.f.reshape(-1)),
+                   time.perf_counter() - t0, pr))
+    lat, bad, batches = [], 0, []
+    for h, t_sub, pr in hs:
+        rc, u, p, st, info = sdg.sdg_wait(h, pr.nu, pr.np_)
+        sdg.sdg_req_free(h)
+        bad += rc not in (0, sdg.FLOOR)
+        lat.append(info["end_ms"] - info["submit_ms"])
+        batches.append(info["batch"])
+    t_srv = time.perf_counter() - t0
+    sst = sdg.sdg_server_stats(srv)
+    sdg.sdg_server_destroy(srv)
+    log(f"[bench] served {nreq} requests in {t_srv:.2f} s, p50 {np.percentile(lat, 50):.1f} ms "
+        f"p99 {np.percentile(lat, 99):.1f} ms, mean launch group {np.mean(batches):.1f}, failures {bad}")
+    # plain FP64 per-request path on the same arrivals
+    t0 = time.perf_counter()
+    lat64, bad64 = [], 0
+    for r, pr in zip(trace, probs):
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        mesh = sdg.make_mesh(pr.nx, pr.ny, pr.k)
+        u = np.empty(pr.nu)
+        p = np.empty(pr.np_)
+        try:
+            rc, _ = sdg.sdg_solve_stokes(ctx, mesh, o_64, pr.eta, np.ascontiguousarray(pr.f.reshape(-1)),
+                                         None, u, p)
+        except sdg.SDGError:
+            rc = -1
+        bad64 += rc not in (0, sdg.FLOOR)
+        lat64.append((time.perf_counter() - t0 - r["t"]) * 1e3)
+    t_64 = time.perf_counter() - t0
+    log(f"[bench] FP64 per-request path: {t_64:.2f} s, p50 {np.percentile(lat64, 50):.1f} ms "
+        f"p99 {np.percentile(lat64, 99):.1f} ms")
+    return {"workload": f"poisson-{rate:g}-per-s-{nreq}-stokes-requests-n32..64-k2..4-rtol1e-8",
+            "server": {"requests_per_s": nreq / t_srv, "latency_ms": pct(lat), "failures": bad,
+                       "cycle_precision": prec, "slots": 4, "max_batch": 16,
+                       "mean_launch_group": float(np.mean(batches)), "peak_bytes": sst["peak_bytes"]},
+            "fp64_per_request": {"requests_per_s": nreq / t_64, "latency_ms": pct(lat64),
+                                 "failures": bad64}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +165,9 @@ def main():
                     help="arithmetic of the fine-level cycle (operator apply and block smoother); "
                          "the Krylov solvers, true residuals and the coarse Q1 hierarchy stay FP64")
     ap.add_argument("--latency-solves", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the serving run (0 = skip)")
+    ap.add_argument("--serve-prec", choices=["fp64", "fp32", "bf16"], default="fp32")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the traced step after the timed region (per-kernel breakdown)")
     args = ap.parse_args()
@@ -267,6 +338,8 @@ def main():
         "roofline": roof,
         "kernels_traced_step": traced,
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(sdg, ctx, args.serve_requests, 200.0, args.serve_prec)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(P0, st["outer_its"])

@@ -100,6 +100,10 @@ typedef struct sdg_options {
   int32_t viscous_krylov; /* 0: CG (paper); 1: FGMRES (needed when the cycle is not exactly linear) */
   int32_t dedup;          /* 1: share block inverses between elements with equal normalised blocks */
   uint64_t seed;          /* stream of the SplitMix64 start vectors of the eigen-estimates */
+  int32_t graphs;         /* 1: each CG iteration after the first replays a captured HIP graph
+                             (V-cycle, updates, operator apply, readback of the scalars); the
+                             arithmetic is that of the launches it replaces.  Off while tracing. */
+  int32_t reserved_;
 } sdg_options;
 
 typedef struct sdg_stats {
@@ -126,7 +130,7 @@ void sdg_destroy(sdg_ctx* ctx);
 const char* sdg_last_error(void);
 /* Default options: rtol 1e-8, inner_rtol 1e-3 (Section 8.1), restart 30,
  * smooth_dg 2, smooth_h 3 (Section 8), coarsest_n 8, eig_steps 10,
- * cheb 0.1/1.1 (Section 6), FP64 everywhere, CG, dedup on, seed 0. */
+ * cheb 0.1/1.1 (Section 6), FP64 everywhere, CG, dedup on, seed 0, graphs on. */
 void sdg_options_default(sdg_options* opts);
 /* Device bytes a problem of this size needs (deterministic; used for
  * admission).  stokes != 0 adds the pressure and FGMRES workspaces. */
@@ -234,6 +238,59 @@ int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts
  * out[i] = 2 * (z_i >> 11) * 2^-53 - 1, z_i the i-th SplitMix64 output of
  * state `seed` (Steele, Lea & Flood 2014). */
 int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, void* stream);
+
+/* ---- request server (continuous batching of solves on one GPU) --------------
+ * A server owns `slots` worker threads, each with its own HIP stream.
+ * sdg_submit copies the request's host inputs (the caller may free them at
+ * once) and queues it.  A free slot takes the oldest queued request whose
+ * device memory (sdg_required_bytes_batch plus its input and output arrays)
+ * fits into what `mem_budget` has left (0 = 90% of the free device memory at
+ * creation), together with queued requests of the identical shape (mesh,
+ * options, kind, Dirichlet data present or not), up to max_batch, which run
+ * as one batched problem.  A request that does not fit may be overtaken by
+ * later ones at most `bypass` times.  Each request's solver state stays on
+ * the device from setup to the copy of its result; requests on different
+ * slots overlap on the device.  Results are those of the same solve alone up
+ * to rounding order (a batch shares element blocks scaled by the viscosity
+ * ratio).  sdg_wait blocks until the request is done, copies u (and p for
+ * Stokes) to the caller's host arrays (either may be NULL) and returns the
+ * solve's status.  sdg_req_free releases a request (also one still
+ * running: it is then freed when it ends).  sdg_server_destroy finishes every
+ * queued request, then stops the workers; requests must be freed by the
+ * caller.  A request larger than the budget is rejected with SDG_ERR_NOMEM. */
+#define SDG_VISCOUS 0
+#define SDG_STOKES 1
+typedef struct sdg_server_config {
+  int32_t slots;     /* concurrent launch groups, 1..64 (default 4) */
+  int32_t max_batch; /* requests per launch group, 1..4096 (default 16) */
+  int32_t bypass;    /* overtakes of a waiting head request (default 8) */
+  int32_t pad_;
+  size_t mem_budget; /* bytes; 0 = 90% of free device memory */
+} sdg_server_config;
+typedef struct sdg_req_info {
+  double submit_ms, start_ms, end_ms; /* steady-clock times (ms) */
+  int32_t batch;                      /* requests in its launch group */
+  int32_t pad_;
+  size_t bytes;                       /* its admission estimate */
+} sdg_req_info;
+typedef struct sdg_server sdg_server;
+typedef struct sdg_req sdg_req;
+void sdg_server_config_default(sdg_server_config* cfg);
+int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** out);
+void sdg_server_destroy(sdg_server* srv);
+int sdg_submit(sdg_server* srv, const sdg_mesh* mesh, const sdg_options* opts, int kind,
+               const double* eta, const double* f, const double* g, sdg_req** out);
+int sdg_poll(sdg_req* req, int* done);
+int sdg_wait(sdg_req* req, double* u, double* p, sdg_stats* stats, sdg_req_info* info);
+void sdg_req_free(sdg_req* req);
+int sdg_server_stats(sdg_server* srv, int64_t* completed, size_t* peak_bytes, int* peak_busy,
+                     size_t* budget);
+/* Host-only run of the same admission policy on a virtual clock: request i
+ * arrives at arrival_ms[i], holds a slot and bytes[i] for service_ms[i];
+ * start_ms[i] receives its start.  No GPU is used (capacity planning, tests). */
+int sdg_admission_simulate(int n, const double* arrival_ms, const double* service_ms,
+                           const size_t* bytes, int slots, size_t budget, int bypass,
+                           double* start_ms);
 
 /* ---- tile shapes of the SIP operator kernels and their autotuner -------------
  * The SIP apply/residual kernels stage TX x TY element tiles in LDS; each

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdg.so")
 SOURCES = ["sip_kernels.hip", "block_kernels.hip", "coarse_kernels.hip", "vec_kernels.hip",
-           "solver.hip"]
+           "solver.hip", "serve.hip", "admission.cpp"]
 ARCH = os.environ.get("SDG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -35,7 +35,7 @@ def hipcc():
 
 
 def _compile(src, verbose):
-    obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -51,7 +51,7 @@ def build(verbose=False, jobs=None):
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")

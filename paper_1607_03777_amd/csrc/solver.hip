@@ -35,6 +35,7 @@
 
 #include "sdg_common.h"
 #include "sdg_kernels.h"
+#include "runtime.h"
 
 // A context is freed when it has been destroyed and its last problem is
 // gone, so problems destroyed after their context stay valid.
@@ -44,6 +45,7 @@ struct sdg_ctx {
   size_t used = 0;
   int live = 0;
   bool closing = false;
+  std::mutex mu;  // used, live, closing (problems may be created and destroyed from several threads)
   // kernel tracing
   struct TraceRec {
     int cls;
@@ -67,6 +69,7 @@ struct sdg_ctx {
 };
 
 namespace sdg {
+int ctx_device(const sdg_ctx* c) { return c ? c->device : 0; }
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 const char* get_error() { return g_err.c_str(); }
@@ -177,6 +180,10 @@ struct sdg_problem {
   std::vector<int> inner_total, inner_max;
   // tile shape of the SIP kernels: [apply, residual][FP64, FP32]
   int tile[2][2] = {{0, 0}, {0, 0}};
+  // captured CG iteration (two graphs: the roles of the two r.z slots alternate)
+  hipStream_t gs = nullptr;  // private stream used only to capture
+  hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
+  double* cg_x = nullptr;  // fixed iterate buffer of the captured iteration
 };
 
 namespace {
@@ -189,20 +196,25 @@ inline double* sc_h(sdg_problem* P) { return P->dsc + (int64_t)SC_H * P->nb; }
 int palloc(sdg_problem* P, void** out, size_t bytes) {
   *out = nullptr;
   if (bytes == 0) return SDG_OK;
-  if (P->ctx->budget && P->ctx->used + bytes > P->ctx->budget) {
-    set_error("device memory budget exceeded");
-    return SDG_ERR_NOMEM;
+  {
+    std::lock_guard<std::mutex> g(P->ctx->mu);
+    if (P->ctx->budget && P->ctx->used + bytes > P->ctx->budget) {
+      set_error("device memory budget exceeded");
+      return SDG_ERR_NOMEM;
+    }
+    P->ctx->used += bytes;  // reserved before the allocation
   }
   hipError_t e = hipMalloc(out, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
     *out = nullptr;
+    std::lock_guard<std::mutex> g(P->ctx->mu);
+    P->ctx->used -= std::min(P->ctx->used, bytes);
     return SDG_ERR_NOMEM;
   }
   P->allocs.push_back(*out);
   P->bytes += bytes;
-  P->ctx->used += bytes;
   return SDG_OK;
 }
 
@@ -447,6 +459,13 @@ int run_sip_residual_f32(sdg_problem* P, const float* b, const float* u, float* 
 }
 std::array<int, 6> tune_key(const sdg_problem* P, int kernel, int prec) {
   return {P->k, P->mesh.nx, P->mesh.ny, P->nb, kernel, prec};
+}
+void drop_graphs(sdg_problem* P) {
+  for (hipGraphExec_t& g : P->cg_graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 double smoother_bytes(const sdg_problem* P, int flags, int w) {
   const int nvec = 2 + !!(flags & BJ_READ_X) + !!(flags & BJ_READ_D) + !!(flags & BJ_WRITE_D);
@@ -790,11 +809,66 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
 // Batched preconditioned CG with x0 = 0; problem pb stops when
 // ||r||_2 < rtol ||b||_2 (unpreconditioned, recursively updated residual).
 // status[pb]: SDG_OK, SDG_NOT_CONVERGED or SDG_BREAKDOWN.
-int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit, std::vector<int>& its,
+// The part of a CG iteration between two readbacks of the scalars: the
+// V-cycle z = B r, r.z, p = z + beta p, q = A p, p.q, the x/r update and
+// ||r||^2, then the copy of (p.q, ||r||^2) to the pinned mirror.  rzA holds
+// the previous r.z, rzB receives the new one.
+int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
+  const int nb = P->nb;
+  const int64_t n = P->nu;
+  SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
+  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rzB, P->red, P->s));
+  SDG_TRY(cg_update2(n, nb, P->cg_z, P->cg_p, rzB, rzA, P->active, P->s));
+  SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
+  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
+  SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
+                     P->s));
+  SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
+  return SDG_OK;
+}
+
+// Captures cg_body (on the fixed iterate buffer) as a graph, once per parity.
+int cg_graph(sdg_problem* P, int parity, hipGraphExec_t* out) {
+  if (P->cg_graph[parity]) {
+    *out = P->cg_graph[parity];
+    return SDG_OK;
+  }
+  if (!P->gs) SDG_HIP(hipStreamCreateWithFlags(&P->gs, hipStreamNonBlocking));
+  double* rz = sc(P, SC_RZ);
+  double* rz2 = sc(P, SC_RZ2);
+  hipStream_t user = P->s;
+  P->s = P->gs;
+  hipGraph_t g = nullptr;
+  int rc = SDG_OK;
+  if (hipStreamBeginCapture(P->gs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = SDG_ERR_DEVICE;
+  } else {
+    rc = parity == 0 ? cg_body(P, P->cg_x, rz, rz2) : cg_body(P, P->cg_x, rz2, rz);
+    if (hipStreamEndCapture(P->gs, &g) != hipSuccess && rc >= 0) rc = SDG_ERR_DEVICE;
+  }
+  P->s = user;
+  if (rc >= 0 && hipGraphInstantiate(&P->cg_graph[parity], g, nullptr, nullptr, 0) != hipSuccess) {
+    P->cg_graph[parity] = nullptr;
+    rc = SDG_ERR_DEVICE;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (rc < 0) {
+    (void)hipGetLastError();
+    set_error("capture of the CG iteration as a HIP graph failed");
+    return rc;
+  }
+  *out = P->cg_graph[parity];
+  return SDG_OK;
+}
+
+int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int maxit, std::vector<int>& its,
              std::vector<double>& rel, std::vector<int>& status) {
   const int nb = P->nb;
   const int64_t n = P->nu;
   const VSpec S = viscous_spec(P);
+  // replayed iterations work on a fixed iterate buffer (graph arguments)
+  const bool graphs = P->opt.graphs && !P->ctx->trace;
+  double* x = graphs ? P->cg_x : x_out;
   std::vector<double> bn;
   SDG_TRY(vs_norms(P, S, b, bn));
   SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
@@ -814,7 +888,10 @@ int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit,
       ++nact;
     }
   }
-  if (nact == 0) return SDG_OK;
+  if (nact == 0) {
+    if (graphs) SDG_TRY(vec_copy(S.total, x, x_out, P->s));
+    return SDG_OK;
+  }
   SDG_TRY(upload_active(P, act));
   SDG_TRY(vec_copy(S.total, b, P->cg_r, P->s));
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
@@ -822,14 +899,15 @@ int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit,
   double* rz = sc(P, SC_RZ);
   double* rz2 = sc(P, SC_RZ2);
   SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz, P->red, P->s));
+  // first iteration: q = A p, p.q, update, readback
+  SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
+  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
+  SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
+                     P->s));
+  SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
   std::vector<double> rr(nb), pq(nb);
+  int parity = 0;  // 0: rz holds the current r.z; 1: rz2 does
   for (int it = 0; it < maxit && nact > 0; ++it) {
-    SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
-    SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
-    SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
-                       P->s));
-    // one readback per iteration: p.q and ||r||^2 of every problem (adjacent slots)
-    SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
     SDG_HIP(hipStreamSynchronize(P->s));
     std::memcpy(pq.data(), P->hsc, nb * sizeof(double));
     std::memcpy(rr.data(), P->hsc + nb, nb * sizeof(double));
@@ -859,11 +937,17 @@ int cg_solve(sdg_problem* P, const double* b, double* x, double rtol, int maxit,
     }
     if (nact == 0 || it + 1 >= maxit) break;
     if (changed) SDG_TRY(upload_active(P, act));
-    SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
-    SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz2, P->red, P->s));
-    SDG_TRY(cg_update2(n, nb, P->cg_z, P->cg_p, rz2, rz, P->active, P->s));
-    std::swap(rz, rz2);
+    if (graphs) {
+      hipGraphExec_t ge = nullptr;
+      SDG_TRY(cg_graph(P, parity, &ge));
+      SDG_HIP(hipGraphLaunch(ge, P->s));
+    } else {
+      SDG_TRY(parity == 0 ? cg_body(P, x, rz, rz2) : cg_body(P, x, rz2, rz));
+    }
+    parity ^= 1;
   }
+  SDG_HIP(hipStreamSynchronize(P->s));
+  if (graphs) SDG_TRY(vec_copy(S.total, x, x_out, P->s));
   return SDG_OK;
 }
 
@@ -1125,6 +1209,7 @@ void sdg_options_default(sdg_options* o) {
   o->viscous_krylov = 0;
   o->dedup = 1;
   o->seed = 0;
+  o->graphs = 1;
 }
 
 int sdg_create(int device, size_t mem_budget, sdg_ctx** out) {
@@ -1149,8 +1234,13 @@ int sdg_create(int device, size_t mem_budget, sdg_ctx** out) {
 
 void sdg_destroy(sdg_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->live == 0) delete ctx;
-  else ctx->closing = true;
+  bool del;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    del = ctx->live == 0;
+    ctx->closing = true;
+  }
+  if (del) delete ctx;
 }
 
 static bool opts_ok(const sdg_options* o) {
@@ -1240,7 +1330,10 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   const double t0 = now_ms();
   sdg_problem* P = new sdg_problem();
   P->ctx = ctx;
-  ctx->live++;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->live++;
+  }
   P->mesh = *mesh;
   P->opt = o;
   P->s = (hipStream_t)stream;
@@ -1299,7 +1392,7 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   if ((rc = setup_blocks(P)) < 0) return fail(rc);
   if ((rc = setup_coarse(P)) < 0) return fail(rc);
   const int64_t U = P->nu * nbatch;
-  for (double** v : {&P->vr, &P->vd, &P->cg_r, &P->cg_z, &P->cg_p, &P->cg_q})
+  for (double** v : {&P->vr, &P->vd, &P->cg_r, &P->cg_z, &P->cg_p, &P->cg_q, &P->cg_x})
     if ((rc = palloc_t(P, v, U)) < 0) return fail(rc);
   if (low_precision(P))
     for (float** v : {&P->fb, &P->fx, &P->fr, &P->fd})
@@ -1353,12 +1446,19 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
 void sdg_problem_destroy(sdg_problem* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->s);
+  drop_graphs(P);
+  if (P->gs) (void)hipStreamDestroy(P->gs);
   for (void* p : P->allocs) (void)hipFree(p);
   if (P->hsc) (void)hipHostFree(P->hsc);
   if (sdg_ctx* c = P->ctx) {
-    c->used -= std::min(c->used, P->bytes);
-    c->live--;
-    if (c->closing && c->live == 0) delete c;
+    bool del;
+    {
+      std::lock_guard<std::mutex> g(c->mu);
+      c->used -= std::min(c->used, P->bytes);
+      c->live--;
+      del = c->closing && c->live == 0;
+    }
+    if (del) delete c;
   }
   delete P;
 }
@@ -1695,6 +1795,7 @@ int sdg_set_tile(sdg_problem* P, int kernel, int precision, int variant) {
     return SDG_ERR_INVALID;
   }
   P->tile[kernel][precision == SDG_FP64 ? 0 : 1] = variant;
+  drop_graphs(P);
   return SDG_OK;
 }
 
@@ -1752,6 +1853,7 @@ int sdg_autotune(sdg_problem* P, int reps, int* variants, double* us) {
       }
       if (rc < 0) break;
       P->tile[kern][pr] = bestv;
+      drop_graphs(P);
       if (variants) variants[kern * 2 + pr] = bestv;
       if (us) us[kern * 2 + pr] = best;
       std::lock_guard<std::mutex> g(g_tune_mu);

@@ -32,7 +32,8 @@ class sdg_options(ctypes.Structure):
                 ("eig_steps", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("prec_smoother", ctypes.c_int32),
                 ("prec_apply", ctypes.c_int32), ("viscous_krylov", ctypes.c_int32),
-                ("dedup", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("dedup", ctypes.c_int32), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
 
 class sdg_stats(ctypes.Structure):
@@ -45,6 +46,21 @@ class sdg_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class sdg_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("bypass", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]
+
+
+class sdg_req_info(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("end_ms", ctypes.c_double), ("batch", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+VISCOUS, STOKES = 0, 1
 P = ctypes.c_void_p
 PP = ctypes.POINTER(ctypes.c_void_p)
 I = ctypes.c_int
@@ -89,6 +105,16 @@ PROTOTYPES = {
     "sdg_tile_shape": (I, [I, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
     "sdg_set_tile": (I, [P, I, I, I]),
     "sdg_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]),
+    "sdg_server_config_default": (None, [ctypes.POINTER(sdg_server_config)]),
+    "sdg_server_create": (I, [P, ctypes.POINTER(sdg_server_config), PP]),
+    "sdg_server_destroy": (None, [P]),
+    "sdg_submit": (I, [P, MESH, OPTS, I, P, P, P, PP]),
+    "sdg_poll": (I, [P, ctypes.POINTER(I)]),
+    "sdg_wait": (I, [P, P, P, STATS, ctypes.POINTER(sdg_req_info)]),
+    "sdg_req_free": (None, [P]),
+    "sdg_server_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
+                             ctypes.POINTER(I), ctypes.POINTER(ctypes.c_size_t)]),
+    "sdg_admission_simulate": (I, [I, P, P, P, I, ctypes.c_size_t, I, P]),
     "sdg_trace_enable": (I, [P, I]),
     "sdg_trace_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
@@ -327,6 +353,71 @@ def sdg_solve_stokes(ctx, mesh, opts, eta, f, g, u, p):
 
 def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
     return check(lib().sdg_uniform_pm1(ctx, ctypes.c_uint64(seed), n, ptr(out), stream))
+
+
+# ---- request server ------------------------------------------------------------
+def sdg_server_create(ctx, slots=4, max_batch=16, bypass=8, mem_budget=0):
+    cfg = sdg_server_config(slots, max_batch, bypass, 0, mem_budget)
+    h = ctypes.c_void_p()
+    check(lib().sdg_server_create(ctx, ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def sdg_server_destroy(srv):
+    lib().sdg_server_destroy(srv)
+
+
+def _host(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sdg_submit(srv, mesh, opts, kind, eta, f, g=None):
+    """Host numpy inputs (copied by the library); returns a request handle."""
+    eta, f, g = _host(eta), _host(f), _host(g)
+    h = ctypes.c_void_p()
+    check(lib().sdg_submit(srv, ctypes.byref(mesh), ctypes.byref(opts), kind, eta.ctypes.data,
+                           f.ctypes.data, None if g is None else g.ctypes.data, ctypes.byref(h)))
+    return h.value
+
+
+def sdg_poll(req):
+    d = I()
+    check(lib().sdg_poll(req, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def sdg_wait(req, nu, np_=0):
+    """-> (rc, u, p, stats dict, info dict); blocks until the request is done."""
+    u = np.empty(nu)
+    p = np.empty(max(np_, 0)) if np_ else None
+    st = sdg_stats()
+    info = sdg_req_info()
+    rc = check(lib().sdg_wait(req, u.ctypes.data, None if p is None else p.ctypes.data,
+                              ctypes.byref(st), ctypes.byref(info)))
+    return rc, u, p, st.as_dict(), info.as_dict()
+
+
+def sdg_req_free(req):
+    lib().sdg_req_free(req)
+
+
+def sdg_server_stats(srv):
+    c = ctypes.c_int64()
+    pb = ctypes.c_size_t()
+    busy = I()
+    bud = ctypes.c_size_t()
+    check(lib().sdg_server_stats(srv, ctypes.byref(c), ctypes.byref(pb), ctypes.byref(busy), ctypes.byref(bud)))
+    return {"completed": c.value, "peak_bytes": pb.value, "peak_busy": busy.value, "budget": bud.value}
+
+
+def sdg_admission_simulate(arrival_ms, service_ms, nbytes, slots, budget, bypass):
+    a = np.ascontiguousarray(arrival_ms, dtype=np.float64)
+    sv = np.ascontiguousarray(service_ms, dtype=np.float64)
+    by = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    out = np.empty(len(a))
+    check(lib().sdg_admission_simulate(len(a), a.ctypes.data, sv.ctypes.data, by.ctypes.data, slots,
+                                       int(budget), bypass, out.ctypes.data))
+    return out
 
 
 TILE_APPLY, TILE_RESIDUAL = 0, 1

@@ -51,6 +51,8 @@ int main(void) {
          offsetof(sdg_options, cheb_lo));
   printf("%zu %zu %zu\\n", offsetof(sdg_options, prec_smoother), offsetof(sdg_options, seed),
          offsetof(sdg_stats, rel_residual));
+  printf("%zu %zu %zu %zu\\n", sizeof(sdg_server_config), offsetof(sdg_server_config, mem_budget),
+         sizeof(sdg_req_info), offsetof(sdg_req_info, bytes));
   return 0;
 }
 """)
@@ -61,7 +63,9 @@ int main(void) {
     py = [ctypes.sizeof(sdg.sdg_mesh), ctypes.sizeof(sdg.sdg_options), ctypes.sizeof(sdg.sdg_stats),
           sdg.sdg_mesh.lx.offset, sdg.sdg_mesh.k.offset, sdg.sdg_mesh.bc.offset,
           sdg.sdg_options.cheb_lo.offset, sdg.sdg_options.prec_smoother.offset,
-          sdg.sdg_options.seed.offset, sdg.sdg_stats.rel_residual.offset]
+          sdg.sdg_options.seed.offset, sdg.sdg_stats.rel_residual.offset,
+          ctypes.sizeof(sdg.sdg_server_config), sdg.sdg_server_config.mem_budget.offset,
+          ctypes.sizeof(sdg.sdg_req_info), sdg.sdg_req_info.bytes.offset]
     assert vals == py
 
 
