@@ -153,6 +153,51 @@ def serving(sdg, ctx, nreq, rate, prec):
                                  "failures": bad64}}
 
 
+def kernel_probe(sdg, ctx, torch, B, reps):
+    """Only the operator kernels at the step's shape (batch B of the 64 x 64,
+    k = 4 problem): `reps` launches each of the SIP residual and apply, then
+    `reps` plain device copies of the residual's vector (known bytes) that
+    calibrate the HBM counters.  For rocprofv3 counter runs."""
+    from paper_1607_03777_amd import inputs as gen
+    P0 = gen.single_inclusion(N, K, eta_in=ETA_IN)
+    nel, nb = N * N, 2 * (K + 1) ** 2
+    eta = torch.as_tensor(P0.eta, device="cuda").repeat(B)
+    h = sdg.sdg_problem_create_batch(ctx, sdg.make_mesh(N, N, K), sdg.make_options(), B, eta,
+                                     sdg.current_stream())
+    u = torch.randn(B * nel * nb, dtype=torch.float64, device="cuda")
+    b = torch.randn_like(u)
+    r = torch.empty_like(u)
+    for _ in range(reps):
+        sdg.sdg_residual_viscous(h, b, u, r)
+    for _ in range(reps):
+        sdg.sdg_apply_viscous(h, u, r)
+    for _ in range(reps):
+        torch.neg(u, out=r)  # plain elementwise copy: reads and writes one vector
+    torch.cuda.synchronize()
+    sdg.sdg_problem_destroy(h)
+    print(json.dumps({"kernel_probe": {"batch": B, "reps": reps, "vector_bytes": u.numel() * 8,
+                                       "residual_bytes": B * nel * (3 * nb * 8 + 8),
+                                       "apply_bytes": B * nel * (2 * nb * 8 + 8)}}), flush=True)
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "sip_k4_batch16_hbm_traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    k = rec["kernels"].get(kernel)
+    return k["traffic_bytes"] if k else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +210,8 @@ def main():
                     help="arithmetic of the fine-level cycle (operator apply and block smoother); "
                          "the Krylov solvers, true residuals and the coarse Q1 hierarchy stay FP64")
     ap.add_argument("--latency-solves", type=int, default=5)
+    ap.add_argument("--kernel-probe", type=int, default=0,
+                    help="only launch the operator kernels this many times (counter runs)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-prec", choices=["fp64", "fp32", "bf16"], default="fp32")
@@ -183,6 +230,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     ctx = sdg.sdg_create(0, 0)
+    if args.kernel_probe:
+        kernel_probe(sdg, ctx, torch, args.batch, args.kernel_probe)
+        sdg.sdg_destroy(ctx)
+        return
     P0 = gen.single_inclusion(N, K, eta_in=ETA_IN)
     nel = N * N
     nb = 2 * (K + 1) ** 2
@@ -278,9 +329,9 @@ def main():
     # roofline of the dominant kernel: the traced class with the largest
     # time in the traced step, launched back to back at the step's shape
     # (batch B) between two HIP events on the problem's stream
-    kernel_names = {"sip_apply": f"sip_tile_kernel<{K + 1},apply>",
-                    "sip_residual": f"sip_tile_kernel<{K + 1},residual>",
-                    "block_jacobi_smoother": f"bj_group_kernel<{K + 1}>"}
+    kernel_names = {"sip_apply": f"sip_tile_kernel<{K + 1},apply,double,8,4>",
+                    "sip_residual": f"sip_tile_kernel<{K + 1},residual,double,8,4>",
+                    "block_jacobi_smoother": f"bj_group_kernel<{K + 1},double,double,false>"}
     cand = {k: v for k, v in traced.items() if v["bytes_per_launch"] > 0}
     dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else "sip_residual"
     h = sdg.sdg_problem_create_batch(ctx, mesh, opts, B, eta, stream)
@@ -303,7 +354,8 @@ def main():
     log(f"[bench] dominant kernel {kernel_names[dom]}: {t_dom:.2f} us/launch, {gbs:.0f} GB/s; "
         f"sip apply {t_app:.2f} us")
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": kernel_names[dom],
+            "frac": gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(kernel_names[dom]),
+            "kernel": kernel_names[dom],
             "algorithmic_bytes": what, "bytes_per_launch": nbytes, "us_per_launch": t_dom,
             "launches_timed": max(args.kernel_reps, 20)}
 
