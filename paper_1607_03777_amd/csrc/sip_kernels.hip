@@ -32,11 +32,11 @@ namespace sdg {
 
 // Tile shapes (TX x TY elements per workgroup) per K1; variant 0 is the
 // default, the others are candidates for the autotuner.
-constexpr int TILE_NV[8] = {0, 0, 3, 3, 3, 4, 3, 3};
-constexpr int TILE_TX[8][4] = {{0}, {0}, {16, 8, 16, 0}, {8, 16, 8, 0}, {8, 8, 4, 0},
-                               {8, 4, 16, 8}, {4, 8, 4, 0}, {4, 4, 2, 0}};
-constexpr int TILE_TY[8][4] = {{0}, {0}, {8, 8, 4, 0}, {8, 4, 4, 0}, {4, 8, 4, 0},
-                               {4, 4, 2, 2}, {4, 2, 2, 0}, {4, 2, 2, 0}};
+constexpr int TILE_NV[8] = {0, 0, 4, 4, 4, 4, 4, 4};
+constexpr int TILE_TX[8][4] = {{0}, {0}, {8, 16, 8, 16}, {8, 8, 16, 4}, {4, 8, 8, 4},
+                               {4, 8, 8, 4}, {4, 4, 8, 2}, {4, 4, 2, 2}};
+constexpr int TILE_TY[8][4] = {{0}, {0}, {8, 4, 4, 8}, {4, 8, 4, 4}, {4, 4, 2, 2},
+                               {4, 2, 4, 2}, {2, 4, 2, 2}, {2, 4, 2, 4}};
 template <int K1> struct Tile {
   static constexpr int TX = TILE_TX[K1][0], TY = TILE_TY[K1][0];
 };
@@ -164,6 +164,79 @@ __device__ void face_coefs(T* f, int kind, int side, T etam, T etap, T hn, T ht,
       interior_coefs<K1, DIR, T>(z, z, tp, gp, T(0), eta2, alpha, hn, ht, f, 2);
   } else {
     zero_sides<K1, T>(f, 3);
+  }
+}
+
+// Coefficients of mode m of one face (the tile kernel's face phase: one
+// thread per face and mode).  f holds the face's traces; sdm the derivative
+// matrix D(m, i) (zero off its pattern).  o[(s * 2 + d) * 2 + w] receives
+// a (w = 0) and b (w = 1) of side s, component d; the same formulas as
+// face_coefs, written for a runtime mode index.
+template <int K1, int DIR, typename T>
+__device__ __forceinline__ void face_mode(const T* __restrict__ f, int m, int kind, int side, T etam, T etap,
+                                          T hn, T ht, bool isolate, bool skip_interior,
+                                          const T* __restrict__ sdm, T (&o)[8]) {
+  constexpr int N = DIR, TT = 1 - DIR;
+#pragma unroll
+  for (int z = 0; z < 8; ++z) o[z] = T(0);
+  if (kind < 0 || kind == F_NEUMANN || (kind == F_INTERIOR && skip_interior)) return;
+  const T kk = T(K1 * K1);
+  const T c2n = T(2) / hn, c2t = T(2) / ht;
+  auto at = [&](int s, int d, int w, int j) { return f[((s * 2 + d) * 2 + w) * K1 + j]; };
+  if (kind == F_NAVIER) {
+    const T eta = side == 0 ? etam : etap;
+    const T alpha = T(8) * eta * kk / hn;
+    const T sgn = side == 0 ? T(1) : T(-1);
+    const T w = T(4) * eta / hn;
+    const T t = at(side, N, 0, m), g = at(side, N, 1, m);
+    o[(side * 2 + N) * 2 + 0] = c2n * (alpha * t - sgn * w * g);
+    o[(side * 2 + N) * 2 + 1] = -c2n * sgn * w * t;
+    return;
+  }
+  // interior-type face: mm/mp switch the minus/plus traces on or off,
+  // `sides` selects the outputs kept
+  auto core = [&](T mm, T mp, T em, T ep, T alpha, int sides) {
+    T dtm = 0, dtp = 0, dtj = 0;
+    for (int j = m + 1; j < K1; j += 2) {
+      const T c = sdm[m * K1 + j];
+      dtm += c * (mm * at(0, N, 0, j));
+      dtp += c * (mp * at(1, N, 0, j));
+    }
+    for (int j = (m & 1) ^ 1; j < m; j += 2)
+      dtj += sdm[j * K1 + m] * (mm * at(0, TT, 0, j) - mp * at(1, TT, 0, j));
+    const T jn = mm * at(0, N, 0, m) - mp * at(1, N, 0, m);
+    const T jt = mm * at(0, TT, 0, m) - mp * at(1, TT, 0, m);
+    const T sn = c2n * (em * (mm * at(0, N, 1, m)) + ep * (mp * at(1, N, 1, m)));
+    const T st = T(0.5) * (c2t * (em * dtm + ep * dtp) +
+                           c2n * (em * (mm * at(0, TT, 1, m)) + ep * (mp * at(1, TT, 1, m))));
+    const T qn = -sn + alpha * jn;
+    const T qt = -st + alpha * jt;
+    if (sides & 1) {
+      o[(0 * 2 + N) * 2 + 0] = c2n * (qn - em / ht * dtj);
+      o[(0 * 2 + N) * 2 + 1] = -c2n * c2n * em * jn;
+      o[(0 * 2 + TT) * 2 + 0] = c2n * qt;
+      o[(0 * 2 + TT) * 2 + 1] = -c2n / hn * em * jt;
+    }
+    if (sides & 2) {
+      o[(1 * 2 + N) * 2 + 0] = -c2n * (qn + ep / ht * dtj);
+      o[(1 * 2 + N) * 2 + 1] = -c2n * c2n * ep * jn;
+      o[(1 * 2 + TT) * 2 + 0] = -c2n * qt;
+      o[(1 * 2 + TT) * 2 + 1] = -c2n / hn * ep * jt;
+    }
+  };
+  if (kind == F_INTERIOR) {
+    const T alpha = T(4) * (etam > etap ? etam : etap) * kk / hn;
+    if (!isolate) {
+      core(T(1), T(1), etam, etap, alpha, 3);
+    } else {
+      core(T(1), T(0), etam, etap, alpha, 1);
+      core(T(0), T(1), etam, etap, alpha, 2);
+    }
+  } else {  // Dirichlet: zero outer trace, the present side's viscosity counted twice
+    const T eta2 = T(2) * (side == 0 ? etam : etap);
+    const T alpha = T(4) * eta2 * kk / hn;
+    if (side == 0) core(T(1), T(0), eta2, T(0), alpha, 1);
+    else core(T(0), T(1), T(0), eta2, alpha, 2);
   }
 }
 
@@ -342,42 +415,57 @@ __global__ __launch_bounds__(NT, (K1 >= 7 ? 3 : 1)) void sip_tile_kernel(MeshDev
   }
   __syncthreads();
 
-  // ---- S2: one thread per face: traces -> coefficients (in place)
-  for (int q = tid; q < NFV + NFH; q += NT) {
-    T* f = sf + q * FS;
-    if (q < NFV) {
-      const int ty = q / (TX + 1), fx = q % (TX + 1);
-      const int iy = iy0 + ty, ixm = ix0 + fx - 1, ixp = ix0 + fx;
-      const bool pm = (ixm >= 0 && ixm < nx), pp = (ixp < nx);
-      int kind = -1, side = 0;
-      if (iy < ny) {
-        if (pm && pp) kind = F_INTERIOR;
-        else if (!pm && pp) { kind = M.bc[0]; side = 1; }
-        else if (pm && ixp == nx) { kind = M.bc[1]; side = 0; }
+  // ---- S2: one thread per face and mode: traces -> coefficients.  All
+  // items read their traces before any item overwrites them in place.
+  {
+    constexpr int NF = NFV + NFH, NITEM = NF * K1, NIT = (NITEM + NT - 1) / NT;
+    T ov[NIT][8];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int q = it * NT + tid;
+#pragma unroll
+      for (int z = 0; z < 8; ++z) ov[it][z] = T(0);
+      if (q >= NITEM) continue;
+      const int fq = q / K1, m = q - fq * K1;
+      const T* f = sf + fq * FS;
+      if (fq < NFV) {
+        const int ty = fq / (TX + 1), fx = fq - ty * (TX + 1);
+        const int iy = iy0 + ty, ixm = ix0 + fx - 1, ixp = ix0 + fx;
+        const bool pm = (ixm >= 0 && ixm < nx), pp = (ixp < nx);
+        int kind = -1, side = 0;
+        if (iy < ny) {
+          if (pm && pp) kind = F_INTERIOR;
+          else if (!pm && pp) { kind = M.bc[0]; side = 1; }
+          else if (pm && ixp == nx) { kind = M.bc[1]; side = 0; }
+        }
+        const T em = seta[(ty + 1) * EW + fx], ep = seta[(ty + 1) * EW + fx + 1];
+        face_mode<K1, 0, T>(f, m, kind, side, em, ep, hx, hy, MODE == M_BLOCKCOL, MODE == M_COARSECOL, sdm,
+                            ov[it]);
+      } else {
+        const int qq = fq - NFV;
+        const int fy = qq / TX, tx = qq - fy * TX;
+        const int ix = ix0 + tx, iym = iy0 + fy - 1, iyp = iy0 + fy;
+        const bool pm = (iym >= 0 && iym < ny), pp = (iyp < ny);
+        int kind = -1, side = 0;
+        if (ix < nx) {
+          if (pm && pp) kind = F_INTERIOR;
+          else if (!pm && pp) { kind = M.bc[2]; side = 1; }
+          else if (pm && iyp == ny) { kind = M.bc[3]; side = 0; }
+        }
+        const T em = seta[fy * EW + tx + 1], ep = seta[(fy + 1) * EW + tx + 1];
+        face_mode<K1, 1, T>(f, m, kind, side, em, ep, hy, hx, MODE == M_BLOCKCOL, MODE == M_COARSECOL, sdm,
+                            ov[it]);
       }
-      if (kind < 0) {
-        for (int z = 0; z < FW; ++z) f[z] = T(0);
-        continue;
-      }
-      const T em = seta[(ty + 1) * EW + fx], ep = seta[(ty + 1) * EW + fx + 1];
-      face_coefs<K1, 0, T>(f, kind, side, em, ep, hx, hy, MODE == M_BLOCKCOL, MODE == M_COARSECOL);
-    } else {
-      const int qq = q - NFV;
-      const int fy = qq / TX, tx = qq % TX;
-      const int ix = ix0 + tx, iym = iy0 + fy - 1, iyp = iy0 + fy;
-      const bool pm = (iym >= 0 && iym < ny), pp = (iyp < ny);
-      int kind = -1, side = 0;
-      if (ix < nx) {
-        if (pm && pp) kind = F_INTERIOR;
-        else if (!pm && pp) { kind = M.bc[2]; side = 1; }
-        else if (pm && iyp == ny) { kind = M.bc[3]; side = 0; }
-      }
-      if (kind < 0) {
-        for (int z = 0; z < FW; ++z) f[z] = T(0);
-        continue;
-      }
-      const T em = seta[fy * EW + tx + 1], ep = seta[(fy + 1) * EW + tx + 1];
-      face_coefs<K1, 1, T>(f, kind, side, em, ep, hy, hx, MODE == M_BLOCKCOL, MODE == M_COARSECOL);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int q = it * NT + tid;
+      if (q >= NITEM) continue;
+      const int fq = q / K1, m = q - fq * K1;
+      T* f = sf + fq * FS;
+#pragma unroll
+      for (int z = 0; z < 8; ++z) f[z * K1 + m] = ov[it][z];
     }
   }
   __syncthreads();

@@ -83,7 +83,6 @@ def test_apply_parity(sdg, ctx, torch, k, bci):
     u = rng.normal(size=m.nu)
     P = make_problem(sdg, ctx, nx, ny, k, eta, bc)
     b = rng.normal(size=m.nu)
-    first = None
     # every tile shape of the kernels (the mesh leaves ragged tiles for each)
     for var in range(sdg.sdg_tile_variants(k)):
         print(f"[case] tile variant {var} {sdg.sdg_tile_shape(k, var)}", flush=True)
@@ -105,14 +104,6 @@ def test_apply_parity(sdg, ctx, torch, k, bci):
         torch.cuda.synchronize()
         u32 = u.astype(np.float32).astype(np.float64)
         assert_close_componentwise(host(y32).astype(np.float64), A @ u32, abs_bound(A, u32), 6e-7 * 64)
-        # the tile shape changes which elements share a workgroup, not the
-        # arithmetic of any element: outputs are bit-identical
-        outs = (host(y), host(r), host(y32))
-        if first is None:
-            first = outs
-        else:
-            for a, c in zip(outs, first):
-                assert np.array_equal(a, c)
     P.close()
 
 
