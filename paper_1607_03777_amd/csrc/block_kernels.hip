@@ -10,9 +10,10 @@
 // unique block and s_e = eta_rep / eta_e rescales a shared block to the
 // element (blocks with equal face kinds and neighbour viscosity ratios are
 // equal up to the factor eta_K).  Elements are grouped by id_e, so the apply
-// is a small dense product Binv * [r_e1 ... r_eG] per group: one workgroup
-// stages the block and G residual columns in LDS and each thread holds a
-// 4 x 4 register tile of the result.
+// is a small dense product Binv * [r_e1 ... r_eG] per group.  FP64: one
+// wavefront per group of 16 on the matrix cores (FP64 MFMA), fragments read
+// straight from L1/L2 and HBM.  Factored FP32/BF16: one workgroup stages the
+// factor and the residual columns in LDS, 4 x 4 register tiles per thread.
 #include "sdg_common.h"
 #include "sdg_kernels.h"
 
@@ -373,23 +374,117 @@ __global__ __launch_bounds__(256) void bj_group_kernel(BjArgs<TM, TV> A) {
   }
 }
 
-int bj_group_size(int nb) {
+int bj_group_size(int nb, bool full_f64) {
+  if (full_f64) return 16;  // one wavefront's matrix-core columns
   const int nag = ((nb + 3) & ~3) / 4;
   return 4 * (256 / nag);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// FP64 full inverse, one wavefront per work item of up to 16 NG elements, no
+// LDS and no barriers.  Lane (c, kq) = (lane % 16, lane / 16) gathers the
+// residual fragments of elements c + 16 g (rows 4s + kq: 32 contiguous bytes
+// per element across the four lane groups); each block fragment, read from
+// L1/L2 (a block is shared by many work items), feeds NG products; the update
+// reads and writes the rows of the accumulator fragments
+// (D[16t + 4r + kq][c]).  Waves are independent, so the latency of one hides
+// behind the others.
+// ---------------------------------------------------------------------------
+template <int K1, int NG>
+__global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
+  constexpr int NB = 2 * K1 * K1, KP = (NB + 3) & ~3, NT = (NB + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwork) return;
+  const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  const int c = lane & 15, kq = lane >> 4;
+  int64_t ge[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) ge[g] = (c + 16 * g < cnt) ? A.perm[start + c + 16 * g] : -1;
+  const double* B = A.mat + (int64_t)uid * NB * NB;
+  const int flags = A.flags;
+  // operands of the update, fetched ahead of the product
+  double xo[NG][NT][4], dold[NG][NT][4];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * tt + 4 * r + kq;
+        const bool ok = ge[g] >= 0 && i < NB;
+        xo[g][tt][r] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? A.x[ge[g] * NB + i] : 0.0;
+        dold[g][tt][r] = (ok && (flags & BJ_READ_D)) ? A.d[ge[g] * NB + i] : 0.0;
+      }
+  v4d acc[NG][NT];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[g][tt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int s4 = 0; s4 < KP; s4 += 4) {
+    const int k = s4 + kq;
+    double bv[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) bv[g] = (ge[g] >= 0 && k < NB) ? A.r[ge[g] * NB + k] : 0.0;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int i = 16 * tt + c;
+      // A[i][k] = B[k][i] (the block is symmetric)
+      const double a = (k < NB && i < NB) ? B[k * NB + i] : 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[g][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[g], acc[g][tt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (ge[g] < 0) continue;
+    const double sc = A.scale[ge[g]];
+    double* xx = A.x + ge[g] * NB;
+    double* dd = A.d + ge[g] * NB;
+    double ca = 0.0, cb = 1.0;
+    if (!(flags & BJ_APPLY)) {
+      const int64_t pb = ge[g] / A.nel;
+      ca = A.ab[2 * pb];
+      cb = A.ab[2 * pb + 1];
+    }
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * tt + 4 * r + kq;
+        if (i >= NB) continue;
+        const double z = acc[g][tt][r] * sc;
+        if (flags & BJ_APPLY) {
+          xx[i] = z;
+          continue;
+        }
+        double dv = cb * z;
+        if (flags & BJ_READ_D) dv += ca * dold[g][tt][r];
+        if (flags & BJ_FOLD) dv += ca * xo[g][tt][r];
+        if (flags & BJ_WRITE_D) dd[i] = dv;
+        xx[i] = (flags & BJ_READ_X) ? xo[g][tt][r] + dv : dv;
+      }
+  }
 }
 
 template <int K1, typename TM, typename TV, bool TRI>
 static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                      hipStream_t s) {
   BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
-  hipLaunchKernelGGL((bj_group_kernel<K1, TM, TV, TRI>), dim3(P.nwork), dim3(256), 0, s, A);
+  if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
+    hipLaunchKernelGGL((bj_wave_kernel<K1, 1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+  else
+    hipLaunchKernelGGL((bj_group_kernel<K1, TM, TV, TRI>), dim3(P.nwork), dim3(256), 0, s, A);
 }
 
 template <typename TM, typename TV, bool TRI>
 static int launch_group(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                         hipStream_t s) {
   if (P.nwork <= 0) return SDG_OK;
-  if (P.G < 4 || P.G % 4 || P.G > bj_group_size(P.nb)) {
+  if (P.G < 4 || P.G % 4 || P.G > bj_group_size(P.nb, !TRI && sizeof(TM) == 8 && sizeof(TV) == 8)) {
     set_error("block smoother: group size does not fit one workgroup");
     return SDG_ERR_INVALID;
   }

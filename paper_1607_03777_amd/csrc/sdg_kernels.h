@@ -37,8 +37,8 @@ int rhs_assemble(const MeshDev& M, int k, int nbatch, const double* eta, const d
 // packed (optional): also store X = L^{-1} as packed lower triangles
 int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, double* packed = nullptr);
 // Grouped block-Jacobi apply.  Elements perm[start .. start+count) of work
-// item w = work[3w .. 3w+2] = (uid, start, count) share block uid; G columns
-// per workgroup at most (bj_group_size).  scale[ge] = eta_rep / eta_ge;
+// item w = work[3w .. 3w+2] = (uid, start, count) share block uid; G
+// elements per work item at most (bj_group_size).  scale[ge] = eta_rep / eta_ge;
 // ab[pb] = Chebyshev coefficients of problem pb = ge / nel.
 struct BjPlan {
   int nb, G, nwork, nel;
@@ -46,8 +46,10 @@ struct BjPlan {
   const int* work;
   const double* scale;
 };
-// largest G for an element block of nb unknowns
-int bj_group_size(int nb);
+// largest G for an element block of nb unknowns: the FP64 full-inverse form
+// (one wavefront per work item on the matrix cores) or the factored
+// low-precision form (LDS-staged, 4 x 4 register tiles)
+int bj_group_size(int nb, bool full_f64);
 // update flags: d' = b z + a d_old, x' = x + d' (see block_kernels.hip)
 enum BjFlags { BJ_READ_X = 1, BJ_READ_D = 2, BJ_FOLD = 4, BJ_WRITE_D = 8, BJ_APPLY = 16 };
 int bj_cheb_f64(const BjPlan& P, const double* binv, const double* r, const double* ab, double* d, double* x,

@@ -325,8 +325,11 @@ int setup_blocks(sdg_problem* P) {
   P->nuniq = (int)P->reps.size();
   // group the elements by block (counting sort, element order kept inside
   // a group) and cut each group into work items of at most G elements
-  // at least ~512 work items where the batch allows it (one per CU pair)
-  const int G = std::max(16, std::min(bj_group_size(P->NB), 4 * (int)((ntot + 2047) / 2048)));
+  // FP64: 16 elements per wavefront; factored low precision: at least ~512
+  // work items where the batch allows it (one per CU pair)
+  const bool full64 = !(P->opt.prec_apply == SDG_FP32 || P->opt.prec_smoother != SDG_FP64);
+  const int G = full64 ? bj_group_size(P->NB, true)
+                       : std::max(16, std::min(bj_group_size(P->NB, false), 4 * (int)((ntot + 2047) / 2048)));
   std::vector<int> first(P->nuniq + 1, 0);
   for (int64_t ge = 0; ge < ntot; ++ge) ++first[ids[ge] + 1];
   for (int u = 0; u < P->nuniq; ++u) first[u + 1] += first[u];
@@ -1263,7 +1266,7 @@ size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, i
   b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, element permutation, etap
   const int64_t nuniq = opts->dedup ? std::min<int64_t>(nel * nb, 4096) : nel * nb;
   b += nuniq * NB * NB * 8 + nuniq * 8;
-  b += 12 * (nel * nb / bj_group_size((int)NB) + nuniq + 1);  // smoother work list
+  b += 12 * (nel * nb / 16 + nuniq + 1);  // smoother work list (16 elements per item at least)
   const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
   if (low) b += nuniq * NB * (NB + 1) / 2 * (8 + (opts->prec_smoother == SDG_BF16 ? 2 : 4));
   b += nb * nel * 64 * 8;  // coarse local matrices
