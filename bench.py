@@ -174,9 +174,10 @@ def kernel_probe(sdg, ctx, torch, B, reps):
     for _ in range(reps):
         torch.neg(u, out=r)  # plain elementwise copy: reads and writes one vector
     torch.cuda.synchronize()
+    var = sdg.sdg_get_tile(h, sdg.TILE_RESIDUAL, sdg.FP64)
     sdg.sdg_problem_destroy(h)
     print(json.dumps({"kernel_probe": {"batch": B, "reps": reps, "vector_bytes": u.numel() * 8,
-                                       "tile": sdg.sdg_tile_shape(K, 0),
+                                       "tile": sdg.sdg_tile_shape(K, var), "variant": var,
                                        "residual_bytes": B * nel * (3 * nb * 8 + 8),
                                        "apply_bytes": B * nel * (2 * nb * 8 + 8)}}), flush=True)
 
@@ -211,6 +212,8 @@ def main():
                     help="arithmetic of the fine-level cycle (operator apply and block smoother); "
                          "the Krylov solvers, true residuals and the coarse Q1 hierarchy stay FP64")
     ap.add_argument("--latency-solves", type=int, default=5)
+    ap.add_argument("--coarsest-n", type=int, default=8,
+                    help="h-coarsening stops at this many elements per side (dense solve below)")
     ap.add_argument("--kernel-probe", type=int, default=0,
                     help="only launch the operator kernels this many times (counter runs)")
     ap.add_argument("--serve-requests", type=int, default=16,
@@ -251,7 +254,7 @@ def main():
     mesh = sdg.make_mesh(N, N, K)
     prec = {"fp64": (sdg.FP64, sdg.FP64), "fp32": (sdg.FP32, sdg.FP32), "bf16": (sdg.FP32, sdg.BF16)}[args.prec]
     opts = sdg.make_options(rtol=RTOL, inner_rtol=1e-3, max_it=2000, prec_apply=prec[0],
-                            prec_smoother=prec[1])
+                            prec_smoother=prec[1], coarsest_n=args.coarsest_n)
     stream = sdg.current_stream()
 
     def step():
@@ -266,11 +269,16 @@ def main():
         sdg.sdg_problem_destroy(h)
         return st
 
-    # tile shapes of the SIP kernels: the library's default for k = 4 (the
-    # fastest of the candidates in sdg_autotune sweeps at this shape; the
-    # bench keeps it fixed so that its kernels match the committed counters)
-    tile = sdg.sdg_tile_shape(K, 0)
-    tiles = {"apply": tile, "residual": tile}
+    # SIP kernel form: the library's default for k = 4 in FP64 (the fastest
+    # candidate of sdg_autotune sweeps at this shape; the bench keeps it
+    # fixed so that its kernels match the committed counters)
+    tiles = {}
+    h = sdg.sdg_problem_create_batch(ctx, mesh, opts, B, eta, stream)
+    for kern, name in ((sdg.TILE_APPLY, "apply"), (sdg.TILE_RESIDUAL, "residual")):
+        v = sdg.sdg_get_tile(h, kern, sdg.FP64)
+        tiles[name] = {"variant": v, "shape": sdg.sdg_tile_shape(K, v),
+                       "kernel": "sip_wave_kernel" if v == 0 else "sip_tile_kernel"}
+    sdg.sdg_problem_destroy(h)
     log(f"[bench] batch {B}: warmup {args.warmup} steps")
     for i in range(args.warmup):
         st = step()
@@ -335,10 +343,13 @@ def main():
     # roofline of the dominant kernel: the traced class with the largest
     # time in the traced step, launched back to back at the step's shape
     # (batch B) between two HIP events on the problem's stream
-    ta, tr = tiles["apply"], tiles["residual"]
-    kernel_names = {"sip_apply": f"sip_tile_kernel<{K + 1},apply,double,{ta[0]},{ta[1]}>",
-                    "sip_residual": f"sip_tile_kernel<{K + 1},residual,double,{tr[0]},{tr[1]}>",
-                    "block_jacobi_smoother": f"bj_group_kernel<{K + 1},double,double,false>"}
+    def kname(t, mode):
+        if t["kernel"] == "sip_wave_kernel":
+            return f"sip_wave_kernel<{K + 1},{mode},double>"
+        return f"sip_tile_kernel<{K + 1},{mode},double,{t['shape'][0]},{t['shape'][1]}>"
+    kernel_names = {"sip_apply": kname(tiles["apply"], "apply"),
+                    "sip_residual": kname(tiles["residual"], "residual"),
+                    "block_jacobi_smoother": f"bj_wave_kernel<{K + 1},1>"}
     cand = {k: v for k, v in traced.items() if v["bytes_per_launch"] > 0}
     dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else "sip_residual"
     h = sdg.sdg_problem_create_batch(ctx, mesh, opts, B, eta, stream)

@@ -293,8 +293,12 @@ int sdg_admission_simulate(int n, const double* arrival_ms, const double* servic
                            double* start_ms);
 
 /* ---- tile shapes of the SIP operator kernels and their autotuner -------------
- * The SIP apply/residual kernels stage TX x TY element tiles in LDS; each
- * order k has sdg_tile_variants() candidate shapes (variant 0 = default).
+ * The SIP apply/residual kernels work on TX x TY element tiles; each order k
+ * has sdg_tile_variants() candidates: variant 0 is the wavefront kernel (one
+ * 64-lane wavefront per tile, k+1 lanes per element), variants 1.. the
+ * 256-thread LDS tile kernel at several shapes (sdg_tile_shape).  A new
+ * problem starts from a measured default per order and precision (or the
+ * shape tuned for its size earlier in the process); sdg_get_tile reads and
  * sdg_set_tile picks one for a problem: kernel 0 = apply (y = A u),
  * 1 = residual (r = b - A u); precision SDG_FP64 or SDG_FP32 (the fine-level
  * cycle of the low-precision forms).  sdg_autotune times every candidate on
@@ -307,6 +311,7 @@ int sdg_admission_simulate(int n, const double* arrival_ms, const double* servic
  * cycle.  Results are identical up to rounding order for every shape. */
 int sdg_tile_variants(int k, int* count);
 int sdg_tile_shape(int k, int variant, int* tx, int* ty);
+int sdg_get_tile(const sdg_problem* prob, int kernel, int precision, int* variant);
 int sdg_set_tile(sdg_problem* prob, int kernel, int precision, int variant);
 int sdg_autotune(sdg_problem* prob, int reps, int* variants, double* us);
 

@@ -515,10 +515,13 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_kernel(TailArgs A) {
     const int nn = (L.nx + 1) * (L.ny + 1), n2 = 2 * nn;
     const double* D = A.dense + pb * (int64_t)n2 * n2;
     const double* b = L.b + pb * n2;
-    for (int i = threadIdx.x; i < n2; i += TAIL_NT) {
+    // one wavefront per row: coalesced row reads, shuffle reduction
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i < n2; i += TAIL_NT / 64) {
       double s = 0.0;
-      for (int j = 0; j < n2; ++j) s += D[(int64_t)i * n2 + j] * b[j];
-      L.x[pb * n2 + i] = s;
+      for (int j = lane; j < n2; j += 64) s += D[(int64_t)i * n2 + j] * b[j];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+      if (lane == 0) L.x[pb * n2 + i] = s;
     }
     __syncthreads();
   }
@@ -543,8 +546,196 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_kernel(TailArgs A) {
   }
 }
 
+// The same h-cycle with every operand of the small levels staged in LDS:
+// per level the stencil (36 values per node), the inverse diagonal and the
+// vectors b, x, r, d; only the restricted right-hand side of the first tail
+// level comes from HBM and only its solution goes back; the dense inverse of
+// the last level is read from L2.  Each sweep is then LDS traffic only.
+__device__ __forceinline__ int tail_nn(const TailLevel& L) { return (L.nx + 1) * (L.ny + 1); }
+
+__global__ __launch_bounds__(TAIL_NT) void coarse_tail_lds_kernel(TailArgs A) {
+  extern __shared__ double lds[];
+  const int64_t pb = blockIdx.x;
+  const int nb = A.nbatch, nl = A.nlev;
+  const int t = threadIdx.x;
+  // per level: st[36][nn], dinv[2nn], b[2nn], x[2nn], r[2nn], d[2nn]
+  double* base[TAIL_MAXLEV];
+  {
+    int64_t off = 0;
+    for (int l = 0; l < nl; ++l) {
+      base[l] = lds + off;
+      off += 46 * (int64_t)tail_nn(A.lev[l]);
+    }
+  }
+  auto ST = [&](int l) { return base[l]; };
+  auto DI = [&](int l) { return base[l] + 36 * tail_nn(A.lev[l]); };
+  auto BV = [&](int l) { return base[l] + 38 * tail_nn(A.lev[l]); };
+  auto XV = [&](int l) { return base[l] + 40 * tail_nn(A.lev[l]); };
+  auto RV = [&](int l) { return base[l] + 42 * tail_nn(A.lev[l]); };
+  auto DV = [&](int l) { return base[l] + 44 * tail_nn(A.lev[l]); };
+  for (int l = 0; l < nl; ++l) {
+    const TailLevel& L = A.lev[l];
+    const int nn = tail_nn(L);
+    const int64_t NN = (int64_t)nb * nn;
+    if (l < nl - 1) {
+      double* st = ST(l);
+      for (int q = t; q < 36 * nn; q += TAIL_NT) {
+        const int k = q / nn, node = q - k * nn;
+        st[q] = L.st[(int64_t)k * NN + pb * nn + node];
+      }
+      for (int q = t; q < 2 * nn; q += TAIL_NT) DI(l)[q] = L.dinv[pb * 2 * nn + q];
+    }
+    if (l == 0)
+      for (int q = t; q < 2 * nn; q += TAIL_NT) BV(0)[q] = L.b[pb * 2 * nn + q];
+  }
+  __syncthreads();
+  auto resid = [&](int l) {
+    const TailLevel& L = A.lev[l];
+    const int nn = tail_nn(L), nxp = L.nx + 1;
+    const double *st = ST(l), *b = BV(l), *x = XV(l);
+    double* r = RV(l);
+    // one thread per unknown (node, component)
+    for (int q = t; q < 2 * nn; q += TAIL_NT) {
+      const int node = q >> 1, c = q & 1;
+      const int jx = node % nxp, jy = node / nxp;
+      double rv = b[q];
+#pragma unroll
+      for (int sy = -1; sy <= 1; ++sy)
+#pragma unroll
+        for (int sx = -1; sx <= 1; ++sx) {
+          const int gx = jx + sx, gy = jy + sy;
+          if (gx < 0 || gx > L.nx || gy < 0 || gy > L.ny) continue;
+          const int sidx = (sy + 1) * 3 + (sx + 1);
+          const int nbn = gy * nxp + gx;
+          rv -= st[(sidx * 4 + 2 * c) * nn + node] * x[nbn * 2] + st[(sidx * 4 + 2 * c + 1) * nn + node] * x[nbn * 2 + 1];
+        }
+      r[q] = rv;
+    }
+  };
+  auto cheb = [&](int l, bool zero) {
+    const TailLevel& L = A.lev[l];
+    const int nn = tail_nn(L);
+    double *b = BV(l), *x = XV(l), *r = RV(l), *d = DV(l);
+    const double* di = DI(l);
+    for (int s = 0; s < A.steps; ++s) {
+      const bool first = (s == 0);
+      if (!(first && zero)) {
+        resid(l);
+        __syncthreads();
+      }
+      const double ca = L.ab[(int64_t)(s * nb + pb) * 2], cb = L.ab[(int64_t)(s * nb + pb) * 2 + 1];
+      for (int i = t; i < 2 * nn; i += TAIL_NT) {
+        const double rv = (first && zero) ? b[i] : r[i];
+        const double z = di[i] * rv;
+        const double dv = first ? cb * z : ca * d[i] + cb * z;
+        d[i] = dv;
+        x[i] = (first && zero) ? dv : x[i] + dv;
+      }
+      __syncthreads();
+    }
+  };
+  // descend
+  for (int l = 0; l < nl - 1; ++l) {
+    cheb(l, true);
+    resid(l);
+    __syncthreads();
+    const TailLevel& L = A.lev[l];
+    const TailLevel& C = A.lev[l + 1];
+    const int ncx = C.nx, nfx = L.nx, nfy = L.ny;
+    const int nnc = tail_nn(C);
+    const double* r = RV(l);
+    double* bc = BV(l + 1);
+    for (int i = t; i < 2 * nnc; i += TAIL_NT) {
+      const int c = i & 1, cn = i >> 1;
+      const int cx = cn % (ncx + 1), cy = cn / (ncx + 1);
+      double sum = 0.0;
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int fx = 2 * cx + ox, fy = 2 * cy + oy;
+          if (fx < 0 || fx > nfx || fy < 0 || fy > nfy) continue;
+          sum += (ox == 0 ? 1.0 : 0.5) * (oy == 0 ? 1.0 : 0.5) * r[(fy * (nfx + 1) + fx) * 2 + c];
+        }
+      bc[i] = sum;
+    }
+    __syncthreads();
+  }
+  // coarsest: x = Dinv b (the inverse from L2)
+  {
+    const TailLevel& L = A.lev[nl - 1];
+    const int n2 = 2 * tail_nn(L);
+    const double* D = A.dense + pb * (int64_t)n2 * n2;
+    const double* b = BV(nl - 1);
+    double* x = XV(nl - 1);
+    // each wavefront sums one block of columns for every row (the inverse is
+    // stored exactly symmetric, so row i of a column block is read as
+    // contiguous column entries across the lanes); partial sums go to the
+    // unused stencil space of this level, then one thread per row adds them
+    constexpr int NW = TAIL_NT / 64;
+    const int wave = t >> 6, lane = t & 63;
+    double* part = ST(nl - 1);  // NW * n2 <= 36 nn doubles
+    const int cb = (n2 + NW - 1) / NW, c0 = wave * cb, c1 = min(n2, c0 + cb);
+    for (int i = lane; i < n2; i += 64) {
+      double sum = 0.0;
+      for (int jj = c0; jj < c1; ++jj) sum += D[(int64_t)jj * n2 + i] * b[jj];
+      part[wave * n2 + i] = sum;
+    }
+    __syncthreads();
+    for (int i = t; i < n2; i += TAIL_NT) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += part[w * n2 + i];
+      x[i] = sum;
+    }
+    __syncthreads();
+  }
+  // ascend
+  for (int l = nl - 2; l >= 0; --l) {
+    const TailLevel& L = A.lev[l];
+    const TailLevel& C = A.lev[l + 1];
+    const int ncx = C.nx, nfx = L.nx, nfy = L.ny;
+    const int nnf = tail_nn(L);
+    const double* xc = XV(l + 1);
+    double* x = XV(l);
+    for (int i = t; i < 2 * nnf; i += TAIL_NT) {
+      const int c = i & 1, fn = i >> 1;
+      const int fx = fn % (nfx + 1), fy = fn / (nfx + 1);
+      const double wx = (fx & 1) ? 0.5 : 1.0, wy = (fy & 1) ? 0.5 : 1.0;
+      double sum = 0.0;
+      for (int py = fy >> 1; py <= (fy + 1) >> 1; ++py)
+        for (int px = fx >> 1; px <= (fx + 1) >> 1; ++px) sum += wx * wy * xc[(py * (ncx + 1) + px) * 2 + c];
+      x[i] += sum;
+    }
+    __syncthreads();
+    cheb(l, false);
+  }
+  // the first tail level's solution back to HBM
+  {
+    const TailLevel& L = A.lev[0];
+    const int nn = tail_nn(L);
+    for (int q = t; q < 2 * nn; q += TAIL_NT) L.x[pb * 2 * nn + q] = XV(0)[q];
+  }
+}
+
+size_t coarse_tail_lds_bytes(const TailArgs& A) {
+  size_t n = 0;
+  for (int l = 0; l < A.nlev; ++l) n += 46 * (size_t)(A.lev[l].nx + 1) * (A.lev[l].ny + 1);
+  return n * sizeof(double);
+}
+
 int coarse_tail(const TailArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(coarse_tail_kernel, dim3(A.nbatch), dim3(TAIL_NT), 0, s, A);
+  const size_t lds = coarse_tail_lds_bytes(A);
+  // the LDS form needs the kernel's dynamic LDS limit raised above 64 KB
+  static int lds_ok = -1;  // once per process: -1 unknown, 0 no, 1 yes
+  if (lds_ok < 0) {
+    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&coarse_tail_lds_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+    if (!lds_ok) (void)hipGetLastError();
+  }
+  if (lds_ok == 1 && A.nlev >= 2 && lds <= 150 * 1024) {
+    hipLaunchKernelGGL(coarse_tail_lds_kernel, dim3(A.nbatch), dim3(TAIL_NT), lds, s, A);
+  } else {
+    hipLaunchKernelGGL(coarse_tail_kernel, dim3(A.nbatch), dim3(TAIL_NT), 0, s, A);
+  }
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

@@ -17,6 +17,7 @@ int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const 
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
                      const float* u, float* r, hipStream_t s, int var = 0);
 int sip_tile_variants(int k);
+int sip_tile_default(int k, bool fp32);
 void sip_tile_shape(int k, int var, int* tx, int* ty);
 // Diagonal blocks A_KK of the listed elements (one workgroup per listed
 // element): blocks[i][a][b] for element elems[i] of problem elems_pb[i].

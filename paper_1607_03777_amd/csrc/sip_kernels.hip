@@ -30,8 +30,10 @@
 
 namespace sdg {
 
-// Tile shapes (TX x TY elements per workgroup) per K1; variant 0 is the
-// default, the others are candidates for the autotuner.
+// Shapes of the 256-thread tile kernel (TX x TY elements per workgroup) per
+// K1.  The operator's variant 0 is the wavefront kernel; variants 1..4 are
+// these tile shapes (candidates for the autotuner), the first of which also
+// serves the block and coarse-column modes.
 constexpr int TILE_NV[8] = {0, 0, 4, 4, 4, 4, 4, 4};
 constexpr int TILE_TX[8][4] = {{0}, {0}, {8, 16, 8, 16}, {8, 8, 16, 4}, {4, 8, 8, 4},
                                {4, 8, 8, 4}, {4, 4, 8, 2}, {4, 4, 2, 2}};
@@ -607,6 +609,291 @@ __global__ __launch_bounds__(NT, (K1 >= 7 ? 3 : 1)) void sip_tile_kernel(MeshDev
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront kernel (apply / residual): one 64-lane wavefront per tile of
+// WT::TX x WT::TY elements, K1 lanes per element.  Lane (el, j) first holds
+// row j of both components of its element (x-direction work: x-face traces,
+// S_x), then, through the element staged in LDS, column j (y-direction
+// work: y-face traces, S_y, the mixed term of y0), then mode j of its
+// element's four faces (face coefficients, applied to its own row and
+// column) and the mixed term of y1; the column results come back to the row
+// lanes through LDS.  Traces of neighbours outside the tile are formed by
+// the boundary lanes from their rows/columns in HBM/L2.  Every loop runs
+// over compile-time mode counts; the lane's element and row are decoded
+// once.
+// ---------------------------------------------------------------------------
+template <int K1> struct WaveTile;
+template <> struct WaveTile<2> { static constexpr int TX = 8, TY = 4; };
+template <> struct WaveTile<3> { static constexpr int TX = 7, TY = 3; };
+template <> struct WaveTile<4> { static constexpr int TX = 4, TY = 4; };
+template <> struct WaveTile<5> { static constexpr int TX = 4, TY = 3; };
+template <> struct WaveTile<6> { static constexpr int TX = 5, TY = 2; };
+template <> struct WaveTile<7> { static constexpr int TX = 3, TY = 3; };
+
+template <int K1, int MODE, typename T>
+__global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
+                                                      const T* __restrict__ bvec, T* __restrict__ y,
+                                                      const double* __restrict__ eta_all, int64_t vec_stride) {
+  constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
+  constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY;
+  static_assert(E * K1 <= 64, "tile does not fit a wavefront");
+  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), FW = 8 * K1, FS = FW + 1, EW = TX + 2;
+  __shared__ T su[E * NB];                // [el][d][j][i]; later the column results
+  __shared__ T sf[(NFV + NFH) * FS];      // face records [s][d][w][m]
+  __shared__ T seta[(TY + 2) * EW];
+  __shared__ T sdm[K1 * K1];
+  const int lane = threadIdx.x;
+  const int nx = M.nx, ny = M.ny;
+  const int ntx = (nx + TX - 1) / TX;
+  const int ix0 = (blockIdx.x % ntx) * TX, iy0 = (blockIdx.x / ntx) * TY;
+  const int64_t pb = blockIdx.y;
+  const double* eta = eta_all + pb * (int64_t)nx * ny;
+  u += pb * vec_stride;
+  y += pb * vec_stride;
+  if (MODE == M_RESID) bvec += pb * vec_stride;
+  const T hx = T(M.hx), hy = T(M.hy);
+
+  const int el = lane / K1, j = lane - el * K1;  // j: row, then column, then face mode
+  const bool act = el < E;
+  const int tx = el % TX, ty = el / TX;
+  const int ix = ix0 + tx, iy = iy0 + ty;
+  const bool valid = act && ix < nx && iy < ny;
+  const int64_t ge = (int64_t)iy * nx + ix;
+
+  for (int q = lane; q < (TY + 2) * EW; q += 64) {
+    const int qx = ix0 - 1 + q % EW, qy = iy0 - 1 + q / EW;
+    seta[q] = (qx >= 0 && qx < nx && qy >= 0 && qy < ny) ? T(eta[(int64_t)qy * nx + qx]) : T(0);
+  }
+  for (int q = lane; q < K1 * K1; q += 64) {
+    const int m = q / K1, i = q % K1;
+    sdm[q] = d_nz(m, i) ? T(d_val(m, i)) : T(0);
+  }
+  for (int q = lane; q < (NFV + NFH) * FS; q += 64) sf[q] = T(0);
+  __syncthreads();
+
+  const T et = act ? seta[(ty + 1) * EW + tx + 1] : T(0);
+  const T cxx = T(4) / (hx * hx), cyy = T(4) / (hy * hy), cxy = T(4) / (hx * hy);
+  auto trace4 = [](const T (&v)[K1], T& tl, T& gl, T& tr, T& gr) {
+    tl = gl = tr = gr = T(0);
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      tl += T(e_end(i, 0)) * v[i];
+      gl += T(d_end(i, 0)) * v[i];
+      tr += T(e_end(i, 1)) * v[i];
+      gr += T(d_end(i, 1)) * v[i];
+    }
+  };
+
+  // ---- rows: stage the element, x-face traces, S_x
+  T yr[2][K1], bres[2][K1];
+  if (act) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      T r[K1];
+#pragma unroll
+      for (int i = 0; i < K1; ++i) r[i] = valid ? u[ge * NB + d * KK + j * K1 + i] : T(0);
+      if constexpr (MODE == M_RESID) {
+#pragma unroll
+        for (int i = 0; i < K1; ++i) bres[d][i] = valid ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < K1; ++i) su[el * NB + d * KK + j * K1 + i] = r[i];
+      T tl, gl, tr, gr;
+      trace4(r, tl, gl, tr, gr);
+      T* fl = sf + (ty * (TX + 1) + tx) * FS;      // left face, this element on the plus side
+      T* fr = sf + (ty * (TX + 1) + tx + 1) * FS;  // right face, minus side
+      fl[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
+      fl[((1 * 2 + d) * 2 + 1) * K1 + j] = gl;
+      fr[((0 * 2 + d) * 2 + 0) * K1 + j] = tr;
+      fr[((0 * 2 + d) * 2 + 1) * K1 + j] = gr;
+      // neighbours across the tile's left and right edges
+      if (valid && tx == 0 && ix > 0) {
+        T v[K1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) v[i] = u[(ge - 1) * NB + d * KK + j * K1 + i];
+        T a0, a1, a2, a3;
+        trace4(v, a0, a1, a2, a3);
+        fl[((0 * 2 + d) * 2 + 0) * K1 + j] = a2;
+        fl[((0 * 2 + d) * 2 + 1) * K1 + j] = a3;
+      }
+      if (valid && tx == TX - 1 && ix + 1 < nx) {
+        T v[K1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) v[i] = u[(ge + 1) * NB + d * KK + j * K1 + i];
+        T a0, a1, a2, a3;
+        trace4(v, a0, a1, a2, a3);
+        fr[((1 * 2 + d) * 2 + 0) * K1 + j] = a0;
+        fr[((1 * 2 + d) * 2 + 1) * K1 + j] = a1;
+      }
+      const T cx = (d == 0 ? T(2) : T(1)) * et * cxx;
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < K1; ++l)
+          if (s_nz(i, l)) acc += T(s_val(i, l)) * r[l];
+        yr[d][i] = cx * acc;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- columns (lane column i = j): y-face traces, S_y, mixed term of y0
+  T yc[2][K1];
+  const int ic = j;
+  if (act) {
+    const T* ue = su + el * NB;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      T c[K1];
+#pragma unroll
+      for (int jj = 0; jj < K1; ++jj) c[jj] = ue[d * KK + jj * K1 + ic];
+      T tb, gb, tt, gt;
+      trace4(c, tb, gb, tt, gt);
+      T* fb = sf + (NFV + ty * TX + tx) * FS;        // bottom face, this element on the plus side
+      T* ft = sf + (NFV + (ty + 1) * TX + tx) * FS;  // top face, minus side
+      fb[((1 * 2 + d) * 2 + 0) * K1 + ic] = tb;
+      fb[((1 * 2 + d) * 2 + 1) * K1 + ic] = gb;
+      ft[((0 * 2 + d) * 2 + 0) * K1 + ic] = tt;
+      ft[((0 * 2 + d) * 2 + 1) * K1 + ic] = gt;
+      if (valid && ty == 0 && iy > 0) {
+        T v[K1];
+#pragma unroll
+        for (int jj = 0; jj < K1; ++jj) v[jj] = u[(ge - nx) * NB + d * KK + jj * K1 + ic];
+        T a0, a1, a2, a3;
+        trace4(v, a0, a1, a2, a3);
+        fb[((0 * 2 + d) * 2 + 0) * K1 + ic] = a2;
+        fb[((0 * 2 + d) * 2 + 1) * K1 + ic] = a3;
+      }
+      if (valid && ty == TY - 1 && iy + 1 < ny) {
+        T v[K1];
+#pragma unroll
+        for (int jj = 0; jj < K1; ++jj) v[jj] = u[(ge + nx) * NB + d * KK + jj * K1 + ic];
+        T a0, a1, a2, a3;
+        trace4(v, a0, a1, a2, a3);
+        ft[((1 * 2 + d) * 2 + 0) * K1 + ic] = a0;
+        ft[((1 * 2 + d) * 2 + 1) * K1 + ic] = a1;
+      }
+      const T cy = (d == 1 ? T(2) : T(1)) * et * cyy;
+#pragma unroll
+      for (int jj = 0; jj < K1; ++jj) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < K1; ++l)
+          if (s_nz(jj, l)) acc += T(s_val(jj, l)) * c[l];
+        yc[d][jj] = cy * acc;
+      }
+    }
+    // D_y^T (D_x u1) on column ic: (D_x u1)[m][ic] = sum_{l > ic} D(ic, l) u1[m][l]
+    T w[K1];
+#pragma unroll
+    for (int m = 0; m < K1; ++m) w[m] = T(0);
+    for (int l = ic + 1; l < K1; l += 2) {
+      const T cdl = sdm[ic * K1 + l];
+#pragma unroll
+      for (int m = 0; m < K1; ++m) w[m] += cdl * ue[KK + m * K1 + l];
+    }
+#pragma unroll
+    for (int jj = 0; jj < K1; ++jj) {
+      T acc = T(0);
+#pragma unroll
+      for (int m = 0; m < K1; ++m)
+        if (d_nz(m, jj)) acc += T(d_val(m, jj)) * w[m];
+      yc[0][jj] += et * cxy * acc;
+    }
+  }
+  __syncthreads();
+
+  // ---- faces (mode m = j of this element's four faces) and the mixed term of y1
+  if (act) {
+    const int m = j;
+    T o[8];
+    // x-faces: left (this element = plus side), right (minus side)
+    {
+      const int kind = ix > 0 ? F_INTERIOR : M.bc[0];
+      face_mode<K1, 0, T>(sf + (ty * (TX + 1) + tx) * FS, m, valid ? kind : -1, 1, seta[(ty + 1) * EW + tx], et,
+                          hx, hy, false, false, sdm, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 0)) + b * T(d_end(i, 0));
+      }
+    }
+    {
+      const int kind = ix + 1 < nx ? F_INTERIOR : M.bc[1];
+      face_mode<K1, 0, T>(sf + (ty * (TX + 1) + tx + 1) * FS, m, valid ? kind : -1, 0, et,
+                          seta[(ty + 1) * EW + tx + 2], hx, hy, false, false, sdm, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 1)) + b * T(d_end(i, 1));
+      }
+    }
+    // y-faces: bottom (plus side), top (minus side), applied to column m
+    {
+      const int kind = iy > 0 ? F_INTERIOR : M.bc[2];
+      face_mode<K1, 1, T>(sf + (NFV + ty * TX + tx) * FS, m, valid ? kind : -1, 1, seta[ty * EW + tx + 1], et, hy,
+                          hx, false, false, sdm, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int jj = 0; jj < K1; ++jj) yc[d][jj] += a * T(e_end(jj, 0)) + b * T(d_end(jj, 0));
+      }
+    }
+    {
+      const int kind = iy + 1 < ny ? F_INTERIOR : M.bc[3];
+      face_mode<K1, 1, T>(sf + (NFV + (ty + 1) * TX + tx) * FS, m, valid ? kind : -1, 0, et,
+                          seta[(ty + 2) * EW + tx + 1], hy, hx, false, false, sdm, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int jj = 0; jj < K1; ++jj) yc[d][jj] += a * T(e_end(jj, 1)) + b * T(d_end(jj, 1));
+      }
+    }
+    // D_x^T (D_y u0) on row j: (D_y u0)[j][m'] = sum_{l > j} D(j, l) u0[l][m']
+    const T* ue = su + el * NB;
+    T r0[K1];
+#pragma unroll
+    for (int mm = 0; mm < K1; ++mm) r0[mm] = T(0);
+    for (int l = j + 1; l < K1; l += 2) {
+      const T cdl = sdm[j * K1 + l];
+#pragma unroll
+      for (int mm = 0; mm < K1; ++mm) r0[mm] += cdl * ue[l * K1 + mm];
+    }
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int mm = 0; mm < K1; ++mm)
+        if (d_nz(mm, i)) acc += T(d_val(mm, i)) * r0[mm];
+      yr[1][i] += et * cxy * acc;
+    }
+  }
+  __syncthreads();
+  // column results back to rows
+  if (act) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int jj = 0; jj < K1; ++jj) su[el * NB + d * KK + jj * K1 + ic] = yc[d][jj];
+  }
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        const T v = yr[d][i] + su[el * NB + d * KK + j * K1 + i];
+        if constexpr (MODE == M_RESID) y[ge * NB + d * KK + j * K1 + i] = bres[d][i] - v;
+        else y[ge * NB + d * KK + j * K1 + i] = v;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // B^T u (divergence) and B p (gradient): one thread per element (and
 // component for B p); neighbour traces are read directly.
 // ---------------------------------------------------------------------------
@@ -898,17 +1185,28 @@ static void launch_var(const MeshDev& M, int nbatch, const T* u, const T* b, T* 
 }
 
 template <int K1, int MODE, typename T>
+static void launch_wave(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
+                        hipStream_t s) {
+  constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
+  const int ntiles = ceil_div(M.nx, TX) * ceil_div(M.ny, TY);
+  const int64_t stride = (int64_t)M.nx * M.ny * 2 * K1 * K1;
+  hipLaunchKernelGGL((sip_wave_kernel<K1, MODE, T>), dim3(ntiles, nbatch), dim3(64), 0, s, M, u, b, y, eta, stride);
+}
+
+// var: 0 = wavefront kernel, 1..TILE_NV = tile kernel shapes (apply/residual)
+template <int K1, int MODE, typename T>
 static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
                        double* out_mat, hipStream_t s, int var = 0) {
-  if (var < 0 || var >= TILE_NV[K1]) {
+  if (var < 0 || var > TILE_NV[K1]) {
     set_error("tile variant out of range");
     return SDG_ERR_INVALID;
   }
-  if (MODE == M_APPLY || MODE == M_RESID) {
+  if constexpr (MODE == M_APPLY || MODE == M_RESID) {
     switch (var) {
-      case 0: launch_var<K1, MODE, T, 0>(M, nbatch, u, b, y, eta, out_mat, s); break;
-      case 1: launch_var<K1, MODE, T, 1>(M, nbatch, u, b, y, eta, out_mat, s); break;
-      case 2: launch_var<K1, MODE, T, 2>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      case 0: launch_wave<K1, MODE, T>(M, nbatch, u, b, y, eta, s); break;
+      case 1: launch_var<K1, MODE, T, 0>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      case 2: launch_var<K1, MODE, T, 1>(M, nbatch, u, b, y, eta, out_mat, s); break;
+      case 3: launch_var<K1, MODE, T, 2>(M, nbatch, u, b, y, eta, out_mat, s); break;
       default:
         if constexpr (TILE_NV[K1] > 3) launch_var<K1, MODE, T, 3>(M, nbatch, u, b, y, eta, out_mat, s);
         break;
@@ -920,11 +1218,27 @@ static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* 
   return SDG_OK;
 }
 
-int sip_tile_variants(int k) { return (k >= 1 && k <= 6) ? TILE_NV[k + 1] : 0; }
+int sip_tile_variants(int k) { return (k >= 1 && k <= 6) ? TILE_NV[k + 1] + 1 : 0; }
+// default shape per order and precision, from sweeps at 64 x 64 x 16
+// problems: FP64 k <= 4 the first tile shape, otherwise the wavefront kernel
+int sip_tile_default(int k, bool fp32) { return (!fp32 && k <= 4) ? 1 : 0; }
 void sip_tile_shape(int k, int var, int* tx, int* ty) {
-  const bool ok = k >= 1 && k <= 6 && var >= 0 && var < TILE_NV[k + 1];
-  *tx = ok ? TILE_TX[k + 1][var] : 0;
-  *ty = ok ? TILE_TY[k + 1][var] : 0;
+  const bool ok = k >= 1 && k <= 6 && var >= 0 && var <= TILE_NV[k + 1];
+  *tx = *ty = 0;
+  if (!ok) return;
+  if (var > 0) {
+    *tx = TILE_TX[k + 1][var - 1];
+    *ty = TILE_TY[k + 1][var - 1];
+    return;
+  }
+  switch (k + 1) {
+    case 2: *tx = WaveTile<2>::TX; *ty = WaveTile<2>::TY; break;
+    case 3: *tx = WaveTile<3>::TX; *ty = WaveTile<3>::TY; break;
+    case 4: *tx = WaveTile<4>::TX; *ty = WaveTile<4>::TY; break;
+    case 5: *tx = WaveTile<5>::TX; *ty = WaveTile<5>::TY; break;
+    case 6: *tx = WaveTile<6>::TX; *ty = WaveTile<6>::TY; break;
+    default: *tx = WaveTile<7>::TX; *ty = WaveTile<7>::TY; break;
+  }
 }
 template <int K1>
 static int launch_block_list(const MeshDev& M, const double* eta, const int* elems, int nlist,

@@ -1361,7 +1361,7 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
     for (int kern = 0; kern < 2; ++kern)
       for (int pr = 0; pr < 2; ++pr) {
         auto it = g_tune.find(tune_key(P, kern, pr));
-        if (it != g_tune.end()) P->tile[kern][pr] = it->second;
+        P->tile[kern][pr] = it != g_tune.end() ? it->second : sip_tile_default(P->k, pr == 1);
       }
   }
   auto fail = [&](int rc) {
@@ -1788,6 +1788,15 @@ int sdg_tile_shape(int k, int variant, int* tx, int* ty) {
     return SDG_ERR_INVALID;
   }
   sip_tile_shape(k, variant, tx, ty);
+  return SDG_OK;
+}
+
+int sdg_get_tile(const sdg_problem* P, int kernel, int precision, int* variant) {
+  if (!P || !variant || kernel < 0 || kernel > 1 || (precision != SDG_FP64 && precision != SDG_FP32)) {
+    set_error("invalid problem, kernel or precision");
+    return SDG_ERR_INVALID;
+  }
+  *variant = P->tile[kernel][precision == SDG_FP64 ? 0 : 1];
   return SDG_OK;
 }
 

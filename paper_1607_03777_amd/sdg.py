@@ -103,6 +103,7 @@ PROTOTYPES = {
     "sdg_uniform_pm1": (I, [P, ctypes.c_uint64, ctypes.c_int64, P, P]),
     "sdg_tile_variants": (I, [I, ctypes.POINTER(I)]),
     "sdg_tile_shape": (I, [I, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "sdg_get_tile": (I, [P, I, I, ctypes.POINTER(I)]),
     "sdg_set_tile": (I, [P, I, I, I]),
     "sdg_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double)]),
     "sdg_server_config_default": (None, [ctypes.POINTER(sdg_server_config)]),
@@ -433,6 +434,12 @@ def sdg_tile_shape(k, variant):
     tx, ty = I(), I()
     check(lib().sdg_tile_shape(k, variant, ctypes.byref(tx), ctypes.byref(ty)))
     return tx.value, ty.value
+
+
+def sdg_get_tile(prob, kernel, precision):
+    v = I()
+    check(lib().sdg_get_tile(prob, kernel, precision, ctypes.byref(v)))
+    return v.value
 
 
 def sdg_set_tile(prob, kernel, precision, variant):
