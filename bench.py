@@ -200,6 +200,35 @@ def recorded_traffic(kernel):
     return k["traffic_bytes"] if k else None
 
 
+def batched(sdg, ctx, nreq):
+    """Batching form: nreq independent viscous solves, n in {16, 32, 64, 128},
+    k in 2..5, log10 viscosity a Gaussian random field (correlation length
+    0.1, standard deviation 1.5), smooth random force, FP32 cycle with FP64
+    Krylov and residual, rtol 1e-8; submitted at once to the server, which
+    groups equal shapes into batched problems."""
+    from paper_1607_03777_amd import inputs as gen
+    probs = [gen.grf_problem(seed) for seed in range(nreq)]
+    opts = sdg.make_options(rtol=RTOL, max_it=3000, prec_apply=sdg.FP32, prec_smoother=sdg.FP32)
+    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=64)
+    t0 = time.perf_counter()
+    hs = [sdg.sdg_submit(srv, sdg.make_mesh(p.nx, p.ny, p.k), opts, sdg.VISCOUS, p.eta, p.f.reshape(-1))
+          for p in probs]
+    bad, dofs, its, groups = 0, 0, [], []
+    for h, p in zip(hs, probs):
+        rc, u, _, st, info = sdg.sdg_wait(h, p.nu)
+        sdg.sdg_req_free(h)
+        bad += rc not in (0, sdg.FLOOR)
+        dofs += p.nu
+        its.append(st["outer_its"])
+        groups.append(info["batch"])
+    t = time.perf_counter() - t0
+    sdg.sdg_server_destroy(srv)
+    log(f"[bench] batched: {nreq} viscous solves in {t:.2f} s ({nreq / t:.1f} solves/s), failures {bad}")
+    return {"workload": f"{nreq}-grf-viscous-n16..128-k2..5-rtol1e-8", "solves_per_s": nreq / t,
+            "dof_per_s": dofs / t, "seconds": t, "failures": bad, "cycle_precision": "fp32",
+            "mean_cg_its": float(np.mean(its)), "mean_launch_group": float(np.mean(groups))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +245,8 @@ def main():
                     help="h-coarsening stops at this many elements per side (dense solve below)")
     ap.add_argument("--kernel-probe", type=int, default=0,
                     help="only launch the operator kernels this many times (counter runs)")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="requests of the batched heterogeneous viscous workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving run (0 = skip)")
     ap.add_argument("--serve-prec", choices=["fp64", "fp32", "bf16"], default="fp32")
@@ -411,6 +442,8 @@ def main():
     }
     if args.serve_requests > 0:
         out["serving"] = serving(sdg, ctx, args.serve_requests, 200.0, args.serve_prec)
+    if args.batched > 0:
+        out["batched"] = batched(sdg, ctx, args.batched)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(P0, st["outer_its"])

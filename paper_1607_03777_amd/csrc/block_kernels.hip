@@ -10,10 +10,10 @@
 // unique block and s_e = eta_rep / eta_e rescales a shared block to the
 // element (blocks with equal face kinds and neighbour viscosity ratios are
 // equal up to the factor eta_K).  Elements are grouped by id_e, so the apply
-// is a small dense product Binv * [r_e1 ... r_eG] per group.  FP64: one
-// wavefront per group of 16 on the matrix cores (FP64 MFMA), fragments read
-// straight from L1/L2 and HBM.  Factored FP32/BF16: one workgroup stages the
-// factor and the residual columns in LDS, 4 x 4 register tiles per thread.
+// is a small dense product Binv * [r_e1 ... r_eG] per group: one wavefront
+// per group of 16 on the matrix cores (FP64 MFMA), fragments read straight
+// from L1/L2 and HBM, for the FP64 inverse and for the factored FP32/BF16
+// form alike.
 #include "sdg_common.h"
 #include "sdg_kernels.h"
 
@@ -131,21 +131,11 @@ int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s) 
 // grouped apply
 //
 // Work item w = (uid, start, count): elements perm[start .. start+count) all
-// use block uid.  The kernel is specialised on K1 = k + 1, so the block size
-// NB = 2 K1^2, the padded row length NBP (NB rounded up to 4) and the
-// largest group GMAX are compile-time constants and every staging loop
-// unrolls into independent loads.  LDS holds the matrix as [b][a] rows
-// (FP64 inverse: Binv, symmetric; factored: X^T and X, zero outside the
-// triangle) and the residual columns as R[b][e].  Thread t owns rows
-// a0 .. a0+3 (a0 = 4 (t mod NAG)) of elements e0 .. e0+3 (e0 = 4 (t div NAG)).
-// The operands of the Chebyshev update are fetched before the product, so
-// their latency hides behind it.
-//
-// Update (z = s_e Binv r_e, per-problem coefficients ab[pb] = (a, b)):
-// d' = b z + a d_old, x' = x + d', where d_old is d (BJ_READ_D) or x itself
-// (BJ_FOLD: the step after a start from zero, whose direction equals x);
-// without BJ_READ_X the old x is zero; d' is stored only with BJ_WRITE_D;
-// BJ_APPLY stores z in x instead.
+// use block uid.  Update (z = s_e Binv r_e, per-problem coefficients
+// ab[pb] = (a, b)): d' = b z + a d_old, x' = x + d', where d_old is d
+// (BJ_READ_D) or x itself (BJ_FOLD: the step after a start from zero, whose
+// direction equals x); without BJ_READ_X the old x is zero; d' is stored
+// only with BJ_WRITE_D; BJ_APPLY stores z in x instead.
 // ---------------------------------------------------------------------------
 template <typename TM, typename TV>
 struct BjArgs {
@@ -161,223 +151,9 @@ struct BjArgs {
   int flags;
 };
 
-template <typename TM>
-__device__ __forceinline__ float ld_f32(const TM* p) {
-  if constexpr (sizeof(TM) == 2) return __uint_as_float(((uint32_t)*p) << 16);
-  else return float(*p);
-}
-
-template <int K1>
-struct BjShape {
-  static constexpr int NB = 2 * K1 * K1;
-  static constexpr int NBP = (NB + 3) & ~3;
-  static constexpr int NAG = NBP / 4;
-  static constexpr int GMAX = 4 * (256 / NAG);
-};
-
-template <typename TC>
-__device__ __forceinline__ void tile_fma(TC (&acc)[4][4], const TC* __restrict__ mrow,
-                                         const TC* __restrict__ rrow) {
-  TC m[4], v[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    m[i] = mrow[i];
-    v[i] = rrow[i];
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = fma(m[i], v[j], acc[i][j]);
-}
-
-template <typename TV>
-struct Pair {
-  TV v[2];
-};
-template <typename TV>
-__device__ __forceinline__ Pair<TV> ld2(const TV* p) {
-  if constexpr (sizeof(TV) == 8) {
-    const double2 q = *reinterpret_cast<const double2*>(p);
-    return Pair<TV>{{q.x, q.y}};
-  } else {
-    const float2 q = *reinterpret_cast<const float2*>(p);
-    return Pair<TV>{{q.x, q.y}};
-  }
-}
-template <typename TV>
-__device__ __forceinline__ void st2(TV* p, TV a, TV b) {
-  if constexpr (sizeof(TV) == 8) *reinterpret_cast<double2*>(p) = make_double2(a, b);
-  else *reinterpret_cast<float2*>(p) = make_float2(a, b);
-}
-
-template <int K1, typename TM, typename TV, bool TRI>
-__global__ __launch_bounds__(256) void bj_group_kernel(BjArgs<TM, TV> A) {
-  using TC = TV;  // FP64 vectors accumulate in FP64, FP32 vectors in FP32
-  using S = BjShape<K1>;
-  constexpr int NB = S::NB, NBP = S::NBP, NAG = S::NAG, GMAX = S::GMAX;
-  __shared__ __align__(16) TC M0[NB * NBP];
-  __shared__ __align__(16) TC M1[TRI ? NB * NBP : 4];
-  __shared__ __align__(16) TC R[NB * GMAX];
-  __shared__ __align__(16) TC Y[TRI ? NB * GMAX : 4];
-  __shared__ int sperm[GMAX];
-  const int G = A.G;
-  const int t = threadIdx.x;
-  const int uid = A.work[3 * blockIdx.x], start = A.work[3 * blockIdx.x + 1],
-            cnt = A.work[3 * blockIdx.x + 2];
-  for (int q = t; q < cnt; q += 256) sperm[q] = A.perm[start + q];
-
-  if constexpr (!TRI) {
-    const TM* B = A.mat + (int64_t)uid * NB * NB;
-#pragma unroll
-    for (int i0 = 0; i0 < NB * NBP; i0 += 256) {
-      const int i = i0 + t;
-      if (i < NB * NBP) {
-        const int b = i / NBP, a = i - b * NBP;
-        M0[i] = a < NB ? TC(B[b * NB + a]) : TC(0);
-      }
-    }
-  } else {
-    // packed lower triangle: X[a][b] (b <= a) at a(a+1)/2 + b
-    const TM* X = A.mat + (int64_t)uid * NB * (NB + 1) / 2;
-#pragma unroll
-    for (int i0 = 0; i0 < NB * NBP; i0 += 256) {
-      const int i = i0 + t;
-      if (i < NB * NBP) {
-        const int b = i / NBP, a = i - b * NBP;
-        M0[i] = (a < NB && b <= a) ? TC(ld_f32(X + a * (a + 1) / 2 + b)) : TC(0);  // X^T[b][a]
-        M1[i] = (a <= b) ? TC(ld_f32(X + b * (b + 1) / 2 + a)) : TC(0);            // X[b][a]
-      }
-    }
-  }
-  __syncthreads();  // sperm
-  {
-    constexpr int NLD = (NB * GMAX + 255) / 256;
-    TV v[NLD];
-#pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int i = q * 256 + t;
-      const int e = i / NB, b = i - e * NB;
-      v[q] = e < cnt ? A.r[(int64_t)sperm[e] * NB + b] : TV(0);
-    }
-#pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int i = q * 256 + t;
-      const int e = i / NB, b = i - e * NB;
-      if (e < G) R[b * G + e] = TC(v[q]);
-    }
-  }
-
-  const int ag = t % NAG, eg = t / NAG;
-  const int a0 = 4 * ag, e0 = 4 * eg;
-  const bool act = e0 < cnt;  // e0 < cnt <= G
-  const bool hi = a0 + 2 < NB;  // rows a0+2, a0+3 exist (NB is even)
-  const int flags = A.flags;
-  // operands of the update, fetched ahead of the product
-  int64_t ge[4];
-  TV xo[4][4], dold[4][4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    ge[j] = -1;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) xo[j][i] = dold[j][i] = TV(0);
-  }
-  if (act) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (e0 + j >= cnt) break;
-      ge[j] = sperm[e0 + j];
-      const TV* xx = A.x + ge[j] * NB + a0;
-      const TV* dd = A.d + ge[j] * NB + a0;
-      if (flags & BJ_READ_X) {
-        Pair<TV> p = ld2(xx);
-        xo[j][0] = p.v[0];
-        xo[j][1] = p.v[1];
-        if (hi) {
-          p = ld2(xx + 2);
-          xo[j][2] = p.v[0];
-          xo[j][3] = p.v[1];
-        }
-      }
-      if (flags & BJ_READ_D) {
-        Pair<TV> p = ld2(dd);
-        dold[j][0] = p.v[0];
-        dold[j][1] = p.v[1];
-        if (hi) {
-          p = ld2(dd + 2);
-          dold[j][2] = p.v[0];
-          dold[j][3] = p.v[1];
-        }
-      }
-    }
-  }
-  __syncthreads();  // R, M0, M1
-
-  TC acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
-  if constexpr (!TRI) {
-    if (act)
-#pragma unroll 2
-      for (int b = 0; b < NB; ++b) tile_fma(acc, M0 + b * NBP + a0, R + b * G + e0);
-  } else {
-    // y = X r (rows a0..a0+3 need b <= a0+3), then z = X^T y (c >= a0)
-    if (act) {
-      const int bend = min(a0 + 4, NB);
-      for (int b = 0; b < bend; ++b) tile_fma(acc, M0 + b * NBP + a0, R + b * G + e0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (a0 + i < NB)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) Y[(a0 + i) * G + e0 + j] = acc[i][j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
-    if (act)
-      for (int c = a0; c < NB; ++c) tile_fma(acc, M1 + c * NBP + a0, Y + c * G + e0);
-  }
-  if (!act) return;
-
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (ge[j] < 0) break;
-    const double sc = A.scale[ge[j]];
-    TV* xx = A.x + ge[j] * NB + a0;
-    TV* dd = A.d + ge[j] * NB + a0;
-    TV xn[4], dn[4];
-    if (flags & BJ_APPLY) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xn[i] = TV(double(acc[i][j]) * sc);
-    } else {
-      const int64_t pb = ge[j] / A.nel;
-      const double ca = A.ab[2 * pb], cb = A.ab[2 * pb + 1];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double z = double(acc[i][j]) * sc;
-        double dv = cb * z;
-        if (flags & BJ_READ_D) dv += ca * double(dold[j][i]);
-        if (flags & BJ_FOLD) dv += ca * double(xo[j][i]);
-        dn[i] = TV(dv);
-        xn[i] = TV((flags & BJ_READ_X) ? double(xo[j][i]) + dv : dv);
-      }
-      if (flags & BJ_WRITE_D) {
-        st2(dd, dn[0], dn[1]);
-        if (hi) st2(dd + 2, dn[2], dn[3]);
-      }
-    }
-    st2(xx, xn[0], xn[1]);
-    if (hi) st2(xx + 2, xn[2], xn[3]);
-  }
-}
-
-int bj_group_size(int nb, bool full_f64) {
-  if (full_f64) return 16;  // one wavefront's matrix-core columns
-  const int nag = ((nb + 3) & ~3) / 4;
-  return 4 * (256 / nag);
+int bj_group_size(int nb) {
+  (void)nb;
+  return 16;  // one wavefront's matrix-core columns
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -470,6 +246,104 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Factored low-precision smoother on the matrix cores, one wavefront per work
+// item of up to 16 elements: y = X r, then z = X^T y, X = L^{-1} the packed
+// lower-triangular factor in FP32 or BF16 storage, vectors in FP32, products
+// accumulated in FP64 MFMA (the same lane layout as bj_wave_kernel).  The
+// accumulator fragment of y for rows 16t + 4r + lane/16 is exactly the
+// B-operand fragment the second product needs for its k-step 16t + 4r, so y
+// never leaves the registers.  Triangular zero blocks are skipped at compile
+// time.
+// ---------------------------------------------------------------------------
+template <typename TM>
+__device__ __forceinline__ double ldw(const TM* p) {
+  if constexpr (sizeof(TM) == 2) return double(__uint_as_float(((uint32_t)*p) << 16));
+  else return double(*p);
+}
+
+template <int K1, typename TM>
+__global__ __launch_bounds__(256) void bj_wave_tri_kernel(BjArgs<TM, float> A, int nwork) {
+  constexpr int NB = 2 * K1 * K1, KP = (NB + 3) & ~3, NT = (NB + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwork) return;
+  const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  const int c = lane & 15, kq = lane >> 4;
+  const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
+  const TM* X = A.mat + (int64_t)uid * NB * (NB + 1) / 2;
+  const int flags = A.flags;
+  float xo[NT][4], dold[NT][4];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * tt + 4 * r + kq;
+      const bool ok = ge >= 0 && i < NB;
+      xo[tt][r] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? A.x[ge * NB + i] : 0.f;
+      dold[tt][r] = (ok && (flags & BJ_READ_D)) ? A.d[ge * NB + i] : 0.f;
+    }
+  // y = X r
+  v4d y[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) y[tt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < KP; s4 += 4) {
+    const int k = s4 + kq;
+    const double b = (ge >= 0 && k < NB) ? double(A.r[ge * NB + k]) : 0.0;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      if (s4 > 16 * tt + 15) continue;  // X[i][k] = 0 for k > i
+      const int i = 16 * tt + c;
+      const double a = (k <= i && i < NB) ? ldw(X + i * (i + 1) / 2 + k) : 0.0;
+      y[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, y[tt], 0, 0, 0);
+    }
+  }
+  // z = X^T y; k-step s4 = 16 t' + 4 r' takes y[t'][r'] as its B fragment
+  v4d z[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) z[tt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < KP; s4 += 4) {
+    const int k = s4 + kq;
+    const double b = y[s4 / 16][(s4 % 16) / 4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      if (s4 + 3 < 16 * tt) continue;  // X^T[i][k] = X[k][i] = 0 for k < i
+      const int i = 16 * tt + c;
+      const double a = (i <= k && k < NB) ? ldw(X + k * (k + 1) / 2 + i) : 0.0;
+      z[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z[tt], 0, 0, 0);
+    }
+  }
+  if (ge < 0) return;
+  const double sc = A.scale[ge];
+  float* xx = A.x + ge * NB;
+  float* dd = A.d + ge * NB;
+  double ca = 0.0, cb = 1.0;
+  if (!(flags & BJ_APPLY)) {
+    const int64_t pb = ge / A.nel;
+    ca = A.ab[2 * pb];
+    cb = A.ab[2 * pb + 1];
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * tt + 4 * r + kq;
+      if (i >= NB) continue;
+      const double zv = z[tt][r] * sc;
+      if (flags & BJ_APPLY) {
+        xx[i] = float(zv);
+        continue;
+      }
+      double dv = cb * zv;
+      if (flags & BJ_READ_D) dv += ca * double(dold[tt][r]);
+      if (flags & BJ_FOLD) dv += ca * double(xo[tt][r]);
+      if (flags & BJ_WRITE_D) dd[i] = float(dv);
+      xx[i] = (flags & BJ_READ_X) ? float(double(xo[tt][r]) + dv) : float(dv);
+    }
+}
+
 template <int K1, typename TM, typename TV, bool TRI>
 static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                      hipStream_t s) {
@@ -477,14 +351,14 @@ static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* 
   if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
     hipLaunchKernelGGL((bj_wave_kernel<K1, 1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
   else
-    hipLaunchKernelGGL((bj_group_kernel<K1, TM, TV, TRI>), dim3(P.nwork), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((bj_wave_tri_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
 }
 
 template <typename TM, typename TV, bool TRI>
 static int launch_group(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                         hipStream_t s) {
   if (P.nwork <= 0) return SDG_OK;
-  if (P.G < 4 || P.G % 4 || P.G > bj_group_size(P.nb, !TRI && sizeof(TM) == 8 && sizeof(TV) == 8)) {
+  if (P.G < 4 || P.G % 4 || P.G > 16) {  // one wavefront's 16 matrix-core columns
     set_error("block smoother: group size does not fit one workgroup");
     return SDG_ERR_INVALID;
   }

@@ -47,10 +47,8 @@ struct BjPlan {
   const int* work;
   const double* scale;
 };
-// largest G for an element block of nb unknowns: the FP64 full-inverse form
-// (one wavefront per work item on the matrix cores) or the factored
-// low-precision form (LDS-staged, 4 x 4 register tiles)
-int bj_group_size(int nb, bool full_f64);
+// largest G for an element block of nb unknowns (one wavefront per work item)
+int bj_group_size(int nb);
 // update flags: d' = b z + a d_old, x' = x + d' (see block_kernels.hip)
 enum BjFlags { BJ_READ_X = 1, BJ_READ_D = 2, BJ_FOLD = 4, BJ_WRITE_D = 8, BJ_APPLY = 16 };
 int bj_cheb_f64(const BjPlan& P, const double* binv, const double* r, const double* ab, double* d, double* x,

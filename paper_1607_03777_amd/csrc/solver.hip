@@ -325,11 +325,8 @@ int setup_blocks(sdg_problem* P) {
   P->nuniq = (int)P->reps.size();
   // group the elements by block (counting sort, element order kept inside
   // a group) and cut each group into work items of at most G elements
-  // FP64: 16 elements per wavefront; factored low precision: at least ~512
-  // work items where the batch allows it (one per CU pair)
-  const bool full64 = !(P->opt.prec_apply == SDG_FP32 || P->opt.prec_smoother != SDG_FP64);
-  const int G = full64 ? bj_group_size(P->NB, true)
-                       : std::max(16, std::min(bj_group_size(P->NB, false), 4 * (int)((ntot + 2047) / 2048)));
+  // 16 elements per work item: one wavefront's matrix-core columns
+  const int G = bj_group_size(P->NB);
   std::vector<int> first(P->nuniq + 1, 0);
   for (int64_t ge = 0; ge < ntot; ++ge) ++first[ids[ge] + 1];
   for (int u = 0; u < P->nuniq; ++u) first[u + 1] += first[u];
