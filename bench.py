@@ -380,7 +380,7 @@ def main():
         return f"sip_tile_kernel<{K + 1},{mode},double,{t['shape'][0]},{t['shape'][1]}>"
     kernel_names = {"sip_apply": kname(tiles["apply"], "apply"),
                     "sip_residual": kname(tiles["residual"], "residual"),
-                    "block_jacobi_smoother": f"bj_wave_kernel<{K + 1},1>"}
+                    "block_jacobi_smoother": f"bj_wave_kernel<{K + 1}>"}
     cand = {k: v for k, v in traced.items() if v["bytes_per_launch"] > 0}
     dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else "sip_residual"
     h = sdg.sdg_problem_create_batch(ctx, mesh, opts, B, eta, stream)

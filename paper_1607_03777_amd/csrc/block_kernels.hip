@@ -157,100 +157,106 @@ int bj_group_size(int nb) {
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Row order of the FP64 kernel.  Within every 16-row group the lane group q
+// (= lane / 16) holds rows 8h + 2q + s, h, s in {0, 1}: two adjacent pairs,
+// so vectors move as 16-byte pairs and each element's 128-byte stretch of a
+// group is read by one instruction pair.  The matrix-core products follow
+// that order: k-step (g, h, s) contracts rows 16g + 8h + 2q + s, and block
+// row 16t + perm16(i) feeds accumulator row i, where
+// perm16(4r + q) = 8(r >> 1) + 2q + (r & 1); accumulator component r of
+// lane group q then holds output row 16t + 8(r >> 1) + 2q + (r & 1), the
+// same pair layout as the inputs.
+__device__ __forceinline__ int perm16(int i) { return 8 * (i >> 3) + 2 * (i & 3) + ((i >> 2) & 1); }
 
 // ---------------------------------------------------------------------------
-// FP64 full inverse, one wavefront per work item of up to 16 NG elements, no
-// LDS and no barriers.  Lane (c, kq) = (lane % 16, lane / 16) gathers the
-// residual fragments of elements c + 16 g (rows 4s + kq: 32 contiguous bytes
-// per element across the four lane groups); each block fragment, read from
-// L1/L2 (a block is shared by many work items), feeds NG products; the update
-// reads and writes the rows of the accumulator fragments
-// (D[16t + 4r + kq][c]).  Waves are independent, so the latency of one hides
+// FP64 full inverse, one wavefront per work item of up to 16 elements, no
+// LDS and no barriers.  Lane (c, q) = (lane % 16, lane / 16) works on
+// element c; its residual, x and d rows come in 16-byte pairs (row order
+// above), each block fragment pair, read from L1/L2 (a block is shared by
+// many work items), feeds two products.  The update operands are fetched
+// before the product.  Waves are independent, so the latency of one hides
 // behind the others.
 // ---------------------------------------------------------------------------
-template <int K1, int NG>
+template <int K1>
 __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
-  constexpr int NB = 2 * K1 * K1, KP = (NB + 3) & ~3, NT = (NB + 15) / 16;
+  constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwork) return;
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
-  const int c = lane & 15, kq = lane >> 4;
-  int64_t ge[NG];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) ge[g] = (c + 16 * g < cnt) ? A.perm[start + c + 16 * g] : -1;
+  const int c = lane & 15, q = lane >> 4;
+  const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
   const double* B = A.mat + (int64_t)uid * NB * NB;
+  const int prow = perm16(c);
   const int flags = A.flags;
-  // operands of the update, fetched ahead of the product
-  double xo[NG][NT][4], dold[NG][NT][4];
+  // operands of the update: rows 16t + 8h + 2q, +1
+  v2d xo[NT][2], dold[NT][2];
 #pragma unroll
-  for (int g = 0; g < NG; ++g)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * tt + 4 * r + kq;
-        const bool ok = ge[g] >= 0 && i < NB;
-        xo[g][tt][r] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? A.x[ge[g] * NB + i] : 0.0;
-        dold[g][tt][r] = (ok && (flags & BJ_READ_D)) ? A.d[ge[g] * NB + i] : 0.0;
-      }
-  v4d acc[NG][NT];
-#pragma unroll
-  for (int g = 0; g < NG; ++g)
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) acc[g][tt] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-  for (int s4 = 0; s4 < KP; s4 += 4) {
-    const int k = s4 + kq;
-    double bv[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g) bv[g] = (ge[g] >= 0 && k < NB) ? A.r[ge[g] * NB + k] : 0.0;
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      const int i = 16 * tt + c;
-      // A[i][k] = B[k][i] (the block is symmetric)
-      const double a = (k < NB && i < NB) ? B[k * NB + i] : 0.0;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc[g][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[g], acc[g][tt], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      const int i = 16 * t + 8 * h + 2 * q;
+      const bool ok = ge >= 0 && i < NB;
+      xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2d*>(A.x + ge * NB + i)
+                                                          : v2d{0.0, 0.0};
+      dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2d*>(A.d + ge * NB + i) : v2d{0.0, 0.0};
     }
+  v4d acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int g = 0; g < NT; ++g)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (16 * g + 8 * h >= NB) continue;
+      const int k0 = 16 * g + 8 * h + 2 * q;
+      const v2d rb = (ge >= 0 && k0 < NB) ? *reinterpret_cast<const v2d*>(A.r + ge * NB + k0) : v2d{0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int arow = 16 * t + prow;
+        // A[i][k] = Binv[arow][k] (the block is symmetric either way)
+        const v2d a = (arow < NB && k0 < NB) ? *reinterpret_cast<const v2d*>(B + arow * NB + k0) : v2d{0.0, 0.0};
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, rb.x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, rb.y, acc[t], 0, 0, 0);
+      }
+    }
+  if (ge < 0) return;
+  const double sc = A.scale[ge];
+  double* xx = A.x + ge * NB;
+  double* dd = A.d + ge * NB;
+  double ca = 0.0, cb = 1.0;
+  if (!(flags & BJ_APPLY)) {
+    const int64_t pb = ge / A.nel;
+    ca = A.ab[2 * pb];
+    cb = A.ab[2 * pb + 1];
   }
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    if (ge[g] < 0) continue;
-    const double sc = A.scale[ge[g]];
-    double* xx = A.x + ge[g] * NB;
-    double* dd = A.d + ge[g] * NB;
-    double ca = 0.0, cb = 1.0;
-    if (!(flags & BJ_APPLY)) {
-      const int64_t pb = ge[g] / A.nel;
-      ca = A.ab[2 * pb];
-      cb = A.ab[2 * pb + 1];
-    }
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * tt + 4 * r + kq;
-        if (i >= NB) continue;
-        const double z = acc[g][tt][r] * sc;
-        if (flags & BJ_APPLY) {
-          xx[i] = z;
-          continue;
-        }
-        double dv = cb * z;
-        if (flags & BJ_READ_D) dv += ca * dold[g][tt][r];
-        if (flags & BJ_FOLD) dv += ca * xo[g][tt][r];
-        if (flags & BJ_WRITE_D) dd[i] = dv;
-        xx[i] = (flags & BJ_READ_X) ? xo[g][tt][r] + dv : dv;
+    for (int h = 0; h < 2; ++h) {
+      const int i = 16 * t + 8 * h + 2 * q;
+      if (i >= NB) continue;
+      const v2d z = v2d{acc[t][2 * h], acc[t][2 * h + 1]} * sc;
+      if (flags & BJ_APPLY) {
+        *reinterpret_cast<v2d*>(xx + i) = z;
+        continue;
       }
-  }
+      v2d dv = cb * z;
+      if (flags & BJ_READ_D) dv += ca * dold[t][h];
+      if (flags & BJ_FOLD) dv += ca * xo[t][h];
+      if (flags & BJ_WRITE_D) *reinterpret_cast<v2d*>(dd + i) = dv;
+      *reinterpret_cast<v2d*>(xx + i) = (flags & BJ_READ_X) ? xo[t][h] + dv : dv;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Factored low-precision smoother on the matrix cores, one wavefront per work
 // item of up to 16 elements: y = X r, then z = X^T y, X = L^{-1} the packed
 // lower-triangular factor in FP32 or BF16 storage, vectors in FP32, products
-// accumulated in FP64 MFMA (the same lane layout as bj_wave_kernel).  The
+// accumulated in FP64 MFMA in natural row order (accumulator component r of
+// lane group lane/16 holds row 16t + 4r + lane/16).  The
 // accumulator fragment of y for rows 16t + 4r + lane/16 is exactly the
 // B-operand fragment the second product needs for its k-step 16t + 4r, so y
 // never leaves the registers.  Triangular zero blocks are skipped at compile
@@ -349,7 +355,7 @@ static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* 
                      hipStream_t s) {
   BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
   if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
-    hipLaunchKernelGGL((bj_wave_kernel<K1, 1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+    hipLaunchKernelGGL((bj_wave_kernel<K1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
   else
     hipLaunchKernelGGL((bj_wave_tri_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
 }
@@ -362,9 +368,10 @@ static int launch_group(const BjPlan& P, const TM* mat, const TV* r, const doubl
     set_error("block smoother: group size does not fit one workgroup");
     return SDG_ERR_INVALID;
   }
-  // the update moves pairs of values: x and d must be aligned to two values
+  // vectors move in pairs of values: r, x and d must be aligned to two values
   const uintptr_t al = 2 * sizeof(TV);
-  if (reinterpret_cast<uintptr_t>(x) % al || reinterpret_cast<uintptr_t>(d) % al) {
+  if (reinterpret_cast<uintptr_t>(x) % al || reinterpret_cast<uintptr_t>(d) % al ||
+      reinterpret_cast<uintptr_t>(r) % al || reinterpret_cast<uintptr_t>(mat) % 16) {
     set_error("block smoother: vectors must be aligned to two values");
     return SDG_ERR_INVALID;
   }

@@ -37,6 +37,15 @@ __host__ __device__ __forceinline__ constexpr bool d_nz(int m, int i) { return m
 __host__ __device__ __forceinline__ double d_val(int m, int i) {
   return sqrt((2.0 * m + 1.0) * (2.0 * i + 1.0));
 }
+// Workgroups of one launch are handed to the eight XCDs of the chip in turn
+// (linear id modulo 8), and each XCD has its own L2.  xcd_order maps the
+// linear id to a logical index such that every XCD receives one contiguous
+// range of logical indices: neighbouring tiles then share an L2.  It is a
+// bijection on [0, total).
+__device__ __forceinline__ uint32_t xcd_order(uint32_t lid, uint32_t total) {
+  const uint32_t q = total >> 3, r = total & 7, x = lid & 7, k = lid >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
 // 1D stiffness S = D^T D: int lhat_i' lhat_l' = sqrt((2i+1)(2l+1))/2 *
 // min(i,l)(min(i,l)+1) when i + l is even, else 0.
 __host__ __device__ __forceinline__ constexpr bool s_nz(int i, int l) {

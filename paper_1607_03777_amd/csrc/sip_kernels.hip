@@ -612,14 +612,18 @@ __global__ __launch_bounds__(NT, (K1 >= 7 ? 3 : 1)) void sip_tile_kernel(MeshDev
 // Wavefront kernel (apply / residual): one 64-lane wavefront per tile of
 // WT::TX x WT::TY elements, K1 lanes per element.  Lane (el, j) first holds
 // row j of both components of its element (x-direction work: x-face traces,
-// S_x), then, through the element staged in LDS, column j (y-direction
-// work: y-face traces, S_y, the mixed term of y0), then mode j of its
-// element's four faces (face coefficients, applied to its own row and
-// column) and the mixed term of y1; the column results come back to the row
-// lanes through LDS.  Traces of neighbours outside the tile are formed by
-// the boundary lanes from their rows/columns in HBM/L2.  Every loop runs
-// over compile-time mode counts; the lane's element and row are decoded
-// once.
+// S_x), then mode j of its element's two x-faces (face coefficients applied
+// to its own row); then, through the element staged in LDS, column j
+// (y-direction work: y-face traces, S_y, the mixed term of y0), then mode j
+// of the two y-faces (applied to its own column) and the mixed term of y1;
+// the column results come back to the row lanes through LDS.  The x-faces
+// and the y-faces take turns in one face buffer, so a wavefront holds about
+// 10 KB of LDS at k = 4 in FP64 and sixteen of them fit a compute unit.
+// Traces of neighbours outside the tile are formed by the edge lanes from
+// their rows/columns in HBM/L2, requested together with the tile's own rows
+// so that their latency overlaps; every face slot is written in each phase
+// (zeros where the mesh ends).  The few entries of the derivative matrix D a
+// lane needs (row and column of its mode j) are held in registers.
 // ---------------------------------------------------------------------------
 template <int K1> struct WaveTile;
 template <> struct WaveTile<2> { static constexpr int TX = 8, TY = 4; };
@@ -629,49 +633,139 @@ template <> struct WaveTile<5> { static constexpr int TX = 4, TY = 3; };
 template <> struct WaveTile<6> { static constexpr int TX = 5, TY = 2; };
 template <> struct WaveTile<7> { static constexpr int TX = 3, TY = 3; };
 
+// Face coefficients at mode m (the formulas of face_mode above), with the
+// derivative entries taken from registers: up[t] = D(m, m+1+2t),
+// dn[t] = D(m-1-2t, m); ihn = 1/hn and iht = 1/ht are passed in, so the
+// coefficients take no divisions.
+template <int K1, int DIR, typename T>
+__device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int kind, int side, T etam, T etap,
+                                            T ihn, T iht, const T (&up)[K1 / 2], const T (&dn)[K1 / 2],
+                                            T (&o)[8]) {
+  constexpr int N = DIR, TT = 1 - DIR;
+#pragma unroll
+  for (int z = 0; z < 8; ++z) o[z] = T(0);
+  if (kind < 0 || kind == F_NEUMANN) return;
+  const T kk = T(K1 * K1);
+  const T c2n = T(2) * ihn, c2t = T(2) * iht;
+  auto at = [&](int s, int d, int w, int j) { return f[((s * 2 + d) * 2 + w) * K1 + j]; };
+  if (kind == F_NAVIER) {
+    const T eta = side == 0 ? etam : etap;
+    const T alpha = T(8) * eta * kk * ihn;
+    const T sgn = side == 0 ? T(1) : T(-1);
+    const T w = T(4) * eta * ihn;
+    const T t = at(side, N, 0, m), g = at(side, N, 1, m);
+    o[(side * 2 + N) * 2 + 0] = c2n * (alpha * t - sgn * w * g);
+    o[(side * 2 + N) * 2 + 1] = -c2n * sgn * w * t;
+    return;
+  }
+  // interior face; a Dirichlet face switches the outer trace off and counts
+  // the present side's viscosity twice
+  T mm = T(1), mp = T(1), em = etam, ep = etap, alpha;
+  int sides = 3;
+  if (kind == F_INTERIOR) {
+    alpha = T(4) * (etam > etap ? etam : etap) * kk * ihn;
+  } else {
+    const T eta2 = T(2) * (side == 0 ? etam : etap);
+    alpha = T(4) * eta2 * kk * ihn;
+    if (side == 0) {
+      mp = T(0);
+      em = eta2;
+      ep = T(0);
+      sides = 1;
+    } else {
+      mm = T(0);
+      em = T(0);
+      ep = eta2;
+      sides = 2;
+    }
+  }
+  T dtm = 0, dtp = 0, dtj = 0;
+#pragma unroll
+  for (int t = 0; t < K1 / 2; ++t) {
+    const int jp = m + 1 + 2 * t, jn = m - 1 - 2 * t;
+    if (jp < K1) {
+      dtm += up[t] * (mm * at(0, N, 0, jp));
+      dtp += up[t] * (mp * at(1, N, 0, jp));
+    }
+    if (jn >= 0) dtj += dn[t] * (mm * at(0, TT, 0, jn) - mp * at(1, TT, 0, jn));
+  }
+  const T jn = mm * at(0, N, 0, m) - mp * at(1, N, 0, m);
+  const T jt = mm * at(0, TT, 0, m) - mp * at(1, TT, 0, m);
+  const T sn = c2n * (em * (mm * at(0, N, 1, m)) + ep * (mp * at(1, N, 1, m)));
+  const T st = T(0.5) * (c2t * (em * dtm + ep * dtp) +
+                         c2n * (em * (mm * at(0, TT, 1, m)) + ep * (mp * at(1, TT, 1, m))));
+  const T qn = -sn + alpha * jn;
+  const T qt = -st + alpha * jt;
+  if (sides & 1) {
+    o[(0 * 2 + N) * 2 + 0] = c2n * (qn - em * iht * dtj);
+    o[(0 * 2 + N) * 2 + 1] = -c2n * c2n * em * jn;
+    o[(0 * 2 + TT) * 2 + 0] = c2n * qt;
+    o[(0 * 2 + TT) * 2 + 1] = -c2n * ihn * em * jt;
+  }
+  if (sides & 2) {
+    o[(1 * 2 + N) * 2 + 0] = -c2n * (qn + ep * iht * dtj);
+    o[(1 * 2 + N) * 2 + 1] = -c2n * c2n * ep * jn;
+    o[(1 * 2 + TT) * 2 + 0] = -c2n * qt;
+    o[(1 * 2 + TT) * 2 + 1] = -c2n * ihn * ep * jt;
+  }
+}
+
 template <int K1, int MODE, typename T>
 __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
                                                       const T* __restrict__ bvec, T* __restrict__ y,
                                                       const double* __restrict__ eta_all, int64_t vec_stride) {
   constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
-  constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY;
+  constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY, NH = K1 / 2;
   static_assert(E * K1 <= 64, "tile does not fit a wavefront");
-  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), FW = 8 * K1, FS = FW + 1, EW = TX + 2;
-  __shared__ T su[E * NB];                // [el][d][j][i]; later the column results
-  __shared__ T sf[(NFV + NFH) * FS];      // face records [s][d][w][m]
-  __shared__ T seta[(TY + 2) * EW];
-  __shared__ T sdm[K1 * K1];
+  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), NF = NFV > NFH ? NFV : NFH, FS = 8 * K1 + 1;
+  __shared__ T su[E * NB];  // [el][d][j][i]; later the column results
+  __shared__ T sf[NF * FS];  // face records [s][d][w][m]: the x-faces, then the y-faces
   const int lane = threadIdx.x;
   const int nx = M.nx, ny = M.ny;
   const int ntx = (nx + TX - 1) / TX;
-  const int ix0 = (blockIdx.x % ntx) * TX, iy0 = (blockIdx.x / ntx) * TY;
-  const int64_t pb = blockIdx.y;
+  // tiles in XCD-contiguous order (the grid is tiles x problems)
+  const uint32_t lt = xcd_order(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int tile = (int)(lt % gridDim.x);
+  const int ix0 = (tile % ntx) * TX, iy0 = (tile / ntx) * TY;
+  const int64_t pb = lt / gridDim.x;
   const double* eta = eta_all + pb * (int64_t)nx * ny;
   u += pb * vec_stride;
   y += pb * vec_stride;
   if (MODE == M_RESID) bvec += pb * vec_stride;
-  const T hx = T(M.hx), hy = T(M.hy);
+  const T ihx = T(1.0 / M.hx), ihy = T(1.0 / M.hy);
 
-  const int el = lane / K1, j = lane - el * K1;  // j: row, then column, then face mode
+  const int el = lane / K1, j = lane - el * K1;  // j: row, then face mode and column
   const bool act = el < E;
   const int tx = el % TX, ty = el / TX;
   const int ix = ix0 + tx, iy = iy0 + ty;
   const bool valid = act && ix < nx && iy < ny;
   const int64_t ge = (int64_t)iy * nx + ix;
 
-  for (int q = lane; q < (TY + 2) * EW; q += 64) {
-    const int qx = ix0 - 1 + q % EW, qy = iy0 - 1 + q / EW;
-    seta[q] = (qx >= 0 && qx < nx && qy >= 0 && qy < ny) ? T(eta[(int64_t)qy * nx + qx]) : T(0);
+  // viscosity of the element and of its neighbours (the element's own where
+  // the mesh ends: boundary faces read only the present side)
+  T et = T(0), eL = T(0), eR = T(0), eB = T(0), eT = T(0);
+  if (valid) {
+    et = T(eta[ge]);
+    eL = ix > 0 ? T(eta[ge - 1]) : et;
+    eR = ix + 1 < nx ? T(eta[ge + 1]) : et;
+    eB = iy > 0 ? T(eta[ge - nx]) : et;
+    eT = iy + 1 < ny ? T(eta[ge + nx]) : et;
   }
-  for (int q = lane; q < K1 * K1; q += 64) {
-    const int m = q / K1, i = q % K1;
-    sdm[q] = d_nz(m, i) ? T(d_val(m, i)) : T(0);
+  T up[NH], dn[NH];
+#pragma unroll
+  for (int t = 0; t < NH; ++t) {
+    T a = T(0), b = T(0);
+#pragma unroll
+    for (int q = 0; q < K1; ++q)
+      if (j == q) {
+        if (q + 1 + 2 * t < K1) a = T(d_val(q, q + 1 + 2 * t));
+        if (q - 1 - 2 * t >= 0) b = T(d_val(q - 1 - 2 * t, q));
+      }
+    up[t] = a;
+    dn[t] = b;
   }
-  for (int q = lane; q < (NFV + NFH) * FS; q += 64) sf[q] = T(0);
-  __syncthreads();
 
-  const T et = act ? seta[(ty + 1) * EW + tx + 1] : T(0);
-  const T cxx = T(4) / (hx * hx), cyy = T(4) / (hy * hy), cxy = T(4) / (hx * hy);
+  const T cxx = T(4) * ihx * ihx, cyy = T(4) * ihy * ihy, cxy = T(4) * ihx * ihy;
   auto trace4 = [](const T (&v)[K1], T& tl, T& gl, T& tr, T& gr) {
     tl = gl = tr = gr = T(0);
 #pragma unroll
@@ -683,46 +777,51 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     }
   };
 
+  // neighbour data outside the tile, requested up front with the element's
+  // own rows: edge lanes in x take row j of the left/right neighbour, edge
+  // lanes in y column j of the bottom/top neighbour (tiles are at least two
+  // elements wide and tall, so a lane needs at most one of each)
+  const int64_t gx = (tx == 0 && ix > 0) ? ge - 1 : (tx == TX - 1 && ix + 1 < nx) ? ge + 1 : -1;
+  const int64_t gy = (ty == 0 && iy > 0) ? ge - nx : (ty == TY - 1 && iy + 1 < ny) ? ge + nx : -1;
+  T hxr[2][K1], hyc[2][K1];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      hxr[d][i] = (valid && gx >= 0) ? u[gx * NB + d * KK + j * K1 + i] : T(0);
+      hyc[d][i] = (valid && gy >= 0) ? u[gy * NB + d * KK + i * K1 + j] : T(0);
+    }
+
   // ---- rows: stage the element, x-face traces, S_x
-  T yr[2][K1], bres[2][K1];
+  T yr[2][K1];
+  T* fl = sf + (ty * (TX + 1) + tx) * FS;  // left x-face, this element on the plus side
+  T* fr = fl + FS;                          // right x-face, minus side
   if (act) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       T r[K1];
 #pragma unroll
       for (int i = 0; i < K1; ++i) r[i] = valid ? u[ge * NB + d * KK + j * K1 + i] : T(0);
-      if constexpr (MODE == M_RESID) {
-#pragma unroll
-        for (int i = 0; i < K1; ++i) bres[d][i] = valid ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
-      }
 #pragma unroll
       for (int i = 0; i < K1; ++i) su[el * NB + d * KK + j * K1 + i] = r[i];
       T tl, gl, tr, gr;
       trace4(r, tl, gl, tr, gr);
-      T* fl = sf + (ty * (TX + 1) + tx) * FS;      // left face, this element on the plus side
-      T* fr = sf + (ty * (TX + 1) + tx + 1) * FS;  // right face, minus side
       fl[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
       fl[((1 * 2 + d) * 2 + 1) * K1 + j] = gl;
       fr[((0 * 2 + d) * 2 + 0) * K1 + j] = tr;
       fr[((0 * 2 + d) * 2 + 1) * K1 + j] = gr;
-      // neighbours across the tile's left and right edges
-      if (valid && tx == 0 && ix > 0) {
-        T v[K1];
-#pragma unroll
-        for (int i = 0; i < K1; ++i) v[i] = u[(ge - 1) * NB + d * KK + j * K1 + i];
+      // the outer sides of the tile's left and right faces (zero where the
+      // mesh ends: hxr is zero there)
+      if (tx == 0 || tx == TX - 1) {
         T a0, a1, a2, a3;
-        trace4(v, a0, a1, a2, a3);
-        fl[((0 * 2 + d) * 2 + 0) * K1 + j] = a2;
-        fl[((0 * 2 + d) * 2 + 1) * K1 + j] = a3;
-      }
-      if (valid && tx == TX - 1 && ix + 1 < nx) {
-        T v[K1];
-#pragma unroll
-        for (int i = 0; i < K1; ++i) v[i] = u[(ge + 1) * NB + d * KK + j * K1 + i];
-        T a0, a1, a2, a3;
-        trace4(v, a0, a1, a2, a3);
-        fr[((1 * 2 + d) * 2 + 0) * K1 + j] = a0;
-        fr[((1 * 2 + d) * 2 + 1) * K1 + j] = a1;
+        trace4(hxr[d], a0, a1, a2, a3);
+        if (tx == 0) {
+          fl[((0 * 2 + d) * 2 + 0) * K1 + j] = a2;
+          fl[((0 * 2 + d) * 2 + 1) * K1 + j] = a3;
+        } else {
+          fr[((1 * 2 + d) * 2 + 0) * K1 + j] = a0;
+          fr[((1 * 2 + d) * 2 + 1) * K1 + j] = a1;
+        }
       }
       const T cx = (d == 0 ? T(2) : T(1)) * et * cxx;
 #pragma unroll
@@ -737,11 +836,48 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   }
   __syncthreads();
 
-  // ---- columns (lane column i = j): y-face traces, S_y, mixed term of y0
+  // ---- x-faces at mode m = j, applied to row j
+  if (act) {
+    T o[8];
+    {
+      const int kind = ix > 0 ? F_INTERIOR : M.bc[0];
+      face_mode_w<K1, 0, T>(fl, j, valid ? kind : -1, 1, eL, et, ihx, ihy, up, dn, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 0)) + b * T(d_end(i, 0));
+      }
+    }
+    {
+      const int kind = ix + 1 < nx ? F_INTERIOR : M.bc[1];
+      face_mode_w<K1, 0, T>(fr, j, valid ? kind : -1, 0, et, eR, ihx, ihy, up, dn, o);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 1)) + b * T(d_end(i, 1));
+      }
+    }
+  }
+  __syncthreads();  // the face buffer is free again
+
+  // the residual's right-hand side, requested before the column work
+  T bres[2][K1];
+  if constexpr (MODE == M_RESID) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int i = 0; i < K1; ++i) bres[d][i] = valid ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
+  }
+
+  // ---- columns (lane column ic = j): y-face traces, S_y, mixed term of y0
   T yc[2][K1];
   const int ic = j;
+  const T* ue = su + el * NB;
+  T* fb = sf + (ty * TX + tx) * FS;        // bottom y-face, this element on the plus side
+  T* ft = sf + ((ty + 1) * TX + tx) * FS;  // top y-face, minus side
   if (act) {
-    const T* ue = su + el * NB;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       T c[K1];
@@ -749,29 +885,20 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       for (int jj = 0; jj < K1; ++jj) c[jj] = ue[d * KK + jj * K1 + ic];
       T tb, gb, tt, gt;
       trace4(c, tb, gb, tt, gt);
-      T* fb = sf + (NFV + ty * TX + tx) * FS;        // bottom face, this element on the plus side
-      T* ft = sf + (NFV + (ty + 1) * TX + tx) * FS;  // top face, minus side
       fb[((1 * 2 + d) * 2 + 0) * K1 + ic] = tb;
       fb[((1 * 2 + d) * 2 + 1) * K1 + ic] = gb;
       ft[((0 * 2 + d) * 2 + 0) * K1 + ic] = tt;
       ft[((0 * 2 + d) * 2 + 1) * K1 + ic] = gt;
-      if (valid && ty == 0 && iy > 0) {
-        T v[K1];
-#pragma unroll
-        for (int jj = 0; jj < K1; ++jj) v[jj] = u[(ge - nx) * NB + d * KK + jj * K1 + ic];
+      if (ty == 0 || ty == TY - 1) {
         T a0, a1, a2, a3;
-        trace4(v, a0, a1, a2, a3);
-        fb[((0 * 2 + d) * 2 + 0) * K1 + ic] = a2;
-        fb[((0 * 2 + d) * 2 + 1) * K1 + ic] = a3;
-      }
-      if (valid && ty == TY - 1 && iy + 1 < ny) {
-        T v[K1];
-#pragma unroll
-        for (int jj = 0; jj < K1; ++jj) v[jj] = u[(ge + nx) * NB + d * KK + jj * K1 + ic];
-        T a0, a1, a2, a3;
-        trace4(v, a0, a1, a2, a3);
-        ft[((1 * 2 + d) * 2 + 0) * K1 + ic] = a0;
-        ft[((1 * 2 + d) * 2 + 1) * K1 + ic] = a1;
+        trace4(hyc[d], a0, a1, a2, a3);
+        if (ty == 0) {
+          fb[((0 * 2 + d) * 2 + 0) * K1 + ic] = a2;
+          fb[((0 * 2 + d) * 2 + 1) * K1 + ic] = a3;
+        } else {
+          ft[((1 * 2 + d) * 2 + 0) * K1 + ic] = a0;
+          ft[((1 * 2 + d) * 2 + 1) * K1 + ic] = a1;
+        }
       }
       const T cy = (d == 1 ? T(2) : T(1)) * et * cyy;
 #pragma unroll
@@ -787,10 +914,13 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     T w[K1];
 #pragma unroll
     for (int m = 0; m < K1; ++m) w[m] = T(0);
-    for (int l = ic + 1; l < K1; l += 2) {
-      const T cdl = sdm[ic * K1 + l];
 #pragma unroll
-      for (int m = 0; m < K1; ++m) w[m] += cdl * ue[KK + m * K1 + l];
+    for (int t = 0; t < NH; ++t) {
+      const int l = ic + 1 + 2 * t;
+      if (l < K1) {
+#pragma unroll
+        for (int m = 0; m < K1; ++m) w[m] += up[t] * ue[KK + m * K1 + l];
+      }
     }
 #pragma unroll
     for (int jj = 0; jj < K1; ++jj) {
@@ -803,38 +933,12 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   }
   __syncthreads();
 
-  // ---- faces (mode m = j of this element's four faces) and the mixed term of y1
+  // ---- y-faces at mode m = j, applied to column j; mixed term of y1
   if (act) {
-    const int m = j;
     T o[8];
-    // x-faces: left (this element = plus side), right (minus side)
-    {
-      const int kind = ix > 0 ? F_INTERIOR : M.bc[0];
-      face_mode<K1, 0, T>(sf + (ty * (TX + 1) + tx) * FS, m, valid ? kind : -1, 1, seta[(ty + 1) * EW + tx], et,
-                          hx, hy, false, false, sdm, o);
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
-#pragma unroll
-        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 0)) + b * T(d_end(i, 0));
-      }
-    }
-    {
-      const int kind = ix + 1 < nx ? F_INTERIOR : M.bc[1];
-      face_mode<K1, 0, T>(sf + (ty * (TX + 1) + tx + 1) * FS, m, valid ? kind : -1, 0, et,
-                          seta[(ty + 1) * EW + tx + 2], hx, hy, false, false, sdm, o);
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
-#pragma unroll
-        for (int i = 0; i < K1; ++i) yr[d][i] += a * T(e_end(i, 1)) + b * T(d_end(i, 1));
-      }
-    }
-    // y-faces: bottom (plus side), top (minus side), applied to column m
     {
       const int kind = iy > 0 ? F_INTERIOR : M.bc[2];
-      face_mode<K1, 1, T>(sf + (NFV + ty * TX + tx) * FS, m, valid ? kind : -1, 1, seta[ty * EW + tx + 1], et, hy,
-                          hx, false, false, sdm, o);
+      face_mode_w<K1, 1, T>(fb, j, valid ? kind : -1, 1, eB, et, ihy, ihx, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
@@ -844,8 +948,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     }
     {
       const int kind = iy + 1 < ny ? F_INTERIOR : M.bc[3];
-      face_mode<K1, 1, T>(sf + (NFV + (ty + 1) * TX + tx) * FS, m, valid ? kind : -1, 0, et,
-                          seta[(ty + 2) * EW + tx + 1], hy, hx, false, false, sdm, o);
+      face_mode_w<K1, 1, T>(ft, j, valid ? kind : -1, 0, et, eT, ihy, ihx, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
@@ -854,14 +957,16 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       }
     }
     // D_x^T (D_y u0) on row j: (D_y u0)[j][m'] = sum_{l > j} D(j, l) u0[l][m']
-    const T* ue = su + el * NB;
     T r0[K1];
 #pragma unroll
     for (int mm = 0; mm < K1; ++mm) r0[mm] = T(0);
-    for (int l = j + 1; l < K1; l += 2) {
-      const T cdl = sdm[j * K1 + l];
 #pragma unroll
-      for (int mm = 0; mm < K1; ++mm) r0[mm] += cdl * ue[l * K1 + mm];
+    for (int t = 0; t < NH; ++t) {
+      const int l = j + 1 + 2 * t;
+      if (l < K1) {
+#pragma unroll
+        for (int mm = 0; mm < K1; ++mm) r0[mm] += up[t] * ue[l * K1 + mm];
+      }
     }
 #pragma unroll
     for (int i = 0; i < K1; ++i) {
@@ -886,9 +991,10 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     for (int d = 0; d < 2; ++d)
 #pragma unroll
       for (int i = 0; i < K1; ++i) {
+        const int64_t g = ge * NB + d * KK + j * K1 + i;
         const T v = yr[d][i] + su[el * NB + d * KK + j * K1 + i];
-        if constexpr (MODE == M_RESID) y[ge * NB + d * KK + j * K1 + i] = bres[d][i] - v;
-        else y[ge * NB + d * KK + j * K1 + i] = v;
+        if constexpr (MODE == M_RESID) y[g] = bres[d][i] - v;
+        else y[g] = v;
       }
   }
 }
@@ -1219,9 +1325,13 @@ static int launch_tile(const MeshDev& M, int nbatch, const T* u, const T* b, T* 
 }
 
 int sip_tile_variants(int k) { return (k >= 1 && k <= 6) ? TILE_NV[k + 1] + 1 : 0; }
-// default shape per order and precision, from sweeps at 64 x 64 x 16
-// problems: FP64 k <= 4 the first tile shape, otherwise the wavefront kernel
-int sip_tile_default(int k, bool fp32) { return (!fp32 && k <= 4) ? 1 : 0; }
+// default kernel form per order and precision, from sweeps at 64 x 64 x 16
+// (k = 4) and 64 x 64 x 8 problems: the wavefront kernel for every order
+int sip_tile_default(int k, bool fp32) {
+  (void)k;
+  (void)fp32;
+  return 0;
+}
 void sip_tile_shape(int k, int var, int* tx, int* ty) {
   const bool ok = k >= 1 && k <= 6 && var >= 0 && var <= TILE_NV[k + 1];
   *tx = *ty = 0;
