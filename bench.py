@@ -155,9 +155,10 @@ def serving(sdg, ctx, nreq, rate, prec):
 
 def kernel_probe(sdg, ctx, torch, B, reps):
     """Only the operator kernels at the step's shape (batch B of the 64 x 64,
-    k = 4 problem): `reps` launches each of the SIP residual and apply, then
-    `reps` plain device copies of the residual's vector (known bytes) that
-    calibrate the HBM counters.  For rocprofv3 counter runs."""
+    k = 4 problem): `reps` launches each of the SIP residual, the SIP apply
+    and the block-Jacobi apply, then `reps` plain device copies of the
+    residual's vector (known bytes) that calibrate the HBM counters.  For
+    rocprofv3 counter runs."""
     from paper_1607_03777_amd import inputs as gen
     P0 = gen.single_inclusion(N, K, eta_in=ETA_IN)
     nel, nb = N * N, 2 * (K + 1) ** 2
@@ -172,6 +173,8 @@ def kernel_probe(sdg, ctx, torch, B, reps):
     for _ in range(reps):
         sdg.sdg_apply_viscous(h, u, r)
     for _ in range(reps):
+        sdg.sdg_apply_blockjacobi(h, u, r)
+    for _ in range(reps):
         torch.neg(u, out=r)  # plain elementwise copy: reads and writes one vector
     torch.cuda.synchronize()
     var = sdg.sdg_get_tile(h, sdg.TILE_RESIDUAL, sdg.FP64)
@@ -179,25 +182,26 @@ def kernel_probe(sdg, ctx, torch, B, reps):
     print(json.dumps({"kernel_probe": {"batch": B, "reps": reps, "vector_bytes": u.numel() * 8,
                                        "tile": sdg.sdg_tile_shape(K, var), "variant": var,
                                        "residual_bytes": B * nel * (3 * nb * 8 + 8),
-                                       "apply_bytes": B * nel * (2 * nb * 8 + 8)}}), flush=True)
+                                       "apply_bytes": B * nel * (2 * nb * 8 + 8),
+                                       "blockjacobi_bytes": B * nel * (2 * nb * 8 + 12)}}), flush=True)
 
 
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel's source changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "sip_k4_batch16_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", "sip_and_smoother_k4_batch16_hbm_traffic.md")
     try:
         text = open(path).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        k = rec["kernels"][kernel]
+        src = open(os.path.join(ROOT, k["source"]), "rb").read()
     except (OSError, AttributeError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if hashlib.sha256(src).hexdigest() != k["source_sha256"]:
         return None
-    k = rec["kernels"].get(kernel)
-    return k["traffic_bytes"] if k else None
+    return k["traffic_bytes"]
 
 
 def batched(sdg, ctx, nreq):
