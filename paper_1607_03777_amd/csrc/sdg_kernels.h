@@ -16,6 +16,13 @@ int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const 
                   hipStream_t s, int var = 0);
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
                      const float* u, float* r, hipStream_t s, int var = 0);
+// y = A u with the wavefront kernel, and the partial sums of u.y: one per
+// (problem, tile) at part[pb * tiles + tile] (capacity part_cap values);
+// reduce_parts then forms u.y per problem.  sip_apply_dot_parts gives the
+// number of partials.
+int sip_apply_dot(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
+                  double* part, int part_cap, hipStream_t s);
+int sip_apply_dot_parts(const MeshDev& M, int k, int nbatch);
 int sip_tile_variants(int k);
 int sip_tile_default(int k, bool fp32);
 void sip_tile_shape(int k, int var, int* tx, int* ty);
@@ -96,6 +103,8 @@ int cheb_update(int64_t n, double a, const double* z, double b, double* d, doubl
 int cheb_update_f32(int64_t n, double a, const float* z, double b, float* d, float* x, int mode,
                     hipStream_t s);
 // out[j] = <V_j, w> for j < m, V row-major [m][n]; result in device memory
+// out[j] = sum of part[j * nparts .. (j + 1) * nparts), in a fixed order
+int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s);
 int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,
               double* scratch, hipStream_t s);
 // w -= sum_j h[j] V_j (h in device memory)

@@ -710,15 +710,21 @@ __device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int 
   }
 }
 
+// dotp (apply only, may be null): receives u.y over the tile, one partial per
+// (problem, tile) at dotp[pb * tiles + tile], summed in a fixed order.
 template <int K1, int MODE, typename T>
 __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
                                                       const T* __restrict__ bvec, T* __restrict__ y,
-                                                      const double* __restrict__ eta_all, int64_t vec_stride) {
+                                                      const double* __restrict__ eta_all, int64_t vec_stride,
+                                                      double* __restrict__ dotp) {
   constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
   constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY, NH = K1 / 2;
   static_assert(E * K1 <= 64, "tile does not fit a wavefront");
   constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), NF = NFV > NFH ? NFV : NFH, FS = 8 * K1 + 1;
-  __shared__ T su[E * NB];  // [el][d][j][i]; later the column results
+  // element stride in su: odd from k = 3 on (fewer LDS bank conflicts between
+  // the row and column passes; within the same LDS allocation granule)
+  constexpr int ES = NB + (K1 >= 4 ? 1 : 0);
+  __shared__ T su[E * ES];  // [el][d][j][i]; later the column results
   __shared__ T sf[NF * FS];  // face records [s][d][w][m]: the x-faces, then the y-faces
   const int lane = threadIdx.x;
   const int nx = M.nx, ny = M.ny;
@@ -803,7 +809,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
       for (int i = 0; i < K1; ++i) r[i] = valid ? u[ge * NB + d * KK + j * K1 + i] : T(0);
 #pragma unroll
-      for (int i = 0; i < K1; ++i) su[el * NB + d * KK + j * K1 + i] = r[i];
+      for (int i = 0; i < K1; ++i) su[el * ES + d * KK + j * K1 + i] = r[i];
       T tl, gl, tr, gr;
       trace4(r, tl, gl, tr, gr);
       fl[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
@@ -874,7 +880,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   // ---- columns (lane column ic = j): y-face traces, S_y, mixed term of y0
   T yc[2][K1];
   const int ic = j;
-  const T* ue = su + el * NB;
+  const T* ue = su + el * ES;
   T* fb = sf + (ty * TX + tx) * FS;        // bottom y-face, this element on the plus side
   T* ft = sf + ((ty + 1) * TX + tx) * FS;  // top y-face, minus side
   if (act) {
@@ -977,13 +983,22 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       yr[1][i] += et * cxy * acc;
     }
   }
+  // u.y = u.(row part) + u.(column part), with u still staged in LDS
+  double dot = 0.0;
+  if (MODE == M_APPLY && dotp && valid) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int i = 0; i < K1; ++i)
+        dot += double(ue[d * KK + j * K1 + i]) * double(yr[d][i]) + double(ue[d * KK + i * K1 + ic]) * double(yc[d][i]);
+  }
   __syncthreads();
   // column results back to rows
   if (act) {
 #pragma unroll
     for (int d = 0; d < 2; ++d)
 #pragma unroll
-      for (int jj = 0; jj < K1; ++jj) su[el * NB + d * KK + jj * K1 + ic] = yc[d][jj];
+      for (int jj = 0; jj < K1; ++jj) su[el * ES + d * KK + jj * K1 + ic] = yc[d][jj];
   }
   __syncthreads();
   if (valid) {
@@ -992,10 +1007,15 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
       for (int i = 0; i < K1; ++i) {
         const int64_t g = ge * NB + d * KK + j * K1 + i;
-        const T v = yr[d][i] + su[el * NB + d * KK + j * K1 + i];
+        const T v = yr[d][i] + su[el * ES + d * KK + j * K1 + i];
         if constexpr (MODE == M_RESID) y[g] = bres[d][i] - v;
         else y[g] = v;
       }
+  }
+  if (MODE == M_APPLY && dotp) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+    if (lane == 0) dotp[pb * gridDim.x + tile] = dot;
   }
 }
 
@@ -1290,13 +1310,17 @@ static void launch_var(const MeshDev& M, int nbatch, const T* u, const T* b, T* 
                      M, u, b, y, eta, out_mat, nullptr, stride);
 }
 
+template <int K1>
+static int wave_tiles(const MeshDev& M) {
+  return ceil_div(M.nx, WaveTile<K1>::TX) * ceil_div(M.ny, WaveTile<K1>::TY);
+}
 template <int K1, int MODE, typename T>
 static void launch_wave(const MeshDev& M, int nbatch, const T* u, const T* b, T* y, const double* eta,
-                        hipStream_t s) {
-  constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
-  const int ntiles = ceil_div(M.nx, TX) * ceil_div(M.ny, TY);
+                        hipStream_t s, double* dotp = nullptr) {
+  const int ntiles = wave_tiles<K1>(M);
   const int64_t stride = (int64_t)M.nx * M.ny * 2 * K1 * K1;
-  hipLaunchKernelGGL((sip_wave_kernel<K1, MODE, T>), dim3(ntiles, nbatch), dim3(64), 0, s, M, u, b, y, eta, stride);
+  hipLaunchKernelGGL((sip_wave_kernel<K1, MODE, T>), dim3(ntiles, nbatch), dim3(64), 0, s, M, u, b, y, eta, stride,
+                     dotp);
 }
 
 // var: 0 = wavefront kernel, 1..TILE_NV = tile kernel shapes (apply/residual)
@@ -1375,6 +1399,34 @@ int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const doub
               hipStream_t s, int var) {
   SDG_K1_SWITCH(k + 1, return (launch_tile<KK1, M_APPLY, double>(M, nbatch, u, nullptr, y, eta, nullptr, s, var)));
   return SDG_OK;
+}
+template <int K1>
+static int launch_apply_dot(const MeshDev& M, int nbatch, const double* eta, const double* u, double* y,
+                            double* part, int part_cap, hipStream_t s) {
+  const int ntiles = wave_tiles<K1>(M);
+  if ((int64_t)ntiles * nbatch > part_cap) {
+    set_error("apply with dot: too many tiles for the partial-sum buffer");
+    return SDG_ERR_INVALID;
+  }
+  launch_wave<K1, M_APPLY, double>(M, nbatch, u, nullptr, y, eta, s, part);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int sip_apply_dot(const MeshDev& M, int k, int nbatch, const double* eta, const double* u, double* y,
+                  double* part, int part_cap, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_apply_dot<KK1>(M, nbatch, eta, u, y, part, part_cap, s)));
+  return SDG_OK;
+}
+int sip_apply_dot_parts(const MeshDev& M, int k, int nbatch) {
+  switch (k + 1) {
+    case 2: return wave_tiles<2>(M) * nbatch;
+    case 3: return wave_tiles<3>(M) * nbatch;
+    case 4: return wave_tiles<4>(M) * nbatch;
+    case 5: return wave_tiles<5>(M) * nbatch;
+    case 6: return wave_tiles<6>(M) * nbatch;
+    case 7: return wave_tiles<7>(M) * nbatch;
+    default: return 0;
+  }
 }
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
                  const double* u, double* r, hipStream_t s, int var) {

@@ -445,6 +445,20 @@ int run_sip_apply(sdg_problem* P, const double* u, double* y) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8),
                 [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s, P->tile[0][0]); });
 }
+// y = A u and out[pb] = u.y.  With the wavefront kernel the product is
+// summed inside the operator kernel (per-tile partials, then a fixed-order
+// sum), which saves a pass over u and y; otherwise apply, then dot.
+int run_sip_apply_dot(sdg_problem* P, const double* u, double* y, double* out) {
+  const int parts = sip_apply_dot_parts(P->M, P->k, P->nb);
+  if (P->tile[0][0] != 0 || parts <= 0 || parts > RED_SCRATCH) {
+    SDG_TRY(run_sip_apply(P, u, y));
+    return bmulti_dot(P->nu, P->nb, 1, u, 0, y, out, P->red, P->s);
+  }
+  SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8), [&] {
+    return sip_apply_dot(P->M, P->k, P->nb, P->eta, u, y, P->red, RED_SCRATCH, P->s);
+  }));
+  return reduce_parts(parts / P->nb, P->nb, P->red, out, P->s);
+}
 int run_sip_residual(sdg_problem* P, const double* b, const double* u, double* r) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 8) + elem_bytes(P, 8),
                 [&] { return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s, P->tile[1][0]); });
@@ -819,8 +833,7 @@ int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
   SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rzB, P->red, P->s));
   SDG_TRY(cg_update2(n, nb, P->cg_z, P->cg_p, rzB, rzA, P->active, P->s));
-  SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
-  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
+  SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
   SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                      P->s));
   SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
@@ -900,8 +913,7 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
   double* rz2 = sc(P, SC_RZ2);
   SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz, P->red, P->s));
   // first iteration: q = A p, p.q, update, readback
-  SDG_TRY(run_sip_apply(P, P->cg_p, P->cg_q));
-  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_p, 0, P->cg_q, sc(P, SC_PQ), P->red, P->s));
+  SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
   SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                      P->s));
   SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));

@@ -108,6 +108,13 @@ __global__ __launch_bounds__(VT) void reduce_stage2(int nparts, const double* __
   if (threadIdx.x == 0) out[j] = s;
 }
 
+int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s) {
+  if (nout <= 0) return SDG_OK;
+  hipLaunchKernelGGL(reduce_stage2, dim3(nout), dim3(VT), 0, s, nparts, part, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
 static inline int red_blocks(int64_t n) {
   int64_t b = (n + VT - 1) / VT;
   return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
