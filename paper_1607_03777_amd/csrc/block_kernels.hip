@@ -171,27 +171,33 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ int perm16(int i) { return 8 * (i >> 3) + 2 * (i & 3) + ((i >> 2) & 1); }
 
 // ---------------------------------------------------------------------------
-// FP64 full inverse, one wavefront per work item of up to 16 elements, no
-// LDS and no barriers.  Lane (c, q) = (lane % 16, lane / 16) works on
-// element c; its residual, x and d rows come in 16-byte pairs (row order
-// above), each block fragment pair, read from L1/L2 (a block is shared by
-// many work items), feeds two products.  The update operands are fetched
-// before the product.  Waves are independent, so the latency of one hides
-// behind the others.
+// FP64 full inverse, one wavefront per work item of up to 16 elements.  Lane
+// (c, q) = (lane % 16, lane / 16) works on element c; its residual, x and d
+// rows come in 16-byte pairs (row order above), and each block fragment pair
+// feeds two products.  Work items are sorted by block, so the four
+// wavefronts of a workgroup nearly always share one: the workgroup stages
+// the block of its first work item in LDS once (rows padded to NB + 2
+// values) and a wavefront with that block reads its fragments from there;
+// any other wavefront reads them from L1/L2.  Blocks above 72 x 72 (k = 6)
+// stay in L1/L2, and so do the 50 x 50 blocks of k = 4, where the staging
+// barrier measured slower than the fragment loads it saves (k = 2, 3, 5 run
+// 4-14% faster staged).  The update operands are fetched first.
 // ---------------------------------------------------------------------------
 template <int K1>
 __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
   constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
+  constexpr bool STAGE = NB <= 72 && K1 != 5;
+  constexpr int LDB = NB + 2;
+  __shared__ double sB[STAGE ? NB * LDB : 2];
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= nwork) return;
-  const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  const bool wvalid = w < nwork;
+  const int uid = wvalid ? A.work[3 * w] : -1;
+  const int start = wvalid ? A.work[3 * w + 1] : 0, cnt = wvalid ? A.work[3 * w + 2] : 0;
   const int c = lane & 15, q = lane >> 4;
   const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
-  const double* B = A.mat + (int64_t)uid * NB * NB;
-  const int prow = perm16(c);
   const int flags = A.flags;
-  // operands of the update: rows 16t + 8h + 2q, +1
+  // operands of the update (rows 16t + 8h + 2q, +1), requested first
   v2d xo[NT][2], dold[NT][2];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -203,6 +209,20 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
                                                           : v2d{0.0, 0.0};
       dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2d*>(A.d + ge * NB + i) : v2d{0.0, 0.0};
     }
+  // blockIdx.x * 4 < nwork: the grid has ceil(nwork / 4) workgroups
+  const int uid0 = A.work[3 * (blockIdx.x * 4)];
+  if constexpr (STAGE) {
+    const double* B0 = A.mat + (int64_t)uid0 * NB * NB;
+    for (int e2 = threadIdx.x; e2 < NB * NB / 2; e2 += 256) {
+      const int row = (2 * e2) / NB, col = 2 * e2 - row * NB;  // NB is even: pairs stay in a row
+      *reinterpret_cast<v2d*>(sB + row * LDB + col) = *reinterpret_cast<const v2d*>(B0 + 2 * e2);
+    }
+    __syncthreads();
+  }
+  if (!wvalid) return;
+  const double* B = A.mat + (int64_t)uid * NB * NB;
+  const bool from_lds = STAGE && uid == uid0;
+  const int prow = perm16(c);
   v4d acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -217,7 +237,10 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
       for (int t = 0; t < NT; ++t) {
         const int arow = 16 * t + prow;
         // A[i][k] = Binv[arow][k] (the block is symmetric either way)
-        const v2d a = (arow < NB && k0 < NB) ? *reinterpret_cast<const v2d*>(B + arow * NB + k0) : v2d{0.0, 0.0};
+        v2d a = v2d{0.0, 0.0};
+        if (arow < NB && k0 < NB)
+          a = from_lds ? *reinterpret_cast<const v2d*>(sB + arow * LDB + k0)
+                       : *reinterpret_cast<const v2d*>(B + arow * NB + k0);
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, rb.x, acc[t], 0, 0, 0);
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, rb.y, acc[t], 0, 0, 0);
       }
