@@ -12,6 +12,10 @@ int sip_apply(const MeshDev& M, int k, int nbatch, const double* eta, const doub
               hipStream_t s, int var = 0);
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
                  const double* u, double* r, hipStream_t s, int var = 0);
+// r = b - A u restricted to its Q1 modes (i, j <= 1), wavefront kernel:
+// rq[pb][e][d][j][i], 8 values per element (the layout of a k = 1 vector)
+int sip_residual_q1(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
+                    const double* u, double* rq, hipStream_t s);
 int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
                   hipStream_t s, int var = 0);
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,

@@ -245,7 +245,7 @@ __device__ __forceinline__ void face_mode(const T* __restrict__ f, int m, int ki
 // ---------------------------------------------------------------------------
 // tile kernel
 // ---------------------------------------------------------------------------
-enum ApplyMode { M_APPLY = 0, M_RESID = 1, M_BLOCKCOL = 2, M_COARSECOL = 3 };
+enum ApplyMode { M_APPLY = 0, M_RESID = 1, M_BLOCKCOL = 2, M_COARSECOL = 3, M_RESQ1 = 4 };
 
 // MODE M_APPLY / M_RESID: tile grid over the mesh (blockIdx.y = problem).
 // MODE M_BLOCKCOL: TX = TY = 1, blockIdx.x indexes `elems` (global element
@@ -735,9 +735,11 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   const int ix0 = (tile % ntx) * TX, iy0 = (tile / ntx) * TY;
   const int64_t pb = lt / gridDim.x;
   const double* eta = eta_all + pb * (int64_t)nx * ny;
+  constexpr bool RES = MODE == M_RESID || MODE == M_RESQ1;
   u += pb * vec_stride;
-  y += pb * vec_stride;
-  if (MODE == M_RESID) bvec += pb * vec_stride;
+  // M_RESQ1 writes the residual's Q1 modes only: [pb][e][d][j][i], i, j <= 1
+  y += MODE == M_RESQ1 ? pb * (int64_t)nx * ny * 8 : pb * vec_stride;
+  if (RES) bvec += pb * vec_stride;
   const T ihx = T(1.0 / M.hx), ihy = T(1.0 / M.hy);
 
   const int el = lane / K1, j = lane - el * K1;  // j: row, then face mode and column
@@ -870,11 +872,14 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 
   // the residual's right-hand side, requested before the column work
   T bres[2][K1];
-  if constexpr (MODE == M_RESID) {
+  if constexpr (RES) {
 #pragma unroll
     for (int d = 0; d < 2; ++d)
 #pragma unroll
-      for (int i = 0; i < K1; ++i) bres[d][i] = valid ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
+      for (int i = 0; i < K1; ++i) {
+        const bool need = MODE == M_RESID || (j < 2 && i < 2);
+        bres[d][i] = (valid && need) ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
+      }
   }
 
   // ---- columns (lane column ic = j): y-face traces, S_y, mixed term of y0
@@ -1001,7 +1006,17 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       for (int jj = 0; jj < K1; ++jj) su[el * ES + d * KK + jj * K1 + ic] = yc[d][jj];
   }
   __syncthreads();
-  if (valid) {
+  if constexpr (MODE == M_RESQ1) {
+    if (valid && j < 2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const T v = yr[d][i] + su[el * ES + d * KK + j * K1 + i];
+          y[ge * 8 + d * 4 + j * 2 + i] = bres[d][i] - v;
+        }
+    }
+  } else if (valid) {
 #pragma unroll
     for (int d = 0; d < 2; ++d)
 #pragma unroll
@@ -1427,6 +1442,15 @@ int sip_apply_dot_parts(const MeshDev& M, int k, int nbatch) {
     case 7: return wave_tiles<7>(M) * nbatch;
     default: return 0;
   }
+}
+int sip_residual_q1(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
+                    const double* u, double* rq, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, {
+    launch_wave<KK1, M_RESQ1, double>(M, nbatch, u, b, rq, eta, s);
+    SDG_CHECK_LAUNCH();
+    return SDG_OK;
+  });
+  return SDG_OK;
 }
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
                  const double* u, double* r, hipStream_t s, int var) {

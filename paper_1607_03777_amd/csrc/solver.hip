@@ -619,8 +619,13 @@ int hcycle(sdg_problem* P, int li) {
 
 int vcycle64(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(cheb_dg64(P, b, x, true));
-  SDG_TRY(run_sip_residual(P, b, x, P->vr));
-  SDG_TRY(p_restrict(P->M, P->k, P->nb, P->vr, P->lev[0].b, P->s));
+  // only the Q1 modes of the residual reach the coarse space: the operator
+  // kernel writes just those (8 values per element, laid out as a k = 1
+  // vector) and the restriction reads them with k = 1
+  // algorithmic bytes: u, eta, the Q1 modes of b, the 8 values written
+  SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 8) + 17 * elem_bytes(P, 8),
+                 [&] { return sip_residual_q1(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s); }));
+  SDG_TRY(p_restrict(P->M, 1, P->nb, P->vr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
   SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
   SDG_TRY(cheb_dg64(P, b, x, false));
