@@ -107,6 +107,9 @@ int cheb_update(int64_t n, double a, const double* z, double b, double* d, doubl
 int cheb_update_f32(int64_t n, double a, const float* z, double b, float* d, float* x, int mode,
                     hipStream_t s);
 // out[j] = <V_j, w> for j < m, V row-major [m][n]; result in device memory
+// host_dst[0..n) = src[0..n) (host_dst pinned), then *host_seq = ++*dev_count
+int publish_scalars(const double* src, int n, double* host_dst, unsigned* dev_count, unsigned* host_seq,
+                    hipStream_t s);
 // out[j] = sum of part[j * nparts .. (j + 1) * nparts), in a fixed order
 int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s);
 int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,

@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <array>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -170,6 +171,12 @@ struct sdg_problem {
   double* red = nullptr;
   double* dsc = nullptr;  // device scalars (see SC_* offsets)
   double* hsc = nullptr;  // pinned host mirror
+  // published CG scalars: pinned copy, sequence number written by the
+  // device after them, the device-side counter and the host's count
+  double* hpub = nullptr;
+  unsigned* hseq = nullptr;
+  unsigned* dcount = nullptr;
+  unsigned seq = 0;
   int* active = nullptr;  // device [nb]
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
   double *gV = nullptr, *gZ = nullptr, *gw = nullptr, *gt = nullptr;
@@ -245,6 +252,35 @@ int to_host(sdg_problem* P, void* dst, const void* src, size_t bytes) {
 int to_dev(sdg_problem* P, void* dst, const void* src, size_t bytes) {
   SDG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, P->s));
   SDG_HIP(hipStreamSynchronize(P->s));
+  return SDG_OK;
+}
+// Enqueue the publication of n device scalars; returns the sequence number
+// the host waits for.
+int publish(sdg_problem* P, const double* src, int n, unsigned* seq_out) {
+  SDG_TRY(publish_scalars(src, n, P->hpub, P->dcount, P->hseq, P->s));
+  *seq_out = ++P->seq;
+  return SDG_OK;
+}
+// Wait until the device has published sequence number `seq` (spinning on
+// the pinned flag, then copy the scalars out).  A wait beyond a few seconds
+// falls back to a stream synchronisation, which reports device errors.
+int wait_published(sdg_problem* P, unsigned seq, int n, double* out) {
+  volatile unsigned* flag = P->hseq;
+  const auto t0 = std::chrono::steady_clock::now();
+  int spins = 0;
+  while (*flag != seq) {
+    if (++spins % 1024 == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5)) {
+      SDG_HIP(hipStreamSynchronize(P->s));
+      if (*flag != seq) {
+        set_error("published scalars did not arrive");
+        return SDG_ERR_DEVICE;
+      }
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  std::memcpy(out, const_cast<const double*>(P->hpub), n * sizeof(double));
   return SDG_OK;
 }
 int read_dev(sdg_problem* P, const double* src, int n, double* out) {
@@ -841,8 +877,8 @@ int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
   SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
   SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                      P->s));
-  SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
-  return SDG_OK;
+  // (p.q, ||r||^2) to the pinned mirror; the host counts the publications
+  return publish_scalars(sc(P, SC_PQ), 2 * nb, P->hpub, P->dcount, P->hseq, P->s);
 }
 
 // Captures cg_body (on the fixed iterate buffer) as a graph, once per parity.
@@ -888,7 +924,8 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
   const bool graphs = P->opt.graphs && !P->ctx->trace;
   double* x = graphs ? P->cg_x : x_out;
   std::vector<double> bn;
-  SDG_TRY(vs_norms(P, S, b, bn));
+  SDG_TRY(vs_norms(P, S, b, bn));  // synchronises the stream
+  P->seq = *const_cast<volatile unsigned*>(P->hseq);  // the device's count of publications so far
   SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
   its.assign(nb, 0);
   rel.assign(nb, 0.0);
@@ -921,13 +958,14 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
   SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
   SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                      P->s));
-  SDG_HIP(hipMemcpyAsync(P->hsc, sc(P, SC_PQ), 2 * nb * sizeof(double), hipMemcpyDeviceToHost, P->s));
-  std::vector<double> rr(nb), pq(nb);
+  unsigned expect = 0;
+  SDG_TRY(publish(P, sc(P, SC_PQ), 2 * nb, &expect));
+  std::vector<double> rr(nb), pq(nb), both(2 * nb);
   int parity = 0;  // 0: rz holds the current r.z; 1: rz2 does
   for (int it = 0; it < maxit && nact > 0; ++it) {
-    SDG_HIP(hipStreamSynchronize(P->s));
-    std::memcpy(pq.data(), P->hsc, nb * sizeof(double));
-    std::memcpy(rr.data(), P->hsc + nb, nb * sizeof(double));
+    SDG_TRY(wait_published(P, expect, 2 * nb, both.data()));
+    std::memcpy(pq.data(), both.data(), nb * sizeof(double));
+    std::memcpy(rr.data(), both.data() + nb, nb * sizeof(double));
     bool changed = false;
     for (int pb = 0; pb < nb; ++pb) {
       if (!act[pb]) continue;
@@ -961,6 +999,7 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
     } else {
       SDG_TRY(parity == 0 ? cg_body(P, x, rz, rz2) : cg_body(P, x, rz2, rz));
     }
+    expect = ++P->seq;  // the iteration ends with one publication
     parity ^= 1;
   }
   SDG_HIP(hipStreamSynchronize(P->s));
@@ -1419,11 +1458,16 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   const int64_t nsc = (int64_t)(SC_COUNT_FIXED + std::max(o.restart, o.eig_steps) + 4) * nbatch * 2;
   if ((rc = palloc_t(P, &P->dsc, nsc)) < 0) return fail(rc);
   if ((rc = palloc_t(P, &P->active, nbatch)) < 0) return fail(rc);
-  if (hipHostMalloc((void**)&P->hsc, nsc * sizeof(double)) != hipSuccess) {
+  if (hipHostMalloc((void**)&P->hsc, nsc * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&P->hpub, (2 * nbatch + 2) * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     set_error("pinned allocation failed");
     return fail(SDG_ERR_NOMEM);
   }
+  P->hseq = reinterpret_cast<unsigned*>(P->hpub + 2 * nbatch);
+  *P->hseq = 0u;
+  if ((rc = palloc_t(P, &P->dcount, 1)) < 0) return fail(rc);
+  SDG_HIP(hipMemsetAsync(P->dcount, 0, sizeof(unsigned), P->s));
   // Chebyshev bounds
   std::vector<double> lam;
   if ((rc = arnoldi(P, -1, lam, nullptr)) < 0) return fail(rc);
@@ -1467,6 +1511,7 @@ void sdg_problem_destroy(sdg_problem* P) {
   if (P->gs) (void)hipStreamDestroy(P->gs);
   for (void* p : P->allocs) (void)hipFree(p);
   if (P->hsc) (void)hipHostFree(P->hsc);
+  if (P->hpub) (void)hipHostFree(P->hpub);
   if (sdg_ctx* c = P->ctx) {
     bool del;
     {

@@ -108,6 +108,27 @@ __global__ __launch_bounds__(VT) void reduce_stage2(int nparts, const double* __
   if (threadIdx.x == 0) out[j] = s;
 }
 
+// Copies n scalars into pinned host memory and then, after a system-scope
+// fence, bumps a device counter and stores its new value into *host_seq:
+// once the host reads the expected sequence number, the scalars are there.
+// One thread; the counter makes every replay of a captured graph publish a
+// new number.
+__global__ void publish_kernel(const double* __restrict__ src, int n, double* host_dst,
+                               unsigned* __restrict__ dev_count, volatile unsigned* host_seq) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < n; ++i) host_dst[i] = src[i];
+  const unsigned v = *dev_count + 1u;
+  *dev_count = v;
+  __threadfence_system();
+  *host_seq = v;
+}
+int publish_scalars(const double* src, int n, double* host_dst, unsigned* dev_count, unsigned* host_seq,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(64), 0, s, src, n, host_dst, dev_count, host_seq);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
 int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s) {
   if (nout <= 0) return SDG_OK;
   hipLaunchKernelGGL(reduce_stage2, dim3(nout), dim3(VT), 0, s, nparts, part, out);
