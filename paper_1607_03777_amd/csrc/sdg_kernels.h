@@ -110,6 +110,10 @@ int cheb_update_f32(int64_t n, double a, const float* z, double b, float* d, flo
 // host_dst[0..n) = src[0..n) (host_dst pinned), then *host_seq = ++*dev_count
 int publish_scalars(const double* src, int n, double* host_dst, unsigned* dev_count, unsigned* host_seq,
                     hipStream_t s);
+// out[i] = sum over q < nseg of parts[q * n + i], in order of q
+int seg_sum(int64_t n, int nseg, const double* parts, double* out, hipStream_t s);
+// hs[pb] = done[pb] ? 0 : sqrt(max(sq[pb], 0))
+int norm_mask(int nb, const double* sq, const int* done, double* hs, hipStream_t s);
 // out[j] = sum of part[j * nparts .. (j + 1) * nparts), in a fixed order
 int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s);
 int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,

@@ -180,6 +180,8 @@ struct sdg_problem {
   int* active = nullptr;  // device [nb]
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
   double *gV = nullptr, *gZ = nullptr, *gw = nullptr, *gt = nullptr;
+  double* gcoef = nullptr;  // FGMRES coefficients on the device
+  int* gdone = nullptr;     // FGMRES: problems finished within the cycle
   int64_t gn = 0;  // per-problem length of the FGMRES vectors
   bool neumann = false;
   double setup_ms = 0;
@@ -1019,8 +1021,25 @@ int ensure_gmres(sdg_problem* P, int64_t n_per_problem) {
   SDG_TRY(palloc_t(P, &P->gZ, (int64_t)m * tot));
   SDG_TRY(palloc_t(P, &P->gw, tot));
   SDG_TRY(palloc_t(P, &P->gt, P->nu * P->nb));
+  // two passes of m + 1 coefficients, the masked norm, and the per-segment
+  // partials (two segments of m + 1 values)
+  SDG_TRY(palloc_t(P, &P->gcoef, (int64_t)(4 * (m + 1) + 4) * P->nb));
+  SDG_TRY(palloc_t(P, &P->gdone, P->nb));
   P->gn = n_per_problem;
   return SDG_OK;
+}
+
+// dst[pb][i] = V_i . w per problem for i < mj, on the device, summed over
+// the segments of S in order (segb: scratch of S.nseg * nb * mj values)
+int vs_dots_dev(sdg_problem* P, const VSpec& S, int mj, const double* V, int64_t ldv, const double* w,
+                double* dst, double* segb) {
+  const int nb = P->nb;
+  if (S.nseg == 1)
+    return bmulti_dot(S.seg[0].n, nb, mj, V + S.seg[0].off, ldv, w + S.seg[0].off, dst, P->red, P->s);
+  for (int q = 0; q < S.nseg; ++q)
+    SDG_TRY(bmulti_dot(S.seg[q].n, nb, mj, V + S.seg[q].off, ldv, w + S.seg[q].off,
+                       segb + (int64_t)q * nb * mj, P->red, P->s));
+  return seg_sum((int64_t)nb * mj, S.nseg, segb, dst, P->s);
 }
 
 // Batched right-preconditioned FGMRES(restart), classical Gram-Schmidt
@@ -1075,24 +1094,39 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
       done[pb] = !act[pb];
       est_conv[pb] = 0;
     }
+    bool done_changed = true;  // the device copy of `done` is refreshed before use
     for (int j = 0; j < m; ++j) {
       double* zj = Z + (int64_t)j * ldv;
       SDG_TRY(prec(V + (int64_t)j * ldv, zj));
       SDG_TRY(project(zj));
       SDG_TRY(matvec(zj, w));
-      std::vector<double> h((size_t)nb * (j + 1), 0.0), part;
+      // classical Gram-Schmidt twice and the new vector's norm, with the
+      // coefficients kept on the device: hbuf = [pass 0 | pass 1 | norms],
+      // read back once per iteration
+      const int mj = j + 1;
+      double* hbuf = P->gcoef;
+      double* segb = P->gcoef + (int64_t)(2 * (m + 1) + 2) * nb;
       for (int pass = 0; pass < 2; ++pass) {
-        SDG_TRY(vs_dots(P, S, j + 1, V, ldv, w, part));
-        SDG_TRY(upload_scalars(P, sc_h(P), part));
-        SDG_TRY(vs_axpy(P, S, j + 1, V, ldv, sc_h(P), w));
-        for (size_t i = 0; i < h.size(); ++i) h[i] += part[i];
+        double* hp = hbuf + (int64_t)pass * nb * mj;
+        SDG_TRY(vs_dots_dev(P, S, mj, V, ldv, w, hp, segb));
+        SDG_TRY(vs_axpy(P, S, mj, V, ldv, hp, w));
       }
-      std::vector<double> hn;
-      SDG_TRY(vs_norms(P, S, w, hn));
-      std::vector<double> hs(nb);
-      for (int pb = 0; pb < nb; ++pb) hs[pb] = done[pb] ? 0.0 : hn[pb];
-      SDG_TRY(upload_scalars(P, sc(P, SC_BN), hs));
-      SDG_TRY(vs_div(P, S, sc(P, SC_BN), w, V + (int64_t)(j + 1) * ldv));
+      double* hsq = hbuf + (int64_t)(2 * (m + 1) + 1) * nb;  // w.w per problem
+      double* hs_dev = hbuf + (int64_t)2 * nb * mj;
+      if (done_changed) {
+        std::vector<int> di(nb);
+        for (int pb = 0; pb < nb; ++pb) di[pb] = done[pb] ? 1 : 0;
+        SDG_TRY(to_dev(P, P->gdone, di.data(), nb * sizeof(int)));
+        done_changed = false;
+      }
+      SDG_TRY(vs_dots_dev(P, S, 1, w, 0, w, hsq, segb));
+      SDG_TRY(norm_mask(nb, hsq, P->gdone, hs_dev, P->s));
+      SDG_TRY(vs_div(P, S, hs_dev, w, V + (int64_t)(j + 1) * ldv));
+      std::vector<double> hb((size_t)2 * nb * mj + nb);
+      SDG_TRY(read_dev(P, hbuf, (int)hb.size(), hb.data()));
+      std::vector<double> h((size_t)nb * mj), hn(nb);
+      for (size_t i = 0; i < h.size(); ++i) h[i] = (0.0 + hb[i]) + hb[(size_t)nb * mj + i];
+      for (int pb = 0; pb < nb; ++pb) hn[pb] = hb[(size_t)2 * nb * mj + pb];
       bool all_done = true;
       for (int pb = 0; pb < nb; ++pb) {
         if (done[pb]) continue;
@@ -1112,6 +1146,7 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
           status[pb] = SDG_BREAKDOWN;
           act[pb] = 0;
           done[pb] = 1;
+          done_changed = true;
           continue;
         }
         c[j] = col[j] / den;
@@ -1124,7 +1159,10 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
         jd[pb] = j + 1;
         const double est = std::fabs(gg[j + 1]) / bn[pb];
         if (est < rtol) est_conv[pb] = 1;
-        if (est < rtol || hn[pb] == 0.0 || its[pb] >= maxit) done[pb] = 1;
+        if (est < rtol || hn[pb] == 0.0 || its[pb] >= maxit) {
+          done[pb] = 1;
+          done_changed = true;
+        }
         all_done = all_done && done[pb];
       }
       ++total;

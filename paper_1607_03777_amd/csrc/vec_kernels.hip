@@ -129,6 +129,35 @@ int publish_scalars(const double* src, int n, double* host_dst, unsigned* dev_co
   return SDG_OK;
 }
 
+// out[i] = sum over q of parts[q * n + i], q in order from 0.0 (the same sum
+// the host forms over the segments of a Stokes vector)
+__global__ void seg_sum_kernel(int64_t n, int nseg, const double* __restrict__ parts, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < nseg; ++q) s += parts[q * n + i];
+  out[i] = s;
+}
+int seg_sum(int64_t n, int nseg, const double* parts, double* out, hipStream_t s) {
+  if (n <= 0) return SDG_OK;
+  hipLaunchKernelGGL(seg_sum_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, nseg, parts, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+// hs[pb] = done[pb] ? 0 : sqrt(max(sq[pb], 0))
+__global__ void norm_mask_kernel(int nb, const double* __restrict__ sq, const int* __restrict__ done,
+                                 double* __restrict__ hs) {
+  const int pb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pb >= nb) return;
+  const double v = sq[pb];
+  hs[pb] = done[pb] ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
+}
+int norm_mask(int nb, const double* sq, const int* done, double* hs, hipStream_t s) {
+  hipLaunchKernelGGL(norm_mask_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, s, nb, sq, done, hs);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
 int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s) {
   if (nout <= 0) return SDG_OK;
   hipLaunchKernelGGL(reduce_stage2, dim3(nout), dim3(VT), 0, s, nparts, part, out);
