@@ -13,7 +13,7 @@
 // is a small dense product Binv * [r_e1 ... r_eG] per group: one wavefront
 // per group of 16 on the matrix cores (FP64 MFMA), fragments read straight
 // from L1/L2 and HBM, for the FP64 inverse and for the factored FP32/BF16
-// form alike.
+// form (FP64 and FP32 matrix cores respectively) alike.
 #include "sdg_common.h"
 #include "sdg_kernels.h"
 
@@ -100,28 +100,49 @@ int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, doubl
 }
 
 
-__global__ void f64_to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) out[g] = (float)in[g];
-}
-__global__ void f64_to_bf16_kernel(const double* __restrict__ in, uint16_t* __restrict__ out,
-                                   int64_t n) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+// Low-precision factors: from the packed FP64 X = L^{-1} (row a holds
+// X[a][0..a] at offset a(a+1)/2) to two full square matrices per block in
+// the storage type, out[u][0] = X (zeros above the diagonal) and
+// out[u][1] = X^T (zeros below), so that both products of the smoother read
+// their operands as contiguous row pairs.
+__device__ __forceinline__ uint16_t to_bf16(double v) {
   // round to nearest even from the FP32 value
-  const uint32_t u = __float_as_uint((float)in[g]);
+  const uint32_t u = __float_as_uint((float)v);
   const uint32_t lsb = (u >> 16) & 1u;
-  out[g] = (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
-int convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
-  if (n <= 0) return SDG_OK;
-  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, out, n);
+template <typename TM>
+__global__ void tri_square_kernel(const double* __restrict__ packed, int n, int64_t nmat, TM* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (g >= nmat * nn) return;
+  const int64_t u = g / nn;
+  const int a = (int)((g - u * nn) / n), b = (int)(g - u * nn - (int64_t)a * n);
+  const double* pk = packed + u * ((int64_t)n * (n + 1) / 2);
+  const double x = b <= a ? pk[(int64_t)a * (a + 1) / 2 + b] : 0.0;   // X[a][b]
+  const double xt = a <= b ? pk[(int64_t)b * (b + 1) / 2 + a] : 0.0;  // X^T[a][b] = X[b][a]
+  TM* o = out + u * 2 * nn + (int64_t)a * n + b;
+  if constexpr (sizeof(TM) == 2) {
+    o[0] = to_bf16(x);
+    o[nn] = to_bf16(xt);
+  } else {
+    o[0] = TM(x);
+    o[nn] = TM(xt);
+  }
+}
+int tri_square_f32(const double* packed, int n, int nmat, float* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nmat * n * n;
+  if (tot <= 0) return SDG_OK;
+  hipLaunchKernelGGL(tri_square_kernel<float>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n, (int64_t)nmat,
+                     out);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
-int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s) {
-  if (n <= 0) return SDG_OK;
-  hipLaunchKernelGGL(f64_to_bf16_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, out, n);
+int tri_square_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nmat * n * n;
+  if (tot <= 0) return SDG_OK;
+  hipLaunchKernelGGL(tri_square_kernel<uint16_t>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n,
+                     (int64_t)nmat, out);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
@@ -275,75 +296,97 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
 }
 
 // ---------------------------------------------------------------------------
-// Factored low-precision smoother on the matrix cores, one wavefront per work
-// item of up to 16 elements: y = X r, then z = X^T y, X = L^{-1} the packed
-// lower-triangular factor in FP32 or BF16 storage, vectors in FP32, products
-// accumulated in FP64 MFMA in natural row order (accumulator component r of
-// lane group lane/16 holds row 16t + 4r + lane/16).  The
-// accumulator fragment of y for rows 16t + 4r + lane/16 is exactly the
-// B-operand fragment the second product needs for its k-step 16t + 4r, so y
-// never leaves the registers.  Triangular zero blocks are skipped at compile
-// time.
+// Factored low-precision smoother, one wavefront per work item of up to 16
+// elements: y = X r, then z = X^T y, on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32), X = L^{-1} and X^T stored as full squares in
+// FP32 or BF16, vectors in FP32.  The rows follow the pair order of the
+// FP64 kernel (lane group q holds rows 16g + 8h + 2q + s), so vectors and
+// factor rows move as pairs.  The FP32 product puts D row 4q + r in
+// component r of lane group q (checked on the GPU), so block row
+// 16t + permf(i) feeds accumulator row i with
+// permf(4q + r) = 8(r >> 1) + 2q + (r & 1): component r then holds output
+// row 16t + 8(r >> 1) + 2q + (r & 1), and the accumulator of y is exactly
+// the operand the second product needs for its k-steps.  Zero blocks of
+// the triangles (row group below or above the column group) are skipped at
+// compile time.
 // ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int permf(int i) { return 8 * ((i & 3) >> 1) + 2 * (i >> 2) + (i & 1); }
 template <typename TM>
-__device__ __forceinline__ double ldw(const TM* p) {
-  if constexpr (sizeof(TM) == 2) return double(__uint_as_float(((uint32_t)*p) << 16));
-  else return double(*p);
+__device__ __forceinline__ v2f ld_pair(const TM* p) {
+  if constexpr (sizeof(TM) == 2) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    return v2f{__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u)};
+  } else {
+    return *reinterpret_cast<const v2f*>(p);
+  }
 }
 
 template <int K1, typename TM>
-__global__ __launch_bounds__(256) void bj_wave_tri_kernel(BjArgs<TM, float> A, int nwork) {
-  constexpr int NB = 2 * K1 * K1, KP = (NB + 3) & ~3, NT = (NB + 15) / 16;
+__global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, int nwork) {
+  constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwork) return;
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
-  const int c = lane & 15, kq = lane >> 4;
+  const int c = lane & 15, q = lane >> 4;
   const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
-  const TM* X = A.mat + (int64_t)uid * NB * (NB + 1) / 2;
+  const TM* X = A.mat + (int64_t)uid * 2 * NB * NB;
+  const TM* XT = X + NB * NB;
+  const int prow = permf(c);
   const int flags = A.flags;
-  float xo[NT][4], dold[NT][4];
+  // operands of the update (rows 16t + 8h + 2q, +1), requested first
+  v2f xo[NT][2], dold[NT][2];
 #pragma unroll
-  for (int tt = 0; tt < NT; ++tt)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * tt + 4 * r + kq;
+    for (int h = 0; h < 2; ++h) {
+      const int i = 16 * t + 8 * h + 2 * q;
       const bool ok = ge >= 0 && i < NB;
-      xo[tt][r] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? A.x[ge * NB + i] : 0.f;
-      dold[tt][r] = (ok && (flags & BJ_READ_D)) ? A.d[ge * NB + i] : 0.f;
+      xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2f*>(A.x + ge * NB + i)
+                                                          : v2f{0.f, 0.f};
+      dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2f*>(A.d + ge * NB + i) : v2f{0.f, 0.f};
     }
   // y = X r
-  v4d y[NT];
+  v4f y[NT];
 #pragma unroll
-  for (int tt = 0; tt < NT; ++tt) y[tt] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) y[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int s4 = 0; s4 < KP; s4 += 4) {
-    const int k = s4 + kq;
-    const double b = (ge >= 0 && k < NB) ? double(A.r[ge * NB + k]) : 0.0;
+  for (int g = 0; g < NT; ++g)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      if (s4 > 16 * tt + 15) continue;  // X[i][k] = 0 for k > i
-      const int i = 16 * tt + c;
-      const double a = (k <= i && i < NB) ? ldw(X + i * (i + 1) / 2 + k) : 0.0;
-      y[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, y[tt], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      if (16 * g + 8 * h >= NB) continue;
+      const int k0 = 16 * g + 8 * h + 2 * q;
+      const v2f rb = (ge >= 0 && k0 < NB) ? *reinterpret_cast<const v2f*>(A.r + ge * NB + k0) : v2f{0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (g > t) continue;  // X is zero above the diagonal
+        const int arow = 16 * t + prow;
+        const v2f a = (arow < NB && k0 < NB) ? ld_pair(X + arow * NB + k0) : v2f{0.f, 0.f};
+        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, rb.x, y[t], 0, 0, 0);
+        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, rb.y, y[t], 0, 0, 0);
+      }
     }
-  }
-  // z = X^T y; k-step s4 = 16 t' + 4 r' takes y[t'][r'] as its B fragment
-  v4d z[NT];
+  // z = X^T y; the k-step (g, h, s) takes component 2h + s of y[g]
+  v4f z[NT];
 #pragma unroll
-  for (int tt = 0; tt < NT; ++tt) z[tt] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int s4 = 0; s4 < KP; s4 += 4) {
-    const int k = s4 + kq;
-    const double b = y[s4 / 16][(s4 % 16) / 4];
+  for (int g = 0; g < NT; ++g)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      if (s4 + 3 < 16 * tt) continue;  // X^T[i][k] = X[k][i] = 0 for k < i
-      const int i = 16 * tt + c;
-      const double a = (i <= k && k < NB) ? ldw(X + k * (k + 1) / 2 + i) : 0.0;
-      z[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z[tt], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      if (16 * g + 8 * h >= NB) continue;
+      const int k0 = 16 * g + 8 * h + 2 * q;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (g < t) continue;  // X^T is zero below the diagonal
+        const int arow = 16 * t + prow;
+        const v2f a = (arow < NB && k0 < NB) ? ld_pair(XT + arow * NB + k0) : v2f{0.f, 0.f};
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, y[g][2 * h], z[t], 0, 0, 0);
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, y[g][2 * h + 1], z[t], 0, 0, 0);
+      }
     }
-  }
   if (ge < 0) return;
   const double sc = A.scale[ge];
   float* xx = A.x + ge * NB;
@@ -355,21 +398,30 @@ __global__ __launch_bounds__(256) void bj_wave_tri_kernel(BjArgs<TM, float> A, i
     cb = A.ab[2 * pb + 1];
   }
 #pragma unroll
-  for (int tt = 0; tt < NT; ++tt)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * tt + 4 * r + kq;
+    for (int h = 0; h < 2; ++h) {
+      const int i = 16 * t + 8 * h + 2 * q;
       if (i >= NB) continue;
-      const double zv = z[tt][r] * sc;
+      const double z0 = double(z[t][2 * h]) * sc, z1 = double(z[t][2 * h + 1]) * sc;
       if (flags & BJ_APPLY) {
-        xx[i] = float(zv);
+        *reinterpret_cast<v2f*>(xx + i) = v2f{float(z0), float(z1)};
         continue;
       }
-      double dv = cb * zv;
-      if (flags & BJ_READ_D) dv += ca * double(dold[tt][r]);
-      if (flags & BJ_FOLD) dv += ca * double(xo[tt][r]);
-      if (flags & BJ_WRITE_D) dd[i] = float(dv);
-      xx[i] = (flags & BJ_READ_X) ? float(double(xo[tt][r]) + dv) : float(dv);
+      double d0 = cb * z0, d1 = cb * z1;
+      if (flags & BJ_READ_D) {
+        d0 += ca * double(dold[t][h].x);
+        d1 += ca * double(dold[t][h].y);
+      }
+      if (flags & BJ_FOLD) {
+        d0 += ca * double(xo[t][h].x);
+        d1 += ca * double(xo[t][h].y);
+      }
+      if (flags & BJ_WRITE_D) *reinterpret_cast<v2f*>(dd + i) = v2f{float(d0), float(d1)};
+      if (flags & BJ_READ_X)
+        *reinterpret_cast<v2f*>(xx + i) = v2f{float(double(xo[t][h].x) + d0), float(double(xo[t][h].y) + d1)};
+      else
+        *reinterpret_cast<v2f*>(xx + i) = v2f{float(d0), float(d1)};
     }
 }
 
@@ -380,7 +432,7 @@ static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* 
   if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
     hipLaunchKernelGGL((bj_wave_kernel<K1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
   else
-    hipLaunchKernelGGL((bj_wave_tri_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+    hipLaunchKernelGGL((bj_wave_lp_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
 }
 
 template <typename TM, typename TV, bool TRI>

@@ -16,6 +16,8 @@ int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const d
 // rq[pb][e][d][j][i], 8 values per element (the layout of a k = 1 vector)
 int sip_residual_q1(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
                     const double* u, double* rq, hipStream_t s);
+int sip_residual_q1_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
+                        const float* u, float* rq, hipStream_t s);
 int sip_apply_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* u, float* y,
                   hipStream_t s, int var = 0);
 int sip_residual_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
@@ -73,8 +75,9 @@ int bj_tri_cheb_bf16(const BjPlan& P, const uint16_t* X, const float* r, const d
 int bj_tri_apply_f32(const BjPlan& P, const float* X, const float* r, float* z, hipStream_t s);
 int bj_tri_apply_bf16(const BjPlan& P, const uint16_t* X, const float* r, float* z, hipStream_t s);
 // Convert FP64 inverses to FP32 / BF16 storage.
-int convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
-int convert_f64_bf16(const double* in, uint16_t* out, int64_t n, hipStream_t s);
+// packed FP64 factors X -> [nmat][2][n][n] squares (X, then X^T) in FP32 / BF16
+int tri_square_f32(const double* packed, int n, int nmat, float* out, hipStream_t s);
+int tri_square_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s);
 
 // Transfers and coarse levels (coarse_kernels.hip)
 int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s);

@@ -1443,16 +1443,21 @@ int sip_apply_dot_parts(const MeshDev& M, int k, int nbatch) {
     default: return 0;
   }
 }
-template <int K1>
-static int launch_resq1(const MeshDev& M, int nbatch, const double* eta, const double* b, const double* u,
-                        double* rq, hipStream_t s) {
-  launch_wave<K1, M_RESQ1, double>(M, nbatch, u, b, rq, eta, s);
+template <int K1, typename T>
+static int launch_resq1(const MeshDev& M, int nbatch, const double* eta, const T* b, const T* u, T* rq,
+                        hipStream_t s) {
+  launch_wave<K1, M_RESQ1, T>(M, nbatch, u, b, rq, eta, s);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
 int sip_residual_q1(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,
                     const double* u, double* rq, hipStream_t s) {
-  SDG_K1_SWITCH(k + 1, return (launch_resq1<KK1>(M, nbatch, eta, b, u, rq, s)));
+  SDG_K1_SWITCH(k + 1, return (launch_resq1<KK1, double>(M, nbatch, eta, b, u, rq, s)));
+  return SDG_OK;
+}
+int sip_residual_q1_f32(const MeshDev& M, int k, int nbatch, const double* eta, const float* b,
+                        const float* u, float* rq, hipStream_t s) {
+  SDG_K1_SWITCH(k + 1, return (launch_resq1<KK1, float>(M, nbatch, eta, b, u, rq, s)));
   return SDG_OK;
 }
 int sip_residual(const MeshDev& M, int k, int nbatch, const double* eta, const double* b,

@@ -404,14 +404,14 @@ int setup_blocks(sdg_problem* P) {
       set_error("element block " + std::to_string(P->reps[i]) + " is not positive definite");
       return SDG_ERR_UNSUPPORTED;
     }
-  // low precision: the inverse Cholesky factor X = L^{-1} (packed lower
-  // triangle) in FP32 or BF16; the smoother applies X^T X
+  // low precision: the inverse Cholesky factor X = L^{-1} in FP32 or BF16,
+  // as full squares X and X^T per block; the smoother applies X^T X
   if (low && P->opt.prec_smoother == SDG_BF16) {
-    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * npk));
-    SDG_TRY(convert_f64_bf16(packed, P->binv16, (int64_t)P->nuniq * npk, P->s));
+    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * 2 * nbb));
+    SDG_TRY(tri_square_bf16(packed, P->NB, P->nuniq, P->binv16, P->s));
   } else if (low) {
-    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * npk));
-    SDG_TRY(convert_f64_f32(packed, P->binv32, (int64_t)P->nuniq * npk, P->s));
+    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * 2 * nbb));
+    SDG_TRY(tri_square_f32(packed, P->NB, P->nuniq, P->binv32, P->s));
   }
   return SDG_OK;
 }
@@ -675,8 +675,10 @@ int vcycle32(sdg_problem* P, const double* b, double* x) {
   const int64_t n = P->nu * P->nb;
   SDG_TRY(d2f(n, b, P->fb, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, true));
-  SDG_TRY(run_sip_residual_f32(P, P->fb, P->fx, P->fr));
-  SDG_TRY(p_restrict_f32(P->M, P->k, P->nb, P->fr, P->lev[0].b, P->s));
+  // the residual's Q1 modes only (as in the FP64 cycle)
+  SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 4) + 9 * elem_bytes(P, 8),
+                 [&] { return sip_residual_q1_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s); }));
+  SDG_TRY(p_restrict_f32(P->M, 1, P->nb, P->fr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
   SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, false));
