@@ -228,9 +228,27 @@ def batched(sdg, ctx, nreq):
     t = time.perf_counter() - t0
     sdg.sdg_server_destroy(srv)
     log(f"[bench] batched: {nreq} viscous solves in {t:.2f} s ({nreq / t:.1f} solves/s), failures {bad}")
+    # the same solves through the plain FP64 path: one request at a time, no
+    # batching, FP64 cycle (host arrays in and out, as the server's)
+    o_64 = sdg.make_options(rtol=RTOL, max_it=3000)
+    t0 = time.perf_counter()
+    bad64 = 0
+    for p in probs:
+        u = np.empty(p.nu)
+        try:
+            rc, _ = sdg.sdg_solve_viscous(ctx, sdg.make_mesh(p.nx, p.ny, p.k), o_64, p.eta,
+                                          np.ascontiguousarray(p.f.reshape(-1)), None, u)
+        except sdg.SDGError:
+            rc = -1
+        bad64 += rc not in (0, sdg.FLOOR)
+    t64 = time.perf_counter() - t0
+    log(f"[bench] plain FP64 per-request path: {t64:.2f} s ({nreq / t64:.1f} solves/s), failures {bad64}; "
+        f"batched/plain {t64 / t:.2f}x")
     return {"workload": f"{nreq}-grf-viscous-n16..128-k2..5-rtol1e-8", "solves_per_s": nreq / t,
             "dof_per_s": dofs / t, "seconds": t, "failures": bad, "cycle_precision": "fp32",
-            "mean_cg_its": float(np.mean(its)), "mean_launch_group": float(np.mean(groups))}
+            "mean_cg_its": float(np.mean(its)), "mean_launch_group": float(np.mean(groups)),
+            "fp64_per_request": {"solves_per_s": nreq / t64, "seconds": t64, "failures": bad64},
+            "speedup_vs_fp64_per_request": t64 / t}
 
 
 def main():
@@ -249,7 +267,7 @@ def main():
                     help="h-coarsening stops at this many elements per side (dense solve below)")
     ap.add_argument("--kernel-probe", type=int, default=0,
                     help="only launch the operator kernels this many times (counter runs)")
-    ap.add_argument("--batched", type=int, default=0,
+    ap.add_argument("--batched", type=int, default=64,
                     help="requests of the batched heterogeneous viscous workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving run (0 = skip)")

@@ -5,4 +5,9 @@
 
 namespace sdg {
 int ctx_device(const sdg_ctx* c);
+// Device memory through the context's block cache: ctx_alloc returns null
+// on failure; ctx_release takes the same byte count, and no queued work may
+// still use the block.
+void* ctx_alloc(sdg_ctx* c, size_t bytes);
+void ctx_release(sdg_ctx* c, void* p, size_t bytes);
 }  // namespace sdg

@@ -124,12 +124,13 @@ void run_group(sdg_server* S, const std::vector<sdg_req*>& grp, hipStream_t s) {
   const int64_t ne = n_el(r0.mesh), nu = n_u(r0.mesh), np = n_p(r0.mesh), ng = n_g(r0.mesh);
   double *de = nullptr, *df = nullptr, *dg = nullptr, *du = nullptr, *dp = nullptr;
   int rc = SDG_OK;
+  // staging arrays from the context's block cache (a group of the same
+  // shape as an earlier one reuses its blocks)
+  auto bytes_of = [](int64_t n) { return (size_t)std::max<int64_t>(n, 1) * sizeof(double); };
   auto al = [&](double** q, int64_t n) {
     if (rc < 0) return;
-    if (hipMalloc((void**)q, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess) {
-      (void)hipGetLastError();
-      rc = SDG_ERR_NOMEM;
-    }
+    *q = (double*)sdg::ctx_alloc(S->ctx, bytes_of(n));
+    if (!*q) rc = SDG_ERR_NOMEM;
   };
   al(&de, nb * ne);
   al(&df, nb * nu);
@@ -161,8 +162,13 @@ void run_group(sdg_server* S, const std::vector<sdg_req*>& grp, hipStream_t s) {
     if (hipStreamSynchronize(s) != hipSuccess) rc = SDG_ERR_DEVICE;
   }
   sdg_problem_destroy(P);
-  for (double* q : {de, df, dg, du, dp})
-    if (q) (void)hipFree(q);
+  // no queued work uses the staging arrays any more: drain the stream (the
+  // solve may have stopped on an error with work still queued)
+  (void)hipStreamSynchronize(s);
+  const int64_t ns[5] = {nb * ne, nb * nu, nb * ng, nb * nu, nb * np};
+  double* qs[5] = {de, df, dg, du, dp};
+  for (int i = 0; i < 5; ++i)
+    if (qs[i]) sdg::ctx_release(S->ctx, qs[i], bytes_of(ns[i]));
   const double t = wall_ms();
   const std::string err = rc < 0 ? std::string(sdg_last_error()) : std::string();
   for (int i = 0; i < nb; ++i) {

@@ -60,12 +60,19 @@ struct sdg_ctx {
   int64_t tr_n[SDG_TRACE_CLASSES] = {};
   double tr_ms[SDG_TRACE_CLASSES] = {};
   double tr_bytes[SDG_TRACE_CLASSES] = {};
+  // device blocks released by finished problems and temporaries, kept for
+  // reuse by size (hipFree synchronises the whole device, hipMalloc is slow;
+  // batched and served groups of one shape ask for the same sizes again).
+  // A block enters the cache only once no queued work uses it.  Guarded by mu.
+  std::multimap<size_t, void*> cache;
+  size_t cached = 0;
   ~sdg_ctx() {
     for (auto& r : pending) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& kv : cache) (void)hipFree(kv.second);
   }
 };
 
@@ -146,7 +153,7 @@ struct sdg_problem {
   int k = 0, K1 = 0, NB = 0, NPE = 0;
   int nel = 0;
   int64_t nu = 0, np = 0;  // per problem
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;
   size_t bytes = 0;
   double* eta = nullptr;   // [nb][nel]
   double* etap = nullptr;  // [nb][np], eta over the pressure modes
@@ -202,9 +209,54 @@ enum { SC_RZ = 0, SC_RZ2, SC_PQ, SC_RR, SC_BN, SC_H, SC_COUNT_FIXED };
 inline double* sc(sdg_problem* P, int slot) { return P->dsc + (int64_t)slot * P->nb; }
 inline double* sc_h(sdg_problem* P) { return P->dsc + (int64_t)SC_H * P->nb; }
 
+// Device memory through the context's cache: a released block of the same
+// (256-byte rounded) size is reused; otherwise hipMalloc, and on failure the
+// cache is emptied and the allocation tried once more.
+size_t cache_size(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+int ctx_get(sdg_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->cache.find(bytes);
+    if (it != c->cache.end()) {
+      *out = it->second;
+      c->cache.erase(it);
+      c->cached -= bytes;
+      return SDG_OK;
+    }
+  }
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::multimap<size_t, void*> drop;
+    {
+      std::lock_guard<std::mutex> g(c->mu);
+      drop.swap(c->cache);
+      c->cached = 0;
+    }
+    for (auto& kv : drop) (void)hipFree(kv.second);
+    e = hipMalloc(out, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    *out = nullptr;
+    return SDG_ERR_NOMEM;
+  }
+  return SDG_OK;
+}
+// The caller guarantees that no queued work still uses the block.
+void ctx_put(sdg_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(c->mu);
+  c->cache.emplace(bytes, p);
+  c->cached += bytes;
+}
+
 int palloc(sdg_problem* P, void** out, size_t bytes) {
   *out = nullptr;
   if (bytes == 0) return SDG_OK;
+  bytes = cache_size(bytes);
   {
     std::lock_guard<std::mutex> g(P->ctx->mu);
     if (P->ctx->budget && P->ctx->used + bytes > P->ctx->budget) {
@@ -213,18 +265,29 @@ int palloc(sdg_problem* P, void** out, size_t bytes) {
     }
     P->ctx->used += bytes;  // reserved before the allocation
   }
-  hipError_t e = hipMalloc(out, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
-    *out = nullptr;
+  if (ctx_get(P->ctx, bytes, out) < 0) {
     std::lock_guard<std::mutex> g(P->ctx->mu);
     P->ctx->used -= std::min(P->ctx->used, bytes);
     return SDG_ERR_NOMEM;
   }
-  P->allocs.push_back(*out);
+  P->allocs.push_back({*out, bytes});
   P->bytes += bytes;
   return SDG_OK;
+}
+// Temporaries of one call: from the cache, returned after the problem's
+// stream has drained (all work that used them is done).
+template <typename T>
+int tmp_get(sdg_problem* P, T** out, int64_t n) {
+  void* p = nullptr;
+  const int rc = ctx_get(P->ctx, cache_size((size_t)std::max<int64_t>(n, 1) * sizeof(T)), &p);
+  *out = (T*)p;
+  return rc;
+}
+template <typename T>
+void tmp_put(sdg_problem* P, T* p, int64_t n) {
+  if (!p) return;
+  (void)hipStreamSynchronize(P->s);
+  ctx_put(P->ctx, (void*)p, cache_size((size_t)std::max<int64_t>(n, 1) * sizeof(T)));
 }
 
 template <typename T>
@@ -779,13 +842,17 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
   S.total = n * nb;
   double *V = nullptr, *w = nullptr, *dH = nullptr, *lam = nullptr;
   int* dms = nullptr;
-  if (hipMalloc((void**)&V, (size_t)(m + 1) * S.total * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&w, (size_t)S.total * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&dH, (size_t)(m + 1) * m * nb * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&lam, (size_t)nb * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&dms, (size_t)nb * sizeof(int)) != hipSuccess) {
-    (void)hipGetLastError();
-    for (void* q : {(void*)V, (void*)w, (void*)dH, (void*)lam, (void*)dms}) (void)hipFree(q);
+  const int64_t nV = (int64_t)(m + 1) * S.total, nH = (int64_t)(m + 1) * m * nb;
+  auto release = [&] {
+    tmp_put(P, V, nV);
+    tmp_put(P, w, S.total);
+    tmp_put(P, dH, nH);
+    tmp_put(P, lam, nb);
+    tmp_put(P, dms, nb);
+  };
+  if (tmp_get(P, &V, nV) < 0 || tmp_get(P, &w, S.total) < 0 || tmp_get(P, &dH, nH) < 0 ||
+      tmp_get(P, &lam, nb) < 0 || tmp_get(P, &dms, nb) < 0) {
+    release();
     set_error("allocation of the Arnoldi workspace failed");
     return SDG_ERR_NOMEM;
   }
@@ -855,8 +922,7 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
     lambda.resize(nb);
     if ((rc = read_dev(P, lam, nb, lambda.data())) < 0) break;
   } while (0);
-  (void)hipStreamSynchronize(P->s);
-  for (void* q : {(void*)V, (void*)w, (void*)dH, (void*)lam, (void*)dms}) (void)hipFree(q);
+  release();  // synchronises the stream first
   if (rc < 0) return rc;
   if (hess_out) *hess_out = H;
   return SDG_OK;
@@ -1549,7 +1615,11 @@ void sdg_problem_destroy(sdg_problem* P) {
   (void)hipStreamSynchronize(P->s);
   drop_graphs(P);
   if (P->gs) (void)hipStreamDestroy(P->gs);
-  for (void* p : P->allocs) (void)hipFree(p);
+  // the stream has drained: the blocks go back to the context's cache
+  if (P->ctx)
+    for (auto& a : P->allocs) ctx_put(P->ctx, a.first, a.second);
+  else
+    for (auto& a : P->allocs) (void)hipFree(a.first);
   if (P->hsc) (void)hipHostFree(P->hsc);
   if (P->hpub) (void)hipHostFree(P->hpub);
   if (sdg_ctx* c = P->ctx) {
@@ -1731,10 +1801,10 @@ int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, doub
   const int64_t U = P->nu * P->nb;
   double* F = nullptr;
   double* G = nullptr;
-  SDG_HIP(hipMalloc((void**)&F, U * sizeof(double)));
-  if (hipMalloc((void**)&G, std::max<int64_t>(P->np * P->nb, 1) * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFree(F);
+  const int64_t nG = std::max<int64_t>(P->np * P->nb, 1);
+  if (tmp_get(P, &F, U) < 0 || tmp_get(P, &G, nG) < 0) {
+    tmp_put(P, F, U);
+    tmp_put(P, G, nG);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
@@ -1762,9 +1832,8 @@ int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, doub
     if (rc >= 0)
       for (int pb = 0; pb < P->nb; ++pb) rel[pb] = fn[pb] > 0 ? rn[pb] / fn[pb] : 0.0;
   }
-  (void)hipStreamSynchronize(P->s);
-  (void)hipFree(F);
-  (void)hipFree(G);
+  tmp_put(P, F, U);  // synchronises the stream first
+  tmp_put(P, G, nG);
   if (rc < 0) return rc;
   return fill_stats(P, st, status, its, rel, t0, false);
 }
@@ -1776,10 +1845,9 @@ int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, doubl
   const int64_t U = P->nu * P->nb;
   double* b = nullptr;
   double* x = nullptr;
-  SDG_HIP(hipMalloc((void**)&b, S.total * sizeof(double)));
-  if (hipMalloc((void**)&x, S.total * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFree(b);
+  if (tmp_get(P, &b, S.total) < 0 || tmp_get(P, &x, S.total) < 0) {
+    tmp_put(P, b, S.total);
+    tmp_put(P, x, S.total);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
@@ -1802,9 +1870,8 @@ int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, doubl
         hipMemcpyAsync(p, x + U, P->np * P->nb * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess)
       rc = SDG_ERR_DEVICE;
   }
-  (void)hipStreamSynchronize(P->s);
-  (void)hipFree(b);
-  (void)hipFree(x);
+  tmp_put(P, b, S.total);  // synchronises the stream first
+  tmp_put(P, x, S.total);
   if (rc < 0) return rc;
   return fill_stats(P, st, status, its, rel, t0, true);
 }
@@ -1822,13 +1889,17 @@ static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
   const int64_t ng = (int64_t)(2 * mesh->nx + 2 * mesh->ny) * 2 * (mesh->k + 1);
   double *de = nullptr, *df = nullptr, *dg = nullptr, *du = nullptr, *dp = nullptr;
   int rc = SDG_OK;
+  // staging arrays from the context's cache (returned below, after the
+  // synchronous copies and the problem's own drain)
+  auto bytes_of = [](int64_t n) { return cache_size((size_t)std::max<int64_t>(n, 1) * sizeof(double)); };
   auto al = [&](double** q, int64_t n) {
     if (rc < 0) return;
-    if (hipMalloc((void**)q, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess) {
-      (void)hipGetLastError();
+    void* v = nullptr;
+    if (ctx_get(ctx, bytes_of(n), &v) < 0) {
       set_error("allocation failed");
       rc = SDG_ERR_NOMEM;
     }
+    *q = (double*)v;
   };
   al(&de, nel);
   al(&df, nu);
@@ -1857,9 +1928,11 @@ static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
       }
     }
   }
-  sdg_problem_destroy(P);
-  for (double* q : {de, df, dg, du, dp})
-    if (q) (void)hipFree(q);
+  sdg_problem_destroy(P);  // drains the problem's stream; the copies above are synchronous
+  const int64_t ns[5] = {nel, nu, ng, nu, np};
+  double* qs[5] = {de, df, dg, du, dp};
+  for (int i = 0; i < 5; ++i)
+    if (qs[i]) ctx_put(ctx, qs[i], bytes_of(ns[i]));
   return rc;
 }
 
@@ -2032,3 +2105,11 @@ int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out, void* s
 }
 
 }  // extern "C"
+
+namespace sdg {
+void* ctx_alloc(sdg_ctx* c, size_t bytes) {
+  void* p = nullptr;
+  return ctx_get(c, cache_size(bytes), &p) < 0 ? nullptr : p;
+}
+void ctx_release(sdg_ctx* c, void* p, size_t bytes) { ctx_put(c, p, cache_size(bytes)); }
+}  // namespace sdg
