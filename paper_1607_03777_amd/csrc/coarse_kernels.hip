@@ -573,15 +573,37 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_lds_kernel(TailArgs A) {
   auto XV = [&](int l) { return base[l] + 40 * tail_nn(A.lev[l]); };
   auto RV = [&](int l) { return base[l] + 42 * tail_nn(A.lev[l]); };
   auto DV = [&](int l) { return base[l] + 44 * tail_nn(A.lev[l]); };
+  // this problem's Chebyshev coefficients of every smoothed level (all but
+  // the dense coarsest, which has none) and step, after the levels: ab[l][s][2]
+  double* sab;
+  {
+    int64_t off = 0;
+    for (int l = 0; l < nl; ++l) off += 46 * (int64_t)tail_nn(A.lev[l]);
+    sab = lds + off;
+  }
+  for (int q = t; q < (nl - 1) * A.steps; q += TAIL_NT) {
+    const int l = q / A.steps, st_ = q - l * A.steps;
+    sab[2 * q] = A.lev[l].ab[(int64_t)(st_ * nb + pb) * 2];
+    sab[2 * q + 1] = A.lev[l].ab[(int64_t)(st_ * nb + pb) * 2 + 1];
+  }
+  // stage the levels: four loads in flight per thread and round
   for (int l = 0; l < nl; ++l) {
     const TailLevel& L = A.lev[l];
     const int nn = tail_nn(L);
     const int64_t NN = (int64_t)nb * nn;
     if (l < nl - 1) {
       double* st = ST(l);
-      for (int q = t; q < 36 * nn; q += TAIL_NT) {
-        const int k = q / nn, node = q - k * nn;
-        st[q] = L.st[(int64_t)k * NN + pb * nn + node];
+      for (int q0 = t; q0 < 36 * nn; q0 += 4 * TAIL_NT) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * TAIL_NT;
+          const int k = q / nn, node = q - k * nn;
+          v[u] = q < 36 * nn ? L.st[(int64_t)k * NN + pb * nn + node] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u * TAIL_NT < 36 * nn) st[q0 + u * TAIL_NT] = v[u];
       }
       for (int q = t; q < 2 * nn; q += TAIL_NT) DI(l)[q] = L.dinv[pb * 2 * nn + q];
     }
@@ -623,7 +645,7 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_lds_kernel(TailArgs A) {
         resid(l);
         __syncthreads();
       }
-      const double ca = L.ab[(int64_t)(s * nb + pb) * 2], cb = L.ab[(int64_t)(s * nb + pb) * 2 + 1];
+      const double ca = sab[2 * (l * A.steps + s)], cb = sab[2 * (l * A.steps + s) + 1];
       for (int i = t; i < 2 * nn; i += TAIL_NT) {
         const double rv = (first && zero) ? b[i] : r[i];
         const double z = di[i] * rv;
@@ -674,9 +696,19 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_lds_kernel(TailArgs A) {
     const int wave = t >> 6, lane = t & 63;
     double* part = ST(nl - 1);  // NW * n2 <= 36 nn doubles
     const int cb = (n2 + NW - 1) / NW, c0 = wave * cb, c1 = min(n2, c0 + cb);
+    constexpr int CBMAX = 16;  // column blocks up to 16 wide: the loads of a lane are issued together
     for (int i = lane; i < n2; i += 64) {
       double sum = 0.0;
-      for (int jj = c0; jj < c1; ++jj) sum += D[(int64_t)jj * n2 + i] * b[jj];
+      if (cb <= CBMAX) {
+        double dv[CBMAX];
+#pragma unroll
+        for (int u = 0; u < CBMAX; ++u) dv[u] = (c0 + u < c1) ? D[(int64_t)(c0 + u) * n2 + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CBMAX; ++u)
+          if (c0 + u < c1) sum += dv[u] * b[c0 + u];
+      } else {
+        for (int jj = c0; jj < c1; ++jj) sum += D[(int64_t)jj * n2 + i] * b[jj];
+      }
       part[wave * n2 + i] = sum;
     }
     __syncthreads();
@@ -719,6 +751,7 @@ __global__ __launch_bounds__(TAIL_NT) void coarse_tail_lds_kernel(TailArgs A) {
 size_t coarse_tail_lds_bytes(const TailArgs& A) {
   size_t n = 0;
   for (int l = 0; l < A.nlev; ++l) n += 46 * (size_t)(A.lev[l].nx + 1) * (A.lev[l].ny + 1);
+  n += 2 * (size_t)A.nlev * A.steps;  // Chebyshev coefficients
   return n * sizeof(double);
 }
 
