@@ -633,11 +633,34 @@ template <> struct WaveTile<5> { static constexpr int TX = 4, TY = 3; };
 template <> struct WaveTile<6> { static constexpr int TX = 5, TY = 2; };
 template <> struct WaveTile<7> { static constexpr int TX = 3, TY = 3; };
 
+// LDS layout of the wavefront kernel.  The staged element is stored
+// transposed, su[(d K1 + col) S + el K1 + row], so that the row pass (lane
+// (el, j) touching row j) addresses consecutive words and the column pass
+// (lane (el, i) touching column i) addresses el K1 + i S; a face record is
+// split by slot, sf[slot Q + face K1 + mode], so that the lanes of adjacent
+// elements touch consecutive words.  S and Q are the strides with the fewest
+// LDS bank conflicts (32 and 64 banks of 4 bytes) among those that keep the
+// workgroups per compute unit of the element-major layout.
+template <int K1, typename T> struct WaveLds;
+template <> struct WaveLds<2, double> { static constexpr int S = 65, Q = 80; };
+template <> struct WaveLds<3, double> { static constexpr int S = 65, Q = 84; };
+template <> struct WaveLds<4, double> { static constexpr int S = 65, Q = 80; };
+template <> struct WaveLds<5, double> { static constexpr int S = 63, Q = 80; };
+template <> struct WaveLds<6, double> { static constexpr int S = 65, Q = 90; };
+template <> struct WaveLds<7, double> { static constexpr int S = 63, Q = 84; };
+template <> struct WaveLds<2, float> { static constexpr int S = 65, Q = 80; };
+template <> struct WaveLds<3, float> { static constexpr int S = 65, Q = 84; };
+template <> struct WaveLds<4, float> { static constexpr int S = 65, Q = 80; };
+template <> struct WaveLds<5, float> { static constexpr int S = 62, Q = 80; };
+template <> struct WaveLds<6, float> { static constexpr int S = 65, Q = 90; };
+template <> struct WaveLds<7, float> { static constexpr int S = 63, Q = 84; };
+
 // Face coefficients at mode m (the formulas of face_mode above), with the
-// derivative entries taken from registers: up[t] = D(m, m+1+2t),
+// record's slots QS apart and the derivative entries taken from registers:
+// up[t] = D(m, m+1+2t),
 // dn[t] = D(m-1-2t, m); ihn = 1/hn and iht = 1/ht are passed in, so the
 // coefficients take no divisions.
-template <int K1, int DIR, typename T>
+template <int K1, int DIR, int QS, typename T>
 __device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int kind, int side, T etam, T etap,
                                             T ihn, T iht, const T (&up)[K1 / 2], const T (&dn)[K1 / 2],
                                             T (&o)[8]) {
@@ -647,7 +670,7 @@ __device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int 
   if (kind < 0 || kind == F_NEUMANN) return;
   const T kk = T(K1 * K1);
   const T c2n = T(2) * ihn, c2t = T(2) * iht;
-  auto at = [&](int s, int d, int w, int j) { return f[((s * 2 + d) * 2 + w) * K1 + j]; };
+  auto at = [&](int s, int d, int w, int j) { return f[((s * 2 + d) * 2 + w) * QS + j]; };
   if (kind == F_NAVIER) {
     const T eta = side == 0 ? etam : etap;
     const T alpha = T(8) * eta * kk * ihn;
@@ -720,12 +743,15 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   constexpr int TX = WaveTile<K1>::TX, TY = WaveTile<K1>::TY;
   constexpr int KK = K1 * K1, NB = 2 * KK, E = TX * TY, NH = K1 / 2;
   static_assert(E * K1 <= 64, "tile does not fit a wavefront");
-  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), NF = NFV > NFH ? NFV : NFH, FS = 8 * K1 + 1;
-  // element stride in su: odd from k = 3 on (fewer LDS bank conflicts between
-  // the row and column passes; within the same LDS allocation granule)
-  constexpr int ES = NB + (K1 >= 4 ? 1 : 0);
-  __shared__ T su[E * ES];  // [el][d][j][i]; later the column results
-  __shared__ T sf[NF * FS];  // face records [s][d][w][m]: the x-faces, then the y-faces
+  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1), NF = NFV > NFH ? NFV : NFH;
+  constexpr int S = WaveLds<K1, T>::S, Q = WaveLds<K1, T>::Q;
+  static_assert(S >= E * K1 && Q >= NF * K1, "LDS strides too small");
+  __shared__ T su[(2 * K1 - 1) * S + E * K1];  // [d][col][el][row]; later the column results
+  __shared__ T sf[7 * Q + NF * K1];  // face records: slots (s, d, w) of [face][m]; x-faces, then y-faces
+  // element e's entry (row, col) of component d
+  auto SU = [&](int e, int d, int row, int col) -> T& { return su[(d * K1 + col) * S + e * K1 + row]; };
+  // slot (s, d, w) of the face record at fp, mode m
+  auto FA = [&](T* fp, int sd, int d, int w, int m) -> T& { return fp[((sd * 2 + d) * 2 + w) * Q + m]; };
   const int lane = threadIdx.x;
   const int nx = M.nx, ny = M.ny;
   const int ntx = (nx + TX - 1) / TX;
@@ -802,8 +828,8 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 
   // ---- rows: stage the element, x-face traces, S_x
   T yr[2][K1];
-  T* fl = sf + (ty * (TX + 1) + tx) * FS;  // left x-face, this element on the plus side
-  T* fr = fl + FS;                          // right x-face, minus side
+  T* fl = sf + (ty * (TX + 1) + tx) * K1;  // left x-face, this element on the plus side
+  T* fr = fl + K1;                          // right x-face, minus side
   if (act) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
@@ -811,24 +837,24 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
       for (int i = 0; i < K1; ++i) r[i] = valid ? u[ge * NB + d * KK + j * K1 + i] : T(0);
 #pragma unroll
-      for (int i = 0; i < K1; ++i) su[el * ES + d * KK + j * K1 + i] = r[i];
+      for (int i = 0; i < K1; ++i) SU(el, d, j, i) = r[i];
       T tl, gl, tr, gr;
       trace4(r, tl, gl, tr, gr);
-      fl[((1 * 2 + d) * 2 + 0) * K1 + j] = tl;
-      fl[((1 * 2 + d) * 2 + 1) * K1 + j] = gl;
-      fr[((0 * 2 + d) * 2 + 0) * K1 + j] = tr;
-      fr[((0 * 2 + d) * 2 + 1) * K1 + j] = gr;
+      FA(fl, 1, d, 0, j) = tl;
+      FA(fl, 1, d, 1, j) = gl;
+      FA(fr, 0, d, 0, j) = tr;
+      FA(fr, 0, d, 1, j) = gr;
       // the outer sides of the tile's left and right faces (zero where the
       // mesh ends: hxr is zero there)
       if (tx == 0 || tx == TX - 1) {
         T a0, a1, a2, a3;
         trace4(hxr[d], a0, a1, a2, a3);
         if (tx == 0) {
-          fl[((0 * 2 + d) * 2 + 0) * K1 + j] = a2;
-          fl[((0 * 2 + d) * 2 + 1) * K1 + j] = a3;
+          FA(fl, 0, d, 0, j) = a2;
+          FA(fl, 0, d, 1, j) = a3;
         } else {
-          fr[((1 * 2 + d) * 2 + 0) * K1 + j] = a0;
-          fr[((1 * 2 + d) * 2 + 1) * K1 + j] = a1;
+          FA(fr, 1, d, 0, j) = a0;
+          FA(fr, 1, d, 1, j) = a1;
         }
       }
       const T cx = (d == 0 ? T(2) : T(1)) * et * cxx;
@@ -849,7 +875,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     T o[8];
     {
       const int kind = ix > 0 ? F_INTERIOR : M.bc[0];
-      face_mode_w<K1, 0, T>(fl, j, valid ? kind : -1, 1, eL, et, ihx, ihy, up, dn, o);
+      face_mode_w<K1, 0, Q, T>(fl, j, valid ? kind : -1, 1, eL, et, ihx, ihy, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
@@ -859,7 +885,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     }
     {
       const int kind = ix + 1 < nx ? F_INTERIOR : M.bc[1];
-      face_mode_w<K1, 0, T>(fr, j, valid ? kind : -1, 0, et, eR, ihx, ihy, up, dn, o);
+      face_mode_w<K1, 0, Q, T>(fr, j, valid ? kind : -1, 0, et, eR, ihx, ihy, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
@@ -885,30 +911,29 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   // ---- columns (lane column ic = j): y-face traces, S_y, mixed term of y0
   T yc[2][K1];
   const int ic = j;
-  const T* ue = su + el * ES;
-  T* fb = sf + (ty * TX + tx) * FS;        // bottom y-face, this element on the plus side
-  T* ft = sf + ((ty + 1) * TX + tx) * FS;  // top y-face, minus side
+  T* fb = sf + (ty * TX + tx) * K1;        // bottom y-face, this element on the plus side
+  T* ft = sf + ((ty + 1) * TX + tx) * K1;  // top y-face, minus side
   if (act) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       T c[K1];
 #pragma unroll
-      for (int jj = 0; jj < K1; ++jj) c[jj] = ue[d * KK + jj * K1 + ic];
+      for (int jj = 0; jj < K1; ++jj) c[jj] = SU(el, d, jj, ic);
       T tb, gb, tt, gt;
       trace4(c, tb, gb, tt, gt);
-      fb[((1 * 2 + d) * 2 + 0) * K1 + ic] = tb;
-      fb[((1 * 2 + d) * 2 + 1) * K1 + ic] = gb;
-      ft[((0 * 2 + d) * 2 + 0) * K1 + ic] = tt;
-      ft[((0 * 2 + d) * 2 + 1) * K1 + ic] = gt;
+      FA(fb, 1, d, 0, ic) = tb;
+      FA(fb, 1, d, 1, ic) = gb;
+      FA(ft, 0, d, 0, ic) = tt;
+      FA(ft, 0, d, 1, ic) = gt;
       if (ty == 0 || ty == TY - 1) {
         T a0, a1, a2, a3;
         trace4(hyc[d], a0, a1, a2, a3);
         if (ty == 0) {
-          fb[((0 * 2 + d) * 2 + 0) * K1 + ic] = a2;
-          fb[((0 * 2 + d) * 2 + 1) * K1 + ic] = a3;
+          FA(fb, 0, d, 0, ic) = a2;
+          FA(fb, 0, d, 1, ic) = a3;
         } else {
-          ft[((1 * 2 + d) * 2 + 0) * K1 + ic] = a0;
-          ft[((1 * 2 + d) * 2 + 1) * K1 + ic] = a1;
+          FA(ft, 1, d, 0, ic) = a0;
+          FA(ft, 1, d, 1, ic) = a1;
         }
       }
       const T cy = (d == 1 ? T(2) : T(1)) * et * cyy;
@@ -930,7 +955,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       const int l = ic + 1 + 2 * t;
       if (l < K1) {
 #pragma unroll
-        for (int m = 0; m < K1; ++m) w[m] += up[t] * ue[KK + m * K1 + l];
+        for (int m = 0; m < K1; ++m) w[m] += up[t] * SU(el, 1, m, l);
       }
     }
 #pragma unroll
@@ -949,7 +974,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     T o[8];
     {
       const int kind = iy > 0 ? F_INTERIOR : M.bc[2];
-      face_mode_w<K1, 1, T>(fb, j, valid ? kind : -1, 1, eB, et, ihy, ihx, up, dn, o);
+      face_mode_w<K1, 1, Q, T>(fb, j, valid ? kind : -1, 1, eB, et, ihy, ihx, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(1 * 2 + d) * 2 + 0], b = o[(1 * 2 + d) * 2 + 1];
@@ -959,7 +984,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     }
     {
       const int kind = iy + 1 < ny ? F_INTERIOR : M.bc[3];
-      face_mode_w<K1, 1, T>(ft, j, valid ? kind : -1, 0, et, eT, ihy, ihx, up, dn, o);
+      face_mode_w<K1, 1, Q, T>(ft, j, valid ? kind : -1, 0, et, eT, ihy, ihx, up, dn, o);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const T a = o[(0 * 2 + d) * 2 + 0], b = o[(0 * 2 + d) * 2 + 1];
@@ -976,7 +1001,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       const int l = j + 1 + 2 * t;
       if (l < K1) {
 #pragma unroll
-        for (int mm = 0; mm < K1; ++mm) r0[mm] += up[t] * ue[l * K1 + mm];
+        for (int mm = 0; mm < K1; ++mm) r0[mm] += up[t] * SU(el, 0, l, mm);
       }
     }
 #pragma unroll
@@ -995,7 +1020,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     for (int d = 0; d < 2; ++d)
 #pragma unroll
       for (int i = 0; i < K1; ++i)
-        dot += double(ue[d * KK + j * K1 + i]) * double(yr[d][i]) + double(ue[d * KK + i * K1 + ic]) * double(yc[d][i]);
+        dot += double(SU(el, d, j, i)) * double(yr[d][i]) + double(SU(el, d, i, ic)) * double(yc[d][i]);
   }
   __syncthreads();
   // column results back to rows
@@ -1003,7 +1028,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
     for (int d = 0; d < 2; ++d)
 #pragma unroll
-      for (int jj = 0; jj < K1; ++jj) su[el * ES + d * KK + jj * K1 + ic] = yc[d][jj];
+      for (int jj = 0; jj < K1; ++jj) SU(el, d, jj, ic) = yc[d][jj];
   }
   __syncthreads();
   if constexpr (MODE == M_RESQ1) {
@@ -1012,7 +1037,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
       for (int d = 0; d < 2; ++d)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          const T v = yr[d][i] + su[el * ES + d * KK + j * K1 + i];
+          const T v = yr[d][i] + SU(el, d, j, i);
           y[ge * 8 + d * 4 + j * 2 + i] = bres[d][i] - v;
         }
     }
@@ -1022,7 +1047,7 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
       for (int i = 0; i < K1; ++i) {
         const int64_t g = ge * NB + d * KK + j * K1 + i;
-        const T v = yr[d][i] + su[el * ES + d * KK + j * K1 + i];
+        const T v = yr[d][i] + SU(el, d, j, i);
         if constexpr (MODE == M_RESID) y[g] = bres[d][i] - v;
         else y[g] = v;
       }
