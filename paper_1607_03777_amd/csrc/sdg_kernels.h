@@ -149,6 +149,22 @@ int cg_update1(int64_t n, int nbatch, const double* p, const double* q, double* 
                hipStream_t s);
 int cg_update2(int64_t n, int nbatch, const double* z, double* p, const double* rz_new, const double* rz_old,
                const int* active, hipStream_t s);
+// The CG steps with the preceding reduction's second stage folded in (the
+// same summation order as reduce_stage2, one launch fewer each):
+// partials of <x[pb], y[pb]>, *nparts per problem (first stage only)
+int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* part, int cap, int* nparts,
+               hipStream_t s);
+// rz_new[pb] = sum of rzpart[pb * nparts ..]; then cg_update2
+int cg_update2_red(int64_t n, int nbatch, const double* z, double* p, const double* rzpart, int nparts,
+                   double* rz_new, const double* rz_old, const int* active, hipStream_t s);
+// pq_out[pb] = sum of pqpart[pb * npq ..]; then cg_update1 with the partials
+// of ||r||^2 in rrpart (*nrr per problem, at most rr_cap in all)
+int cg_update1_red(int64_t n, int nbatch, const double* p, const double* q, double* x, double* r, const double* rz,
+                   const double* pqpart, int npq, double* pq_out, const int* active, double* rrpart,
+                   int rr_cap, int* nrr, hipStream_t s);
+// rr[pb] = sum of rrpart[pb * nrr ..]; then publish_scalars(src, n, ...)
+int publish_red(const double* rrpart, int nrr, int nbatch, double* rr, const double* src, int n, double* host_dst,
+                unsigned* dev_count, unsigned* host_seq, hipStream_t s);
 // ab[pb] = (a, b) Chebyshev coefficients per problem
 int bcheb_update(int64_t n, int nbatch, const double* ab, const double* z, double* d, double* x, int mode,
                  hipStream_t s);

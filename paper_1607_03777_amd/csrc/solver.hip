@@ -560,6 +560,21 @@ int run_sip_apply_dot(sdg_problem* P, const double* u, double* y, double* out) {
   }));
   return reduce_parts(parts / P->nb, P->nb, P->red, out, P->s);
 }
+// y = A u and the partial sums of u.y, *nparts per problem in P->red (at
+// most cap in all): the operator kernel's per-tile partials, or a first
+// reduction stage after a plain apply
+int run_sip_apply_dot_parts(sdg_problem* P, const double* u, double* y, int cap, int* nparts) {
+  const int parts = sip_apply_dot_parts(P->M, P->k, P->nb);
+  if (P->tile[0][0] != 0 || parts <= 0 || parts > cap) {
+    SDG_TRY(run_sip_apply(P, u, y));
+    return bdot_parts(P->nu, P->nb, u, y, P->red, cap, nparts, P->s);
+  }
+  SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8), [&] {
+    return sip_apply_dot(P->M, P->k, P->nb, P->eta, u, y, P->red, cap, P->s);
+  }));
+  *nparts = parts / P->nb;
+  return SDG_OK;
+}
 int run_sip_residual(sdg_problem* P, const double* b, const double* u, double* r) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 8) + elem_bytes(P, 8),
                 [&] { return sip_residual(P->M, P->k, P->nb, P->eta, b, u, r, P->s, P->tile[1][0]); });
@@ -941,14 +956,19 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
 int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
   const int nb = P->nb;
   const int64_t n = P->nu;
+  // partial sums live in the two halves of the reduction scratch: r.z and
+  // p.q in the first, ||r||^2 in the second (written while p.q's are read)
+  constexpr int HALF = RED_SCRATCH / 2;
+  double* part_rr = P->red + HALF;
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
-  SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rzB, P->red, P->s));
-  SDG_TRY(cg_update2(n, nb, P->cg_z, P->cg_p, rzB, rzA, P->active, P->s));
-  SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
-  SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
-                     P->s));
+  int nrz = 0, npq = 0, nrr = 0;
+  SDG_TRY(bdot_parts(n, nb, P->cg_r, P->cg_z, P->red, HALF, &nrz, P->s));
+  SDG_TRY(cg_update2_red(n, nb, P->cg_z, P->cg_p, P->red, nrz, rzB, rzA, P->active, P->s));
+  SDG_TRY(run_sip_apply_dot_parts(P, P->cg_p, P->cg_q, HALF, &npq));
+  SDG_TRY(cg_update1_red(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, P->red, npq, sc(P, SC_PQ), P->active, part_rr,
+                         HALF, &nrr, P->s));
   // (p.q, ||r||^2) to the pinned mirror; the host counts the publications
-  return publish_scalars(sc(P, SC_PQ), 2 * nb, P->hpub, P->dcount, P->hseq, P->s);
+  return publish_red(part_rr, nrr, nb, sc(P, SC_RR), sc(P, SC_PQ), 2 * nb, P->hpub, P->dcount, P->hseq, P->s);
 }
 
 // Captures cg_body (on the fixed iterate buffer) as a graph, once per parity.

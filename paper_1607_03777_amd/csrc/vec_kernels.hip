@@ -169,6 +169,12 @@ static inline int red_blocks(int64_t n) {
   int64_t b = (n + VT - 1) / VT;
   return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
 }
+// blocks per problem of the CG kernels that read all partials of a reduction
+constexpr int CG_BLOCKS = 128;
+static inline int cg_blocks(int64_t n) {
+  const int b = red_blocks(n);
+  return b < CG_BLOCKS ? b : CG_BLOCKS;
+}
 
 int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,
               double* scratch, hipStream_t s) {
@@ -436,6 +442,22 @@ int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const
   return SDG_OK;
 }
 
+// first stage of <x[pb], y[pb]>: *nparts partials per problem at
+// part[pb * nparts + i] (at most cap in all)
+int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* part, int cap, int* nparts,
+               hipStream_t s) {
+  if (nbatch <= 0 || nbatch > cap) {
+    set_error("reduction scratch too small for this batch");
+    return SDG_ERR_INVALID;
+  }
+  int nb = cg_blocks(n);
+  if ((int64_t)nb * nbatch > cap) nb = std::max(1, cap / nbatch);
+  *nparts = nb;
+  hipLaunchKernelGGL(bmultidot_stage1, dim3(nb, nbatch), dim3(VT), 0, s, n, 1, x, (int64_t)0, y, part);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
 // w[pb] -= sum_j h[pb][j] V_j[pb]
 __global__ void bmulti_axpy_kernel(int64_t n, int nbatch, int m, const double* __restrict__ V, int64_t ldv,
                                    const double* __restrict__ h, double* __restrict__ w) {
@@ -603,6 +625,129 @@ __global__ void bhess_eig_kernel(int nbatch, const double* __restrict__ Hin, con
 int bhessenberg_max_eig(int nbatch, const double* H, const int* ms, int ld, int64_t hstride, double* out,
                         hipStream_t s) {
   hipLaunchKernelGGL(bhess_eig_kernel, dim3(ceil_div(nbatch, 64)), dim3(64), 0, s, nbatch, H, ms, ld, hstride, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// CG steps with the preceding reduction's second stage folded in.  Every
+// block first sums its problem's partials with the loop and block_sum of
+// reduce_stage2 (the same order, so the same value in every block), then
+// does its slice of the update; block 0 of each problem stores the sum.  As
+// every block reads all partials, these kernels and the first stage that
+// feeds them use at most CG_BLOCKS blocks per problem.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_total(int nparts, const double* __restrict__ part) {
+  __shared__ double tot;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += VT) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) tot = s;
+  __syncthreads();
+  const double t = tot;
+  __syncthreads();
+  return t;
+}
+
+// rz_new[pb] = sum of rzpart[pb][0 .. nparts); p = z + (rz_new / rz_old) p
+__global__ __launch_bounds__(VT) void cg_update2_red_kernel(int64_t n, const double* __restrict__ z,
+                                                            double* __restrict__ p,
+                                                            const double* __restrict__ rzpart, int nparts,
+                                                            double* __restrict__ rz_new,
+                                                            const double* __restrict__ rz_old,
+                                                            const int* __restrict__ active) {
+  const int pb = blockIdx.y;
+  const double rz = block_total(nparts, rzpart + (int64_t)pb * nparts);
+  if (blockIdx.x == 0 && threadIdx.x == 0) rz_new[pb] = rz;
+  if (!active[pb]) return;
+  const double beta = rz / rz_old[pb];
+  const int64_t off = (int64_t)pb * n;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT)
+    p[off + g] = z[off + g] + beta * p[off + g];
+}
+int cg_update2_red(int64_t n, int nbatch, const double* z, double* p, const double* rzpart, int nparts,
+                   double* rz_new, const double* rz_old, const int* active, hipStream_t s) {
+  if (n <= 0 || nbatch <= 0) return SDG_OK;
+  hipLaunchKernelGGL(cg_update2_red_kernel, dim3(cg_blocks(n), nbatch), dim3(VT), 0, s, n, z, p, rzpart, nparts,
+                     rz_new, rz_old, active);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// pq[pb] = sum of pqpart[pb][0 .. npq); alpha = active ? rz/pq : 0;
+// x += alpha p; r -= alpha q; partial sums of ||r||^2 into rrpart[pb][blk]
+__global__ __launch_bounds__(VT) void cg_update1_red_kernel(int64_t n, const double* __restrict__ p,
+                                                            const double* __restrict__ q, double* __restrict__ x,
+                                                            double* __restrict__ r, const double* __restrict__ rz,
+                                                            const double* __restrict__ pqpart, int npq,
+                                                            double* __restrict__ pq_out,
+                                                            const int* __restrict__ active,
+                                                            double* __restrict__ rrpart) {
+  const int pb = blockIdx.y;
+  const double pq = block_total(npq, pqpart + (int64_t)pb * npq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) pq_out[pb] = pq;
+  const double a = (active[pb] && pq > 0.0) ? rz[pb] / pq : 0.0;
+  const int64_t off = (int64_t)pb * n;
+  double s = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+    const double rv = r[off + g] - a * q[off + g];
+    x[off + g] += a * p[off + g];
+    r[off + g] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) rrpart[(int64_t)pb * gridDim.x + blockIdx.x] = s;
+}
+int cg_update1_red(int64_t n, int nbatch, const double* p, const double* q, double* x, double* r, const double* rz,
+                   const double* pqpart, int npq, double* pq_out, const int* active, double* rrpart,
+                   int rr_cap, int* nrr, hipStream_t s) {
+  if (n <= 0 || nbatch <= 0) return SDG_OK;
+  int nb = cg_blocks(n);
+  if ((int64_t)nb * nbatch > rr_cap) nb = std::max(1, rr_cap / nbatch);
+  if ((int64_t)nb * nbatch > rr_cap) {
+    set_error("reduction scratch too small for this batch");
+    return SDG_ERR_INVALID;
+  }
+  *nrr = nb;
+  hipLaunchKernelGGL(cg_update1_red_kernel, dim3(nb, nbatch), dim3(VT), 0, s, n, p, q, x, r, rz, pqpart, npq, pq_out,
+                     active, rrpart);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// rr[pb] = sum of rrpart[pb][0 .. nrr) for every problem, then the
+// publication of publish_kernel: src[0 .. n) to pinned host memory, a system
+// fence, the device counter and its new value to *host_seq.  One block: a
+// group of tp lanes (a power of two, at most a wavefront) per problem, each
+// lane summing every tp-th partial, then the group's lanes in xor order.
+__global__ __launch_bounds__(VT) void publish_red_kernel(const double* __restrict__ rrpart, int nrr, int nbatch,
+                                                         double* rr, const double* src, int n, double* host_dst,
+                                                         unsigned* __restrict__ dev_count,
+                                                         volatile unsigned* host_seq) {
+  int tp = 64;
+  while (tp > 1 && tp * nbatch > VT) tp >>= 1;
+  const int groups = VT / tp, g = threadIdx.x / tp, l = threadIdx.x % tp;
+  for (int pb0 = 0; pb0 < nbatch; pb0 += groups) {
+    const int pb = pb0 + g;
+    double s = 0.0;
+    if (pb < nbatch)
+      for (int i = l; i < nrr; i += tp) s += rrpart[(int64_t)pb * nrr + i];
+    for (int off = tp / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (pb < nbatch && l == 0) rr[pb] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < n; ++i) host_dst[i] = src[i];
+  const unsigned v = *dev_count + 1u;
+  *dev_count = v;
+  __threadfence_system();
+  *host_seq = v;
+}
+int publish_red(const double* rrpart, int nrr, int nbatch, double* rr, const double* src, int n, double* host_dst,
+                unsigned* dev_count, unsigned* host_seq, hipStream_t s) {
+  hipLaunchKernelGGL(publish_red_kernel, dim3(1), dim3(VT), 0, s, rrpart, nrr, nbatch, rr, src, n, host_dst,
+                     dev_count, host_seq);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
