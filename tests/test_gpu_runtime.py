@@ -88,6 +88,36 @@ def test_autotune_picks_valid_shapes_and_keeps_results(sdg, torch):
         sdg.sdg_destroy(ctx)
 
 
+def test_cg_with_tile_kernel_apply_matches_wavefront(sdg, torch):
+    """The CG takes p.q from the wavefront operator kernel's per-tile partial
+    sums, or, when the apply runs on a tile-kernel shape, from a separate
+    first reduction stage; in both cases the update kernels finish the sums.
+    A batch of two problems solved each way converges to the same solution."""
+    ctx = sdg.sdg_create(0, 0)
+    try:
+        n, k = 24, 4
+        P0 = gen.single_inclusion(n, k, eta_in=1e3)
+        P1 = gen.random_problem(n, k, 7, contrast=1e2)
+        etas = np.stack([P0.eta, P1.eta])
+        f = torch.as_tensor(np.concatenate([P0.f.reshape(-1), P1.f.reshape(-1)]), device="cuda")
+        print(f"[case] cg apply forms n={n} k={k} batch 2", flush=True)
+        wave = sdg.Problem(ctx, n, n, k, etas, rtol=1e-10)
+        tile = sdg.Problem(ctx, n, n, k, etas, rtol=1e-10)
+        assert sdg.sdg_get_tile(wave.h, sdg.TILE_APPLY, sdg.FP64) == 0
+        sdg.sdg_set_tile(tile.h, sdg.TILE_APPLY, sdg.FP64, 1)
+        uw, stw = wave.solve_viscous(f)
+        ut, stt = tile.solve_viscous(f)
+        for a, b in zip(stw, stt):
+            assert a["status"] == 0 and b["status"] == 0, (a, b)
+            # the two forms differ only in rounding order (CG iterations)
+            assert abs(a["outer_its"] - b["outer_its"]) <= 2, (a, b)
+        assert float((ut - uw).norm() / uw.norm()) <= 1e-8
+        tile.close()
+        wave.close()
+    finally:
+        sdg.sdg_destroy(ctx)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_graph_replay_matches_eager(sdg, torch, prec):
     """CG iterations replayed from captured HIP graphs give bit-identical
