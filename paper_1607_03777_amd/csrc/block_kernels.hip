@@ -202,12 +202,18 @@ __device__ __forceinline__ int perm16(int i) { return 8 * (i >> 3) + 2 * (i & 3)
 // any other wavefront reads them from L1/L2.  Blocks above 72 x 72 (k = 6)
 // stay in L1/L2, and so do the 50 x 50 blocks of k = 4, where the staging
 // barrier measured slower than the fragment loads it saves (k = 2, 3, 5 run
-// 4-14% faster staged).  The update operands are fetched first.
+// 4-14% faster staged).  The update operands are fetched first.  For k >= 5
+// the product is software-pipelined: the fragments of the next k-step are
+// requested before the products of the current one.
 // ---------------------------------------------------------------------------
 template <int K1>
 __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
   constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
   constexpr bool STAGE = NB <= 72 && K1 != 5;
+  // software-pipelined product for the large blocks (k >= 5: 31.0 vs 39.7 us
+  // at k = 5, 48.6 vs 55.3 us at k = 6, 64 x 64 x 16); below, its extra
+  // registers cost a wavefront per SIMD and the plain loop is faster
+  constexpr bool PIPE = K1 >= 6;
   constexpr int LDB = NB + 2;
   __shared__ double sB[STAGE ? NB * LDB : 2];
   const int lane = threadIdx.x & 63;
@@ -247,25 +253,63 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
   v4d acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  if constexpr (!PIPE) {
 #pragma unroll
-  for (int g = 0; g < NT; ++g)
+    for (int g = 0; g < NT; ++g)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (16 * g + 8 * h >= NB) continue;
-      const int k0 = 16 * g + 8 * h + 2 * q;
-      const v2d rb = (ge >= 0 && k0 < NB) ? *reinterpret_cast<const v2d*>(A.r + ge * NB + k0) : v2d{0.0, 0.0};
+      for (int h = 0; h < 2; ++h) {
+        if (16 * g + 8 * h >= NB) continue;
+        const int k0 = 16 * g + 8 * h + 2 * q;
+        const v2d rb = (ge >= 0 && k0 < NB) ? *reinterpret_cast<const v2d*>(A.r + ge * NB + k0) : v2d{0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int arow = 16 * t + prow;
+          // A[i][k] = Binv[arow][k] (the block is symmetric either way)
+          v2d a = v2d{0.0, 0.0};
+          if (arow < NB && k0 < NB)
+            a = from_lds ? *reinterpret_cast<const v2d*>(sB + arow * LDB + k0)
+                         : *reinterpret_cast<const v2d*>(B + arow * NB + k0);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, rb.x, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, rb.y, acc[t], 0, 0, 0);
+        }
+      }
+  } else {
+    // Every load of the product is unconditional (an address clamped into the
+    // block or the vector, the value zeroed by a select where it lies outside),
+    // and the loads of k-step s + 1 are issued before the products of k-step
+    // s, so a wavefront waits for one L2 round trip at a time while the matrix
+    // cores work, not for one per k-step after they finish.  Idle lanes read
+    // element 0.  k-step s contracts rows 8 s + 2 q, + 1 (s = 2 g + h).
+    const int64_t gsafe = ge >= 0 ? ge : 0;
+    constexpr int NS = (NB + 7) / 8;
+    auto load_step = [&](int st, v2d& rb, v2d (&a)[NT]) {
+      const int k0 = 8 * st + 2 * q;
+      const bool kin = k0 < NB;  // k0 is even and NB even: the pair is inside
+      rb = *reinterpret_cast<const v2d*>(A.r + gsafe * NB + (kin ? k0 : 0));
+      if (!(ge >= 0 && kin)) rb = v2d{0.0, 0.0};
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int arow = 16 * t + prow;
+        const bool ok = arow < NB && kin;
         // A[i][k] = Binv[arow][k] (the block is symmetric either way)
-        v2d a = v2d{0.0, 0.0};
-        if (arow < NB && k0 < NB)
-          a = from_lds ? *reinterpret_cast<const v2d*>(sB + arow * LDB + k0)
-                       : *reinterpret_cast<const v2d*>(B + arow * NB + k0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, rb.x, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, rb.y, acc[t], 0, 0, 0);
+        a[t] = from_lds ? *reinterpret_cast<const v2d*>(sB + (ok ? arow * LDB + k0 : 0))
+                        : *reinterpret_cast<const v2d*>(B + (ok ? arow * NB + k0 : 0));
+        if (!ok) a[t] = v2d{0.0, 0.0};
+      }
+    };
+    v2d rbuf[2], abuf[2][NT];
+    load_step(0, rbuf[0], abuf[0]);
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int cu = st & 1;
+      if (st + 1 < NS) load_step(st + 1, rbuf[cu ^ 1], abuf[cu ^ 1]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[cu][t].x, rbuf[cu].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[cu][t].y, rbuf[cu].y, acc[t], 0, 0, 0);
       }
     }
+  }
   if (ge < 0) return;
   const double sc = A.scale[ge];
   double* xx = A.x + ge * NB;
