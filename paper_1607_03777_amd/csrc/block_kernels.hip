@@ -392,45 +392,59 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
                                                           : v2f{0.f, 0.f};
       dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2f*>(A.d + ge * NB + i) : v2f{0.f, 0.f};
     }
-  // y = X r
-  v4f y[NT];
+  // y = X r, then z = X^T y; the k-step (g, h, s) of z = X^T y takes
+  // component 2h + s of y[g].  Both products run as one sequence of 2 NS
+  // k-steps whose loads are unconditional (clamped addresses, zeroed by
+  // select) and issued one k-step ahead of the products, so the factor
+  // fragments of the next k-step (and X^T's first ones, during the last
+  // steps of y = X r) are in flight while the matrix cores work.
+  constexpr int NS = (NB + 7) / 8;
+  const int64_t gsafe = ge >= 0 ? ge : 0;
+  auto load_step = [&](int u, v2f& rb, v2f (&a)[NT]) {
+    const bool second = u >= NS;
+    const int st = second ? u - NS : u, g = st >> 1, k0 = 8 * st + 2 * q;
+    const bool kin = k0 < NB;  // k0 is even and NB even: the pair is inside
+    if (!second) {
+      rb = *reinterpret_cast<const v2f*>(A.r + gsafe * NB + (kin ? k0 : 0));
+      if (!(ge >= 0 && kin)) rb = v2f{0.f, 0.f};
+    }
+    const TM* M = second ? XT : X;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) y[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t) {
+      if (second ? g < t : g > t) continue;  // X is zero above, X^T below the diagonal
+      const int arow = 16 * t + prow;
+      const bool ok = arow < NB && kin;
+      a[t] = ld_pair(M + (ok ? arow * NB + k0 : 0));
+      if (!ok) a[t] = v2f{0.f, 0.f};
+    }
+  };
+  v4f y[NT], z[NT];
 #pragma unroll
-  for (int g = 0; g < NT; ++g)
+  for (int t = 0; t < NT; ++t) y[t] = z[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  v2f rbuf[2], abuf[2][NT];
+  load_step(0, rbuf[0], abuf[0]);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (16 * g + 8 * h >= NB) continue;
-      const int k0 = 16 * g + 8 * h + 2 * q;
-      const v2f rb = (ge >= 0 && k0 < NB) ? *reinterpret_cast<const v2f*>(A.r + ge * NB + k0) : v2f{0.f, 0.f};
+  for (int u = 0; u < 2 * NS; ++u) {
+    const int cu = u & 1;
+    if (u + 1 < 2 * NS) load_step(u + 1, rbuf[cu ^ 1], abuf[cu ^ 1]);
+    if (u < NS) {
+      const int g = u >> 1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        if (g > t) continue;  // X is zero above the diagonal
-        const int arow = 16 * t + prow;
-        const v2f a = (arow < NB && k0 < NB) ? ld_pair(X + arow * NB + k0) : v2f{0.f, 0.f};
-        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, rb.x, y[t], 0, 0, 0);
-        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, rb.y, y[t], 0, 0, 0);
+        if (g > t) continue;
+        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(abuf[cu][t].x, rbuf[cu].x, y[t], 0, 0, 0);
+        y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(abuf[cu][t].y, rbuf[cu].y, y[t], 0, 0, 0);
       }
-    }
-  // z = X^T y; the k-step (g, h, s) takes component 2h + s of y[g]
-  v4f z[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int g = 0; g < NT; ++g)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (16 * g + 8 * h >= NB) continue;
-      const int k0 = 16 * g + 8 * h + 2 * q;
+    } else {
+      const int st = u - NS, g = st >> 1, h = st & 1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        if (g < t) continue;  // X^T is zero below the diagonal
-        const int arow = 16 * t + prow;
-        const v2f a = (arow < NB && k0 < NB) ? ld_pair(XT + arow * NB + k0) : v2f{0.f, 0.f};
-        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, y[g][2 * h], z[t], 0, 0, 0);
-        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, y[g][2 * h + 1], z[t], 0, 0, 0);
+        if (g < t) continue;
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(abuf[cu][t].x, y[g][2 * h], z[t], 0, 0, 0);
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(abuf[cu][t].y, y[g][2 * h + 1], z[t], 0, 0, 0);
       }
     }
+  }
   if (ge < 0) return;
   const double sc = A.scale[ge];
   float* xx = A.x + ge * NB;
