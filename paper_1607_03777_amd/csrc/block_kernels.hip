@@ -224,18 +224,22 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
   const int c = lane & 15, q = lane >> 4;
   const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
   const int flags = A.flags;
-  // operands of the update (rows 16t + 8h + 2q, +1), requested first
+  // operands of the update (rows 16t + 8h + 2q, +1): requested first, or,
+  // with the pipelined product, right after its first k-step's loads
   v2d xo[NT][2], dold[NT][2];
+  auto load_ops = [&]() {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = 16 * t + 8 * h + 2 * q;
-      const bool ok = ge >= 0 && i < NB;
-      xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2d*>(A.x + ge * NB + i)
-                                                          : v2d{0.0, 0.0};
-      dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2d*>(A.d + ge * NB + i) : v2d{0.0, 0.0};
-    }
+      for (int h = 0; h < 2; ++h) {
+        const int i = 16 * t + 8 * h + 2 * q;
+        const bool ok = ge >= 0 && i < NB;
+        xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2d*>(A.x + ge * NB + i)
+                                                            : v2d{0.0, 0.0};
+        dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2d*>(A.d + ge * NB + i) : v2d{0.0, 0.0};
+      }
+  };
+  if constexpr (!PIPE) load_ops();
   // blockIdx.x * 4 < nwork: the grid has ceil(nwork / 4) workgroups
   const int uid0 = A.work[3 * (blockIdx.x * 4)];
   if constexpr (STAGE) {
@@ -299,6 +303,7 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
     };
     v2d rbuf[2], abuf[2][NT];
     load_step(0, rbuf[0], abuf[0]);
+    load_ops();
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
       const int cu = st & 1;
