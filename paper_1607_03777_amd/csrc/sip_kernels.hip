@@ -736,7 +736,7 @@ __device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int 
 // dotp (apply only, may be null): receives u.y over the tile, one partial per
 // (problem, tile) at dotp[pb * tiles + tile], summed in a fixed order.
 template <int K1, int MODE, typename T>
-__global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
+__global__ __launch_bounds__(64, (K1 <= 5 ? 4 : 1)) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
                                                       const T* __restrict__ bvec, T* __restrict__ y,
                                                       const double* __restrict__ eta_all, int64_t vec_stride,
                                                       double* __restrict__ dotp) {
@@ -775,15 +775,26 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   const bool valid = act && ix < nx && iy < ny;
   const int64_t ge = (int64_t)iy * nx + ix;
 
+  // Every global load below is unconditional: lanes outside the mesh (and
+  // lanes without a neighbour to read) load from an element of the mesh and
+  // discard the value by a select.  Loads under branches made the compiler
+  // wait for earlier loads between the branches, several HBM round trips per
+  // wavefront instead of one.
+  const int64_t gs = valid ? ge : 0;
   // viscosity of the element and of its neighbours (the element's own where
   // the mesh ends: boundary faces read only the present side)
-  T et = T(0), eL = T(0), eR = T(0), eB = T(0), eT = T(0);
-  if (valid) {
-    et = T(eta[ge]);
-    eL = ix > 0 ? T(eta[ge - 1]) : et;
-    eR = ix + 1 < nx ? T(eta[ge + 1]) : et;
-    eB = iy > 0 ? T(eta[ge - nx]) : et;
-    eT = iy + 1 < ny ? T(eta[ge + nx]) : et;
+  T et, eL, eR, eB, eT;
+  {
+    const double v0 = eta[gs];
+    const double vl = eta[valid && ix > 0 ? gs - 1 : gs];
+    const double vr = eta[valid && ix + 1 < nx ? gs + 1 : gs];
+    const double vb = eta[valid && iy > 0 ? gs - nx : gs];
+    const double vt = eta[valid && iy + 1 < ny ? gs + nx : gs];
+    et = valid ? T(v0) : T(0);
+    eL = valid ? T(vl) : T(0);
+    eR = valid ? T(vr) : T(0);
+    eB = valid ? T(vb) : T(0);
+    eT = valid ? T(vt) : T(0);
   }
   T up[NH], dn[NH];
 #pragma unroll
@@ -817,13 +828,22 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
   // elements wide and tall, so a lane needs at most one of each)
   const int64_t gx = (tx == 0 && ix > 0) ? ge - 1 : (tx == TX - 1 && ix + 1 < nx) ? ge + 1 : -1;
   const int64_t gy = (ty == 0 && iy > 0) ? ge - nx : (ty == TY - 1 && iy + 1 < ny) ? ge + nx : -1;
+  const bool hx = valid && gx >= 0, hy = valid && gy >= 0;
+  const int64_t gxs = hx ? gx : gs, gys = hy ? gy : gs;
   T hxr[2][K1], hyc[2][K1];
 #pragma unroll
   for (int d = 0; d < 2; ++d)
 #pragma unroll
     for (int i = 0; i < K1; ++i) {
-      hxr[d][i] = (valid && gx >= 0) ? u[gx * NB + d * KK + j * K1 + i] : T(0);
-      hyc[d][i] = (valid && gy >= 0) ? u[gy * NB + d * KK + i * K1 + j] : T(0);
+      hxr[d][i] = u[gxs * NB + d * KK + j * K1 + i];
+      hyc[d][i] = u[gys * NB + d * KK + i * K1 + j];
+    }
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      if (!hx) hxr[d][i] = T(0);
+      if (!hy) hyc[d][i] = T(0);
     }
 
   // ---- rows: stage the element, x-face traces, S_x
@@ -835,7 +855,10 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
     for (int d = 0; d < 2; ++d) {
       T r[K1];
 #pragma unroll
-      for (int i = 0; i < K1; ++i) r[i] = valid ? u[ge * NB + d * KK + j * K1 + i] : T(0);
+      for (int i = 0; i < K1; ++i) r[i] = u[gs * NB + d * KK + j * K1 + i];
+#pragma unroll
+      for (int i = 0; i < K1; ++i)
+        if (!valid) r[i] = T(0);
 #pragma unroll
       for (int i = 0; i < K1; ++i) SU(el, d, j, i) = r[i];
       T tl, gl, tr, gr;
@@ -904,7 +927,8 @@ __global__ __launch_bounds__(64) void sip_wave_kernel(MeshDev M, const T* __rest
 #pragma unroll
       for (int i = 0; i < K1; ++i) {
         const bool need = MODE == M_RESID || (j < 2 && i < 2);
-        bres[d][i] = (valid && need) ? bvec[ge * NB + d * KK + j * K1 + i] : T(0);
+        bres[d][i] = (MODE == M_RESID || i < 2) ? bvec[gs * NB + d * KK + j * K1 + i] : T(0);
+        if (!(valid && need)) bres[d][i] = T(0);
       }
   }
 
