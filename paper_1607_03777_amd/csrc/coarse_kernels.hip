@@ -40,14 +40,23 @@ __global__ void p_restrict_kernel(int nx, int ny, int k1, double hx, double hy, 
   const int node = (int)(gn - pb * nn);
   const int jx = node % (nx + 1), jy = node / (nx + 1);
   const int KK = k1 * k1, NB = 2 * KK;
+  // unconditional loads (an absent element's index clamped to element 0,
+  // its terms dropped by select)
   double s = 0.0;
+#pragma unroll
   for (int b = 0; b < 2; ++b)
+#pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int ex = jx - a, ey = jy - b;  // element whose vertex (a, b) is this node
-      if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
-      const TV* re = r + ((pb * ny + ey) * (int64_t)nx + ex) * NB + c * KK;
+      const bool in = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
+      const TV* re = r + ((pb * ny + (in ? ey : 0)) * (int64_t)nx + (in ? ex : 0)) * NB + c * KK;
+#pragma unroll
       for (int j = 0; j < 2; ++j)
-        for (int i = 0; i < 2; ++i) s += pcd_coef(i, j, a, b, hx, hy) * double(re[j * k1 + i]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const double t = pcd_coef(i, j, a, b, hx, hy) * double(re[j * k1 + i]);
+          s += in ? t : 0.0;
+        }
     }
   rc[g] = s;
 }
@@ -214,18 +223,22 @@ __global__ void stencil_kernel(int nx, int ny, int nbatch, const double* __restr
   const int node = (int)(g - pb * nn);
   const int jx = node % (nx + 1), jy = node / (nx + 1);
   const int64_t NN = (int64_t)nbatch * nn;
+  // unconditional loads (a neighbour index clamped into the grid, the term
+  // dropped by select): loads under branches were waited for one by one
   double y0 = 0.0, y1 = 0.0;
 #pragma unroll
   for (int sy = -1; sy <= 1; ++sy)
 #pragma unroll
     for (int sx = -1; sx <= 1; ++sx) {
       const int gx = jx + sx, gy = jy + sy;
-      if (gx < 0 || gx > nx || gy < 0 || gy > ny) continue;
+      const bool in = gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
       const int sidx = (sy + 1) * 3 + (sx + 1);
-      const int64_t nb = pb * nn + (int64_t)gy * (nx + 1) + gx;
+      const int64_t nb = pb * nn + (in ? (int64_t)gy * (nx + 1) + gx : node);
       const double x0 = x[nb * 2], x1 = x[nb * 2 + 1];
-      y0 += st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
-      y1 += st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+      const double t0 = st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
+      const double t1 = st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+      y0 += in ? t0 : 0.0;
+      y1 += in ? t1 : 0.0;
     }
   if (RESID) {
     y[g * 2] = b[g * 2] - y0;
@@ -278,12 +291,17 @@ __global__ void h_restrict_kernel(int ncx, int ncy, int nbatch, const double* __
   const int64_t pb = gn / nnc;
   const int cn = (int)(gn - pb * nnc);
   const int cx = cn % (ncx + 1), cy = cn / (ncx + 1);
+  // unconditional loads (index clamped into the grid, term dropped by select)
   double s = 0.0;
+#pragma unroll
   for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
     for (int ox = -1; ox <= 1; ++ox) {
       const int fx = 2 * cx + ox, fy = 2 * cy + oy;
-      if (fx < 0 || fx > nfx || fy < 0 || fy > nfy) continue;
-      s += w1(ox) * w1(oy) * rf[(pb * nnf + (int64_t)fy * (nfx + 1) + fx) * 2 + c];
+      const bool in = fx >= 0 && fx <= nfx && fy >= 0 && fy <= nfy;
+      const int64_t fi = in ? (int64_t)fy * (nfx + 1) + fx : (int64_t)(2 * cy) * (nfx + 1) + 2 * cx;
+      const double t = w1(ox) * w1(oy) * rf[(pb * nnf + fi) * 2 + c];
+      s += in ? t : 0.0;
     }
   rc[g] = s;
 }
@@ -300,10 +318,19 @@ __global__ void h_prolong_kernel(int ncx, int ncy, int nbatch, const double* __r
   const int fn = (int)(gn - pb * nnf);
   const int fx = fn % (nfx + 1), fy = fn / (nfx + 1);
   const double wx = (fx & 1) ? 0.5 : 1.0, wy = (fy & 1) ? 0.5 : 1.0;
+  // parents (fx >> 1 .. (fx + 1) >> 1) x (fy >> 1 .. (fy + 1) >> 1), one or
+  // two per direction: four unconditional loads, the repeated parent of an
+  // even index dropped by select
+  const int px0 = fx >> 1, px1 = (fx + 1) >> 1, py0 = fy >> 1, py1 = (fy + 1) >> 1;
+  const double* e = ec + pb * nnc * 2 + c;
+  const double e00 = e[((int64_t)py0 * (ncx + 1) + px0) * 2], e01 = e[((int64_t)py0 * (ncx + 1) + px1) * 2];
+  const double e10 = e[((int64_t)py1 * (ncx + 1) + px0) * 2], e11 = e[((int64_t)py1 * (ncx + 1) + px1) * 2];
+  const bool two_x = px1 != px0, two_y = py1 != py0;
   double s = 0.0;
-  for (int py = fy >> 1; py <= (fy + 1) >> 1; ++py)
-    for (int px = fx >> 1; px <= (fx + 1) >> 1; ++px)
-      s += wx * wy * ec[(pb * nnc + (int64_t)py * (ncx + 1) + px) * 2 + c];
+  s += wx * wy * e00;
+  s += two_x ? wx * wy * e01 : 0.0;
+  s += two_y ? wx * wy * e10 : 0.0;
+  s += (two_x && two_y) ? wx * wy * e11 : 0.0;
   xf[g] += s;
 }
 int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s) {
@@ -400,17 +427,20 @@ __global__ void hcheb_kernel(int nx, int ny, int nbatch, const double* __restric
   const int64_t NN = (int64_t)nbatch * nn;
   double r0 = rhs[g * 2], r1 = rhs[g * 2 + 1];
   if (mode != 1) {
+    // unconditional loads, as in stencil_kernel
 #pragma unroll
     for (int sy = -1; sy <= 1; ++sy)
 #pragma unroll
       for (int sx = -1; sx <= 1; ++sx) {
         const int gx = jx + sx, gy = jy + sy;
-        if (gx < 0 || gx > nx || gy < 0 || gy > ny) continue;
+        const bool in = gx >= 0 && gx <= nx && gy >= 0 && gy <= ny;
         const int sidx = (sy + 1) * 3 + (sx + 1);
-        const int64_t nb = pb * nn + (int64_t)gy * (nx + 1) + gx;
+        const int64_t nb = pb * nn + (in ? (int64_t)gy * (nx + 1) + gx : node);
         const double x0 = xi[nb * 2], x1 = xi[nb * 2 + 1];
-        r0 -= st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
-        r1 -= st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+        const double t0 = st[(sidx * 4 + 0) * NN + g] * x0 + st[(sidx * 4 + 1) * NN + g] * x1;
+        const double t1 = st[(sidx * 4 + 2) * NN + g] * x0 + st[(sidx * 4 + 3) * NN + g] * x1;
+        r0 -= in ? t0 : 0.0;
+        r1 -= in ? t1 : 0.0;
       }
   }
   const double ca = ab[2 * pb], cb = ab[2 * pb + 1];
