@@ -202,18 +202,22 @@ __device__ __forceinline__ int perm16(int i) { return 8 * (i >> 3) + 2 * (i & 3)
 // any other wavefront reads them from L1/L2.  Blocks above 72 x 72 (k = 6)
 // stay in L1/L2, and so do the 50 x 50 blocks of k = 4, where the staging
 // barrier measured slower than the fragment loads it saves (k = 2, 3, 5 run
-// 4-14% faster staged).  The update operands are fetched first.  For k >= 5
+// 4-14% faster staged).  The update operands are fetched first.  For k >= 4
 // the product is software-pipelined: the fragments of the next k-step are
 // requested before the products of the current one.
 // ---------------------------------------------------------------------------
 template <int K1>
-__global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
+__global__ __launch_bounds__(256, (K1 == 5 ? 4 : 1)) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
   constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
   constexpr bool STAGE = NB <= 72 && K1 != 5;
-  // software-pipelined product for the large blocks (k >= 5: 31.0 vs 39.7 us
-  // at k = 5, 48.6 vs 55.3 us at k = 6, 64 x 64 x 16); below, its extra
-  // registers cost a wavefront per SIMD and the plain loop is faster
-  constexpr bool PIPE = K1 >= 6;
+  // software-pipelined product from k = 4 on (plain apply at 64 x 64 x 16:
+  // k = 4 19.3 -> 17.5 us, k = 5 39.7 -> 30.8 us, k = 6 55.3 -> 48.9 us);
+  // below, the plain loop is as fast.  At k = 4 the update operands are
+  // requested after the product and the launch bounds ask for four
+  // wavefronts per SIMD: held through the product, the operands and the
+  // double buffers cost one wavefront (21.7 us)
+  constexpr bool PIPE = K1 >= 5;
+  constexpr bool LATE_OPS = K1 == 5;
   constexpr int LDB = NB + 2;
   __shared__ double sB[STAGE ? NB * LDB : 2];
   const int lane = threadIdx.x & 63;
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
     };
     v2d rbuf[2], abuf[2][NT];
     load_step(0, rbuf[0], abuf[0]);
-    load_ops();
+    if constexpr (!LATE_OPS) load_ops();
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
       const int cu = st & 1;
@@ -314,6 +318,7 @@ __global__ __launch_bounds__(256) void bj_wave_kernel(BjArgs<double, double> A, 
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[cu][t].y, rbuf[cu].y, acc[t], 0, 0, 0);
       }
     }
+    if constexpr (LATE_OPS) load_ops();
   }
   if (ge < 0) return;
   const double sc = A.scale[ge];
