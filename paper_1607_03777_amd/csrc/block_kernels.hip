@@ -207,17 +207,17 @@ __device__ __forceinline__ int perm16(int i) { return 8 * (i >> 3) + 2 * (i & 3)
 // requested before the products of the current one.
 // ---------------------------------------------------------------------------
 template <int K1>
-__global__ __launch_bounds__(256, (K1 == 5 ? 4 : 1)) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
+__global__ __launch_bounds__(256, (K1 == 5 ? 4 : K1 == 6 ? 3 : K1 == 7 ? 2 : 1)) void bj_wave_kernel(BjArgs<double, double> A, int nwork) {
   constexpr int NB = 2 * K1 * K1, NT = (NB + 15) / 16;
   constexpr bool STAGE = NB <= 72 && K1 != 5;
   // software-pipelined product from k = 4 on (plain apply at 64 x 64 x 16:
-  // k = 4 19.3 -> 17.5 us, k = 5 39.7 -> 30.8 us, k = 6 55.3 -> 48.9 us);
-  // below, the plain loop is as fast.  At k = 4 the update operands are
-  // requested after the product and the launch bounds ask for four
-  // wavefronts per SIMD: held through the product, the operands and the
-  // double buffers cost one wavefront (21.7 us)
+  // k = 4 19.3 -> 17.5 us, k = 5 39.7 -> 30.8 us, k = 6 55.3 -> 44.6 us);
+  // below, the plain loop is as fast.  The update operands are requested
+  // after the product and the launch bounds ask for one wavefront per SIMD
+  // more than the product would leave: held through it, the operands and
+  // the double buffers cost one (k = 4: 21.7 us)
   constexpr bool PIPE = K1 >= 5;
-  constexpr bool LATE_OPS = K1 == 5;
+  constexpr bool LATE_OPS = K1 >= 5;
   constexpr int LDB = NB + 2;
   __shared__ double sB[STAGE ? NB * LDB : 2];
   const int lane = threadIdx.x & 63;
