@@ -390,18 +390,6 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
   const TM* XT = X + NB * NB;
   const int prow = permf(c);
   const int flags = A.flags;
-  // operands of the update (rows 16t + 8h + 2q, +1), requested first
-  v2f xo[NT][2], dold[NT][2];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = 16 * t + 8 * h + 2 * q;
-      const bool ok = ge >= 0 && i < NB;
-      xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2f*>(A.x + ge * NB + i)
-                                                          : v2f{0.f, 0.f};
-      dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2f*>(A.d + ge * NB + i) : v2f{0.f, 0.f};
-    }
   // y = X r, then z = X^T y; the k-step (g, h, s) of z = X^T y takes
   // component 2h + s of y[g].  Both products run as one sequence of 2 NS
   // k-steps whose loads are unconditional (clamped addresses, zeroed by
@@ -455,6 +443,19 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
       }
     }
   }
+  // operands of the update (rows 16t + 8h + 2q, +1), requested after the
+  // products so that they stay out of their register peak
+  v2f xo[NT][2], dold[NT][2];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = 16 * t + 8 * h + 2 * q;
+      const bool ok = ge >= 0 && i < NB;
+      xo[t][h] = (ok && (flags & (BJ_READ_X | BJ_FOLD))) ? *reinterpret_cast<const v2f*>(A.x + ge * NB + i)
+                                                          : v2f{0.f, 0.f};
+      dold[t][h] = (ok && (flags & BJ_READ_D)) ? *reinterpret_cast<const v2f*>(A.d + ge * NB + i) : v2f{0.f, 0.f};
+    }
   if (ge < 0) return;
   const double sc = A.scale[ge];
   float* xx = A.x + ge * NB;
