@@ -735,6 +735,8 @@ __device__ __forceinline__ void face_mode_w(const T* __restrict__ f, int m, int 
 
 // dotp (apply only, may be null): receives u.y over the tile, one partial per
 // (problem, tile) at dotp[pb * tiles + tile], summed in a fixed order.
+// Up to k = 4 the launch bounds ask for four wavefronts per SIMD (the
+// unconditional loads would otherwise take the residual to 132 VGPRs).
 template <int K1, int MODE, typename T>
 __global__ __launch_bounds__(64, (K1 <= 5 ? 4 : 1)) void sip_wave_kernel(MeshDev M, const T* __restrict__ u,
                                                       const T* __restrict__ bvec, T* __restrict__ y,
