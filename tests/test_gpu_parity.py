@@ -256,7 +256,9 @@ def test_eig_estimates_parity(sdg, ctx, torch):
     P.close()
 
 
-@pytest.mark.parametrize("k", [2, 4])
+# k = 4, 5, 6 cover the pipelined FP64 smoother's Chebyshev steps (the
+# update operands read after the product)
+@pytest.mark.parametrize("k", [2, 4, 5, 6])
 def test_vcycle_parity(sdg, ctx, torch, k):
     nx = ny = 16
     P0 = gen.single_inclusion(nx, k, eta_in=1e4)
