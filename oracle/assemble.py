@@ -37,6 +37,13 @@ and B_h gets q (u.n) on Dirichlet faces as on Navier faces.
 Basis: psi_ij(x, y) = (2/sqrt(h_x h_y)) lhat_i(xi) lhat_j(eta) with
 lhat_i = sqrt((2i+1)/2) L_i, hence L2(K)-orthonormal (Section 5 states the
 Legendre basis is pairwise orthogonal and the pressure basis orthonormal).
+
+Precision: every assembly routine takes `dtype` (float64 by default).  With
+numpy.longdouble the quadrature points, basis values, element sizes and all
+products are carried in the 64-bit-mantissa type, which gives the matrices
+to about 1e-19 relative: the reference against which residuals below the
+FP64 rounding floor are measured (the extended-precision residual of
+Section 8.3.1).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -50,36 +57,44 @@ PENALTY_NF = 4.0  # n_F = number of faces of a quadrilateral, eq. (sipg_penalty)
 # ----------------------------------------------------------------------------
 # basis evaluation
 # ----------------------------------------------------------------------------
+def _h(mesh, dtype):
+    """Element sizes l/n in the working type."""
+    return (np.asarray(mesh.lx, dtype=dtype) / mesh.nx,
+            np.asarray(mesh.ly, dtype=dtype) / mesh.ny)
+
+
 def velocity_basis(k, hx, hy, xi, eta):
     """Vector basis phi_a, a = (d*(k+1) + j)*(k+1) + i, at reference points.
 
     Returns val[a, q, c] (component c of phi_a) and grad[a, q, c, r]
     (d/dx_r of component c)."""
     k1 = k + 1
-    c = 2.0 / np.sqrt(hx * hy)
+    dt = np.asarray(xi).dtype
+    c = 2 / np.sqrt(hx * hy)
     lx, dlx = onb_values(k, xi), onb_derivs(k, xi)
     ly, dly = onb_values(k, eta), onb_derivs(k, eta)
     nq = len(xi)
     nb = 2 * k1 * k1
-    val = np.zeros((nb, nq, 2))
-    grad = np.zeros((nb, nq, 2, 2))
+    val = np.zeros((nb, nq, 2), dtype=dt)
+    grad = np.zeros((nb, nq, 2, 2), dtype=dt)
     for d in range(2):
         for j in range(k1):
             for i in range(k1):
                 a = (d * k1 + j) * k1 + i
                 val[a, :, d] = c * lx[i] * ly[j]
-                grad[a, :, d, 0] = c * (2.0 / hx) * dlx[i] * ly[j]
-                grad[a, :, d, 1] = c * (2.0 / hy) * lx[i] * dly[j]
+                grad[a, :, d, 0] = c * (2 / hx) * dlx[i] * ly[j]
+                grad[a, :, d, 1] = c * (2 / hy) * lx[i] * dly[j]
     return val, grad
 
 
 def pressure_basis(k, hx, hy, xi, eta):
     """Scalar basis chi_m, m = j*k + i (0 <= i, j < k), values [m, q]."""
-    c = 2.0 / np.sqrt(hx * hy)
+    dt = np.asarray(xi).dtype
+    c = 2 / np.sqrt(hx * hy)
     if k < 1:
-        return np.zeros((0, len(xi)))
+        return np.zeros((0, len(xi)), dtype=dt)
     lx, ly = onb_values(k - 1, xi), onb_values(k - 1, eta)
-    out = np.zeros((k * k, len(xi)))
+    out = np.zeros((k * k, len(xi)), dtype=dt)
     for j in range(k):
         for i in range(k):
             out[j * k + i] = c * lx[i] * ly[j]
@@ -88,11 +103,11 @@ def pressure_basis(k, hx, hy, xi, eta):
 
 def strain(grad):
     """eps(u) = (grad u + grad u^T)/2, acting on the last two axes."""
-    return 0.5 * (grad + np.swapaxes(grad, -1, -2))
+    return (grad + np.swapaxes(grad, -1, -2)) / 2
 
 
-def _volume_points(k):
-    g, w = gauss(k + 2)
+def _volume_points(k, dtype=np.float64):
+    g, w = gauss(k + 2, dtype)
     xi, eta = np.meshgrid(g, g, indexing="xy")
     wq = np.outer(w, w)
     return xi.ravel(), eta.ravel(), wq.ravel()
@@ -100,16 +115,17 @@ def _volume_points(k):
 
 def _side_points(k, side, hx, hy):
     """Reference points, physical line weights and outward normal on one side
-    of an element."""
-    g, w = gauss(k + 2)
+    of an element (in the type of hx)."""
+    dt = np.asarray(hx).dtype
+    g, w = gauss(k + 2, dt)
     one = np.ones_like(g)
     if side == LEFT:
-        return -one, g, w * hy / 2, np.array([-1.0, 0.0])
+        return -one, g, w * hy / 2, np.array([-1, 0], dtype=dt)
     if side == RIGHT:
-        return one, g, w * hy / 2, np.array([1.0, 0.0])
+        return one, g, w * hy / 2, np.array([1, 0], dtype=dt)
     if side == BOTTOM:
-        return g, -one, w * hx / 2, np.array([0.0, -1.0])
-    return g, one, w * hx / 2, np.array([0.0, 1.0])
+        return g, -one, w * hx / 2, np.array([0, -1], dtype=dt)
+    return g, one, w * hx / 2, np.array([0, 1], dtype=dt)
 
 
 def trace_constant(k, side, hx, hy):
@@ -122,11 +138,11 @@ def trace_constant(k, side, hx, hy):
 # reference (unit-coefficient) local matrices.  M[a, b] = form(u=phi_b, v=phi_a)
 # ----------------------------------------------------------------------------
 def volume_matrix(k, hx, hy):
-    xi, eta, w = _volume_points(k)
-    w = w * hx * hy / 4.0
+    xi, eta, w = _volume_points(k, np.asarray(hx).dtype)
+    w = w * hx * hy / 4
     _, grad = velocity_basis(k, hx, hy, xi, eta)
     eps = strain(grad)
-    return 2.0 * np.einsum("aqcr,bqcr,q->ab", eps, eps, w)
+    return 2 * np.einsum("aqcr,bqcr,q->ab", eps, eps, w)
 
 
 def interior_face_unit_blocks(k, hx, hy, direction):
@@ -170,7 +186,7 @@ def boundary_unit_blocks(k, hx, hy, side, kind):
     """Unit blocks (coefficient eta_K, eta_K, sigma_F) of one boundary side."""
     xi, eta, w, n = _side_points(k, side, hx, hy)
     val, grad = velocity_basis(k, hx, hy, xi, eta)
-    eps2 = 2.0 * strain(grad)  # 2 eps(phi)
+    eps2 = 2 * strain(grad)  # 2 eps(phi)
     if kind == NAVIER:
         nsn = np.einsum("c,aqcr,r->aq", n, eps2, n)  # n . 2 eps(phi) n
         vn = np.einsum("aqc,c->aq", val, n)  # phi . n
@@ -184,41 +200,43 @@ def boundary_unit_blocks(k, hx, hy, side, kind):
         B3 = np.einsum("bqc,aqc,q->ab", val, val, w)
     else:
         nb = val.shape[0]
-        B1 = B2 = B3 = np.zeros((nb, nb))
+        B1 = B2 = B3 = np.zeros((nb, nb), dtype=val.dtype)
     return B1, B2, B3
 
 
 # ----------------------------------------------------------------------------
 # face coefficients
 # ----------------------------------------------------------------------------
-def face_data(mesh: Mesh, eta, penalty_nf=PENALTY_NF, eta_override=None):
+def face_data(mesh: Mesh, eta, penalty_nf=PENALTY_NF, eta_override=None, dtype=np.float64):
     """Interior faces as arrays (minus, plus, eta_F, sigma_F) per direction and
     boundary faces as (side, element, eta_F, sigma_F).
 
     eta_override (optional scalar) replaces eta_F in the penalty by a global
     value (used only to contrast local and global penalties)."""
     k = mesh.k
+    hx, hy = _h(mesh, dtype)
+    eta = np.asarray(eta, dtype=dtype)
     out = {}
     faces = mesh.interior_faces()
     for direction in (0, 1):
         f = [(m, p) for m, p, dr in faces if dr == direction]
         m = np.array([a for a, _ in f], dtype=np.int64)
         p = np.array([b for _, b in f], dtype=np.int64)
-        etaf = np.maximum(eta[m], eta[p]) if len(f) else np.zeros(0)
+        etaf = np.maximum(eta[m], eta[p]) if len(f) else np.zeros(0, dtype=dtype)
         side_m = RIGHT if direction == 0 else TOP
         side_p = LEFT if direction == 0 else BOTTOM
-        cf = max(trace_constant(k, side_m, mesh.hx, mesh.hy),
-                 trace_constant(k, side_p, mesh.hx, mesh.hy))
+        cf = max(trace_constant(k, side_m, hx, hy),
+                 trace_constant(k, side_p, hx, hy))
         etap = etaf if eta_override is None else np.full_like(etaf, eta_override)
-        sigma = penalty_nf * etap * 1.0 * cf
+        sigma = penalty_nf * etap * cf
         out[direction] = (m, p, etaf, sigma)
     bnd = []
     for side, e, fi in mesh.boundary_faces():
         kind = mesh.bc[side]
         etaf = eta[e]
         etap = etaf if eta_override is None else eta_override
-        cf = trace_constant(k, side, mesh.hx, mesh.hy)
-        sigma = penalty_nf * etap * 2.0 * cf if kind != NEUMANN else 0.0
+        cf = trace_constant(k, side, hx, hy)
+        sigma = penalty_nf * etap * 2 * cf if kind != NEUMANN else 0 * cf
         bnd.append((side, e, fi, kind, etaf, sigma))
     out["boundary"] = bnd
     return out
@@ -241,14 +259,15 @@ def _bsr(blocks_rows, blocks_cols, blocks, nrow_blocks, ncol_blocks):
 
 
 def assemble_A_blocks(mesh: Mesh, eta, penalty_nf=PENALTY_NF,
-                      eta_override=None):
+                      eta_override=None, dtype=np.float64):
     """Diagonal blocks (nel, nb, nb) and off-diagonal (row, col, block) lists
     of the SIP matrix A."""
-    k, hx, hy = mesh.k, mesh.hx, mesh.hy
-    eta = np.asarray(eta, dtype=np.float64)
+    k = mesh.k
+    hx, hy = _h(mesh, dtype)
+    eta = np.asarray(eta, dtype=dtype)
     V = volume_matrix(k, hx, hy)
     diag = eta[:, None, None] * V[None]
-    fd = face_data(mesh, eta, penalty_nf, eta_override)
+    fd = face_data(mesh, eta, penalty_nf, eta_override, dtype)
     orow, ocol, oblk = [], [], []
     for direction in (0, 1):
         m, p, _, sigma = fd[direction]
@@ -286,14 +305,15 @@ def assemble_A_blocks(mesh: Mesh, eta, penalty_nf=PENALTY_NF,
     else:
         nb = mesh.nbu
         orow = ocol = np.zeros(0, dtype=np.int64)
-        oblk = np.zeros((0, nb, nb))
+        oblk = np.zeros((0, nb, nb), dtype=dtype)
     return diag, (orow, ocol, oblk)
 
 
-def assemble_A(mesh: Mesh, eta, penalty_nf=PENALTY_NF, eta_override=None):
-    """Sparse (BSR) FP64 SIP matrix A, A[a, b] = A_h(phi_b, phi_a)."""
+def assemble_A(mesh: Mesh, eta, penalty_nf=PENALTY_NF, eta_override=None,
+               dtype=np.float64):
+    """Sparse (BSR) SIP matrix A, A[a, b] = A_h(phi_b, phi_a)."""
     diag, (orow, ocol, oblk) = assemble_A_blocks(mesh, eta, penalty_nf,
-                                                 eta_override)
+                                                 eta_override, dtype)
     nel = mesh.nel
     rows = np.concatenate([np.arange(nel), orow])
     cols = np.concatenate([np.arange(nel), ocol])
@@ -301,12 +321,13 @@ def assemble_A(mesh: Mesh, eta, penalty_nf=PENALTY_NF, eta_override=None):
     return _bsr(rows, cols, blocks, nel, nel)
 
 
-def assemble_B(mesh: Mesh):
+def assemble_B(mesh: Mesh, dtype=np.float64):
     """Sparse B, B[a, m] = B_h(phi_a, chi_m) (velocity rows, pressure cols)."""
-    k, hx, hy = mesh.k, mesh.hx, mesh.hy
+    k = mesh.k
+    hx, hy = _h(mesh, dtype)
     nel = mesh.nel
-    xi, et, w = _volume_points(k)
-    w = w * hx * hy / 4.0
+    xi, et, w = _volume_points(k, dtype)
+    w = w * hx * hy / 4
     _, grad = velocity_basis(k, hx, hy, xi, et)
     chi = pressure_basis(k, hx, hy, xi, et)
     div = grad[:, :, 0, 0] + grad[:, :, 1, 1]
@@ -331,7 +352,7 @@ def assemble_B(mesh: Mesh):
         # {q}[[v.n]] with q on side s, v on side t: 1/2 q^s (v^t . n^t)
         for s in range(2):
             for t in range(2):
-                blk = 0.5 * np.einsum("aq,mq,q->am", vn[t], ch[s], wf)
+                blk = np.einsum("aq,mq,q->am", vn[t], ch[s], wf) / 2
                 rows.append(el[t])
                 cols.append(el[s])
                 blks.append(np.repeat(blk[None], len(m), axis=0))
@@ -351,28 +372,30 @@ def assemble_B(mesh: Mesh):
     # sum duplicate (row, col) blocks before building the BSR structure
     key = rows * nel + cols
     uk, inv = np.unique(key, return_inverse=True)
-    summed = np.zeros((len(uk),) + blks.shape[1:])
+    summed = np.zeros((len(uk),) + blks.shape[1:], dtype=dtype)
     np.add.at(summed, inv, blks)
     return _bsr(uk // nel, uk % nel, summed, nel, nel)
 
 
 def face_basis(k, length, tau):
     """Face-orthonormal basis sqrt(2/|e|) lhat_m(tau), shape (k+1, nq)."""
-    return np.sqrt(2.0 / length) * onb_values(k, tau)
+    return np.sqrt(2 / length) * onb_values(k, tau)
 
 
-def assemble_rhs(mesh: Mesh, eta, f, g=None, penalty_nf=PENALTY_NF):
+def assemble_rhs(mesh: Mesh, eta, f, g=None, penalty_nf=PENALTY_NF, dtype=np.float64):
     """F (velocity) and G (pressure) right-hand sides.
 
     f: modal body force, shape (nel, 2, k+1, k+1); F = int f.v = f because the
     basis is orthonormal.  g: Dirichlet data (nbfaces, 2, k+1) or None."""
-    k, hx, hy = mesh.k, mesh.hx, mesh.hy
-    F = np.array(f, dtype=np.float64).reshape(-1).copy()
-    G = np.zeros(mesh.np_)
+    k = mesh.k
+    hx, hy = _h(mesh, dtype)
+    F = np.array(f, dtype=dtype).reshape(-1).copy()
+    G = np.zeros(mesh.np_, dtype=dtype)
     if g is None or all(b != DIRICHLET for b in mesh.bc):
         return F, G
-    g = np.asarray(g, dtype=np.float64).reshape(mesh.nbfaces(), 2, k + 1)
-    fd = face_data(mesh, np.asarray(eta, dtype=np.float64), penalty_nf)
+    g = np.asarray(g, dtype=dtype).reshape(mesh.nbfaces(), 2, k + 1)
+    eta = np.asarray(eta, dtype=dtype)
+    fd = face_data(mesh, eta, penalty_nf, dtype=dtype)
     nbu, nbp = mesh.nbu, mesh.nbp
     for side, e, fi, kind, etaf, sigma in fd["boundary"]:
         if kind != DIRICHLET:
@@ -382,7 +405,7 @@ def assemble_rhs(mesh: Mesh, eta, f, g=None, penalty_nf=PENALTY_NF):
         length = hy if side in (LEFT, RIGHT) else hx
         gq = np.einsum("dm,mq->qd", g[fi], face_basis(k, length, tau))
         val, grad = velocity_basis(k, hx, hy, xs, ys)
-        sn = np.einsum("aqcr,r->aqc", 2.0 * strain(grad), n)
+        sn = np.einsum("aqcr,r->aqc", 2 * strain(grad), n)
         lift = (-eta[e] * np.einsum("aqc,qc,q->a", sn, gq, wf)
                 + sigma * np.einsum("aqc,qc,q->a", val, gq, wf))
         F[e * nbu:(e + 1) * nbu] += lift
