@@ -157,3 +157,28 @@ def solve_stokes_ext(mesh: Mesh, eta, f, g=None, method="lu"):
     if border:
         p = _mean_zero(mesh, p)
     return u, p
+
+
+def stokes_error_estimate(mesh: Mesh, eta, f, u_hi, p_hi, u_lo=None, p_lo=None, rtol=1e-8, maxit=60, **mg):
+    """Relative velocity and pressure error of an FP64-pair Stokes iterate,
+    for meshes where a refined reference is too costly: the error e solves
+    K e = r with r = b - K x formed in long double, and e is obtained by the
+    paper's own iteration (FGMRES with the block preconditioner and the
+    hp-multigrid inner solve, StokesSolver) to rtol relative to ||r||.  A
+    residual reduction of 1e-8 fixes e to about a percent (a loose one does
+    not: the error of a random perturbation needs it).  Returns
+    (|e_u| / |u|, |e_p| / |p|, ||r|| / ||b||)."""
+    from .multigrid import StokesSolver
+    K, b = stokes_system(mesh, eta, f)
+    x = np.concatenate([_pair(u_hi, u_lo), _pair(p_hi, p_lo)])
+    r = b - K @ x
+    rel = float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(b * b)))
+    r64 = np.asarray(r, dtype=np.float64)
+    nu = mesh.nu
+    S = StokesSolver(mesh, eta, **mg)
+    eu, ep, _, _ = S.solve(r64[:nu], r64[nu:], rtol=rtol, maxit=maxit)
+    xu = np.asarray(x[:nu], dtype=np.float64)
+    xp = np.asarray(x[nu:], dtype=np.float64)
+    if mesh.no_neumann():
+        xp = np.asarray(_mean_zero(mesh, xp), dtype=np.float64)
+    return (float(np.linalg.norm(eu) / np.linalg.norm(xu)), float(np.linalg.norm(ep) / np.linalg.norm(xp)), rel)

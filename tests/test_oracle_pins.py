@@ -559,3 +559,23 @@ def test_refined_stokes_lu_and_block_agree():
     # the FP64 LU's pressure itself is off by about 1e-7 here (it is fixed
     # through B only): the refined reference is the one to compare against
     assert np.linalg.norm(pa.astype(np.float64) - pd) <= 1e-6 * np.linalg.norm(pd)
+
+
+def test_stokes_error_estimate_matches_true_error():
+    """The error estimate (long-double residual, the paper's iteration to
+    1e-8 on the error equation) gives the distance of a randomly perturbed
+    iterate to the refined solution to within 5%."""
+    from oracle import refine as rf
+    P = gen.single_inclusion(8, 2, eta_in=1e3)
+    m = Mesh(8, 8, 2)
+    u, p = rf.solve_stokes_ext(m, P.eta, P.f, method="lu")
+    rng = np.random.default_rng(4)
+    du = 1e-7 * np.linalg.norm(u.astype(np.float64)) / np.sqrt(m.nu) * rng.normal(size=m.nu)
+    dp = 1e-6 * np.linalg.norm(p.astype(np.float64)) / np.sqrt(m.np_) * rng.normal(size=m.np_)
+    dp = dp - (asm.pressure_mean_vector(m) @ dp) / (m.lx * m.ly) * asm.pressure_mean_vector(m)
+    uh, ph = (u.astype(np.float64) + du), (p.astype(np.float64) + dp)
+    eu_true = float(np.linalg.norm((uh.astype(LD) - u).astype(np.float64)) / np.linalg.norm(u.astype(np.float64)))
+    ep_true = float(np.linalg.norm((ph.astype(LD) - p).astype(np.float64)) / np.linalg.norm(p.astype(np.float64)))
+    eu, ep, rel = rf.stokes_error_estimate(m, P.eta, P.f, uh, ph, coarsest_n=4, inner_rtol=1e-6)
+    assert abs(eu / eu_true - 1) <= 0.05 and abs(ep / ep_true - 1) <= 0.05, (eu, eu_true, ep, ep_true)
+    assert rel > 0
