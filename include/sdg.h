@@ -59,9 +59,11 @@ extern "C" {
 #define SDG_ERR_UNSUPPORTED (-4) /* e.g. singular all-Neumann viscous problem */
 #define SDG_NOT_CONVERGED 1      /* iteration limit reached; last iterate returned */
 #define SDG_BREAKDOWN 2          /* Krylov breakdown; last iterate returned */
-#define SDG_FLOOR 3              /* FGMRES stopped at the FP64 rounding floor of the true residual
-                                    (about eps |K||x| / |b|), above rtol; stats.rel_residual is
-                                    the residual reached */
+#define SDG_FLOOR 3              /* the true residual stagnated above rtol within a small factor of
+                                    the rounding floor of its evaluation (eps |K||x| / |b|, eps of
+                                    FP64, or of the extended residual with opts.refine); the output
+                                    is the best iterate and stats.rel_residual the residual reached.
+                                    A stagnation above that floor returns SDG_NOT_CONVERGED. */
 
 /* boundary side types, sides ordered left, right, bottom, top */
 #define SDG_NAVIER 0
@@ -97,12 +99,24 @@ typedef struct sdg_options {
   int32_t prec_smoother;  /* SDG_FP64: full block inverses; SDG_FP32 / SDG_BF16: inverse Cholesky
                              factors X = L^{-1} (stored as X and X^T), smoother X^T X */
   int32_t prec_apply;     /* SDG_FP64 / SDG_FP32: operator apply inside the cycle */
-  int32_t viscous_krylov; /* 0: CG (paper); 1: FGMRES (needed when the cycle is not exactly linear) */
+  int32_t viscous_krylov; /* viscous solves and the inner solve of the Stokes preconditioner:
+                             0: CG (Section 8.1); 1: FGMRES (standalone viscous solves; needed
+                             when the cycle is not exactly linear); 2: GCR (Section 8.3) */
   int32_t dedup;          /* 1: share block inverses between elements with equal normalised blocks */
   uint64_t seed;          /* stream of the SplitMix64 start vectors of the eigen-estimates */
   int32_t graphs;         /* 1: each CG iteration after the first replays a captured HIP graph
                              (V-cycle, updates, operator apply, readback of the scalars); the
                              arithmetic is that of the launches it replaces.  Off while tracing. */
+  int32_t refine;         /* 0: FP64 iterate and true residual (the residual stops at the FP64
+                             rounding floor, about eps |K||x| / |b|).  1: iterative refinement
+                             in extended precision (in place of the quadruple-precision Krylov
+                             arithmetic of Section 8.3.1): the iterate is a double-FP64 pair and
+                             the true residual is evaluated in double-FP64 with operator
+                             coefficients exact to long double; FGMRES restarts (Stokes, or
+                             viscous_krylov = 1) or CG corrections (viscous, CG) solve for the
+                             correction in FP64.  rtol then bounds the residual of the pair. */
+  int32_t outer_krylov;   /* Stokes solve: 0: right-preconditioned FGMRES (Section 5, 8.1);
+                             1: GCR (Section 8.3, six-inclusion experiment) */
   int32_t reserved_;
 } sdg_options;
 
@@ -226,6 +240,27 @@ int sdg_solve_viscous_dev(sdg_problem* prob, const double* f_dev, const double* 
 int sdg_solve_stokes_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
                          double* u_dev, double* p_dev, sdg_stats* stats);
 
+/* Same solves, returning the iterate of opts.refine = 1 as double-FP64 pairs:
+ * u = u_hi + u_lo (and p = p_hi + p_lo), u_hi the rounded sum.  The low
+ * parts may be NULL; with opts.refine = 0 they are zero. */
+int sdg_solve_viscous_ext_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
+                              double* u_hi_dev, double* u_lo_dev, sdg_stats* stats);
+int sdg_solve_stokes_ext_dev(sdg_problem* prob, const double* f_dev, const double* g_dev,
+                             double* u_hi_dev, double* u_lo_dev, double* p_hi_dev, double* p_lo_dev,
+                             sdg_stats* stats);
+/* Extended-precision residual (the refinement residual of opts.refine):
+ * stokes = 0: r = b - A x;  stokes != 0: [r_u; r_p] = [b_u; b_p] - K [x; p]
+ * with K = [A B; B^T 0] (eq. discretestokes), the vectors stacked
+ * velocity (all problems) then pressure (all problems) as in the Stokes
+ * solves.  x = x_hi + x_lo (x_lo may be NULL), evaluated in double-FP64
+ * arithmetic with the unit blocks of eq. stiffness_form and
+ * eq. divergence_form integrated in long double, rounded to FP64. */
+int sdg_residual_ext(sdg_problem* prob, int stokes, const double* b_dev, const double* x_hi_dev,
+                     const double* x_lo_dev, double* r_dev);
+/* y = |K| |x| in FP64 (stokes as above): the scale of rounding errors in
+ * K x, behind the floor estimate eps |K||x| / |b| of SDG_FLOOR. */
+int sdg_abs_apply(sdg_problem* prob, int stokes, const double* x_dev, double* y_dev);
+
 /* ---- one-shot solves on host arrays (copy in, setup, solve, copy out) ------ */
 int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
                       const double* eta, const double* f, const double* g, double* u,
@@ -233,6 +268,23 @@ int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
 int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts,
                      const double* eta, const double* f, const double* g, double* u,
                      double* p, sdg_stats* stats);
+
+/* ---- batching form: many viscous solves of different meshes and orders ---
+ * n independent viscous solves A_i u_i = F_i (host arrays: eta[i] of nel_i,
+ * f[i] and u[i] of nu_i = nel_i 2 (k_i+1)^2 values; u_lo[i] optional, the
+ * low parts of the refined iterate; no Dirichlet data) under one set of
+ * options.  Requests of identical mesh and order share one batched problem
+ * object (their launches cover all of them); with viscous_krylov = 0 (CG,
+ * with or without refinement) the CG iterations of all groups run in
+ * lockstep and every iteration of every group is one replay of a combined
+ * HIP graph with one parallel branch per group, so problems of different
+ * sizes and orders overlap on the device in a single launch.  Other Krylov
+ * choices solve the groups one after another.  stats: n entries, in request
+ * order.  Returns SDG_OK when all converged, else the largest soft outcome,
+ * or a negative error. */
+int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const sdg_options* opts,
+                            const double* const* eta, const double* const* f, double* const* u,
+                            double* const* u_lo, sdg_stats* stats);
 
 /* ---- SplitMix64 (counter form) on the device, for parity of start vectors --
  * out[i] = 2 * (z_i >> 11) * 2^-53 - 1, z_i the i-th SplitMix64 output of

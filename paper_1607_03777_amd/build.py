@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdg.so")
 SOURCES = ["sip_kernels.hip", "block_kernels.hip", "coarse_kernels.hip", "vec_kernels.hip",
-           "solver.hip", "serve.hip", "admission.cpp"]
+           "ext_kernels.hip", "solver.hip", "serve.hip", "admission.cpp"]
 ARCH = os.environ.get("SDG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -40,7 +40,7 @@ bool same_options(const sdg_options& a, const sdg_options& b) {
          a.smooth_h == b.smooth_h && a.coarsest_n == b.coarsest_n && a.eig_steps == b.eig_steps &&
          a.cheb_lo == b.cheb_lo && a.cheb_hi == b.cheb_hi && a.prec_smoother == b.prec_smoother &&
          a.prec_apply == b.prec_apply && a.viscous_krylov == b.viscous_krylov && a.dedup == b.dedup &&
-         a.seed == b.seed;
+         a.seed == b.seed && a.refine == b.refine && a.outer_krylov == b.outer_krylov;
 }
 
 bool same_shape(const sdg_mesh& a, const sdg_mesh& b) {
@@ -100,6 +100,10 @@ size_t group_bytes(const sdg_req& r, int nb) {
   return sdg_required_bytes_batch(&r.mesh, &r.opts, r.kind, nb) + io_bytes(r, nb);
 }
 
+// Publishes a request's outcome.  The waiter is notified while the lock is
+// held: once it is released the client may free the request at any time
+// (sdg_wait then sdg_req_free), so after the unlock the worker touches the
+// request only to delete it, and only when the client freed it before.
 void finish(sdg_req* r, int rc, const sdg_stats* st, double t_end, int batch, const std::string& err) {
   bool del;
   {
@@ -111,8 +115,8 @@ void finish(sdg_req* r, int rc, const sdg_stats* st, double t_end, int batch, co
     r->batch = batch;
     r->done = true;
     del = r->user_freed;
+    r->cv.notify_all();
   }
-  r->cv.notify_all();
   if (del) delete r;
 }
 

@@ -36,6 +36,7 @@
 
 #include "sdg_common.h"
 #include "sdg_kernels.h"
+#include "ext_kernels.h"
 #include "runtime.h"
 
 // A context is freed when it has been destroyed and its last problem is
@@ -66,7 +67,16 @@ struct sdg_ctx {
   // A block enters the cache only once no queued work uses it.  Guarded by mu.
   std::multimap<size_t, void*> cache;
   size_t cached = 0;
+  // unit-block tables of the extended-precision residual, per (k, nx, ny,
+  // lx, ly, side kinds); device arrays live until the context is freed.
+  // Guarded by mu.
+  struct ExtEntry {
+    sdg::ExtTables T;
+    void* mem = nullptr;
+  };
+  std::map<std::string, ExtEntry> ext;
   ~sdg_ctx() {
+    for (auto& kv : ext) (void)hipFree(kv.second.mem);
     for (auto& r : pending) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
@@ -86,6 +96,7 @@ const char* get_error() { return g_err.c_str(); }
 using namespace sdg;
 
 namespace {
+
 
 constexpr int TAIL_NODES = 17 * 17;  // h-levels with at most this many nodes run in the tail kernel
 constexpr int RED_SCRATCH = 512 * 64;
@@ -134,6 +145,16 @@ struct CLevel {
   double* ab = nullptr;  // [smooth_h][nbatch][2]
   std::vector<double> lmin, lmax;
   bool coarsest = false;
+};
+
+// Workspace of a GCR solve: m search directions p_j (P) and their images
+// q_j = K p_j (Q), both [m][total]; the residual r and the cycle's
+// correction c ([total]); device coefficients and the done mask.
+struct GcrWork {
+  double *Q = nullptr, *Pd = nullptr, *r = nullptr, *c = nullptr;
+  double* coef = nullptr;  // [4 (m + 1) + 4][nb]
+  int* done = nullptr;     // [nb]
+  int m = 0;
 };
 
 double now_ms() {
@@ -200,6 +221,10 @@ struct sdg_problem {
   hipStream_t gs = nullptr;  // private stream used only to capture
   hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
   double* cg_x = nullptr;  // fixed iterate buffer of the captured iteration
+  // extended-precision residual tables (from the context's cache)
+  const ExtTables* ext = nullptr;
+  // GCR workspace of the inner viscous solve
+  GcrWork gi;
 };
 
 namespace {
@@ -587,6 +612,59 @@ int run_sip_residual_f32(sdg_problem* P, const float* b, const float* u, float* 
   return traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, 3 * vec_bytes(P, 4) + elem_bytes(P, 8),
                 [&] { return sip_residual_f32(P->M, P->k, P->nb, P->eta, b, u, r, P->s, P->tile[1][1]); });
 }
+// Unit-block tables of the extended-precision residual for the problem's
+// mesh: integrated on the host in long double once per context and mesh.
+int ensure_ext(sdg_problem* P) {
+  if (P->ext) return SDG_OK;
+  sdg_ctx* c = P->ctx;
+  const sdg_mesh& m = P->mesh;
+  char key[160];
+  std::snprintf(key, sizeof(key), "%d/%d/%d/%.17g/%.17g/%d%d%d%d", m.k, m.nx, m.ny, m.lx, m.ly, m.bc[0], m.bc[1],
+                m.bc[2], m.bc[3]);
+  std::lock_guard<std::mutex> g(c->mu);
+  auto it = c->ext.find(key);
+  if (it == c->ext.end()) {
+    std::vector<double2> TA, TBu, TBp;
+    sdg_ctx::ExtEntry E;
+    ext_unit_blocks(m.k, m.lx, m.ly, m.nx, m.ny, m.bc, TA, TBu, TBp, E.T.cpen);
+    const size_t na = TA.size() * sizeof(double2), nbu = TBu.size() * sizeof(double2);
+    const size_t bytes = na + 2 * nbu;
+    if (hipMalloc(&E.mem, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("allocation of the extended-precision operator tables failed");
+      return SDG_ERR_NOMEM;
+    }
+    char* base = (char*)E.mem;
+    if (hipMemcpy(base, TA.data(), na, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + na, TBu.data(), nbu, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + na + nbu, TBp.data(), nbu, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(E.mem);
+      set_error("upload of the extended-precision operator tables failed");
+      return SDG_ERR_DEVICE;
+    }
+    E.T.A = (const double2*)base;
+    E.T.Bu = (const double2*)(base + na);
+    E.T.Bp = (const double2*)(base + na + nbu);
+    it = c->ext.emplace(key, E).first;
+  }
+  P->ext = &it->second.T;
+  return SDG_OK;
+}
+// r = b - K (xh + xl) in double-FP64 (stokes: velocity then pressure block
+// of the stacked vectors); abs_mode: r = |K||xh|
+int run_ext(sdg_problem* P, bool stokes, bool abs_mode, const double* b, const double* xh, const double* xl,
+            double* r) {
+  SDG_TRY(ensure_ext(P));
+  const int64_t U = P->nu * P->nb;
+  const bool st = stokes && P->np > 0;
+  return ext_residual(P->M, P->k, P->nb, abs_mode, P->eta, b, xh, xl, st ? xh + U : nullptr,
+                      (st && xl) ? xl + U : nullptr, st ? b + U : nullptr, *P->ext, r, st ? r + U : nullptr, P->s);
+}
+// effective unit roundoff of the true residual: FP64 evaluation, or the
+// extended one (coefficients exact to the 64-bit mantissa of long double)
+double resid_eps(const sdg_problem* P) { return P->opt.refine ? 0x1p-63 : 0x1p-53; }
+
 std::array<int, 6> tune_key(const sdg_problem* P, int kernel, int prec) {
   return {P->k, P->mesh.nx, P->mesh.ny, P->nb, kernel, prec};
 }
@@ -1005,95 +1083,415 @@ int cg_graph(sdg_problem* P, int parity, hipGraphExec_t* out) {
   return SDG_OK;
 }
 
-int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int maxit, std::vector<int>& its,
-             std::vector<double>& rel, std::vector<int>& status) {
+// State of one batched CG solve, split so that several problems (of
+// different shapes) can be advanced in lockstep: cg_start runs the first
+// iteration up to the publication of its scalars; cg_poll waits for a
+// publication and decides per problem (converged, breakdown, limit);
+// cg_body_launch enqueues the next iteration (a graph replay, or eager
+// launches while tracing); cg_finish drains the stream and copies the
+// iterate out.  rtol_pb (optional): a tolerance per problem.
+struct CgRun {
+  sdg_problem* P = nullptr;
+  const double* b = nullptr;
+  double* x_out = nullptr;
+  double* x = nullptr;
+  double rtol = 0;
+  int maxit = 0;
+  const std::vector<double>* rtol_pb = nullptr;
+  bool graphs = false;
+  std::vector<int> its, status, act;
+  std::vector<double> rel, bn;
+  int nact = 0, it = 0, parity = 0;
+  unsigned expect = 0;
+  bool running = false;  // an iteration is queued whose scalars are not yet read
+};
+
+int cg_start(CgRun& R, sdg_problem* P, const double* b, double* x_out, double rtol, int maxit,
+             const std::vector<double>* rtol_pb) {
+  R.P = P;
+  R.b = b;
+  R.x_out = x_out;
+  R.rtol = rtol;
+  R.maxit = maxit;
+  R.rtol_pb = rtol_pb;
   const int nb = P->nb;
   const int64_t n = P->nu;
   const VSpec S = viscous_spec(P);
   // replayed iterations work on a fixed iterate buffer (graph arguments)
-  const bool graphs = P->opt.graphs && !P->ctx->trace;
-  double* x = graphs ? P->cg_x : x_out;
-  std::vector<double> bn;
-  SDG_TRY(vs_norms(P, S, b, bn));  // synchronises the stream
+  R.graphs = P->opt.graphs && !P->ctx->trace;
+  R.x = R.graphs ? P->cg_x : x_out;
+  SDG_TRY(vs_norms(P, S, b, R.bn));  // synchronises the stream
   P->seq = *const_cast<volatile unsigned*>(P->hseq);  // the device's count of publications so far
-  SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
-  its.assign(nb, 0);
-  rel.assign(nb, 0.0);
-  status.assign(nb, SDG_OK);
-  std::vector<int> act(nb, 0);
-  int nact = 0;
+  SDG_HIP(hipMemsetAsync(R.x, 0, S.total * sizeof(double), P->s));
+  R.its.assign(nb, 0);
+  R.rel.assign(nb, 0.0);
+  R.status.assign(nb, SDG_OK);
+  R.act.assign(nb, 0);
+  R.nact = 0;
+  R.it = 0;
+  R.parity = 0;
+  R.running = false;
   for (int pb = 0; pb < nb; ++pb) {
-    if (!std::isfinite(bn[pb])) {
-      status[pb] = SDG_BREAKDOWN;
-      rel[pb] = NAN;
-    } else if (bn[pb] > 0.0) {
-      act[pb] = 1;
-      rel[pb] = 1.0;
-      status[pb] = SDG_NOT_CONVERGED;
-      ++nact;
+    if (!std::isfinite(R.bn[pb])) {
+      R.status[pb] = SDG_BREAKDOWN;
+      R.rel[pb] = NAN;
+    } else if (R.bn[pb] > 0.0) {
+      R.act[pb] = 1;
+      R.rel[pb] = 1.0;
+      R.status[pb] = SDG_NOT_CONVERGED;
+      ++R.nact;
     }
   }
-  if (nact == 0) {
-    if (graphs) SDG_TRY(vec_copy(S.total, x, x_out, P->s));
-    return SDG_OK;
-  }
-  SDG_TRY(upload_active(P, act));
+  if (R.nact == 0) return SDG_OK;
+  SDG_TRY(upload_active(P, R.act));
   SDG_TRY(vec_copy(S.total, b, P->cg_r, P->s));
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
   SDG_TRY(vec_copy(S.total, P->cg_z, P->cg_p, P->s));
   double* rz = sc(P, SC_RZ);
-  double* rz2 = sc(P, SC_RZ2);
   SDG_TRY(bmulti_dot(n, nb, 1, P->cg_r, 0, P->cg_z, rz, P->red, P->s));
   // first iteration: q = A p, p.q, update, readback
   SDG_TRY(run_sip_apply_dot(P, P->cg_p, P->cg_q, sc(P, SC_PQ)));
-  SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
+  SDG_TRY(cg_update1(n, nb, P->cg_p, P->cg_q, R.x, P->cg_r, rz, sc(P, SC_PQ), P->active, sc(P, SC_RR), P->red,
                      P->s));
-  unsigned expect = 0;
-  SDG_TRY(publish(P, sc(P, SC_PQ), 2 * nb, &expect));
-  std::vector<double> rr(nb), pq(nb), both(2 * nb);
-  int parity = 0;  // 0: rz holds the current r.z; 1: rz2 does
-  for (int it = 0; it < maxit && nact > 0; ++it) {
-    SDG_TRY(wait_published(P, expect, 2 * nb, both.data()));
-    std::memcpy(pq.data(), both.data(), nb * sizeof(double));
-    std::memcpy(rr.data(), both.data() + nb, nb * sizeof(double));
-    bool changed = false;
-    for (int pb = 0; pb < nb; ++pb) {
-      if (!act[pb]) continue;
-      if (!(pq[pb] > 0.0) || !std::isfinite(pq[pb])) {
-        status[pb] = SDG_BREAKDOWN;
-        act[pb] = 0;
-        --nact;
-        changed = true;
-        continue;
-      }
-      ++its[pb];
-      rel[pb] = std::sqrt(rr[pb] > 0 ? rr[pb] : 0.0) / bn[pb];
-      if (!std::isfinite(rel[pb])) {
-        status[pb] = SDG_BREAKDOWN;
-        act[pb] = 0;
-        --nact;
-        changed = true;
-      } else if (rel[pb] < rtol) {
-        status[pb] = SDG_OK;
-        act[pb] = 0;
-        --nact;
-        changed = true;
-      }
+  SDG_TRY(publish(P, sc(P, SC_PQ), 2 * nb, &R.expect));
+  R.running = true;
+  return SDG_OK;
+}
+
+// Reads the queued iteration's scalars; *more: the solve needs another
+// iteration (the active flags on the device are refreshed if they changed).
+int cg_poll(CgRun& R, bool* more) {
+  *more = false;
+  if (!R.running) return SDG_OK;
+  sdg_problem* P = R.P;
+  const int nb = P->nb;
+  std::vector<double> both(2 * (size_t)nb);
+  SDG_TRY(wait_published(P, R.expect, 2 * nb, both.data()));
+  R.running = false;
+  bool changed = false;
+  for (int pb = 0; pb < nb; ++pb) {
+    if (!R.act[pb]) continue;
+    const double pq = both[pb], rr = both[nb + pb];
+    if (!(pq > 0.0) || !std::isfinite(pq)) {
+      R.status[pb] = SDG_BREAKDOWN;
+      R.act[pb] = 0;
+      --R.nact;
+      changed = true;
+      continue;
     }
-    if (nact == 0 || it + 1 >= maxit) break;
-    if (changed) SDG_TRY(upload_active(P, act));
-    if (graphs) {
+    ++R.its[pb];
+    R.rel[pb] = std::sqrt(rr > 0 ? rr : 0.0) / R.bn[pb];
+    if (!std::isfinite(R.rel[pb])) {
+      R.status[pb] = SDG_BREAKDOWN;
+      R.act[pb] = 0;
+      --R.nact;
+      changed = true;
+    } else if (R.rel[pb] < (R.rtol_pb ? (*R.rtol_pb)[pb] : R.rtol)) {
+      R.status[pb] = SDG_OK;
+      R.act[pb] = 0;
+      --R.nact;
+      changed = true;
+    }
+  }
+  ++R.it;
+  if (R.nact == 0 || R.it >= R.maxit) return SDG_OK;
+  if (changed) SDG_TRY(upload_active(P, R.act));
+  *more = true;
+  return SDG_OK;
+}
+
+// the next iteration on the problem's stream (graph or eager); a caller that
+// launched it inside a combined graph passes launched = true
+int cg_body_launch(CgRun& R, bool launched) {
+  sdg_problem* P = R.P;
+  double* rz = sc(P, SC_RZ);
+  double* rz2 = sc(P, SC_RZ2);
+  if (!launched) {
+    if (R.graphs) {
       hipGraphExec_t ge = nullptr;
-      SDG_TRY(cg_graph(P, parity, &ge));
+      SDG_TRY(cg_graph(P, R.parity, &ge));
       SDG_HIP(hipGraphLaunch(ge, P->s));
     } else {
-      SDG_TRY(parity == 0 ? cg_body(P, x, rz, rz2) : cg_body(P, x, rz2, rz));
+      SDG_TRY(R.parity == 0 ? cg_body(P, R.x, rz, rz2) : cg_body(P, R.x, rz2, rz));
     }
-    expect = ++P->seq;  // the iteration ends with one publication
-    parity ^= 1;
   }
+  R.expect = ++P->seq;  // the iteration ends with one publication
+  R.parity ^= 1;
+  R.running = true;
+  return SDG_OK;
+}
+
+int cg_finish(CgRun& R) {
+  sdg_problem* P = R.P;
   SDG_HIP(hipStreamSynchronize(P->s));
-  if (graphs) SDG_TRY(vec_copy(S.total, x, x_out, P->s));
+  if (R.graphs) SDG_TRY(vec_copy(P->nu * P->nb, R.x, R.x_out, P->s));
+  return SDG_OK;
+}
+
+int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int maxit, std::vector<int>& its,
+             std::vector<double>& rel, std::vector<int>& status, const std::vector<double>* rtol_pb = nullptr) {
+  CgRun R;
+  SDG_TRY(cg_start(R, P, b, x_out, rtol, maxit, rtol_pb));
+  while (true) {
+    bool more = false;
+    SDG_TRY(cg_poll(R, &more));
+    if (!more) break;
+    SDG_TRY(cg_body_launch(R, false));
+  }
+  SDG_TRY(cg_finish(R));
+  its = R.its;
+  rel = R.rel;
+  status = R.status;
+  return SDG_OK;
+}
+
+// Several batched CG solves (problems of different meshes and orders, all
+// on one stream) advanced in lockstep.  With graphs, one iteration of every
+// running solve is a single replay of a combined HIP graph: a fork from a
+// private capture stream, one parallel branch per solve (its V-cycle,
+// updates, operator apply and the publication of its scalars) and a join,
+// so that a single launch covers every shape and the solves overlap on the
+// device.  The combined graph is captured once per set of running solves
+// and parity and reused; a solve that has converged leaves the set.  With a
+// single solve the problem's own captured iteration is replayed.
+struct MultiGraphs {
+  hipStream_t cs = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::map<std::string, hipGraphExec_t> cache;
+  ~MultiGraphs() {
+    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
+  std::string key;
+  for (CgRun* r : A) key += std::to_string((uintptr_t)r->P) + ":" + std::to_string(r->parity) + ";";
+  auto it = G.cache.find(key);
+  if (it != G.cache.end()) {
+    *out = it->second;
+    return SDG_OK;
+  }
+  if (!G.cs) SDG_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+  while (G.ev.size() < A.size() + 1) {
+    hipEvent_t e;
+    SDG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    G.ev.push_back(e);
+  }
+  for (CgRun* r : A)
+    if (!r->P->gs) SDG_HIP(hipStreamCreateWithFlags(&r->P->gs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = SDG_OK;
+  if (hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = SDG_ERR_DEVICE;
+  } else {
+    if (hipEventRecord(G.ev[0], G.cs) != hipSuccess) rc = SDG_ERR_DEVICE;
+    for (size_t i = 0; i < A.size() && rc >= 0; ++i) {
+      sdg_problem* P = A[i]->P;
+      if (hipStreamWaitEvent(P->gs, G.ev[0], 0) != hipSuccess) {
+        rc = SDG_ERR_DEVICE;
+        break;
+      }
+      hipStream_t user = P->s;
+      P->s = P->gs;
+      double* rz = sc(P, SC_RZ);
+      double* rz2 = sc(P, SC_RZ2);
+      rc = A[i]->parity == 0 ? cg_body(P, A[i]->x, rz, rz2) : cg_body(P, A[i]->x, rz2, rz);
+      P->s = user;
+      if (rc >= 0 && (hipEventRecord(G.ev[i + 1], P->gs) != hipSuccess ||
+                      hipStreamWaitEvent(G.cs, G.ev[i + 1], 0) != hipSuccess))
+        rc = SDG_ERR_DEVICE;
+    }
+    if (hipStreamEndCapture(G.cs, &g) != hipSuccess && rc >= 0) rc = SDG_ERR_DEVICE;
+  }
+  hipGraphExec_t ge = nullptr;
+  if (rc >= 0 && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) rc = SDG_ERR_DEVICE;
+  if (g) (void)hipGraphDestroy(g);
+  if (rc < 0) {
+    (void)hipGetLastError();
+    set_error("capture of the combined CG iteration as a HIP graph failed");
+    return rc;
+  }
+  G.cache[key] = ge;
+  *out = ge;
+  return SDG_OK;
+}
+
+// runs[i] already started (cg_start); advances all to completion
+int cg_multi(std::vector<CgRun>& runs, MultiGraphs& G) {
+  while (true) {
+    std::vector<CgRun*> A;
+    for (CgRun& r : runs) {
+      bool more = false;
+      SDG_TRY(cg_poll(r, &more));
+      if (more) A.push_back(&r);
+    }
+    if (A.empty()) break;
+    const bool combined = A.size() > 1 && A[0]->graphs;
+    if (combined) {
+      hipGraphExec_t ge = nullptr;
+      SDG_TRY(multi_graph(G, A, &ge));
+      SDG_HIP(hipGraphLaunch(ge, A[0]->P->s));
+    }
+    for (CgRun* r : A) SDG_TRY(cg_body_launch(*r, combined));
+  }
+  for (CgRun& r : runs) SDG_TRY(cg_finish(r));
+  return SDG_OK;
+}
+
+// Viscous solves by CG with iterative refinement in extended precision
+// (opts.refine with viscous_krylov = 0), for one or several batched
+// problems (in lockstep, see cg_multi): the iterate is the double-FP64 pair
+// (xh, xl); each step solves A d = r by CG in FP64 to a tolerance relative
+// to its right-hand side chosen so that the step reaches rtol (at most 1e-6
+// per step, where FP64 CG stays far from its own floor), adds d in
+// double-FP64 and forms the true residual r = F - A (xh + xl) in extended
+// precision.  Converged problems get a zero right-hand side and stay put.
+// its[pb] counts CG iterations over all steps.
+struct RefineState {
+  sdg_problem* P = nullptr;
+  const double* F = nullptr;
+  double *xh = nullptr, *xl = nullptr, *r = nullptr, *d = nullptr;
+  std::vector<double> bn, tol;
+  std::vector<char> act;
+  std::vector<double> prev;
+  std::vector<int> gaps;
+  std::vector<int> its, status;
+  std::vector<double> rel;
+};
+
+int cg_refine_multi(std::vector<RefineState>& G, double rtol, int maxit, MultiGraphs& MG) {
+  int rc = SDG_OK;
+  for (RefineState& R : G) {
+    sdg_problem* P = R.P;
+    const int nb = P->nb;
+    const VSpec S = viscous_spec(P);
+    if (tmp_get(P, &R.r, S.total) < 0 || tmp_get(P, &R.d, S.total) < 0) {
+      set_error("allocation of the refinement vectors failed");
+      rc = SDG_ERR_NOMEM;
+      break;
+    }
+    R.its.assign(nb, 0);
+    R.rel.assign(nb, 1.0);
+    R.status.assign(nb, SDG_NOT_CONVERGED);
+    R.act.assign(nb, 1);
+    R.prev.assign(nb, 1.0);
+    R.gaps.assign(nb, 0);
+    if ((rc = vs_norms(P, S, R.F, R.bn)) < 0) break;
+    if (hipMemsetAsync(R.xh, 0, S.total * sizeof(double), P->s) != hipSuccess ||
+        hipMemsetAsync(R.xl, 0, S.total * sizeof(double), P->s) != hipSuccess) {
+      rc = SDG_ERR_DEVICE;
+      break;
+    }
+    if ((rc = vec_copy(S.total, R.F, R.r, P->s)) < 0) break;
+  }
+  for (int step = 0; step < 64 && rc >= 0; ++step) {
+    std::vector<CgRun> runs;
+    std::vector<RefineState*> stepping;
+    runs.reserve(G.size());
+    for (RefineState& R : G) {
+      sdg_problem* P = R.P;
+      const int nb = P->nb;
+      const VSpec S = viscous_spec(P);
+      std::vector<double> rn;
+      if ((rc = vs_norms(P, S, R.r, rn)) < 0) break;
+      std::vector<char> stag(nb, 0);
+      bool any_stag = false;
+      int used = 0;
+      for (int pb = 0; pb < nb; ++pb) {
+        used = std::max(used, R.its[pb]);
+        if (!R.act[pb]) continue;
+        if (!(R.bn[pb] > 0.0)) {
+          R.rel[pb] = std::isfinite(R.bn[pb]) ? 0.0 : NAN;
+          R.status[pb] = std::isfinite(R.bn[pb]) ? SDG_OK : SDG_BREAKDOWN;
+          R.act[pb] = 0;
+          continue;
+        }
+        R.rel[pb] = rn[pb] / R.bn[pb];
+        if (!std::isfinite(R.rel[pb])) {
+          R.status[pb] = SDG_BREAKDOWN;
+          R.act[pb] = 0;
+        } else if (R.rel[pb] < rtol) {
+          R.status[pb] = SDG_OK;
+          R.act[pb] = 0;
+        } else if (step > 0) {
+          R.gaps[pb] = R.rel[pb] > 0.5 * R.prev[pb] ? R.gaps[pb] + 1 : 0;
+          if (R.gaps[pb] >= 2) {
+            stag[pb] = 1;
+            any_stag = true;
+          } else if (R.its[pb] >= maxit) {
+            R.act[pb] = 0;  // NOT_CONVERGED
+          }
+        }
+        R.prev[pb] = R.rel[pb];
+      }
+      if (any_stag) {
+        std::vector<double> kx;
+        if ((rc = run_ext(P, false, true, nullptr, R.xh, nullptr, R.d)) < 0) break;
+        if ((rc = vs_norms(P, S, R.d, kx)) < 0) break;
+        for (int pb = 0; pb < nb; ++pb)
+          if (stag[pb]) {
+            R.status[pb] = R.rel[pb] <= 4.0 * resid_eps(P) * kx[pb] / R.bn[pb] ? SDG_FLOOR : SDG_NOT_CONVERGED;
+            R.act[pb] = 0;
+          }
+      }
+      int nact = 0;
+      std::vector<double> keep(nb, 0.0);
+      R.tol.assign(nb, 0.5);
+      for (int pb = 0; pb < nb; ++pb) {
+        if (!R.act[pb]) continue;
+        ++nact;
+        keep[pb] = 1.0;
+        R.tol[pb] = std::min(0.5, std::max(1e-6, 0.5 * rtol * R.bn[pb] / rn[pb]));
+      }
+      if (nact == 0 || used >= maxit) continue;
+      // converged problems: zero right-hand side (the CG leaves them at 0)
+      if ((rc = upload_scalars(P, sc(P, SC_BN), keep)) < 0) break;
+      if ((rc = vs_div(P, S, sc(P, SC_BN), R.r, R.r)) < 0) break;
+      runs.emplace_back();
+      if ((rc = cg_start(runs.back(), P, R.r, R.d, rtol, maxit - used, &R.tol)) < 0) break;
+      stepping.push_back(&R);
+    }
+    if (rc < 0 || runs.empty()) break;
+    if ((rc = cg_multi(runs, MG)) < 0) break;
+    for (size_t i = 0; i < runs.size() && rc >= 0; ++i) {
+      RefineState& R = *stepping[i];
+      sdg_problem* P = R.P;
+      for (int pb = 0; pb < P->nb; ++pb) {
+        if (!R.act[pb]) continue;
+        R.its[pb] += runs[i].its[pb];
+        if (runs[i].status[pb] == SDG_BREAKDOWN) {
+          R.status[pb] = SDG_BREAKDOWN;
+          R.act[pb] = 0;
+        }
+      }
+      const int64_t tot = P->nu * P->nb;
+      if ((rc = dd_accumulate(tot, R.d, R.xh, R.xl, P->s)) < 0) break;
+      if ((rc = run_ext(P, false, false, R.F, R.xh, R.xl, R.r)) < 0) break;
+    }
+  }
+  for (RefineState& R : G) {
+    const int64_t tot = R.P->nu * R.P->nb;
+    tmp_put(R.P, R.r, tot);  // synchronises the stream first
+    tmp_put(R.P, R.d, tot);
+    R.r = R.d = nullptr;
+  }
+  return rc;
+}
+
+int cg_refine(sdg_problem* P, const double* F, double* xh, double* xl, double rtol, int maxit,
+              std::vector<int>& its, std::vector<double>& rel, std::vector<int>& status) {
+  std::vector<RefineState> G(1);
+  G[0].P = P;
+  G[0].F = F;
+  G[0].xh = xh;
+  G[0].xl = xl;
+  MultiGraphs MG;
+  SDG_TRY(cg_refine_multi(G, rtol, maxit, MG));
+  its = G[0].its;
+  rel = G[0].rel;
+  status = G[0].status;
   return SDG_OK;
 }
 
@@ -1132,9 +1530,18 @@ int vs_dots_dev(sdg_problem* P, const VSpec& S, int mj, const double* V, int64_t
 
 // Batched right-preconditioned FGMRES(restart), classical Gram-Schmidt
 // applied twice, x0 = 0; each problem stops on its own true residual.
-template <typename MV, typename PC, typename PJ>
-int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double rtol, int maxit, MV matvec,
-           PC prec, PJ project, std::vector<int>& its, std::vector<double>& rel, std::vector<int>& status) {
+//
+// Each restart is a step of iterative refinement: the cycle solves for a
+// correction from the current true residual.  resid(x, xlo, w) forms that
+// residual, w = b - K x; with xlo != nullptr (opts.refine) the iterate is
+// the double-FP64 pair (x, xlo), the correction is accumulated into it in
+// double-FP64 and resid evaluates the residual in extended precision, so
+// the restarts drive the residual below the FP64 floor.  abs_apply(x, y)
+// forms y = |K||x| for the floor estimate of a stagnating problem.
+template <typename MV, typename PC, typename PJ, typename RS, typename AB>
+int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double* xlo, double rtol, int maxit,
+           MV matvec, PC prec, PJ project, RS resid, AB abs_apply, std::vector<int>& its, std::vector<double>& rel,
+           std::vector<int>& status) {
   const int m = P->opt.restart, nb = P->nb;
   SDG_TRY(ensure_gmres(P, S.total / nb));
   double* V = P->gV;
@@ -1146,6 +1553,7 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
   std::vector<double> bn, beta;
   SDG_TRY(vs_norms(P, S, w, bn));
   SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
+  if (xlo) SDG_HIP(hipMemsetAsync(xlo, 0, S.total * sizeof(double), P->s));
   its.assign(nb, 0);
   rel.assign(nb, 0.0);
   status.assign(nb, SDG_OK);
@@ -1276,13 +1684,21 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
       for (int pb = 0; pb < nb; ++pb)
         for (int i = 0; i < jmax; ++i) yc[(size_t)pb * jmax + i] = y[(size_t)pb * m + i];
       SDG_TRY(upload_scalars(P, sc_h(P), yc));
-      SDG_TRY(vs_combine(P, S, jmax, Z, ldv, sc_h(P), x));
+      if (xlo) {
+        // the correction Z y, accumulated into the double-FP64 iterate
+        SDG_HIP(hipMemsetAsync(w, 0, S.total * sizeof(double), P->s));
+        SDG_TRY(vs_combine(P, S, jmax, Z, ldv, sc_h(P), w));
+        SDG_TRY(dd_accumulate(S.total, w, x, xlo, P->s));
+      } else {
+        SDG_TRY(vs_combine(P, S, jmax, Z, ldv, sc_h(P), x));
+      }
     }
-    // true residual
-    SDG_TRY(matvec(x, w));
-    SDG_TRY(vec_axpby(S.total, 1.0, b_in, -1.0, w, P->s));
+    // true residual (the next cycle's right-hand side)
+    SDG_TRY(resid(x, xlo, w));
     SDG_TRY(project(w));
     SDG_TRY(vs_norms(P, S, w, beta));
+    std::vector<char> stag(nb, 0);
+    bool any_stag = false;
     for (int pb = 0; pb < nb; ++pb) {
       if (bn[pb] > 0.0 && std::isfinite(bn[pb])) rel[pb] = beta[pb] / bn[pb];
       if (!act[pb]) continue;
@@ -1291,22 +1707,217 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
         act[pb] = 0;
         continue;
       }
-      // rounding floor: the Arnoldi estimate fell below rtol but the true
-      // residual (computed in FP64, accurate only to about
-      // eps |K| |x| / |b|) did not follow, twice without halving
+      // stagnation: the Arnoldi estimate fell below rtol but the true
+      // residual did not follow, twice without halving
       if (est_conv[pb] && rel[pb] > 0.5 * prev_rel[pb]) ++gaps[pb];
       else gaps[pb] = 0;
       prev_rel[pb] = rel[pb];
       if (gaps[pb] >= 2) {
-        status[pb] = SDG_FLOOR;
-        act[pb] = 0;
+        stag[pb] = 1;
+        any_stag = true;
       } else if (its[pb] >= maxit) {
         status[pb] = SDG_NOT_CONVERGED;
         act[pb] = 0;
       }
     }
+    if (any_stag) {
+      // a stagnation is the rounding floor of the residual's evaluation only
+      // if the residual lies within a small factor of eps |K||x| / |b|;
+      // otherwise the iteration failed to converge.  Z is free between
+      // cycles and holds |K||x|.
+      std::vector<double> kx;
+      SDG_TRY(abs_apply(x, Z));
+      SDG_TRY(vs_norms(P, S, Z, kx));
+      for (int pb = 0; pb < nb; ++pb) {
+        if (!stag[pb]) continue;
+        const double fl = resid_eps(P) * kx[pb] / bn[pb];
+        status[pb] = rel[pb] <= 4.0 * fl ? SDG_FLOOR : SDG_NOT_CONVERGED;
+        act[pb] = 0;
+      }
+    }
   }
   return SDG_OK;
+}
+
+// Batched GCR(m) with right preconditioning (the generalised conjugate
+// residual method; flexible, so the preconditioner may change between
+// iterations), x0 = 0.  Iteration j: p = M^{-1} r, q = K p, q and p
+// orthogonalised against the earlier q (classical Gram-Schmidt twice, the
+// same coefficients applied to p), normalised by |q|, then alpha = r.q,
+// x += alpha p, r -= alpha q: |r| is the exact residual norm of the
+// iteration in exact arithmetic and is read back once per iteration.  A
+// problem whose |r| falls below rtol |b| stops (its q and p are masked to
+// zero from then on).  After m iterations, or when every problem stopped,
+// the cycle's correction is added to the iterate and the true residual is
+// formed by resid(x, xlo, r) (extended precision with xlo, as in fgmres):
+// restarts are steps of iterative refinement, and the stagnation and
+// floor logic is that of fgmres.  The paper runs GCR for both loops of its
+// six-inclusion experiment (Section 8.3).
+template <typename MV, typename PC, typename PJ, typename RS, typename AB>
+int gcr(sdg_problem* P, const VSpec& S, const GcrWork& W, const double* b_in, double* x, double* xlo, double rtol,
+        int maxit, MV matvec, PC prec, PJ project, RS resid, AB abs_apply, std::vector<int>& its,
+        std::vector<double>& rel, std::vector<int>& status) {
+  const int m = W.m, nb = P->nb;
+  const int64_t ldv = S.total;
+  double* hsq = W.coef;
+  double* hs = W.coef + nb;
+  double* rr = W.coef + 2 * (int64_t)nb;
+  double* alpha = W.coef + 3 * (int64_t)nb;
+  double* gsc = W.coef + 4 * (int64_t)nb;                // [nb][m] Gram-Schmidt coefficients
+  double* segb = W.coef + (4 + (int64_t)m) * nb;         // per-segment partials
+  SDG_TRY(vec_copy(S.total, b_in, W.r, P->s));
+  SDG_TRY(project(W.r));
+  std::vector<double> bn;
+  SDG_TRY(vs_norms(P, S, W.r, bn));
+  SDG_HIP(hipMemsetAsync(x, 0, S.total * sizeof(double), P->s));
+  if (xlo) SDG_HIP(hipMemsetAsync(xlo, 0, S.total * sizeof(double), P->s));
+  its.assign(nb, 0);
+  rel.assign(nb, 0.0);
+  status.assign(nb, SDG_OK);
+  std::vector<char> act(nb, 0);
+  for (int pb = 0; pb < nb; ++pb) {
+    if (!std::isfinite(bn[pb])) {
+      status[pb] = SDG_BREAKDOWN;
+    } else if (bn[pb] > 0.0) {
+      act[pb] = 1;
+      rel[pb] = 1.0;
+      status[pb] = SDG_NOT_CONVERGED;
+    }
+  }
+  std::vector<int> gaps(nb, 0);
+  std::vector<double> prev_rel(nb, 1.0);
+  std::vector<char> est_conv(nb, 0);
+  int total = 0;
+  while (true) {
+    bool any = false;
+    for (int pb = 0; pb < nb; ++pb) any = any || act[pb];
+    if (!any || total >= maxit) break;
+    // the correction of this cycle (x itself when not refining)
+    double* xc = xlo ? W.c : x;
+    if (xlo) SDG_HIP(hipMemsetAsync(W.c, 0, S.total * sizeof(double), P->s));
+    std::vector<int> di(nb);
+    for (int pb = 0; pb < nb; ++pb) {
+      di[pb] = act[pb] ? 0 : 1;
+      est_conv[pb] = 0;
+    }
+    SDG_TRY(to_dev(P, W.done, di.data(), nb * sizeof(int)));
+    bool all_done = false;
+    for (int j = 0; j < m && !all_done && total < maxit; ++j) {
+      double* pj = W.Pd + (int64_t)j * ldv;
+      double* qj = W.Q + (int64_t)j * ldv;
+      SDG_TRY(prec(W.r, pj));
+      SDG_TRY(project(pj));
+      SDG_TRY(matvec(pj, qj));
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        SDG_TRY(vs_dots_dev(P, S, j, W.Q, ldv, qj, gsc, segb));
+        SDG_TRY(vs_axpy(P, S, j, W.Q, ldv, gsc, qj));
+        SDG_TRY(vs_axpy(P, S, j, W.Pd, ldv, gsc, pj));
+      }
+      // |q| (zero for problems that stopped: their q and p become zero, so
+      // their alpha is zero and x, r stay put)
+      SDG_TRY(vs_dots_dev(P, S, 1, qj, 0, qj, hsq, segb));
+      SDG_TRY(norm_mask(nb, hsq, W.done, hs, P->s));
+      SDG_TRY(vs_div(P, S, hs, qj, qj));
+      SDG_TRY(vs_div(P, S, hs, pj, pj));
+      SDG_TRY(vs_dots_dev(P, S, 1, qj, 0, W.r, alpha, segb));
+      SDG_TRY(vs_combine(P, S, 1, pj, 0, alpha, xc));
+      SDG_TRY(vs_axpy(P, S, 1, qj, 0, alpha, W.r));
+      SDG_TRY(vs_dots_dev(P, S, 1, W.r, 0, W.r, rr, segb));
+      std::vector<double> hb(2 * (size_t)nb);
+      SDG_TRY(read_dev(P, hs, nb, hb.data()));
+      SDG_TRY(read_dev(P, rr, nb, hb.data() + nb));
+      ++total;
+      all_done = true;
+      bool changed = false;
+      for (int pb = 0; pb < nb; ++pb) {
+        if (di[pb]) continue;
+        ++its[pb];
+        const double est = std::sqrt(std::max(hb[nb + pb], 0.0)) / bn[pb];
+        if (!(hb[pb] > 0.0) || !std::isfinite(hb[pb]) || !std::isfinite(est)) {
+          status[pb] = SDG_BREAKDOWN;
+          act[pb] = 0;
+          di[pb] = 1;
+          changed = true;
+          continue;
+        }
+        if (est < rtol) est_conv[pb] = 1;
+        if (est < rtol || its[pb] >= maxit) {
+          di[pb] = 1;
+          changed = true;
+        }
+        all_done = all_done && di[pb];
+      }
+      if (changed) SDG_TRY(to_dev(P, W.done, di.data(), nb * sizeof(int)));
+    }
+    if (xlo) SDG_TRY(dd_accumulate(S.total, W.c, x, xlo, P->s));
+    // true residual, the next cycle's start
+    SDG_TRY(resid(x, xlo, W.r));
+    SDG_TRY(project(W.r));
+    std::vector<double> beta;
+    SDG_TRY(vs_norms(P, S, W.r, beta));
+    std::vector<char> stag(nb, 0);
+    bool any_stag = false;
+    for (int pb = 0; pb < nb; ++pb) {
+      if (bn[pb] > 0.0 && std::isfinite(bn[pb])) rel[pb] = beta[pb] / bn[pb];
+      if (!act[pb]) continue;
+      if (rel[pb] < rtol) {
+        status[pb] = SDG_OK;
+        act[pb] = 0;
+        continue;
+      }
+      if (est_conv[pb] && rel[pb] > 0.5 * prev_rel[pb]) ++gaps[pb];
+      else gaps[pb] = 0;
+      prev_rel[pb] = rel[pb];
+      if (gaps[pb] >= 2) {
+        stag[pb] = 1;
+        any_stag = true;
+      } else if (its[pb] >= maxit) {
+        status[pb] = SDG_NOT_CONVERGED;
+        act[pb] = 0;
+      }
+    }
+    if (any_stag) {
+      std::vector<double> kx;
+      SDG_TRY(abs_apply(x, W.Q));
+      SDG_TRY(vs_norms(P, S, W.Q, kx));
+      for (int pb = 0; pb < nb; ++pb) {
+        if (!stag[pb]) continue;
+        status[pb] = rel[pb] <= 4.0 * resid_eps(P) * kx[pb] / bn[pb] ? SDG_FLOOR : SDG_NOT_CONVERGED;
+        act[pb] = 0;
+      }
+    }
+  }
+  return SDG_OK;
+}
+
+// GCR workspace of the inner viscous solve (separate from the outer
+// solve's Krylov vectors, which are in use while the preconditioner runs)
+int ensure_gcr_inner(sdg_problem* P) {
+  if (P->gi.Q) return SDG_OK;
+  const int m = P->opt.restart;
+  const int64_t tot = P->nu * P->nb;
+  GcrWork& W = P->gi;
+  W.m = m;
+  SDG_TRY(palloc_t(P, &W.Q, (int64_t)m * tot));
+  SDG_TRY(palloc_t(P, &W.Pd, (int64_t)m * tot));
+  SDG_TRY(palloc_t(P, &W.r, tot));
+  SDG_TRY(palloc_t(P, &W.c, tot));
+  SDG_TRY(palloc_t(P, &W.coef, (int64_t)(4 * (m + 1) + 4) * P->nb));
+  SDG_TRY(palloc_t(P, &W.done, P->nb));
+  return SDG_OK;
+}
+// the outer solve's GCR workspace lives in the FGMRES buffers
+GcrWork outer_gcr_work(sdg_problem* P) {
+  GcrWork W;
+  W.m = P->opt.restart;
+  const int64_t tot = P->gn * P->nb;
+  W.Q = P->gV;
+  W.r = P->gV + (int64_t)W.m * tot;
+  W.Pd = P->gZ;
+  W.c = P->gw;
+  W.coef = P->gcoef;
+  W.done = P->gdone;
+  return W;
 }
 
 // Stokes operator K = [A B; B^T 0] on x = [u (all problems); p (all problems)]
@@ -1331,7 +1942,20 @@ int stokes_prec(sdg_problem* P, const double* v, double* z) {
   SDG_TRY(vec_axpby(U, 1.0, v, -1.0, P->gt, P->s));
   std::vector<int> its, st;
   std::vector<double> rel;
-  SDG_TRY(cg_solve(P, P->gt, z, P->opt.inner_rtol, P->opt.inner_max_it, its, rel, st));
+  if (P->opt.viscous_krylov == 2) {
+    // GCR for the inner solve (the paper's six-inclusion setting)
+    SDG_TRY(ensure_gcr_inner(P));
+    const VSpec S = viscous_spec(P);
+    auto mv = [&](const double* xx, double* yy) { return run_sip_apply(P, xx, yy); };
+    auto pc = [&](const double* vv, double* zz) { return vcycle(P, vv, zz); };
+    auto pj = [&](double*) { return SDG_OK; };
+    auto rs = [&](const double* xx, const double*, double* w) { return run_sip_residual(P, P->gt, xx, w); };
+    auto ab = [&](const double* xx, double* yy) { return run_ext(P, false, true, nullptr, xx, nullptr, yy); };
+    SDG_TRY(gcr(P, S, P->gi, P->gt, z, nullptr, P->opt.inner_rtol, P->opt.inner_max_it, mv, pc, pj, rs, ab, its,
+                rel, st));
+  } else {
+    SDG_TRY(cg_solve(P, P->gt, z, P->opt.inner_rtol, P->opt.inner_max_it, its, rel, st));
+  }
   for (int pb = 0; pb < P->nb; ++pb) {
     P->inner_total[pb] += its[pb];
     P->inner_max[pb] = std::max(P->inner_max[pb], its[pb]);
@@ -1432,6 +2056,8 @@ static bool opts_ok(const sdg_options* o) {
   if (o->coarsest_n < 1 || o->eig_steps < 1 || o->eig_steps > 30) return false;
   if (!(o->cheb_lo > 0) || !(o->cheb_hi > o->cheb_lo)) return false;
   if (o->prec_smoother < 0 || o->prec_smoother > 2 || o->prec_apply < 0 || o->prec_apply > 1) return false;
+  if (o->refine < 0 || o->refine > 1 || o->viscous_krylov < 0 || o->viscous_krylov > 2) return false;
+  if (o->outer_krylov < 0 || o->outer_krylov > 1) return false;
   return true;
 }
 
@@ -1466,8 +2092,10 @@ size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, i
   b += RED_SCRATCH * 8 + (SC_COUNT_FIXED + std::max(opts->restart, opts->eig_steps) + 4) * nb * 8 * 2 + nb * 4;
   b += nb * nu * 8 * 4;  // CG
   const int64_t n = stokes ? nu + np : nu;
-  if (stokes || opts->viscous_krylov == 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
+  if (stokes || opts->viscous_krylov >= 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
+  if (stokes && opts->viscous_krylov == 2) b += nb * (2 * (int64_t)opts->restart + 2) * nu * 8;  // inner GCR
   b += nb * (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
+  if (opts->refine) b += nb * 3 * n * 8;  // low part of the iterate, refinement residual and correction
   return b;
 }
 
@@ -1815,59 +2443,96 @@ int sdg_assemble_rhs(sdg_problem* P, const double* f, const double* g, double* F
   return rhs_assemble(P->M, P->k, P->nb, P->eta, f, g, F, G, P->s);
 }
 
-int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, double* u, sdg_stats* st) {
-  PCHECK(f, u);
+}  // extern "C"
+
+namespace {
+
+// Viscous solve behind sdg_solve_viscous_dev / _ext_dev: u (and, for
+// opts.refine, the low part ulo; may be null) of u = A^{-1} F.
+int solve_viscous_impl(sdg_problem* P, const double* f, const double* g, double* u, double* ulo, sdg_stats* st) {
   const double t0 = now_ms();
   const int64_t U = P->nu * P->nb;
+  const bool refine = P->opt.refine != 0;
   double* F = nullptr;
   double* G = nullptr;
+  double* xl = nullptr;
   const int64_t nG = std::max<int64_t>(P->np * P->nb, 1);
-  if (tmp_get(P, &F, U) < 0 || tmp_get(P, &G, nG) < 0) {
+  const bool own_lo = refine && !ulo;
+  if (tmp_get(P, &F, U) < 0 || tmp_get(P, &G, nG) < 0 || (own_lo && tmp_get(P, &xl, U) < 0)) {
     tmp_put(P, F, U);
     tmp_put(P, G, nG);
+    tmp_put(P, xl, U);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
+  if (!own_lo) xl = ulo;
   std::vector<int> its, status;
   std::vector<double> rel;
+  const VSpec S = viscous_spec(P);
   int rc = rhs_assemble(P->M, P->k, P->nb, P->eta, f, g, F, G, P->s);
   if (rc >= 0) {
-    if (P->opt.viscous_krylov == 1) {
-      const VSpec S = viscous_spec(P);
+    if (P->opt.viscous_krylov == 2) {
+      rc = ensure_gmres(P, P->nu);
       auto mv = [&](const double* x, double* y) { return run_sip_apply(P, x, y); };
       auto pc = [&](const double* v, double* z) { return vcycle(P, v, z); };
       auto pj = [&](double*) { return SDG_OK; };
-      rc = fgmres(P, S, F, u, P->opt.rtol, P->opt.max_it, mv, pc, pj, its, rel, status);
+      auto rs = [&](const double* x, const double* lo, double* w) {
+        if (refine) return run_ext(P, false, false, F, x, lo, w);
+        return run_sip_residual(P, F, x, w);
+      };
+      auto ab = [&](const double* x, double* y) { return run_ext(P, false, true, nullptr, x, nullptr, y); };
+      if (rc >= 0)
+        rc = gcr(P, S, outer_gcr_work(P), F, u, refine ? xl : nullptr, P->opt.rtol, P->opt.max_it, mv, pc, pj, rs,
+                 ab, its, rel, status);
+    } else if (P->opt.viscous_krylov == 1) {
+      auto mv = [&](const double* x, double* y) { return run_sip_apply(P, x, y); };
+      auto pc = [&](const double* v, double* z) { return vcycle(P, v, z); };
+      auto pj = [&](double*) { return SDG_OK; };
+      auto rs = [&](const double* x, const double* lo, double* w) {
+        if (refine) return run_ext(P, false, false, F, x, lo, w);
+        return run_sip_residual(P, F, x, w);
+      };
+      auto ab = [&](const double* x, double* y) { return run_ext(P, false, true, nullptr, x, nullptr, y); };
+      rc = fgmres(P, S, F, u, refine ? xl : nullptr, P->opt.rtol, P->opt.max_it, mv, pc, pj, rs, ab, its, rel,
+                  status);
+    } else if (refine) {
+      rc = cg_refine(P, F, u, xl, P->opt.rtol, P->opt.max_it, its, rel, status);
     } else {
       rc = cg_solve(P, F, u, P->opt.rtol, P->opt.max_it, its, rel, status);
     }
   }
-  // true residual ||F - A u|| / ||F|| per problem
+  // true residual ||F - A u|| / ||F|| per problem (extended precision with
+  // the low part when refining)
   if (rc >= 0) {
-    const VSpec S = viscous_spec(P);
     std::vector<double> fn, rn;
     rc = vs_norms(P, S, F, fn);
-    if (rc >= 0) rc = run_sip_residual(P, F, u, P->vr);
+    if (rc >= 0) rc = refine ? run_ext(P, false, false, F, u, xl, P->vr) : run_sip_residual(P, F, u, P->vr);
     if (rc >= 0) rc = vs_norms(P, S, P->vr, rn);
     if (rc >= 0)
       for (int pb = 0; pb < P->nb; ++pb) rel[pb] = fn[pb] > 0 ? rn[pb] / fn[pb] : 0.0;
   }
+  if (rc >= 0 && ulo && !refine && hipMemsetAsync(ulo, 0, U * sizeof(double), P->s) != hipSuccess)
+    rc = SDG_ERR_DEVICE;
   tmp_put(P, F, U);  // synchronises the stream first
   tmp_put(P, G, nG);
+  if (own_lo) tmp_put(P, xl, U);
   if (rc < 0) return rc;
   return fill_stats(P, st, status, its, rel, t0, false);
 }
 
-int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, double* u, double* p, sdg_stats* st) {
-  PCHECK(f, u, p);
+int solve_stokes_impl(sdg_problem* P, const double* f, const double* g, double* u, double* ulo, double* p,
+                      double* plo, sdg_stats* st) {
   const double t0 = now_ms();
   const VSpec S = stokes_spec(P);
   const int64_t U = P->nu * P->nb;
+  const bool refine = P->opt.refine != 0;
   double* b = nullptr;
   double* x = nullptr;
-  if (tmp_get(P, &b, S.total) < 0 || tmp_get(P, &x, S.total) < 0) {
+  double* xl = nullptr;
+  if (tmp_get(P, &b, S.total) < 0 || tmp_get(P, &x, S.total) < 0 || tmp_get(P, &xl, S.total) < 0) {
     tmp_put(P, b, S.total);
     tmp_put(P, x, S.total);
+    tmp_put(P, xl, S.total);
     set_error("allocation failed");
     return SDG_ERR_NOMEM;
   }
@@ -1881,19 +2546,78 @@ int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, doubl
     auto mv = [&](const double* xx, double* yy) { return stokes_matvec(P, xx, yy); };
     auto pc = [&](const double* v, double* z) { return stokes_prec(P, v, z); };
     auto pj = [&](double* v) { return stokes_project(P, v); };
-    rc = fgmres(P, S, b, x, P->opt.rtol, P->opt.max_it, mv, pc, pj, its, rel, status);
+    auto rs = [&](const double* xx, const double* lo, double* w) {
+      if (refine) return run_ext(P, true, false, b, xx, lo, w);
+      SDG_TRY(stokes_matvec(P, xx, w));
+      return vec_axpby(S.total, 1.0, b, -1.0, w, P->s);
+    };
+    auto ab = [&](const double* xx, double* yy) { return run_ext(P, true, true, nullptr, xx, nullptr, yy); };
+    if (P->opt.outer_krylov == 1)
+      rc = gcr(P, S, outer_gcr_work(P), b, x, refine ? xl : nullptr, P->opt.rtol, P->opt.max_it, mv, pc, pj, rs, ab,
+               its, rel, status);
+    else
+      rc = fgmres(P, S, b, x, refine ? xl : nullptr, P->opt.rtol, P->opt.max_it, mv, pc, pj, rs, ab, its, rel,
+                  status);
   }
   if (rc >= 0) {
+    // the pressure of the pair: the constant is fixed on its high part
     rc = stokes_project(P, x);
     if (rc >= 0 && hipMemcpyAsync(u, x, U * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
     if (rc >= 0 && P->np > 0 &&
         hipMemcpyAsync(p, x + U, P->np * P->nb * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess)
       rc = SDG_ERR_DEVICE;
+    if (rc >= 0 && ulo) {
+      if (refine) {
+        if (hipMemcpyAsync(ulo, xl, U * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
+      } else if (hipMemsetAsync(ulo, 0, U * sizeof(double), P->s) != hipSuccess) {
+        rc = SDG_ERR_DEVICE;
+      }
+    }
+    if (rc >= 0 && plo && P->np > 0) {
+      if (refine) {
+        if (hipMemcpyAsync(plo, xl + U, P->np * P->nb * sizeof(double), hipMemcpyDeviceToDevice, P->s) != hipSuccess)
+          rc = SDG_ERR_DEVICE;
+      } else if (hipMemsetAsync(plo, 0, P->np * P->nb * sizeof(double), P->s) != hipSuccess) {
+        rc = SDG_ERR_DEVICE;
+      }
+    }
   }
   tmp_put(P, b, S.total);  // synchronises the stream first
   tmp_put(P, x, S.total);
+  tmp_put(P, xl, S.total);
   if (rc < 0) return rc;
   return fill_stats(P, st, status, its, rel, t0, true);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdg_solve_viscous_dev(sdg_problem* P, const double* f, const double* g, double* u, sdg_stats* st) {
+  PCHECK(f, u);
+  return solve_viscous_impl(P, f, g, u, nullptr, st);
+}
+int sdg_solve_viscous_ext_dev(sdg_problem* P, const double* f, const double* g, double* u, double* ulo,
+                              sdg_stats* st) {
+  PCHECK(f, u);
+  return solve_viscous_impl(P, f, g, u, ulo, st);
+}
+int sdg_solve_stokes_dev(sdg_problem* P, const double* f, const double* g, double* u, double* p, sdg_stats* st) {
+  PCHECK(f, u, p);
+  return solve_stokes_impl(P, f, g, u, nullptr, p, nullptr, st);
+}
+int sdg_solve_stokes_ext_dev(sdg_problem* P, const double* f, const double* g, double* u, double* ulo, double* p,
+                             double* plo, sdg_stats* st) {
+  PCHECK(f, u, p);
+  return solve_stokes_impl(P, f, g, u, ulo, p, plo, st);
+}
+int sdg_residual_ext(sdg_problem* P, int stokes, const double* b, const double* xh, const double* xl, double* r) {
+  PCHECK(b, xh, r);
+  return run_ext(P, stokes != 0, false, b, xh, xl, r);
+}
+int sdg_abs_apply(sdg_problem* P, int stokes, const double* x, double* y) {
+  PCHECK(x, y);
+  return run_ext(P, stokes != 0, true, nullptr, x, nullptr, y);
 }
 
 static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta,
@@ -1954,6 +2678,158 @@ static int host_solve(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opt
   for (int i = 0; i < 5; ++i)
     if (qs[i]) ctx_put(ctx, qs[i], bytes_of(ns[i]));
   return rc;
+}
+
+int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const sdg_options* opts,
+                            const double* const* eta, const double* const* f, double* const* u,
+                            double* const* u_lo, sdg_stats* stats) {
+  if (!ctx || n < 0 || (n > 0 && (!meshes || !eta || !f || !u))) {
+    set_error("invalid argument");
+    return SDG_ERR_INVALID;
+  }
+  if (n == 0) return SDG_OK;
+  sdg_options o;
+  if (opts) o = *opts;
+  else sdg_options_default(&o);
+  for (int i = 0; i < n; ++i)
+    if (!mesh_ok(&meshes[i]) || !eta[i] || !f[i] || !u[i]) {
+      set_error("invalid mesh or NULL array of request " + std::to_string(i));
+      return SDG_ERR_INVALID;
+    }
+  SDG_HIP(hipSetDevice(ctx->device));
+  const double t0 = now_ms();
+  // requests of identical mesh and order form one batched problem
+  std::map<std::string, std::vector<int>> bykey;
+  for (int i = 0; i < n; ++i) {
+    const sdg_mesh& m = meshes[i];
+    char key[160];
+    std::snprintf(key, sizeof(key), "%d/%d/%d/%.17g/%.17g/%d%d%d%d", m.k, m.nx, m.ny, m.lx, m.ly, m.bc[0], m.bc[1],
+                  m.bc[2], m.bc[3]);
+    bykey[key].push_back(i);
+  }
+  struct Grp {
+    std::vector<int> idx;
+    sdg_problem* P = nullptr;
+    double *de = nullptr, *df = nullptr, *dF = nullptr, *dG = nullptr, *du = nullptr, *dul = nullptr;
+    int64_t ne = 0, nu = 0, np = 0;
+  };
+  std::vector<Grp> G;
+  for (auto& kv : bykey) {
+    G.emplace_back();
+    G.back().idx = kv.second;
+  }
+  hipStream_t s = nullptr;
+  SDG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  auto bytes_of = [](int64_t cnt) { return cache_size((size_t)std::max<int64_t>(cnt, 1) * sizeof(double)); };
+  int rc = SDG_OK;
+  for (Grp& g : G) {
+    const sdg_mesh& m = meshes[g.idx[0]];
+    const int nb = (int)g.idx.size();
+    g.ne = (int64_t)m.nx * m.ny;
+    g.nu = g.ne * 2 * (m.k + 1) * (m.k + 1);
+    g.np = g.ne * m.k * m.k;
+    for (double** q : {&g.de}) rc = rc < 0 ? rc : ctx_get(ctx, bytes_of(nb * g.ne), (void**)q);
+    for (double** q : {&g.df, &g.dF, &g.du, &g.dul}) rc = rc < 0 ? rc : ctx_get(ctx, bytes_of(nb * g.nu), (void**)q);
+    if (rc >= 0) rc = ctx_get(ctx, bytes_of(nb * g.np), (void**)&g.dG);
+    for (int i = 0; i < nb && rc >= 0; ++i) {
+      const int r = g.idx[i];
+      if (hipMemcpyAsync(g.de + i * g.ne, eta[r], g.ne * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(g.df + i * g.nu, f[r], g.nu * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("host to device copy failed");
+        rc = SDG_ERR_DEVICE;
+      }
+    }
+    if (rc >= 0) rc = sdg_problem_create_batch(ctx, &m, &o, nb, g.de, s, &g.P);
+    if (rc >= 0) rc = rhs_assemble(g.P->M, g.P->k, nb, g.P->eta, g.df, nullptr, g.dF, g.dG, s);
+    if (rc < 0) break;
+  }
+  // solve: CG groups in lockstep (combined graph per iteration); other
+  // Krylov choices group after group
+  std::vector<std::vector<int>> its(G.size()), status(G.size());
+  std::vector<std::vector<double>> rel(G.size());
+  if (rc >= 0) {
+    MultiGraphs MG;
+    if (o.viscous_krylov == 0 && o.refine) {
+      std::vector<RefineState> R(G.size());
+      for (size_t i = 0; i < G.size(); ++i) {
+        R[i].P = G[i].P;
+        R[i].F = G[i].dF;
+        R[i].xh = G[i].du;
+        R[i].xl = G[i].dul;
+      }
+      rc = cg_refine_multi(R, o.rtol, o.max_it, MG);
+      for (size_t i = 0; i < G.size() && rc >= 0; ++i) {
+        its[i] = R[i].its;
+        rel[i] = R[i].rel;
+        status[i] = R[i].status;
+      }
+    } else if (o.viscous_krylov == 0) {
+      std::vector<CgRun> runs(G.size());
+      for (size_t i = 0; i < G.size() && rc >= 0; ++i) {
+        rc = cg_start(runs[i], G[i].P, G[i].dF, G[i].du, o.rtol, o.max_it, nullptr);
+        if (rc >= 0 && hipMemsetAsync(G[i].dul, 0, G[i].idx.size() * G[i].nu * 8, s) != hipSuccess) rc = SDG_ERR_DEVICE;
+      }
+      if (rc >= 0) rc = cg_multi(runs, MG);
+      for (size_t i = 0; i < G.size() && rc >= 0; ++i) {
+        its[i] = runs[i].its;
+        status[i] = runs[i].status;
+      }
+    } else {
+      for (size_t i = 0; i < G.size() && rc >= 0; ++i) {
+        std::vector<sdg_stats> st(G[i].idx.size());
+        rc = solve_viscous_impl(G[i].P, G[i].df, nullptr, G[i].du, G[i].dul, st.data());
+        for (size_t j = 0; j < st.size() && rc >= 0; ++j) {
+          its[i].push_back(st[j].outer_its);
+          status[i].push_back(st[j].status);
+        }
+      }
+    }
+  }
+  // true residuals (extended with refinement), results to the host
+  for (size_t i = 0; i < G.size() && rc >= 0; ++i) {
+    Grp& g = G[i];
+    sdg_problem* P = g.P;
+    const VSpec S = viscous_spec(P);
+    std::vector<double> fn, rn;
+    rc = vs_norms(P, S, g.dF, fn);
+    if (rc >= 0)
+      rc = o.refine ? run_ext(P, false, false, g.dF, g.du, g.dul, P->vr) : run_sip_residual(P, g.dF, g.du, P->vr);
+    if (rc >= 0) rc = vs_norms(P, S, P->vr, rn);
+    if (rc < 0) break;
+    rel[i].assign(g.idx.size(), 0.0);
+    for (size_t j = 0; j < g.idx.size(); ++j) rel[i][j] = fn[j] > 0 ? rn[j] / fn[j] : 0.0;
+    std::vector<sdg_stats> st(g.idx.size());
+    fill_stats(P, st.data(), status[i], its[i], rel[i], t0, false);
+    for (size_t j = 0; j < g.idx.size() && rc >= 0; ++j) {
+      const int r = g.idx[j];
+      if (stats) stats[r] = st[j];
+      if (hipMemcpyAsync(u[r], g.du + j * g.nu, g.nu * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          (u_lo && u_lo[r] &&
+           hipMemcpyAsync(u_lo[r], g.dul + j * g.nu, g.nu * 8, hipMemcpyDeviceToHost, s) != hipSuccess)) {
+        (void)hipGetLastError();
+        set_error("device to host copy failed");
+        rc = SDG_ERR_DEVICE;
+      }
+    }
+    if (rc >= 0 && hipStreamSynchronize(s) != hipSuccess) rc = SDG_ERR_DEVICE;
+  }
+  int worst = SDG_OK;
+  auto rank = [](int v) { return v == SDG_BREAKDOWN ? 3 : v == SDG_NOT_CONVERGED ? 2 : v == SDG_FLOOR ? 1 : 0; };
+  for (auto& sv : status)
+    for (int v : sv)
+      if (rank(v) > rank(worst)) worst = v;
+  (void)hipStreamSynchronize(s);
+  for (Grp& g : G) {
+    sdg_problem_destroy(g.P);  // drains the stream
+    const int nb = (int)g.idx.size();
+    if (g.de) ctx_put(ctx, g.de, bytes_of(nb * g.ne));
+    for (double* q : {g.df, g.dF, g.du, g.dul})
+      if (q) ctx_put(ctx, q, bytes_of(nb * g.nu));
+    if (g.dG) ctx_put(ctx, g.dG, bytes_of(nb * g.np));
+  }
+  (void)hipStreamDestroy(s);
+  return rc < 0 ? rc : worst;
 }
 
 int sdg_solve_viscous(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, const double* eta,

@@ -304,3 +304,39 @@ def random_problem(n, k, seed, contrast=1e4, bc=(NAVIER,) * 4):
     eta = 10.0 ** rng.uniform(0.0, np.log10(contrast), n * n)
     f = rng.normal(0.0, 1.0, (n * n, 2, k + 1, k + 1))
     return Problem(n, n, k, eta, f, None, bc=tuple(bc), name=f"random-{n}-k{k}-s{seed}")
+
+
+def c2_variant(seed, n=64, k=4, eta_in=1e4):
+    """Seeded variants of the single-inclusion workload for batches of
+    distinct problems: seed 0 is the centred disk of radius 0.25; other
+    seeds move the centre uniformly within 0.1 of (0.5, 0.5) and draw the
+    radius from U[0.2, 0.3].  Viscosity eta_in inside, 1 outside (element
+    maximum), force (0, -1) on elements fully inside; Navier sides."""
+    if seed == 0:
+        cx, cy, r = 0.5, 0.5, 0.25
+    else:
+        rng = np.random.default_rng(20_000 + seed)
+        cx, cy = rng.uniform(0.4, 0.6, 2)
+        r = float(rng.uniform(0.2, 0.3))
+    eta, inside = inclusion_fields(n, n, [(cx, cy, r, eta_in)])
+    f = constant_force_modes(np.zeros(n * n), -inside.astype(float), n, n, k)
+    return Problem(n, n, k, eta, f, None, name=f"inclusion-{n}x{n}-k{k}-s{seed}",
+                   meta={"eta_in": eta_in, "r": r, "centre": (float(cx), float(cy)), "seed": seed})
+
+
+# centres and radii of the six sedimenting inclusions (Section 8.3)
+SINKERS = [(0.84, 0.39, 0.089), (0.79, 0.91, 0.059), (0.33, 0.76, 0.063),
+           (0.55, 0.47, 0.081), (0.14, 0.60, 0.05), (0.24, 0.13, 0.09)]
+
+
+def six_sinkers(n, k, eta2=1e6, rho2=1.2, eta1=1.0, rho1=1.0, g=10.0):
+    """The six sedimenting inclusions of Section 8.3: viscosity eta2 and
+    density rho2 inside, eta1 and rho1 outside, force (0, -g rho); the
+    element takes the maximum viscosity and the minimum density over its
+    closed area (rho2 only on elements fully inside an inclusion, as
+    rho2 > rho1); Neumann on the top side, Navier on the others."""
+    eta, inside = inclusion_fields(n, n, [(cx, cy, r, eta2) for cx, cy, r in SINKERS], background=eta1)
+    rho = np.where(inside, rho2, rho1)
+    f = constant_force_modes(np.zeros(n * n), -g * rho, n, n, k)
+    return Problem(n, n, k, eta, f, None, bc=(NAVIER, NAVIER, NAVIER, NEUMANN),
+                   name=f"sinkers-{n}x{n}-k{k}-eta{eta2:g}", meta={"eta2": eta2, "rho2": rho2, "g": g})

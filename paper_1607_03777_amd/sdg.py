@@ -33,7 +33,7 @@ class sdg_options(ctypes.Structure):
                 ("cheb_hi", ctypes.c_double), ("prec_smoother", ctypes.c_int32),
                 ("prec_apply", ctypes.c_int32), ("viscous_krylov", ctypes.c_int32),
                 ("dedup", ctypes.c_int32), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("refine", ctypes.c_int32), ("outer_krylov", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class sdg_stats(ctypes.Structure):
@@ -98,6 +98,11 @@ PROTOTYPES = {
     "sdg_assemble_rhs": (I, [P, P, P, P, P]),
     "sdg_solve_viscous_dev": (I, [P, P, P, P, STATS]),
     "sdg_solve_stokes_dev": (I, [P, P, P, P, P, STATS]),
+    "sdg_solve_viscous_ext_dev": (I, [P, P, P, P, P, STATS]),
+    "sdg_solve_stokes_ext_dev": (I, [P, P, P, P, P, P, P, STATS]),
+    "sdg_residual_ext": (I, [P, I, P, P, P, P]),
+    "sdg_abs_apply": (I, [P, I, P, P]),
+    "sdg_solve_viscous_batch": (I, [P, I, MESH, OPTS, P, P, P, P, STATS]),
     "sdg_solve_viscous": (I, [P, MESH, OPTS, P, P, P, P, STATS]),
     "sdg_solve_stokes": (I, [P, MESH, OPTS, P, P, P, P, P, STATS]),
     "sdg_uniform_pm1": (I, [P, ctypes.c_uint64, ctypes.c_int64, P, P]),
@@ -336,6 +341,46 @@ def sdg_solve_stokes_dev(prob, f, g, u, p):
     st = (sdg_stats * nb)()
     rc = check(lib().sdg_solve_stokes_dev(prob, ptr(f), ptr(g), ptr(u), ptr(p), st))
     return rc, _stats_out(st, nb)
+
+
+def sdg_solve_viscous_ext_dev(prob, f, g, u_hi, u_lo):
+    nb = sdg_problem_batch(prob)
+    st = (sdg_stats * nb)()
+    rc = check(lib().sdg_solve_viscous_ext_dev(prob, ptr(f), ptr(g), ptr(u_hi), ptr(u_lo), st))
+    return rc, _stats_out(st, nb)
+
+
+def sdg_solve_stokes_ext_dev(prob, f, g, u_hi, u_lo, p_hi, p_lo):
+    nb = sdg_problem_batch(prob)
+    st = (sdg_stats * nb)()
+    rc = check(lib().sdg_solve_stokes_ext_dev(prob, ptr(f), ptr(g), ptr(u_hi), ptr(u_lo), ptr(p_hi),
+                                              ptr(p_lo), st))
+    return rc, _stats_out(st, nb)
+
+
+def sdg_residual_ext(prob, stokes, b, x_hi, x_lo, r):
+    return check(lib().sdg_residual_ext(prob, int(stokes), ptr(b), ptr(x_hi), ptr(x_lo), ptr(r)))
+
+
+def sdg_abs_apply(prob, stokes, x, y):
+    return check(lib().sdg_abs_apply(prob, int(stokes), ptr(x), ptr(y)))
+
+
+def sdg_solve_viscous_batch(ctx, meshes, opts, etas, fs, with_lo=False):
+    """n solves of (possibly) different meshes and orders; host numpy
+    inputs.  Returns (rc, [u_i], [u_lo_i] or None, [stats_i])."""
+    n = len(meshes)
+    marr = (sdg_mesh * n)(*meshes)
+    etas = [np.ascontiguousarray(e, dtype=np.float64) for e in etas]
+    fs = [np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in fs]
+    us = [np.empty(f.size) for f in fs]
+    los = [np.empty(f.size) for f in fs] if with_lo else None
+    PA = ctypes.c_void_p * n
+    st = (sdg_stats * n)()
+    rc = check(lib().sdg_solve_viscous_batch(ctx, n, marr, ctypes.byref(opts), PA(*[e.ctypes.data for e in etas]),
+                                             PA(*[f.ctypes.data for f in fs]), PA(*[u.ctypes.data for u in us]),
+                                             PA(*[l.ctypes.data for l in los]) if with_lo else None, st))
+    return rc, us, los, [st[i].as_dict() for i in range(n)]
 
 
 def sdg_solve_viscous(ctx, mesh, opts, eta, f, g, u):

@@ -117,23 +117,28 @@ def test_sampled_apply_residual_blockjacobi(sdg, ctx, torch, n, k, nbatch):
 
 @pytest.mark.parametrize("k", [4])
 def test_fullsize_viscous_solve_true_residual(sdg, ctx, torch, k):
-    """256 x 256 random-inclusion viscous solve (log10 viscosity in [-3, 3]):
-    converged to 1e-8, or stopped at the FP64 floor; the true residual with
-    the (sample-pinned) operator agrees with the reported one."""
+    """256 x 256 random-inclusion viscous solve (log10 viscosity in [-3, 3])
+    with extended refinement: converged (status 0) to rtol 1e-8 on the
+    double-FP64 pair, a residual that FP64 cannot reach at this size; the
+    reported residual equals a recomputation through the extended residual
+    entry point, whose kernel the extended parity tests pin against the
+    long-double oracle."""
     n = 256
     prob = gen.random_inclusions(n, k, seed=0)
     print(f"[case] full-size viscous solve n={n} k={k}", flush=True)
-    P = sdg.Problem(ctx, n, n, k, prob.eta, rtol=1e-8, max_it=2000)
+    P = sdg.Problem(ctx, n, n, k, prob.eta, rtol=1e-8, max_it=3000, refine=1)
     f = dev(prob.f.reshape(-1))
-    u, st = P.solve_viscous(f)
-    assert st["status"] in (0, sdg.FLOOR), st
+    u, ul = P.zeros(P.nu), P.zeros(P.nu)
+    rc, st = sdg.sdg_solve_viscous_ext_dev(P.h, f, None, u, ul)
+    print(f"[fullsize] {st}", flush=True)
+    assert st["status"] == 0, st
     F = P.zeros(P.nu)
     G = P.zeros(max(P.np, 1))
     sdg.sdg_assemble_rhs(P.h, f, None, F, G)
     r = P.zeros(P.nu)
-    sdg.sdg_residual_viscous(P.h, F, u, r)
+    sdg.sdg_residual_ext(P.h, 0, F, u, ul, r)
     torch.cuda.synchronize()
     rel = float(r.norm() / F.norm())
-    assert rel <= 2e-8 or st["status"] == sdg.FLOOR, rel  # CG stops on its recursive residual
-    assert abs(rel - st["rel_residual"]) <= 0.05 * rel + 1e-15
+    assert rel <= 1e-8, rel
+    assert abs(rel - st["rel_residual"]) <= 1e-3 * rel
     P.close()

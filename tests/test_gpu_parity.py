@@ -304,33 +304,62 @@ def test_viscous_solve_parity(sdg, ctx, torch, n, k, contrast, bc, tol):
 
 def test_stokes_manufactured(sdg, ctx, torch):
     """Exact polynomial Stokes solution with Dirichlet data (velocity Q_2,
-    pressure Q_1): the discrete solution is the exact one."""
+    pressure Q_1): the discrete solution is the exact one.  The pressure
+    amplifies the residual by about 2e5 here (measured: a residual of 5e-13
+    leaves 8e-8 in p, 9e-15 leaves 2e-9), so the solve asks the extended
+    refinement for rtol 1e-14; the FP64 output is then the exact
+    coefficients to 1e-10 (velocity) and 5e-9 (pressure)."""
     P0 = gen.manufactured_stokes(8, 2)
-    P = make_problem(sdg, ctx, 8, 8, 2, P0.eta, P0.bc, rtol=1e-12, inner_rtol=1e-6,
-                     coarsest_n=4, max_it=400)
+    P = make_problem(sdg, ctx, 8, 8, 2, P0.eta, P0.bc, rtol=1e-14, inner_rtol=1e-6,
+                     coarsest_n=4, max_it=400, refine=1)
     u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)), dev(P0.g.reshape(-1)))
     assert st["status"] == 0, st
     ue, pe = P0.meta["u_exact"], P0.meta["p_exact"]
-    assert np.linalg.norm(host(u) - ue) <= 1e-8 * np.linalg.norm(ue), st
-    assert np.linalg.norm(host(p) - pe) <= 1e-6 * np.linalg.norm(pe), st
+    eu = np.linalg.norm(host(u) - ue) / np.linalg.norm(ue)
+    ep = np.linalg.norm(host(p) - pe) / np.linalg.norm(pe)
+    print(f"[manufactured] velocity {eu:.2e} pressure {ep:.2e} {st}", flush=True)
+    assert eu <= 1e-10 and ep <= 5e-9, st
     P.close()
 
 
-# rtol: the smallest true residual FGMRES reaches in FP64 on each case (the
-# Neumann case stagnates near 3e-12)
-@pytest.mark.parametrize("n,k,ein,bc,rtol", [(8, 2, 1e2, (NAVIER,) * 4, 1e-12),
-                                            (6, 3, 1e3, (NAVIER, NAVIER, NAVIER, NEUMANN), 1e-11)])
-def test_stokes_solve_parity(sdg, ctx, torch, n, k, ein, bc, rtol):
+# Against the refined (long-double) oracle solution: the FP64 LU's own
+# pressure carries about 1e-7 relative error on these cases, so it cannot
+# serve as the reference for a tight pressure bound.  rtol 1e-11 on the
+# extended residual; velocity 1e-9, pressure 1e-8.
+@pytest.mark.parametrize("n,k,ein,bc", [(8, 2, 1e2, (NAVIER,) * 4),
+                                       (6, 3, 1e3, (NAVIER, NAVIER, NAVIER, NEUMANN))])
+def test_stokes_solve_parity(sdg, ctx, torch, n, k, ein, bc):
+    from oracle import refine as rf
     P0 = gen.single_inclusion(n, k, eta_in=ein)
     m = Mesh(n, n, k, bc=bc)
-    ud, pd = solve_stokes(m, P0.eta, P0.f)
-    P = make_problem(sdg, ctx, n, n, k, P0.eta, bc, rtol=rtol, inner_rtol=1e-6, coarsest_n=4,
-                     max_it=600)
+    ud, pd = rf.solve_stokes_ext(m, P0.eta, P0.f, method="lu")
+    ud, pd = ud.astype(np.float64), pd.astype(np.float64)
+    P = make_problem(sdg, ctx, n, n, k, P0.eta, bc, rtol=1e-11, inner_rtol=1e-6, coarsest_n=4,
+                     max_it=600, refine=1)
     u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)))
-    assert st["status"] in (0, sdg.FLOOR), st
-    assert np.linalg.norm(host(u) - ud) <= 1e-9 * np.linalg.norm(ud), st
-    # the pressure is determined through B only: one more order of κ
-    assert np.linalg.norm(host(p) - pd) <= 1e-6 * np.linalg.norm(pd), st
+    assert st["status"] == 0, st
+    eu = np.linalg.norm(host(u) - ud) / np.linalg.norm(ud)
+    ep = np.linalg.norm(host(p) - pd) / np.linalg.norm(pd)
+    print(f"[stokes parity] velocity {eu:.2e} pressure {ep:.2e} {st}", flush=True)
+    assert eu <= 1e-9 and ep <= 1e-8, st
+    P.close()
+
+
+# The FP64 path without refinement: it may stop at the FP64 floor, and the
+# library reports SDG_FLOOR only within a small factor of the floor
+# estimate eps |K||x| / |b| (checked here with the same estimate).
+def test_stokes_fp64_floor_is_the_floor(sdg, ctx, torch):
+    P0 = gen.single_inclusion(16, 4, eta_in=1e4)
+    P = make_problem(sdg, ctx, 16, 16, 4, P0.eta, rtol=1e-13, inner_rtol=1e-3, coarsest_n=4, max_it=600)
+    u, p, st = P.solve_stokes(dev(P0.f.reshape(-1)))
+    assert st["status"] == sdg.FLOOR, st
+    x = torch.cat([u, p])
+    y = torch.zeros_like(x)
+    sdg.sdg_abs_apply(P.h, 1, x, y)
+    torch.cuda.synchronize()
+    floor = 2.0 ** -53 * float(y.norm()) / float(np.linalg.norm(P0.f))
+    print(f"[fp64 floor] residual {st['rel_residual']:.2e} floor estimate {floor:.2e}", flush=True)
+    assert st["rel_residual"] <= 4 * floor
     P.close()
 
 
@@ -428,41 +457,117 @@ def test_batch_viscous_matches_solo_and_oracle(sdg, ctx, torch):
 
 
 def test_batch_stokes_matches_oracle(sdg, ctx, torch):
+    from oracle import refine as rf
     n, k = 8, 2
     probs = [gen.single_inclusion(n, k, eta_in=e) for e in (1e1, 1e3)]
     eta = np.stack([p.eta for p in probs])
     f = np.concatenate([p.f.reshape(-1) for p in probs])
-    Pb = make_problem(sdg, ctx, n, n, k, eta, rtol=1e-11, inner_rtol=1e-6, coarsest_n=4, max_it=600)
+    Pb = make_problem(sdg, ctx, n, n, k, eta, rtol=1e-11, inner_rtol=1e-6, coarsest_n=4, max_it=600,
+                      refine=1)
     u, p, stats = Pb.solve_stokes(dev(f))
-    assert all(s["status"] in (0, sdg.FLOOR) for s in stats), stats
+    assert all(s["status"] == 0 for s in stats), stats
     ub, pb_ = host(u).reshape(2, -1), host(p).reshape(2, -1)
     m = Mesh(n, n, k)
     for i, pr in enumerate(probs):
-        ud, pd = solve_stokes(m, pr.eta, pr.f)
+        ud, pd = rf.solve_stokes_ext(m, pr.eta, pr.f, method="lu")
+        ud, pd = ud.astype(np.float64), pd.astype(np.float64)
         assert np.linalg.norm(ub[i] - ud) <= 1e-9 * np.linalg.norm(ud), stats[i]
-        assert np.linalg.norm(pb_[i] - pd) <= 1e-6 * np.linalg.norm(pd), stats[i]
+        assert np.linalg.norm(pb_[i] - pd) <= 1e-8 * np.linalg.norm(pd), stats[i]
     Pb.close()
 
 
-# (n, k, contrast, rtol, velocity bound): the first case has an FP64
-# residual floor eps |A||u|/|F| ~ 1e-10, the second ~ 2e-8 (measured with the
-# oracle), so the second may end at the floor
+# The second case's FP64 residual floor (eps |A||u|/|F| ~ 2e-8) lies above
+# its rtol: the extended refinement reaches it anyway.
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("n,k,ein,rtol,ubound", [(16, 3, 1e2, 1e-9, 1e-9), (16, 4, 1e4, 1e-8, 3e-9)])
-def test_mixed_precision_viscous(sdg, ctx, torch, prec, n, k, ein, rtol, ubound):
+@pytest.mark.parametrize("n,k,ein,rtol", [(16, 3, 1e2, 1e-9), (16, 4, 1e4, 1e-9)])
+def test_mixed_precision_viscous(sdg, ctx, torch, prec, n, k, ein, rtol):
     """FP32 fine-level cycle with FP32 or BF16 block inverses inside FP64
-    FGMRES (iterative refinement): reaches the FP64 tolerance (or the FP64
-    rounding floor) with the FP64 path's accuracy against the direct
-    solution."""
+    FGMRES with extended iterative refinement: reaches rtol on the pair and
+    the refined oracle solution to 1e-9."""
+    from oracle import refine as rf
     P0 = gen.single_inclusion(n, k, eta_in=ein)
     m = Mesh(n, n, k)
-    ud = solve_viscous(m, P0.eta, P0.f)
+    ud = rf.solve_viscous_ext(m, P0.eta, P0.f).astype(np.float64)
     ps = sdg.FP32 if prec == "fp32" else sdg.BF16
     P = make_problem(sdg, ctx, n, n, k, P0.eta, rtol=rtol, max_it=400, coarsest_n=4,
-                     prec_apply=sdg.FP32, prec_smoother=ps, viscous_krylov=1, restart=60)
+                     prec_apply=sdg.FP32, prec_smoother=ps, viscous_krylov=1, restart=60, refine=1)
     u, st = P.solve_viscous(dev(P0.f.reshape(-1)))
     print(f"[mixed] {prec} n={n} k={k} eta={ein}: {st}", flush=True)
-    assert st["status"] in (0, sdg.FLOOR), st
-    assert st["rel_residual"] < max(rtol, 5e-8)
-    assert np.linalg.norm(host(u) - ud) <= ubound * np.linalg.norm(ud), st
+    assert st["status"] == 0, st
+    assert st["rel_residual"] < rtol
+    assert np.linalg.norm(host(u) - ud) <= 1e-9 * np.linalg.norm(ud), st
     P.close()
+
+
+# ----------------------------------------------------------------------------
+# V-cycles at 64 x 64 with the default coarsest_n = 8: the CG-Q1 levels of
+# 65^2 and 33^2 nodes run the per-level kernels (Chebyshev / point-Jacobi
+# sweeps, stencil residual, bilinear restriction and prolongation,
+# Section 6.1.2); only the levels of at most 17^2 nodes and the dense
+# coarsest solve run in the one-workgroup tail.
+# ----------------------------------------------------------------------------
+def _vcycle_case(sdg, torch, ctx, n, k, probs, coarsest_n=8, **opts):
+    """One batched cycle on random vectors with the oracle's Chebyshev
+    bounds; returns per problem (relative difference to the oracle's cycle,
+    cond of the coarsest operator)."""
+    m = Mesh(n, n, k)
+    Hs = [Hierarchy(m, p.eta, coarsest_n=coarsest_n) for p in probs]
+    nbatch = len(probs)
+    P = make_problem(sdg, ctx, n, n, k, np.stack([p.eta for p in probs]), coarsest_n=coarsest_n, **opts)
+    nlev = sdg.sdg_problem_levels(P.h)
+    assert nlev - 1 == len(Hs[0].levels)
+    b = np.zeros((nbatch, nlev, 2))
+    for pb, H in enumerate(Hs):
+        b[pb, : len(H.bounds)] = H.bounds
+    sdg.sdg_set_bounds(P.h, b)
+    rng = np.random.default_rng(5 + k)
+    r = rng.normal(size=(nbatch, m.nu))
+    x = P.zeros(nbatch * m.nu)
+    sdg.sdg_vcycle(P.h, dev(r.ravel()), x)
+    torch.cuda.synchronize()
+    X = host(x).reshape(nbatch, m.nu)
+    out = []
+    for pb, H in enumerate(Hs):
+        xr = H.vcycle(r[pb])
+        kc = np.linalg.cond(H.levels[-1].A.toarray())
+        out.append((np.linalg.norm(X[pb] - xr) / np.linalg.norm(xr), kc))
+    P.close()
+    return out, [(lev.nx, lev.ny) for lev in Hs[0].levels]
+
+
+@pytest.mark.parametrize("k,nbatch", [(2, 3), (4, 1)])
+def test_vcycle_parity_hlevels(sdg, ctx, torch, k, nbatch):
+    """FP64 cycle: equal to the oracle's cycle up to the rounding of the
+    dense coarsest solve (explicit inverse against Cholesky solves), i.e.
+    within a multiple of cond(A_coarsest) * eps."""
+    n = 64
+    probs = [gen.random_inclusions(n, k, seed=s) for s in range(nbatch)]
+    errs, levels = _vcycle_case(sdg, torch, ctx, n, k, probs)
+    assert levels == [(64, 64), (32, 32), (16, 16), (8, 8)]  # 65^2, 33^2 nodes outside the tail
+    for pb, (err, kc) in enumerate(errs):
+        tol = max(1e-11, 50.0 * kc * 2.2e-16)
+        print(f"[vcycle64] k={k} pb={pb} rel err {err:.3e} tol {tol:.1e}", flush=True)
+        assert err <= tol, (pb, err, tol)
+
+
+# FP32 fine-level cycle (operator apply, block smoother with FP32 factors,
+# Q1 residual) around the FP64 coarse hierarchy.  The smoother applies
+# s X~^T X~ r with X = L^{-1} rounded to FP32: its relative error is bounded
+# by about 2 u32 kappa(M_K) (rounding X by u32 perturbs X^T X by
+# 2 u32 |X|^T |X|, and |X|^T |X| ~ ||M_K^{-1}||), the FP32 operator apply by
+# about n_b u32 relative to |A||u|.  Over the 2 + 2 Chebyshev steps and the
+# Q1 residual (coefficients of order one) the cycle's relative deviation
+# from the FP64 cycle therefore stays below 8 u32 max(kappa_max, n_b),
+# kappa_max the largest condition number of the element blocks.
+@pytest.mark.parametrize("n,k,coarsest", [(16, 4, 4), (64, 2, 8)])
+def test_vcycle_parity_fp32_cycle(sdg, ctx, torch, n, k, coarsest):
+    probs = [gen.single_inclusion(n, k, eta_in=1e4)]
+    errs, _ = _vcycle_case(sdg, torch, ctx, n, k, probs, coarsest_n=coarsest, prec_apply=sdg.FP32,
+                           prec_smoother=sdg.FP32)
+    m = Mesh(n, n, k)
+    BJ = BlockJacobi(asm.assemble_A(m, probs[0].eta), m.nbu)
+    kappa = float(np.max(np.linalg.cond(BJ.blocks)))
+    tol = 8 * 2.0 ** -24 * max(kappa, m.nbu)
+    for err, _ in errs:
+        print(f"[vcycle fp32] n={n} k={k} rel err {err:.3e} tol {tol:.1e} (kappa_max {kappa:.2e})", flush=True)
+        assert err <= tol, (err, tol)

@@ -579,3 +579,22 @@ def test_stokes_error_estimate_matches_true_error():
     eu, ep, rel = rf.stokes_error_estimate(m, P.eta, P.f, uh, ph, coarsest_n=4, inner_rtol=1e-6)
     assert abs(eu / eu_true - 1) <= 0.05 and abs(ep / ep_true - 1) <= 0.05, (eu, eu_true, ep, ep_true)
     assert rel > 0
+
+
+def test_six_sinker_inputs_follow_the_paper():
+    """The six-inclusion generator uses the paper's centres, radii,
+    densities, gravity and boundary sides (tests/golden/six_sinkers.json,
+    Section 8.3): elements fully inside carry rho2, elements touching an
+    inclusion carry eta2, the top side is Neumann."""
+    ref = json.load(open(os.path.join(GOLDEN, "six_sinkers.json")))
+    assert [list(c) for c in gen.SINKERS] == ref["centres_radii"]
+    P = gen.six_sinkers(64, 2, eta2=1e3)
+    assert P.bc == (NAVIER, NAVIER, NAVIER, NEUMANN)
+    h = 1.0 / 64
+    fy = P.f[:, 1, 0, 0] / h  # mode (0,0) of a constant force is f sqrt|K|
+    for cx, cy, r in ref["centres_radii"]:
+        ix, iy = int(cx / h), int(cy / h)
+        e = iy * 64 + ix  # the element holding the centre lies fully inside (r > 2 sqrt(2) h)
+        assert P.eta[e] == 1e3 and abs(fy[e] + ref["g"] * ref["rho2"]) < 1e-12
+    far = 0  # the corner element (0, 0) touches no inclusion
+    assert P.eta[far] == 1.0 and abs(fy[far] + ref["g"] * ref["rho1"]) < 1e-12
