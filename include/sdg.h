@@ -292,7 +292,10 @@ int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const s
 int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, void* stream);
 
 /* ---- request server (continuous batching of solves on one GPU) --------------
- * A server owns `slots` worker threads, each with its own HIP stream.
+ * A server owns `slots` worker threads, each with its own HIP stream; while
+ * it runs, the CG iterations of all slots are launched together, one
+ * combined HIP graph per iteration boundary, so a request admitted into a
+ * free slot joins the running launches at its first iteration.
  * sdg_submit copies the request's host inputs (the caller may free them at
  * once) and queues it.  A free slot takes the oldest queued request whose
  * device memory (sdg_required_bytes_batch plus its input and output arrays)
@@ -313,7 +316,7 @@ int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, voi
 #define SDG_VISCOUS 0
 #define SDG_STOKES 1
 typedef struct sdg_server_config {
-  int32_t slots;     /* concurrent launch groups, 1..64 (default 4) */
+  int32_t slots;     /* concurrent launch groups, 1..64 (default 8) */
   int32_t max_batch; /* requests per launch group, 1..4096 (default 16) */
   int32_t bypass;    /* overtakes of a waiting head request (default 8) */
   int32_t pad_;
@@ -337,6 +340,10 @@ int sdg_wait(sdg_req* req, double* u, double* p, sdg_stats* stats, sdg_req_info*
 void sdg_req_free(sdg_req* req);
 int sdg_server_stats(sdg_server* srv, int64_t* completed, size_t* peak_bytes, int* peak_busy,
                      size_t* budget);
+/* Iteration-level batching of the running server: CG iterations launched
+ * (launches), of which combined launches covering the iterations of several
+ * slots at once (combined), and the most slots one launch covered. */
+int sdg_server_launch_stats(sdg_server* srv, int64_t* launches, int64_t* combined, int* max_width);
 /* Host-only run of the same admission policy on a virtual clock: request i
  * arrives at arrival_ms[i], holds a slot and bytes[i] for service_ms[i];
  * start_ms[i] receives its start.  No GPU is used (capacity planning, tests). */

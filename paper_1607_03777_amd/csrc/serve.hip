@@ -11,6 +11,9 @@
 // times; after that admission waits for it.  The solver state of a request
 // (blocks, hierarchy, Krylov vectors) stays on the device from setup to the
 // copy of its result; requests on different slots overlap on the device.
+// While the server runs, the CG iterations of all slots are launched together
+// (the context's combiner): a request admitted into a free slot joins the
+// running launches at its first iteration boundary, whatever its shape.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -279,6 +282,7 @@ int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** o
   S->bypass = c.bypass;
   S->budget = budget;
   S->adm = sdg::Admission(budget, c.slots, c.bypass);
+  sdg::ctx_combine(ctx, 1);
   for (int i = 0; i < c.slots; ++i) S->workers.emplace_back(worker, S);
   *out = S;
   return SDG_OK;
@@ -287,7 +291,7 @@ int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** o
 void sdg_server_config_default(sdg_server_config* c) {
   if (!c) return;
   std::memset(c, 0, sizeof(*c));
-  c->slots = 4;
+  c->slots = 8;
   c->max_batch = 16;
   c->bypass = 8;
   c->mem_budget = 0;
@@ -301,7 +305,20 @@ void sdg_server_destroy(sdg_server* S) {
   }
   S->cv.notify_all();
   for (auto& t : S->workers) t.join();
+  sdg::ctx_combine(S->ctx, 0);
   delete S;
+}
+
+int sdg_server_launch_stats(sdg_server* S, int64_t* launches, int64_t* combined, int* max_width) {
+  if (!S) {
+    sdg::set_error("NULL server");
+    return SDG_ERR_INVALID;
+  }
+  if (launches) *launches = 0;
+  if (combined) *combined = 0;
+  if (max_width) *max_width = 0;
+  sdg::ctx_combine_stats(S->ctx, launches, combined, max_width);
+  return SDG_OK;
 }
 
 int sdg_submit(sdg_server* S, const sdg_mesh* mesh, const sdg_options* opts, int kind, const double* eta,

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <array>
 #include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -39,9 +40,12 @@
 #include "ext_kernels.h"
 #include "runtime.h"
 
+struct SdgCombiner;  // combined launches of concurrent CG iterations (serving)
+
 // A context is freed when it has been destroyed and its last problem is
 // gone, so problems destroyed after their context stay valid.
 struct sdg_ctx {
+  SdgCombiner* comb = nullptr;  // set while a request server runs on the context
   int device = 0;
   size_t budget = 0;
   size_t used = 0;
@@ -1104,7 +1108,12 @@ struct CgRun {
   int nact = 0, it = 0, parity = 0;
   unsigned expect = 0;
   bool running = false;  // an iteration is queued whose scalars are not yet read
+  bool combine = false;  // iterations go through the context's combiner (serving)
 };
+// the context's combiner (defined below)
+int comb_submit(sdg_ctx* c, CgRun& R);
+void comb_enter(sdg_ctx* c);
+void comb_leave(sdg_ctx* c);
 
 int cg_start(CgRun& R, sdg_problem* P, const double* b, double* x_out, double rtol, int maxit,
              const std::vector<double>* rtol_pb) {
@@ -1207,7 +1216,9 @@ int cg_body_launch(CgRun& R, bool launched) {
   double* rz = sc(P, SC_RZ);
   double* rz2 = sc(P, SC_RZ2);
   if (!launched) {
-    if (R.graphs) {
+    if (R.graphs && P->ctx->comb && R.combine) {
+      SDG_TRY(comb_submit(P->ctx, R));
+    } else if (R.graphs) {
       hipGraphExec_t ge = nullptr;
       SDG_TRY(cg_graph(P, R.parity, &ge));
       SDG_HIP(hipGraphLaunch(ge, P->s));
@@ -1232,12 +1243,16 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
              std::vector<double>& rel, std::vector<int>& status, const std::vector<double>* rtol_pb = nullptr) {
   CgRun R;
   SDG_TRY(cg_start(R, P, b, x_out, rtol, maxit, rtol_pb));
+  R.combine = R.graphs && P->ctx->comb != nullptr;
+  if (R.combine) comb_enter(P->ctx);
+  int rc = SDG_OK;
   while (true) {
     bool more = false;
-    SDG_TRY(cg_poll(R, &more));
-    if (!more) break;
-    SDG_TRY(cg_body_launch(R, false));
+    if ((rc = cg_poll(R, &more)) < 0 || !more) break;
+    if ((rc = cg_body_launch(R, false)) < 0) break;
   }
+  if (R.combine) comb_leave(P->ctx);
+  SDG_TRY(rc);
   SDG_TRY(cg_finish(R));
   its = R.its;
   rel = R.rel;
@@ -1318,26 +1333,172 @@ int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
   return SDG_OK;
 }
 
-// runs[i] already started (cg_start); advances all to completion
+// runs[i] already started (cg_start); advances all to completion.  A single
+// solve on a context with a running request server goes through the
+// server's combined launches.
 int cg_multi(std::vector<CgRun>& runs, MultiGraphs& G) {
-  while (true) {
+  const bool via_comb = runs.size() == 1 && runs[0].graphs && runs[0].P->ctx->comb;
+  if (via_comb) {
+    runs[0].combine = true;
+    comb_enter(runs[0].P->ctx);
+  }
+  int rc = SDG_OK;
+  while (rc >= 0) {
     std::vector<CgRun*> A;
     for (CgRun& r : runs) {
       bool more = false;
-      SDG_TRY(cg_poll(r, &more));
+      if ((rc = cg_poll(r, &more)) < 0) break;
       if (more) A.push_back(&r);
     }
-    if (A.empty()) break;
+    if (rc < 0 || A.empty()) break;
     const bool combined = A.size() > 1 && A[0]->graphs;
     if (combined) {
       hipGraphExec_t ge = nullptr;
-      SDG_TRY(multi_graph(G, A, &ge));
-      SDG_HIP(hipGraphLaunch(ge, A[0]->P->s));
+      if ((rc = multi_graph(G, A, &ge)) < 0) break;
+      if (hipGraphLaunch(ge, A[0]->P->s) != hipSuccess) {
+        set_error("hipGraphLaunch of the combined CG iteration failed");
+        rc = SDG_ERR_DEVICE;
+        break;
+      }
     }
-    for (CgRun* r : A) SDG_TRY(cg_body_launch(*r, combined));
+    for (CgRun* r : A)
+      if ((rc = cg_body_launch(*r, combined)) < 0) break;
   }
+  if (via_comb) comb_leave(runs[0].P->ctx);
+  SDG_TRY(rc);
   for (CgRun& r : runs) SDG_TRY(cg_finish(r));
   return SDG_OK;
+}
+
+}  // namespace
+
+// Continuous batching at the iteration level.  While a request server runs,
+// every CG solve of the context (one per server slot, each on its own host
+// thread and stream) hands its next iteration to the context's combiner
+// instead of launching it: the first thread to arrive waits a short window
+// for the other slots that are inside a CG solve, then launches one combined
+// graph (one parallel branch per waiting solve, with event dependencies on
+// every slot's stream) and releases them.  A request admitted into a free
+// slot thus joins the running launches at its first iteration boundary, and
+// the iterations of requests of different shapes overlap on the device in
+// one launch.  The combined graphs are cached per set of solves and
+// parities and dropped with their problems.
+struct SdgCombiner {
+  std::mutex mu;
+  std::condition_variable cv;
+  int members = 0;  // CG solves in progress
+  struct Entry {
+    CgRun* R;
+    bool launched = false;
+    int rc = 0;
+  };
+  std::vector<Entry*> pending;
+  bool leader = false;
+  MultiGraphs G;
+  hipStream_t ls = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t done = nullptr;
+  int64_t launches = 0, combined = 0;
+  int max_width = 0;
+  ~SdgCombiner() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (done) (void)hipEventDestroy(done);
+    if (ls) (void)hipStreamDestroy(ls);
+  }
+};
+
+namespace {
+
+constexpr auto COMBINE_WINDOW = std::chrono::microseconds(150);
+
+void comb_enter(sdg_ctx* c) {
+  SdgCombiner* C = c->comb;
+  std::lock_guard<std::mutex> g(C->mu);
+  ++C->members;
+}
+void comb_leave(sdg_ctx* c) {
+  SdgCombiner* C = c->comb;
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    --C->members;
+  }
+  C->cv.notify_all();
+}
+
+// the launch of one set of iterations (caller holds C->mu; the owners of
+// these solves wait in comb_submit, so their problems may be used here)
+int comb_launch(SdgCombiner* C, std::vector<CgRun*>& A) {
+  std::sort(A.begin(), A.end(), [](CgRun* a, CgRun* b) { return (uintptr_t)a->P < (uintptr_t)b->P; });
+  ++C->launches;
+  C->max_width = std::max(C->max_width, (int)A.size());
+  if (A.size() == 1) {
+    hipGraphExec_t ge = nullptr;
+    SDG_TRY(cg_graph(A[0]->P, A[0]->parity, &ge));
+    SDG_HIP(hipGraphLaunch(ge, A[0]->P->s));
+    return SDG_OK;
+  }
+  ++C->combined;
+  hipGraphExec_t ge = nullptr;
+  SDG_TRY(multi_graph(C->G, A, &ge));
+  if (!C->ls) SDG_HIP(hipStreamCreateWithFlags(&C->ls, hipStreamNonBlocking));
+  if (!C->done) SDG_HIP(hipEventCreateWithFlags(&C->done, hipEventDisableTiming));
+  while (C->ev.size() < A.size()) {
+    hipEvent_t e;
+    SDG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    C->ev.push_back(e);
+  }
+  for (size_t i = 0; i < A.size(); ++i) {
+    SDG_HIP(hipEventRecord(C->ev[i], A[i]->P->s));
+    SDG_HIP(hipStreamWaitEvent(C->ls, C->ev[i], 0));
+  }
+  SDG_HIP(hipGraphLaunch(ge, C->ls));
+  SDG_HIP(hipEventRecord(C->done, C->ls));
+  for (CgRun* r : A) SDG_HIP(hipStreamWaitEvent(r->P->s, C->done, 0));
+  return SDG_OK;
+}
+
+int comb_submit(sdg_ctx* c, CgRun& R) {
+  SdgCombiner* C = c->comb;
+  std::unique_lock<std::mutex> lk(C->mu);
+  SdgCombiner::Entry e{&R};
+  C->pending.push_back(&e);
+  C->cv.notify_all();
+  while (!e.launched) {
+    if (!C->leader) {
+      C->leader = true;
+      C->cv.wait_for(lk, COMBINE_WINDOW, [&] { return (int)C->pending.size() >= C->members; });
+      std::vector<SdgCombiner::Entry*> take;
+      take.swap(C->pending);
+      std::vector<CgRun*> A;
+      for (auto* x : take) A.push_back(x->R);
+      const int rc = comb_launch(C, A);
+      for (auto* x : take) {
+        x->launched = true;
+        x->rc = rc;
+      }
+      C->leader = false;
+      C->cv.notify_all();
+    } else {
+      C->cv.wait(lk);
+    }
+  }
+  return e.rc;
+}
+
+// drop cached combined graphs that contain problem P (it is being destroyed)
+void comb_drop(sdg_ctx* c, const sdg_problem* P) {
+  SdgCombiner* C = c->comb;
+  if (!C) return;
+  std::lock_guard<std::mutex> g(C->mu);
+  const std::string tag = std::to_string((uintptr_t)P) + ":";
+  for (auto it = C->G.cache.begin(); it != C->G.cache.end();) {
+    if (it->first.find(tag) != std::string::npos) {
+      (void)hipGraphExecDestroy(it->second);
+      it = C->G.cache.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 // Viscous solves by CG with iterative refinement in extended precision
@@ -2262,6 +2423,7 @@ void sdg_problem_destroy(sdg_problem* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->s);
   drop_graphs(P);
+  if (P->ctx) comb_drop(P->ctx, P);
   if (P->gs) (void)hipStreamDestroy(P->gs);
   // the stream has drained: the blocks go back to the context's cache
   if (P->ctx)
@@ -3003,6 +3165,23 @@ int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out, void* s
 }  // extern "C"
 
 namespace sdg {
+int ctx_combine(sdg_ctx* c, int on) {
+  if (on) {
+    if (!c->comb) c->comb = new SdgCombiner();
+    return SDG_OK;
+  }
+  delete c->comb;  // no solve may be running (the server's workers have stopped)
+  c->comb = nullptr;
+  return SDG_OK;
+}
+void ctx_combine_stats(sdg_ctx* c, int64_t* launches, int64_t* combined, int* max_width) {
+  SdgCombiner* C = c->comb;
+  if (!C) return;
+  std::lock_guard<std::mutex> g(C->mu);
+  if (launches) *launches = C->launches;
+  if (combined) *combined = C->combined;
+  if (max_width) *max_width = C->max_width;
+}
 void* ctx_alloc(sdg_ctx* c, size_t bytes) {
   void* p = nullptr;
   return ctx_get(c, cache_size(bytes), &p) < 0 ? nullptr : p;

@@ -121,6 +121,8 @@ PROTOTYPES = {
     "sdg_server_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
                              ctypes.POINTER(I), ctypes.POINTER(ctypes.c_size_t)]),
     "sdg_admission_simulate": (I, [I, P, P, P, I, ctypes.c_size_t, I, P]),
+    "sdg_server_launch_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(I)]),
     "sdg_trace_enable": (I, [P, I]),
     "sdg_trace_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
@@ -402,7 +404,7 @@ def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
 
 
 # ---- request server ------------------------------------------------------------
-def sdg_server_create(ctx, slots=4, max_batch=16, bypass=8, mem_budget=0):
+def sdg_server_create(ctx, slots=8, max_batch=16, bypass=8, mem_budget=0):
     cfg = sdg_server_config(slots, max_batch, bypass, 0, mem_budget)
     h = ctypes.c_void_p()
     check(lib().sdg_server_create(ctx, ctypes.byref(cfg), ctypes.byref(h)))
@@ -454,6 +456,12 @@ def sdg_server_stats(srv):
     bud = ctypes.c_size_t()
     check(lib().sdg_server_stats(srv, ctypes.byref(c), ctypes.byref(pb), ctypes.byref(busy), ctypes.byref(bud)))
     return {"completed": c.value, "peak_bytes": pb.value, "peak_busy": busy.value, "budget": bud.value}
+
+
+def sdg_server_launch_stats(srv):
+    n, c, w = ctypes.c_int64(), ctypes.c_int64(), I()
+    check(lib().sdg_server_launch_stats(srv, ctypes.byref(n), ctypes.byref(c), ctypes.byref(w)))
+    return {"launches": n.value, "combined": c.value, "max_width": w.value}
 
 
 def sdg_admission_simulate(arrival_ms, service_ms, nbytes, slots, budget, bypass):

@@ -101,3 +101,65 @@ def test_server_rejects_request_over_budget(sdg, torch):
     finally:
         sdg.sdg_server_destroy(srv)
         sdg.sdg_destroy(ctx)
+
+
+def test_server_staggered_mixed_precision_matches_alone_and_oracle(sdg, torch):
+    """Requests of different shapes and kinds arriving one after another
+    (staggered by a few milliseconds, while earlier ones run) with the
+    mixed-precision options the serving workload uses (FP32 fine-level
+    cycle, extended refinement): the later ones join the running combined
+    launches (some launch covers several slots), requests overlap in time,
+    and every result equals the same solve alone and the refined oracle
+    solution."""
+    import time
+    from oracle import refine as rf
+    ctx = sdg.sdg_create(0, 0)
+    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=2)
+    try:
+        # the pressure amplifies the residual by about 2e4 on the random
+        # problems (measured: rtol 1e-10 leaves 2e-6 in p), so rtol is 1e-13
+        opts = sdg.make_options(rtol=1e-13, inner_rtol=1e-3, coarsest_n=4, max_it=1200, refine=1,
+                                prec_apply=sdg.FP32, prec_smoother=sdg.FP32)
+        reqs = [(gen.random_problem(16, 2, 50, contrast=1e3), 1), (gen.single_inclusion(12, 3, eta_in=1e3), 1),
+                (gen.random_problem(8, 4, 51, contrast=1e2), 0), (gen.random_problem(16, 2, 52, contrast=1e3), 1),
+                (gen.random_problem(12, 3, 53, contrast=1e2), 0), (gen.single_inclusion(16, 2, eta_in=1e4), 1)]
+        handles = []
+        for prob, kind in reqs:
+            mesh = sdg.make_mesh(prob.nx, prob.ny, prob.k, prob.bc)
+            print(f"[case] staggered submit {prob.name} kind={kind}", flush=True)
+            handles.append(sdg.sdg_submit(srv, mesh, opts, kind, prob.eta, prob.f.reshape(-1)))
+            time.sleep(0.004)
+        results = []
+        for (prob, kind), h in zip(reqs, handles):
+            rc, u, p, st, info = sdg.sdg_wait(h, prob.nu, prob.np_ if kind else 0)
+            sdg.sdg_req_free(h)
+            assert rc == 0 and st["rel_residual"] < 1e-13, (prob.name, rc, st)
+            results.append((u, p, info))
+        ls = sdg.sdg_server_launch_stats(srv)
+        print(f"[staggered] launch stats {ls}", flush=True)
+        assert ls["combined"] >= 1 and ls["max_width"] >= 2
+        iv = [(r[2]["start_ms"], r[2]["end_ms"]) for r in results]
+        overlap = max(min(a[1], b[1]) - max(a[0], b[0]) for i, a in enumerate(iv) for b in iv[i + 1:])
+        assert overlap > 0  # at least two requests ran at the same time
+        for (prob, kind), (u, p, info) in zip(reqs, results):
+            mesh = sdg.make_mesh(prob.nx, prob.ny, prob.k, prob.bc)
+            ua = np.empty(prob.nu)
+            f = np.ascontiguousarray(prob.f.reshape(-1))
+            m = Mesh(prob.nx, prob.ny, prob.k, bc=prob.bc)
+            if kind:
+                pa = np.empty(prob.np_)
+                sdg.sdg_solve_stokes(ctx, mesh, opts, prob.eta, f, None, ua, pa)
+                ud, pd = rf.solve_stokes_ext(m, prob.eta, prob.f, method="lu")
+                ud, pd = ud.astype(np.float64), pd.astype(np.float64)
+                assert np.linalg.norm(p - pa) <= 1e-8 * np.linalg.norm(pa), prob.name
+                assert np.linalg.norm(p - pd) <= 1e-8 * np.linalg.norm(pd), prob.name
+            else:
+                sdg.sdg_solve_viscous(ctx, mesh, opts, prob.eta, f, None, ua)
+                ud = rf.solve_viscous_ext(m, prob.eta, prob.f).astype(np.float64)
+            eu_a = np.linalg.norm(u - ua) / np.linalg.norm(ua)
+            eu_o = np.linalg.norm(u - ud) / np.linalg.norm(ud)
+            print(f"[staggered] {prob.name}: vs alone {eu_a:.2e} vs oracle {eu_o:.2e}", flush=True)
+            assert eu_a <= 1e-9 and eu_o <= 1e-9, prob.name
+    finally:
+        sdg.sdg_server_destroy(srv)
+        sdg.sdg_destroy(ctx)

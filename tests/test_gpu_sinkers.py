@@ -2,7 +2,11 @@
 (outer) and viscous (inner) solves, and a Neumann top side, through the C
 ABI against the refined long-double oracle solution.  Iteration counts are
 compared with Table 4 only qualitatively (parity unpinned: the paper's
-counts depend on its h-level choices and rounding)."""
+counts depend on its h-level choices and rounding).  As in the paper's
+six-inclusion runs (one h-level less than for SolCx) the coarsest h-level is
+16 x 16 elements: coarser levels do not resolve the small high-contrast
+inclusions (the oracle's CG with coarsest level 8 x 8 needs 77 iterations to
+1e-3 at 64 x 64, k = 1, against 13 with 16 x 16)."""
 import json
 import os
 
@@ -54,7 +58,7 @@ def test_sinkers_gcr_stokes_matches_oracle(sdg, ctx, torch, eta2):
     m = Mesh(n, n, k, bc=pr.bc)
     print(f"[case] sinkers n={n} k={k} eta2={eta2:g}", flush=True)
     P = sdg.Problem(ctx, n, n, k, pr.eta, bc=pr.bc, rtol=1e-12, inner_rtol=1e-3, max_it=800, refine=1,
-                    outer_krylov=1, viscous_krylov=2)
+                    outer_krylov=1, viscous_krylov=2, coarsest_n=16)
     u, ul, p, pl = P.zeros(P.nu), P.zeros(P.nu), P.zeros(P.np), P.zeros(P.np)
     rc, st = sdg.sdg_solve_stokes_ext_dev(P.h, dev(pr.f.reshape(-1)), None, u, ul, p, pl)
     print(f"[sinkers] {st}", flush=True)
@@ -64,8 +68,14 @@ def test_sinkers_gcr_stokes_matches_oracle(sdg, ctx, torch, eta2):
     uref, pref = uref.astype(np.float64), pref.astype(np.float64)
     eu = np.linalg.norm(host(u) - uref) / np.linalg.norm(uref)
     ep = np.linalg.norm(host(p) - pref) / np.linalg.norm(pref)
-    print(f"[sinkers] residual {res:.2e} velocity {eu:.2e} pressure {ep:.2e}", flush=True)
-    assert res <= 1.2e-12 and eu <= 1e-9 and ep <= 1e-9
+    # the library's and the oracle's evaluations each carry about
+    # 2^-63 |K||x| / |b| (5e-13 here at eta2 = 1e6)
+    K, b = rf.stokes_system(m, pr.eta, pr.f)
+    x = np.concatenate([host(u), host(p)])
+    ld_floor = 2.0 ** -63 * float(np.linalg.norm(abs(K.astype(np.float64)) @ np.abs(x))
+                                  / np.linalg.norm(b.astype(np.float64)))
+    print(f"[sinkers] residual {res:.2e} (floor {ld_floor:.1e}) velocity {eu:.2e} pressure {ep:.2e}", flush=True)
+    assert res <= 1e-12 + 2 * ld_floor and eu <= 1e-9 and ep <= 1e-9
     P.close()
 
 
@@ -73,7 +83,8 @@ def test_sinkers_gcr_viscous_matches_oracle(sdg, ctx, torch):
     n, k = 32, 3
     pr = gen.six_sinkers(n, k, eta2=1e6)
     m = Mesh(n, n, k, bc=pr.bc)
-    P = sdg.Problem(ctx, n, n, k, pr.eta, bc=pr.bc, rtol=1e-10, max_it=800, refine=1, viscous_krylov=2)
+    P = sdg.Problem(ctx, n, n, k, pr.eta, bc=pr.bc, rtol=1e-10, max_it=800, refine=1, viscous_krylov=2,
+                    coarsest_n=16)
     u, ul = P.zeros(P.nu), P.zeros(P.nu)
     rc, st = sdg.sdg_solve_viscous_ext_dev(P.h, dev(pr.f.reshape(-1)), None, u, ul)
     print(f"[sinkers viscous] {st}", flush=True)
@@ -95,7 +106,7 @@ def test_sinkers_iteration_counts_qualitative(sdg, ctx, torch):
         for eta2 in (1e3, 1e6):
             pr = gen.six_sinkers(n, k, eta2=eta2)
             P = sdg.Problem(ctx, n, n, k, pr.eta, bc=pr.bc, rtol=1e-6, inner_rtol=1e-3, max_it=400,
-                            outer_krylov=1, viscous_krylov=2)
+                            outer_krylov=1, viscous_krylov=2, coarsest_n=16)
             u, p, st = P.solve_stokes(dev(pr.f.reshape(-1)))
             outer[(k, eta2)] = st["outer_its"]
             print(f"[sinkers 64] k={k} eta2={eta2:g}: outer {st['outer_its']} inner avg "
@@ -106,5 +117,5 @@ def test_sinkers_iteration_counts_qualitative(sdg, ctx, torch):
             P.close()
     for k in (1, 2, 3):
         t4 = ref["table4_outer_its_64x64_eta1e6"]["k%d" % k]
-        assert outer[(k, 1e6)] <= 3 * t4
+        assert outer[(k, 1e6)] <= 2 * t4
         assert max(outer[(k, 1e3)], outer[(k, 1e6)]) <= 2 * min(outer[(k, 1e3)], outer[(k, 1e6)])
