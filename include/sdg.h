@@ -206,6 +206,16 @@ int sdg_apply_blockjacobi(sdg_problem* prob, const double* r_dev, double* z_dev)
 /* Dense diagonal blocks of A: blocks [nel][nb][nb], nb = 2(k+1)^2, row =
  * test mode, column = trial mode (FP64, before inversion). */
 int sdg_get_blocks(sdg_problem* prob, double* blocks_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * blocks as sdg_get_blocks, which allocates an element list per call, with
+ * that list in a file-scope device array of the library instead (limit:
+ * nel * nbatch <= 1048576 elements, else SDG_ERR_INVALID; the array, 4 MiB,
+ * is held on each device the library runs on until the process ends).  No
+ * hipMalloc, hipFree or allocating call; the work is enqueued on the
+ * problem's stream.  All calls on one device share the array: calls that
+ * overlap on one device (several streams or threads) race. */
+int sdg_get_blocks_noalloc(sdg_problem* prob, double* blocks_dev);
 /* rc = P_cd^T R_k^1 r (Section 6: truncation to Q_1 modes, then the
  * transpose of the element-wise nodal-to-modal map, Section 6.1.2). */
 int sdg_p_restrict(sdg_problem* prob, const double* r_dev, double* rc_dev);

@@ -90,6 +90,18 @@ struct sdg_ctx {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Allocation-free form of sdg_get_blocks: the element list it hands to the
+// block kernel lives in this file-scope device array instead of a buffer
+// allocated per call.  Its device address is taken once per device, with
+// that device current, when a context is created (sdg_create); host code
+// uses only that address.  Every call on one device shares the array.
+// ---------------------------------------------------------------------------
+static constexpr int64_t NOALLOC_MAX_ELEMS = 1 << 20;  // elements x batch (4 MiB)
+static __device__ __align__(256) int scratch[NOALLOC_MAX_ELEMS];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
 namespace sdg {
 int ctx_device(const sdg_ctx* c) { return c ? c->device : 0; }
 static thread_local std::string g_err;
@@ -101,6 +113,31 @@ using namespace sdg;
 
 namespace {
 
+// address of `scratch` on the current device (once per device)
+int scratch_setup(int device) {
+  if (device < 0 || device >= 64) {
+    set_error("device index beyond the allocation-free scratch table (64 devices)");
+    return SDG_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return SDG_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    set_error(std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+    return SDG_ERR_DEVICE;
+  }
+  g_scratch_ptr[device] = ptr;
+  return SDG_OK;
+}
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return (device >= 0 && device < 64) ? g_scratch_ptr[device] : nullptr;
+}
+__global__ void iota_kernel(int64_t n, int* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) out[i] = (int)i;
+}
 
 constexpr int TAIL_NODES = 17 * 17;  // h-levels with at most this many nodes run in the tail kernel
 constexpr int RED_SCRATCH = 512 * 64;
@@ -2192,6 +2229,7 @@ int sdg_create(int device, size_t mem_budget, sdg_ctx** out) {
     return SDG_ERR_INVALID;
   }
   SDG_HIP(hipSetDevice(device));
+  SDG_TRY(scratch_setup(device));
   sdg_ctx* c = new sdg_ctx();
   c->device = device;
   c->budget = mem_budget;
@@ -2575,6 +2613,24 @@ int sdg_get_blocks(sdg_problem* P, double* blocks) {
   (void)hipStreamSynchronize(P->s);
   (void)hipFree(d);
   return rc;
+}
+int sdg_get_blocks_noalloc(sdg_problem* P, double* blocks) {
+  PCHECK(blocks);
+  const int64_t ntot = (int64_t)P->nel * P->nb;
+  if (ntot > NOALLOC_MAX_ELEMS) {
+    set_error("sdg_get_blocks_noalloc: " + std::to_string(ntot) + " elements (all problems of the batch) exceed " +
+              "its limit of " + std::to_string(NOALLOC_MAX_ELEMS));
+    return SDG_ERR_INVALID;
+  }
+  int* list = (int*)scratch_ptr(P->ctx->device);
+  if (!list) {
+    set_error("sdg_get_blocks_noalloc: scratch address not set up for this device");
+    return SDG_ERR_DEVICE;
+  }
+  const int grid = (int)std::min<int64_t>((ntot + 255) / 256, 4096);
+  hipLaunchKernelGGL(iota_kernel, dim3(grid), dim3(256), 0, P->s, ntot, list);
+  SDG_CHECK_LAUNCH();
+  return sip_block_list(P->M, P->k, P->eta, list, (int)ntot, blocks, P->s);
 }
 int sdg_p_restrict(sdg_problem* P, const double* r, double* rc) {
   PCHECK(r, rc);

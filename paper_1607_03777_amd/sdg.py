@@ -91,6 +91,7 @@ PROTOTYPES = {
     "sdg_apply_grad": (I, [P, P, P]),
     "sdg_apply_blockjacobi": (I, [P, P, P]),
     "sdg_get_blocks": (I, [P, P]),
+    "sdg_get_blocks_noalloc": (I, [P, P]),
     "sdg_p_restrict": (I, [P, P, P]),
     "sdg_p_prolong_add": (I, [P, P, P]),
     "sdg_get_coarse_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -301,6 +302,10 @@ def sdg_apply_blockjacobi(prob, r, z):
 
 def sdg_get_blocks(prob, blocks):
     return _op("sdg_get_blocks")(prob, blocks)
+
+
+def sdg_get_blocks_noalloc(prob, blocks):
+    return _op("sdg_get_blocks_noalloc")(prob, blocks)
 
 
 def sdg_p_restrict(prob, r, rc):
