@@ -266,33 +266,36 @@ def batched_leg(sdg, ctx, torch, nreq, pool):
     """Batching form: nreq independent viscous solves, n in {16, 32, 64,
     128}, k in 2..5, log10 viscosity a Gaussian random field (correlation
     length 0.1, std 1.5), smooth random force, rtol 1e-8 with extended
-    refinement (CG corrections).  Four runs isolate the levers: batched
-    through the server (requests of one shape share launches) with the FP32
-    cycle, and with the FP64 cycle; one request at a time (one-shot calls,
-    no batching) with the FP32 cycle, and with the FP64 cycle (the plain
-    FP64 per-request path)."""
+    refinement (CG corrections).  Runs in this process that isolate the
+    levers: the heterogeneous batch call (chunks of 64 requests) with the
+    FP32 and the FP64 cycle; one request at a time (one-shot calls, no
+    batching) with the FP32 cycle, and with the FP64 cycle (the plain FP64
+    per-request path).  The same requests through the request server run
+    in a child process (served_runs)."""
     from paper_1607_03777_amd import inputs as gen
     probs = [gen.grf_problem(seed) for seed in range(nreq)]
     dofs = sum(p.nu for p in probs)
 
-    def served(prec):
+    def batch_call(prec, chunk=64):
+        """sdg_solve_viscous_batch over consecutive chunks of the requests
+        (one call per chunk; within a call the shapes run their CG
+        iterations in lockstep, one combined graph launch per iteration)."""
         pa, ps = PRECS[prec]
         opts = sdg.make_options(rtol=RTOL, max_it=3000, refine=1, prec_apply=pa, prec_smoother=ps)
-        srv = sdg.sdg_server_create(ctx, slots=4, max_batch=64)
         t0 = time.perf_counter()
-        hs = [sdg.sdg_submit(srv, sdg.make_mesh(p.nx, p.ny, p.k), opts, sdg.VISCOUS, p.eta, p.f.reshape(-1))
-              for p in probs]
-        good, its, groups, us = 0, [], [], []
-        for h, p in zip(hs, probs):
-            rc, u, _, st, info = sdg.sdg_wait(h, p.nu)
-            sdg.sdg_req_free(h)
-            good += ok(st)
-            its.append(st["outer_its"])
-            groups.append(info["batch"])
-            us.append(u)
-        t = time.perf_counter() - t0
-        sdg.sdg_server_destroy(srv)
-        return t, good, float(np.mean(its)), float(np.mean(groups)), us
+        good, its, us = 0, [], [None] * nreq
+        for i in range(0, nreq, chunk):
+            part = probs[i:i + chunk]
+            try:
+                _, u, _, sts = sdg.sdg_solve_viscous_batch(ctx, [sdg.make_mesh(p.nx, p.ny, p.k) for p in part], opts,
+                                                           [p.eta for p in part], [p.f for p in part])
+            except sdg.SDGError as e:
+                log(f"[bench] batch call failed: {e}")
+                continue
+            us[i:i + chunk] = u
+            good += sum(ok(st) for st in sts)
+            its += [st["outer_its"] for st in sts]
+        return time.perf_counter() - t0, good, float(np.mean(its)) if its else None, us
 
     def alone(prec):
         pa, ps = PRECS[prec]
@@ -310,41 +313,80 @@ def batched_leg(sdg, ctx, torch, nreq, pool):
         return time.perf_counter() - t0, good
 
     runs = {}
-    t, good, its, grp, us = served("fp32")
-    runs["batched_fp32_cycle"] = {"seconds": t, "solves_per_s": nreq / t, "dof_per_s": dofs / t,
-                                  "converged": good, "mean_cg_its": its, "mean_launch_group": grp}
-    log(f"[bench] batched fp32: {nreq} solves in {t:.2f} s, converged {good}")
-    # oracle checks of sampled requests (smallest meshes: refined references)
-    small = [i for i, p in enumerate(probs) if p.nx <= 32][:3]
-    checks = [pool.apply_async(_oracle_viscous, ((probs[i].nx, probs[i].k, probs[i].eta, probs[i].f,
-                                                  us[i], np.zeros_like(us[i])),)) for i in small]
-    t, good, its, grp, _ = served("fp64")
-    runs["batched_fp64_cycle"] = {"seconds": t, "solves_per_s": nreq / t, "converged": good,
-                                  "mean_cg_its": its, "mean_launch_group": grp}
-    log(f"[bench] batched fp64: {nreq} solves in {t:.2f} s, converged {good}")
+    checks = []
+    for prec in ("fp32", "fp64"):
+        t, good, its, us = batch_call(prec)
+        runs[f"batch_call_{prec}_cycle"] = {"seconds": t, "solves_per_s": nreq / t, "dof_per_s": dofs / t,
+                                            "converged": good, "mean_cg_its": its, "chunk": 64}
+        log(f"[bench] batch call {prec}: {nreq} solves in {t:.2f} s, converged {good}")
+        if prec == "fp32" and pool is not None:
+            # oracle checks of sampled requests (smallest meshes: refined references)
+            small = [i for i, p in enumerate(probs) if p.nx <= 32 and us[i] is not None][:3]
+            checks = [pool.apply_async(_oracle_viscous, ((probs[i].nx, probs[i].k, probs[i].eta, probs[i].f,
+                                                          us[i], np.zeros_like(us[i])),)) for i in small]
     t, good = alone("fp32")
     runs["per_request_fp32_cycle"] = {"seconds": t, "solves_per_s": nreq / t, "converged": good}
     log(f"[bench] per-request fp32: {t:.2f} s, converged {good}")
     t, good = alone("fp64")
     runs["per_request_fp64_plain"] = {"seconds": t, "solves_per_s": nreq / t, "converged": good}
     log(f"[bench] per-request fp64 (plain path): {t:.2f} s, converged {good}")
-    b = runs["batched_fp32_cycle"]["seconds"]
+    plain = runs["per_request_fp64_plain"]["seconds"]
     return {"workload": f"{nreq}-grf-viscous-n16..128-k2..5-rtol1e-8", "runs": runs,
-            "speedup_mixed_batched_vs_plain_fp64": runs["per_request_fp64_plain"]["seconds"] / b,
-            "speedup_batching_alone_fp64": runs["per_request_fp64_plain"]["seconds"]
-            / runs["batched_fp64_cycle"]["seconds"],
-            "speedup_precision_alone_per_request": runs["per_request_fp64_plain"]["seconds"]
-            / runs["per_request_fp32_cycle"]["seconds"],
+            "speedup_mixed_batched_vs_plain_fp64": plain / runs["batch_call_fp32_cycle"]["seconds"],
+            "speedup_batching_alone_fp64": plain / runs["batch_call_fp64_cycle"]["seconds"],
+            "speedup_precision_alone_per_request": plain / runs["per_request_fp32_cycle"]["seconds"],
             "oracle_sample_async": checks}
 
 
-def serving_leg(sdg, ctx, torch, nreq, rate, prec, nmax, kmax, pool):
+def served_runs(sdg, ctx, nreq, slots, max_batch):
+    """The batched leg's requests submitted at once to the request server
+    (requests of one shape share launches, the CG iterations of the slots
+    are combined per iteration), with the FP32 and with the FP64 cycle."""
+    from paper_1607_03777_amd import inputs as gen
+    probs = [gen.grf_problem(seed) for seed in range(nreq)]
+    dofs = sum(p.nu for p in probs)
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        pa, ps = PRECS[prec]
+        opts = sdg.make_options(rtol=RTOL, max_it=3000, refine=1, prec_apply=pa, prec_smoother=ps)
+        srv = sdg.sdg_server_create(ctx, slots=slots, max_batch=max_batch)
+        t0 = time.perf_counter()
+        hs = [sdg.sdg_submit(srv, sdg.make_mesh(p.nx, p.ny, p.k), opts, sdg.VISCOUS, p.eta, p.f.reshape(-1))
+              for p in probs]
+        good, its, groups, failed = 0, [], [], 0
+        for h, p in zip(hs, probs):
+            try:
+                rc, u, _, st, info = sdg.sdg_wait(h, p.nu)
+                good += ok(st)
+                its.append(st["outer_its"])
+                groups.append(info["batch"])
+            except sdg.SDGError as e:
+                failed += 1
+                if failed == 1:
+                    log(f"[bench] served request failed: {e}")
+            sdg.sdg_req_free(h)
+        t = time.perf_counter() - t0
+        ls = sdg.sdg_server_launch_stats(srv)
+        sst = sdg.sdg_server_stats(srv)
+        sdg.sdg_server_destroy(srv)
+        runs[f"served_{prec}_cycle"] = {"seconds": t, "solves_per_s": nreq / t, "dof_per_s": dofs / t,
+                                        "converged": good, "failed": failed,
+                                        "mean_cg_its": float(np.mean(its)) if its else None,
+                                        "mean_launch_group": float(np.mean(groups)) if groups else None,
+                                        "slots": slots, "max_batch": max_batch, "launch_stats": ls,
+                                        "peak_bytes": sst["peak_bytes"], "budget": sst["budget"]}
+        log(f"[bench] served {prec}: {nreq} solves in {t:.2f} s, converged {good}, launches {ls}")
+    return runs
+
+
+def serving_leg(sdg, ctx, nreq, rate, prec, nmax, kmax, slots):
     """Request-server form: a Poisson trace of Stokes requests (n a multiple
     of 16 in [32, nmax], k in [2, kmax], 1-16 disks with contrast 10^U[2,6],
     rtol 1e-8 with extended refinement) replayed in real time into the server
-    (mixed-precision cycle, 4 slots), and the same trace through the plain
-    FP64 per-request path (one-shot solves one after another, FP64 cycle, no
-    batching).  Latency = completion - arrival."""
+    (mixed-precision cycle), and the same trace through the plain FP64
+    per-request path (one-shot solves one after another, FP64 cycle, no
+    batching).  Latency = completion - arrival.  Returns the two smallest
+    requests' results for the oracle's checks."""
     from paper_1607_03777_amd import inputs as gen
     trace = gen.serving_trace(nreq=nreq, rate=rate, seed=0, nmin=32, nmax=nmax, kmin=2, kmax=kmax)
     probs = [gen.serving_problem(r) for r in trace]
@@ -355,7 +397,7 @@ def serving_leg(sdg, ctx, torch, nreq, rate, prec, nmax, kmax, pool):
     def pct(x):
         return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
 
-    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=16)
+    srv = sdg.sdg_server_create(ctx, slots=slots, max_batch=16)
     t0 = time.perf_counter()
     hs = []
     for r, pr in zip(trace, probs):
@@ -374,14 +416,14 @@ def serving_leg(sdg, ctx, torch, nreq, rate, prec, nmax, kmax, pool):
         res.append((pr, u, p))
     t_srv = time.perf_counter() - t0
     sst = sdg.sdg_server_stats(srv)
+    ls = sdg.sdg_server_launch_stats(srv)
     sdg.sdg_server_destroy(srv)
     log(f"[bench] served {nreq} requests in {t_srv:.2f} s, p50 {np.percentile(lat, 50):.0f} ms "
-        f"p99 {np.percentile(lat, 99):.0f} ms, converged {good}")
+        f"p99 {np.percentile(lat, 99):.0f} ms, converged {good}, launches {ls}")
     # refined references by a Stokes LU: only requests small enough for it
     small = [i for i in sorted(range(nreq), key=lambda i: probs[i].nu + probs[i].np_)
              if probs[i].nu + probs[i].np_ <= 60_000][:2]
-    checks = [pool.apply_async(_oracle_stokes, ((res[i][0].nx, res[i][0].k, res[i][0].eta, res[i][0].f,
-                                                 res[i][1], res[i][2]),)) for i in small]
+    samples = [(res[i][0].nx, res[i][0].k, res[i][0].eta, res[i][0].f, res[i][1], res[i][2]) for i in small]
     t0 = time.perf_counter()
     lat64, good64 = [], 0
     for r, pr in zip(trace, probs):
@@ -402,10 +444,55 @@ def serving_leg(sdg, ctx, torch, nreq, rate, prec, nmax, kmax, pool):
         f"p99 {np.percentile(lat64, 99):.0f} ms, converged {good64}")
     return {"workload": f"poisson-{rate:g}-per-s-{nreq}-stokes-requests-n32..{nmax}-k2..{kmax}-rtol1e-8",
             "server": {"requests_per_s": nreq / t_srv, "latency_ms": pct(lat), "converged": good,
-                       "cycle_precision": prec, "slots": 4, "max_batch": 16,
-                       "mean_launch_group": float(np.mean(batches)), "peak_bytes": sst["peak_bytes"]},
+                       "cycle_precision": prec, "slots": slots, "max_batch": 16,
+                       "mean_launch_group": float(np.mean(batches)), "peak_bytes": sst["peak_bytes"],
+                       "launch_stats": ls},
             "fp64_per_request": {"requests_per_s": nreq / t_64, "latency_ms": pct(lat64), "converged": good64},
-            "speedup": t_64 / t_srv, "oracle_sample_async": checks}
+            "speedup": t_64 / t_srv, "oracle_samples": samples}
+
+
+def _child_leg(conn, which, kw):
+    """Entry of the child process that runs a request-server leg on its own
+    context (a failure there cannot take the benchmark line with it)."""
+    try:
+        import torch
+        from paper_1607_03777_amd import sdg
+        torch.cuda.set_device(0)
+        ctx = sdg.sdg_create(0, 0)
+        fn = served_runs if which == "served" else serving_leg
+        res = fn(sdg, ctx, **kw)
+        sdg.sdg_destroy(ctx)
+        conn.send(("ok", res))
+    except Exception as e:  # reported in the JSON line
+        conn.send(("error", repr(e)))
+    conn.close()
+
+
+def isolated_leg(which, kw, timeout_s):
+    """Runs a server leg in a spawned child process; returns its result, or
+    {"failed": ...} when the child raised, died or ran past timeout_s."""
+    mpc = mp.get_context("spawn")
+    rd, wr = mpc.Pipe(duplex=False)
+    proc = mpc.Process(target=_child_leg, args=(wr, which, kw))
+    proc.start()
+    wr.close()
+    msg = None
+    try:
+        if rd.poll(timeout_s):
+            msg = rd.recv()
+    except (EOFError, OSError):
+        msg = None
+    proc.join(60)
+    if proc.is_alive():
+        proc.kill()
+        proc.join()
+    if msg is None:
+        log(f"[bench] {which} leg: child process ended without a result (exit code {proc.exitcode})")
+        return {"failed": f"child process ended without a result (exit code {proc.exitcode})"}
+    if msg[0] != "ok":
+        log(f"[bench] {which} leg failed: {msg[1]}")
+        return {"failed": msg[1]}
+    return msg[1]
 
 
 def kernel_probe(sdg, ctx, torch, B, reps):
@@ -476,6 +563,8 @@ def main():
     ap.add_argument("--c3", default="3,4,5,6", help="orders of the 256 x 256 leg ('' = skip)")
     ap.add_argument("--c3-prec", choices=list(PRECS), default="bf16")
     ap.add_argument("--batched", type=int, default=512, help="requests of the random-field leg (0 = skip)")
+    ap.add_argument("--served", type=int, default=0,
+                    help="also submit the random-field leg's requests to the request server (child process)")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving leg (0 = skip)")
     ap.add_argument("--serve-nmax", type=int, default=128)
     ap.add_argument("--serve-kmax", type=int, default=6)
@@ -677,10 +766,18 @@ def main():
         out["sinkers"] = sinker_leg(sdg, ctx, torch, [int(x) for x in args.sinkers.split(",")], (1, 2, 3))
     if args.batched > 0:
         out["batched"] = batched_leg(sdg, ctx, torch, args.batched, pool)
-    if args.serve_requests > 0:
-        out["serving"] = serving_leg(sdg, ctx, torch, args.serve_requests, 200.0, args.serve_prec,
-                                     args.serve_nmax, args.serve_kmax, pool)
+    # the request-server legs run in child processes with contexts of their
+    # own: this context's cached device memory is released first
     sdg.sdg_destroy(ctx)
+    torch.cuda.empty_cache()
+    if args.batched > 0 and args.served:
+        out["batched"]["runs"].update(isolated_leg("served", {"nreq": args.batched, "slots": 8, "max_batch": 16}, 600))
+    if args.serve_requests > 0:
+        out["serving"] = isolated_leg("serving", {"nreq": args.serve_requests, "rate": 200.0, "prec": args.serve_prec,
+                                                  "nmax": args.serve_nmax, "kmax": args.serve_kmax, "slots": 8}, 600)
+        samples = out["serving"].pop("oracle_samples", [])
+        out["serving"]["oracle_sample_async"] = ([pool.apply_async(_oracle_stokes, (smp,)) for smp in samples]
+                                                 if pool is not None else [])
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(pool_cores, st0["inner_its_total"], st0["outer_its"])

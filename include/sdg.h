@@ -146,8 +146,12 @@ const char* sdg_last_error(void);
  * smooth_dg 2, smooth_h 3 (Section 8), coarsest_n 8, eig_steps 10,
  * cheb 0.1/1.1 (Section 6), FP64 everywhere, CG, dedup on, seed 0, graphs on. */
 void sdg_options_default(sdg_options* opts);
-/* Device bytes a problem of this size needs (deterministic; used for
- * admission).  stokes != 0 adds the pressure and FGMRES workspaces. */
+/* Device bytes a problem of this size needs at most (deterministic, host
+ * only): every element block is counted as distinct, as for a viscosity
+ * that varies from element to element; deduplication (opts->dedup) can
+ * only lower what is used.  stokes != 0 adds the pressure and FGMRES
+ * workspaces.  The request server counts the distinct blocks of each
+ * request from its viscosity instead. */
 size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes);
 size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, int stokes, int nbatch);
 
@@ -352,8 +356,11 @@ int sdg_server_stats(sdg_server* srv, int64_t* completed, size_t* peak_bytes, in
                      size_t* budget);
 /* Iteration-level batching of the running server: CG iterations launched
  * (launches), of which combined launches covering the iterations of several
- * slots at once (combined), and the most slots one launch covered. */
-int sdg_server_launch_stats(sdg_server* srv, int64_t* launches, int64_t* combined, int* max_width);
+ * slots at once (combined), the most slots one launch covered, and the
+ * combined graphs instantiated (graphs; one per new set of running solves,
+ * at most 64 kept).  Any output pointer may be NULL. */
+int sdg_server_launch_stats(sdg_server* srv, int64_t* launches, int64_t* combined, int* max_width,
+                            int64_t* graphs);
 /* Host-only run of the same admission policy on a virtual clock: request i
  * arrives at arrival_ms[i], holds a slot and bytes[i] for service_ms[i];
  * start_ms[i] receives its start.  No GPU is used (capacity planning, tests). */

@@ -3,8 +3,8 @@
 //
 // Requests enter a FIFO queue with host copies of their inputs.  Worker
 // threads (the slots), each with its own HIP stream, take the oldest request
-// whose device memory (sdg_required_bytes_batch plus its input and output
-// arrays) fits into what the budget has left, together with queued requests
+// whose device memory (the problem's bytes with its element blocks counted
+// from its viscosity, plus its input and output arrays) fits into what the budget has left, together with queued requests
 // of the identical shape (mesh, options, kind, Dirichlet data present), up to
 // max_batch of them, which then run as one batched problem.  A request that
 // does not fit may be overtaken by later ones that do, at most `bypass`
@@ -62,7 +62,8 @@ struct sdg_req {
   sdg_stats st{};
   int rc = 0;
   std::string err;  // message of a failed solve (set on the worker thread)
-  size_t bytes = 0;  // admission estimate for this request alone
+  int64_t nuniq = 0;  // distinct element blocks of this request after deduplication
+  size_t bytes = 0;   // admission estimate for this request alone
   double t_submit = 0, t_start = 0, t_end = 0;
   int batch = 0;  // number of requests in the launch group it ran in
   bool done = false;
@@ -99,8 +100,11 @@ size_t io_bytes(const sdg_req& r, int nb) {
          (n_el(r.mesh) + 2 * n_u(r.mesh) + (r.kind ? n_p(r.mesh) : 0) + (r.has_g ? n_g(r.mesh) : 0));
 }
 
-size_t group_bytes(const sdg_req& r, int nb) {
-  return sdg_required_bytes_batch(&r.mesh, &r.opts, r.kind, nb) + io_bytes(r, nb);
+// Device bytes of a launch group of nb requests shaped like r whose
+// distinct element blocks number nuniq in all (the sum over the requests:
+// blocks shared across requests only lower it).
+size_t group_bytes(const sdg_req& r, int nb, int64_t nuniq) {
+  return sdg::required_bytes_blocks(&r.mesh, &r.opts, r.kind, nb, nuniq) + io_bytes(r, nb);
 }
 
 // Publishes a request's outcome.  The waiter is notified while the lock is
@@ -206,15 +210,17 @@ void worker(sdg_server* S) {
       sdg_req* r = S->queue[pick];
       grp.push_back(r);
       S->queue.erase(S->queue.begin() + pick);
-      bytes = group_bytes(*r, 1);
+      bytes = r->bytes;
+      int64_t nuniq = r->nuniq;
       // same-shape requests behind it join the launch group while they fit
       for (size_t i = 0; i < S->queue.size() && (int)grp.size() < S->max_batch;) {
         sdg_req* q = S->queue[i];
-        const size_t nb2 = group_bytes(*r, (int)grp.size() + 1);
+        const size_t nb2 = group_bytes(*r, (int)grp.size() + 1, nuniq + q->nuniq);
         if (q->kind == r->kind && q->has_g == r->has_g && same_shape(q->mesh, r->mesh) &&
             same_options(q->opts, r->opts) && S->adm.fits(nb2)) {
           grp.push_back(q);
           bytes = nb2;
+          nuniq += q->nuniq;
           S->queue.erase(S->queue.begin() + i);
         } else {
           ++i;
@@ -309,7 +315,7 @@ void sdg_server_destroy(sdg_server* S) {
   delete S;
 }
 
-int sdg_server_launch_stats(sdg_server* S, int64_t* launches, int64_t* combined, int* max_width) {
+int sdg_server_launch_stats(sdg_server* S, int64_t* launches, int64_t* combined, int* max_width, int64_t* graphs) {
   if (!S) {
     sdg::set_error("NULL server");
     return SDG_ERR_INVALID;
@@ -317,7 +323,8 @@ int sdg_server_launch_stats(sdg_server* S, int64_t* launches, int64_t* combined,
   if (launches) *launches = 0;
   if (combined) *combined = 0;
   if (max_width) *max_width = 0;
-  sdg::ctx_combine_stats(S->ctx, launches, combined, max_width);
+  if (graphs) *graphs = 0;
+  sdg::ctx_combine_stats(S->ctx, launches, combined, max_width, graphs);
   return SDG_OK;
 }
 
@@ -343,7 +350,8 @@ int sdg_submit(sdg_server* S, const sdg_mesh* mesh, const sdg_options* opts, int
   r->eta.assign(eta, eta + n_el(*mesh));
   r->f.assign(f, f + n_u(*mesh));
   if (g) r->g.assign(g, g + n_g(*mesh));
-  r->bytes = group_bytes(*r, 1);
+  r->nuniq = sdg::unique_blocks(*mesh, r->eta.data(), 1, r->opts.dedup != 0);
+  r->bytes = group_bytes(*r, 1, r->nuniq);
   if (r->bytes > S->budget) {
     delete r;
     sdg::set_error("request needs more device memory than the server's budget");

@@ -33,6 +33,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "sdg_common.h"
@@ -446,8 +447,30 @@ struct BlockKeyHash {
   }
 };
 
+// The diagonal block of element e of one problem (viscosity et) is eta_e
+// times a block fixed by the kinds of its four faces and the face
+// viscosities of eq. (eta_face) relative to eta_e: the key of that block.
+BlockKey block_key(const sdg_mesh& m, const double* et, int e) {
+  const int nx = m.nx, ny = m.ny, ix = e % nx, iy = e / nx;
+  const double ee = et[e];
+  BlockKey key;
+  const int nbs[4] = {ix > 0 ? e - 1 : -1, ix < nx - 1 ? e + 1 : -1, iy > 0 ? e - nx : -1,
+                      iy < ny - 1 ? e + nx : -1};
+  for (int f = 0; f < 4; ++f) {
+    if (nbs[f] >= 0) {
+      key.kind[f] = F_INTERIOR;
+      const double r = et[nbs[f]] / ee;
+      key.ratio[f] = r > 1.0 ? r : 1.0;
+    } else {
+      key.kind[f] = m.bc[f];
+      key.ratio[f] = 1.0;
+    }
+  }
+  return key;
+}
+
 int setup_blocks(sdg_problem* P) {
-  const int nx = P->mesh.nx, ny = P->mesh.ny, nel = P->nel;
+  const int nel = P->nel;
   const int64_t ntot = (int64_t)nel * P->nb;
   std::vector<int> ids(ntot);
   std::vector<double> scale(ntot);
@@ -457,21 +480,8 @@ int setup_blocks(sdg_problem* P) {
     const int64_t pb = ge / nel;
     const int e = (int)(ge - pb * nel);
     const double* et = P->eta_host.data() + pb * nel;
-    const int ix = e % nx, iy = e / nx;
     const double ee = et[e];
-    BlockKey key;
-    const int nbs[4] = {ix > 0 ? e - 1 : -1, ix < nx - 1 ? e + 1 : -1, iy > 0 ? e - nx : -1,
-                        iy < ny - 1 ? e + nx : -1};
-    for (int f = 0; f < 4; ++f) {
-      if (nbs[f] >= 0) {
-        key.kind[f] = F_INTERIOR;
-        const double r = et[nbs[f]] / ee;
-        key.ratio[f] = r > 1.0 ? r : 1.0;
-      } else {
-        key.kind[f] = P->mesh.bc[f];
-        key.ratio[f] = 1.0;
-      }
-    }
+    const BlockKey key = block_key(P->mesh, et, e);
     int id;
     if (P->opt.dedup) {
       auto it = map.find(key);
@@ -1306,17 +1316,36 @@ int cg_solve(sdg_problem* P, const double* b, double* x_out, double rtol, int ma
 // device.  The combined graph is captured once per set of running solves
 // and parity and reused; a solve that has converged leaves the set.  With a
 // single solve the problem's own captured iteration is replayed.
+// The cache holds at most MAX_CACHED graphs: the set of running solves and
+// their parities changes as solves start, finish and (in the server) miss
+// a launch window, and every new combination is a new graph.  A full cache
+// is emptied after the streams its graphs were launched on have drained.
 struct MultiGraphs {
+  static constexpr size_t MAX_CACHED = 64;
   hipStream_t cs = nullptr;
   std::vector<hipEvent_t> ev;
   std::map<std::string, hipGraphExec_t> cache;
+  std::vector<hipStream_t> launched_on;  // streams the cached graphs were launched on
+  int64_t built = 0;                     // graphs instantiated so far
   ~MultiGraphs() {
     for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (cs) (void)hipStreamDestroy(cs);
   }
+  void note_launch(hipStream_t s) {
+    if (std::find(launched_on.begin(), launched_on.end(), s) == launched_on.end()) launched_on.push_back(s);
+  }
+  int flush() {
+    for (hipStream_t s : launched_on) SDG_HIP(hipStreamSynchronize(s));
+    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+    cache.clear();
+    launched_on.clear();
+    return SDG_OK;
+  }
 };
 
+// The graph for one iteration of the solves A (with their parities); the
+// caller launches it on a stream it passes to note_launch.
 int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
   std::string key;
   for (CgRun* r : A) key += std::to_string((uintptr_t)r->P) + ":" + std::to_string(r->parity) + ";";
@@ -1325,6 +1354,7 @@ int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
     *out = it->second;
     return SDG_OK;
   }
+  if (G.cache.size() >= MultiGraphs::MAX_CACHED) SDG_TRY(G.flush());
   if (!G.cs) SDG_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
   while (G.ev.size() < A.size() + 1) {
     hipEvent_t e;
@@ -1342,7 +1372,7 @@ int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
     for (size_t i = 0; i < A.size() && rc >= 0; ++i) {
       sdg_problem* P = A[i]->P;
       if (hipStreamWaitEvent(P->gs, G.ev[0], 0) != hipSuccess) {
-        rc = SDG_ERR_DEVICE;
+        rc = SDG_ERR_DEVICE;  // this branch was not forked: nothing to join
         break;
       }
       hipStream_t user = P->s;
@@ -1351,9 +1381,10 @@ int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
       double* rz2 = sc(P, SC_RZ2);
       rc = A[i]->parity == 0 ? cg_body(P, A[i]->x, rz, rz2) : cg_body(P, A[i]->x, rz2, rz);
       P->s = user;
-      if (rc >= 0 && (hipEventRecord(G.ev[i + 1], P->gs) != hipSuccess ||
-                      hipStreamWaitEvent(G.cs, G.ev[i + 1], 0) != hipSuccess))
-        rc = SDG_ERR_DEVICE;
+      // every forked branch joins the capture stream, also after a failure,
+      // so that the capture can end with no stream left in it
+      if (hipEventRecord(G.ev[i + 1], P->gs) != hipSuccess || hipStreamWaitEvent(G.cs, G.ev[i + 1], 0) != hipSuccess)
+        rc = rc < 0 ? rc : SDG_ERR_DEVICE;
     }
     if (hipStreamEndCapture(G.cs, &g) != hipSuccess && rc >= 0) rc = SDG_ERR_DEVICE;
   }
@@ -1366,6 +1397,7 @@ int multi_graph(MultiGraphs& G, std::vector<CgRun*>& A, hipGraphExec_t* out) {
     return rc;
   }
   G.cache[key] = ge;
+  ++G.built;
   *out = ge;
   return SDG_OK;
 }
@@ -1392,6 +1424,7 @@ int cg_multi(std::vector<CgRun>& runs, MultiGraphs& G) {
     if (combined) {
       hipGraphExec_t ge = nullptr;
       if ((rc = multi_graph(G, A, &ge)) < 0) break;
+      G.note_launch(A[0]->P->s);
       if (hipGraphLaunch(ge, A[0]->P->s) != hipSuccess) {
         set_error("hipGraphLaunch of the combined CG iteration failed");
         rc = SDG_ERR_DEVICE;
@@ -1475,9 +1508,10 @@ int comb_launch(SdgCombiner* C, std::vector<CgRun*>& A) {
     return SDG_OK;
   }
   ++C->combined;
+  if (!C->ls) SDG_HIP(hipStreamCreateWithFlags(&C->ls, hipStreamNonBlocking));
   hipGraphExec_t ge = nullptr;
   SDG_TRY(multi_graph(C->G, A, &ge));
-  if (!C->ls) SDG_HIP(hipStreamCreateWithFlags(&C->ls, hipStreamNonBlocking));
+  C->G.note_launch(C->ls);
   if (!C->done) SDG_HIP(hipEventCreateWithFlags(&C->done, hipEventDisableTiming));
   while (C->ev.size() < A.size()) {
     hipEvent_t e;
@@ -1527,9 +1561,10 @@ void comb_drop(sdg_ctx* c, const sdg_problem* P) {
   SdgCombiner* C = c->comb;
   if (!C) return;
   std::lock_guard<std::mutex> g(C->mu);
+  // keys are "P:parity;" tokens: match P at the start or after a separator
   const std::string tag = std::to_string((uintptr_t)P) + ":";
   for (auto it = C->G.cache.begin(); it != C->G.cache.end();) {
-    if (it->first.find(tag) != std::string::npos) {
+    if (it->first.compare(0, tag.size(), tag) == 0 || it->first.find(";" + tag) != std::string::npos) {
       (void)hipGraphExecDestroy(it->second);
       it = C->G.cache.erase(it);
     } else {
@@ -2187,6 +2222,64 @@ int fill_stats(sdg_problem* P, sdg_stats* st, const std::vector<int>& status, co
 
 }  // namespace
 
+namespace sdg {
+// Device bytes of a batched problem whose element blocks are nuniq distinct
+// matrices after deduplication (at most nel * nbatch).
+size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int stokes, int nbatch, int64_t nuniq) {
+  const int64_t nb = nbatch;
+  const int64_t nel = (int64_t)mesh->nx * mesh->ny;
+  const int64_t NB = 2 * (int64_t)(mesh->k + 1) * (mesh->k + 1);
+  const int64_t nu = nel * NB, np = nel * mesh->k * mesh->k;
+  size_t b = 0;
+  b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, element permutation, etap
+  nuniq = std::max<int64_t>(1, std::min<int64_t>(nuniq, nel * nb));
+  b += nuniq * NB * NB * 8 + nuniq * 8;
+  b += 12 * (nel * nb / 16 + nuniq + 1);  // smoother work list (16 elements per item at least)
+  const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
+  // low precision: the packed FP64 factor and the factor and its transpose
+  // as full squares in the storage type
+  if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + 2 * NB * NB * (opts->prec_smoother == SDG_BF16 ? 2 : 4));
+  b += nb * nel * 64 * 8;  // coarse local matrices
+  int cx = mesh->nx, cy = mesh->ny;
+  while (true) {
+    const int64_t nn = (int64_t)(cx + 1) * (cy + 1);
+    b += nb * nn * (36 + 14) * 8 + opts->smooth_h * nb * 16;
+    const bool more = cx % 2 == 0 && cy % 2 == 0 && cx > opts->coarsest_n && cy > opts->coarsest_n;
+    if (!more) {
+      b += nb * 4 * nn * nn * 8 + nb * 8;
+      break;
+    }
+    cx /= 2;
+    cy /= 2;
+  }
+  b += nb * nu * 8 * 2 + opts->smooth_dg * nb * 16;  // DG cycle vectors
+  if (low) b += nb * nu * 4 * 4;
+  b += RED_SCRATCH * 8 + (SC_COUNT_FIXED + std::max(opts->restart, opts->eig_steps) + 4) * nb * 8 * 2 + nb * 4;
+  b += nb * nu * 8 * 4;  // CG
+  const int64_t n = stokes ? nu + np : nu;
+  // the call's assembled right-hand side and iterate copies: F and G
+  // (viscous), or b, x and the low part (Stokes)
+  b += stokes ? nb * 3 * n * 8 : nb * (nu + np) * 8;
+  if (stokes || opts->viscous_krylov >= 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
+  if (stokes && opts->viscous_krylov == 2) b += nb * (2 * (int64_t)opts->restart + 2) * nu * 8;  // inner GCR
+  b += nb * (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
+  if (opts->refine) b += nb * 3 * n * 8;  // low part of the iterate, refinement residual and correction
+  return b;
+}
+
+
+int64_t unique_blocks(const sdg_mesh& m, const double* eta, int nbatch, bool dedup) {
+  const int64_t nel = (int64_t)m.nx * m.ny, ntot = nel * nbatch;
+  if (!dedup) return ntot;
+  std::unordered_set<BlockKey, BlockKeyHash> seen;
+  for (int64_t ge = 0; ge < ntot; ++ge) {
+    const int64_t pb = ge / nel;
+    seen.insert(block_key(m, eta + pb * nel, (int)(ge - pb * nel)));
+  }
+  return (int64_t)seen.size();
+}
+}  // namespace sdg
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -2262,40 +2355,7 @@ static bool opts_ok(const sdg_options* o) {
 
 size_t sdg_required_bytes_batch(const sdg_mesh* mesh, const sdg_options* opts, int stokes, int nbatch) {
   if (!mesh_ok(mesh) || !opts_ok(opts) || nbatch < 1) return 0;
-  const int64_t nb = nbatch;
-  const int64_t nel = (int64_t)mesh->nx * mesh->ny;
-  const int64_t NB = 2 * (int64_t)(mesh->k + 1) * (mesh->k + 1);
-  const int64_t nu = nel * NB, np = nel * mesh->k * mesh->k;
-  size_t b = 0;
-  b += nb * (nel * 8 * 2 + nel * 4 + np * 8);  // eta, scale, element permutation, etap
-  const int64_t nuniq = opts->dedup ? std::min<int64_t>(nel * nb, 4096) : nel * nb;
-  b += nuniq * NB * NB * 8 + nuniq * 8;
-  b += 12 * (nel * nb / 16 + nuniq + 1);  // smoother work list (16 elements per item at least)
-  const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
-  if (low) b += nuniq * NB * (NB + 1) / 2 * (8 + (opts->prec_smoother == SDG_BF16 ? 2 : 4));
-  b += nb * nel * 64 * 8;  // coarse local matrices
-  int cx = mesh->nx, cy = mesh->ny;
-  while (true) {
-    const int64_t nn = (int64_t)(cx + 1) * (cy + 1);
-    b += nb * nn * (36 + 14) * 8 + opts->smooth_h * nb * 16;
-    const bool more = cx % 2 == 0 && cy % 2 == 0 && cx > opts->coarsest_n && cy > opts->coarsest_n;
-    if (!more) {
-      b += nb * 4 * nn * nn * 8 + nb * 8;
-      break;
-    }
-    cx /= 2;
-    cy /= 2;
-  }
-  b += nb * nu * 8 * 2 + opts->smooth_dg * nb * 16;  // DG cycle vectors
-  if (low) b += nb * nu * 4 * 4;
-  b += RED_SCRATCH * 8 + (SC_COUNT_FIXED + std::max(opts->restart, opts->eig_steps) + 4) * nb * 8 * 2 + nb * 4;
-  b += nb * nu * 8 * 4;  // CG
-  const int64_t n = stokes ? nu + np : nu;
-  if (stokes || opts->viscous_krylov >= 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
-  if (stokes && opts->viscous_krylov == 2) b += nb * (2 * (int64_t)opts->restart + 2) * nu * 8;  // inner GCR
-  b += nb * (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
-  if (opts->refine) b += nb * 3 * n * 8;  // low part of the iterate, refinement residual and correction
-  return b;
+  return required_bytes_blocks(mesh, opts, stokes, nbatch, (int64_t)mesh->nx * mesh->ny * nbatch);
 }
 
 size_t sdg_required_bytes(const sdg_mesh* mesh, const sdg_options* opts, int stokes) {
@@ -3230,13 +3290,14 @@ int ctx_combine(sdg_ctx* c, int on) {
   c->comb = nullptr;
   return SDG_OK;
 }
-void ctx_combine_stats(sdg_ctx* c, int64_t* launches, int64_t* combined, int* max_width) {
+void ctx_combine_stats(sdg_ctx* c, int64_t* launches, int64_t* combined, int* max_width, int64_t* graphs) {
   SdgCombiner* C = c->comb;
   if (!C) return;
   std::lock_guard<std::mutex> g(C->mu);
   if (launches) *launches = C->launches;
   if (combined) *combined = C->combined;
   if (max_width) *max_width = C->max_width;
+  if (graphs) *graphs = C->G.built;
 }
 void* ctx_alloc(sdg_ctx* c, size_t bytes) {
   void* p = nullptr;

@@ -123,7 +123,7 @@ PROTOTYPES = {
                              ctypes.POINTER(I), ctypes.POINTER(ctypes.c_size_t)]),
     "sdg_admission_simulate": (I, [I, P, P, P, I, ctypes.c_size_t, I, P]),
     "sdg_server_launch_stats": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                    ctypes.POINTER(I)]),
+                                    ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int64)]),
     "sdg_trace_enable": (I, [P, I]),
     "sdg_trace_read": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
@@ -464,9 +464,9 @@ def sdg_server_stats(srv):
 
 
 def sdg_server_launch_stats(srv):
-    n, c, w = ctypes.c_int64(), ctypes.c_int64(), I()
-    check(lib().sdg_server_launch_stats(srv, ctypes.byref(n), ctypes.byref(c), ctypes.byref(w)))
-    return {"launches": n.value, "combined": c.value, "max_width": w.value}
+    n, c, w, g = ctypes.c_int64(), ctypes.c_int64(), I(), ctypes.c_int64()
+    check(lib().sdg_server_launch_stats(srv, ctypes.byref(n), ctypes.byref(c), ctypes.byref(w), ctypes.byref(g)))
+    return {"launches": n.value, "combined": c.value, "max_width": w.value, "graphs": g.value}
 
 
 def sdg_admission_simulate(arrival_ms, service_ms, nbytes, slots, budget, bypass):

@@ -559,7 +559,7 @@ def test_vcycle_parity_hlevels(sdg, ctx, torch, k, nbatch):
 # Q1 residual (coefficients of order one) the cycle's relative deviation
 # from the FP64 cycle therefore stays below 8 u32 max(kappa_max, n_b),
 # kappa_max the largest condition number of the element blocks.
-@pytest.mark.parametrize("n,k,coarsest", [(16, 4, 4), (64, 2, 8)])
+@pytest.mark.parametrize("n,k,coarsest", [(16, 4, 4), (64, 2, 8), (16, 5, 4), (16, 6, 4)])
 def test_vcycle_parity_fp32_cycle(sdg, ctx, torch, n, k, coarsest):
     probs = [gen.single_inclusion(n, k, eta_in=1e4)]
     errs, _ = _vcycle_case(sdg, torch, ctx, n, k, probs, coarsest_n=coarsest, prec_apply=sdg.FP32,

@@ -87,3 +87,22 @@ def test_required_bytes_is_host_only_and_monotone(sdg):
     assert 0 < small < big < stokes
     assert sdg.sdg_required_bytes(sdg.make_mesh(0, 4, 2), o, 0) == 0
     assert sdg.sdg_required_bytes(sdg.make_mesh(4, 4, 9), o, 0) == 0
+
+
+@pytest.mark.parametrize("prec_s,width", [(0, 0), (1, 4), (2, 2)])
+def test_required_bytes_bounds_the_element_blocks(sdg, prec_s, width):
+    """The admission figure is an upper bound: every element block counted as
+    distinct (a viscosity that varies per element leaves nothing to
+    deduplicate), each stored as its FP64 inverse and, in low precision, as
+    the packed FP64 factor plus the factor and its transpose as full squares
+    (the setup's allocations)."""
+    n, k, nbatch = 64, 5, 3
+    NB = 2 * (k + 1) ** 2
+    o = sdg.make_options(prec_apply=1 if prec_s else 0, prec_smoother=prec_s)
+    need = sdg.sdg_required_bytes_batch(sdg.make_mesh(n, n, k), o, 0, nbatch)
+    nblk = n * n * nbatch
+    blocks = nblk * NB * NB * 8
+    if prec_s:
+        blocks += nblk * (NB * (NB + 1) // 2 * 8 + 2 * NB * NB * width)
+    vectors = nbatch * n * n * NB * 8 * 7  # at least the CG and cycle vectors
+    assert need >= blocks + vectors
