@@ -188,8 +188,9 @@ def cpu_baseline(pool_cores, gpu_inner, gpu_outer, sample_its=3):
 # ---------------------------------------------------------------------------
 def c3_leg(sdg, ctx, torch, ks, prec):
     """256 x 256 random-inclusion viscous solves (16 disks, log10 viscosity
-    U[-3, 3]), FP32 operator and BF16 block factors in the cycle, FGMRES with
-    extended refinement, rtol 1e-8; one solve per k, setup included."""
+    U[-3, 3]), FP32 operator and BF16 block factors in the cycle (FP32 where
+    the setup finds BF16 too coarse for the blocks), FGMRES with extended
+    refinement, rtol 1e-8; one solve per k, setup included."""
     from paper_1607_03777_amd import inputs as gen
     out = []
     pa, ps = PRECS[prec]
@@ -204,13 +205,15 @@ def c3_leg(sdg, ctx, torch, ks, prec):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = sdg.sdg_problem_create(ctx, sdg.make_mesh(256, 256, k), opts, eta, sdg.current_stream())
+        factors = {0: "fp64", 1: "fp32", 2: "bf16"}[sdg.sdg_problem_smoother_precision(h)]
         rc, st = sdg.sdg_solve_viscous_ext_dev(h, f, None, u, ul)
         sdg.sdg_problem_destroy(h)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         log(f"[bench] C3 256x256 k={k}: {t:.2f} s status={st['status']} its={st['outer_its']} "
-            f"resid={st['rel_residual']:.2e}")
+            f"resid={st['rel_residual']:.2e} factors {factors}")
         out.append({"k": k, "seconds": t, "velocity_dofs": pr.nu, "dof_per_s": pr.nu / t, "status": st["status"],
+                    "smoother_factors": factors,
                     "converged": ok(st), "krylov_its": st["outer_its"], "rel_residual": st["rel_residual"],
                     "setup_ms": st["setup_ms"]})
     return {"workload": "viscous-256x256-16-random-inclusions-log10eta-U[-3,3]-rtol1e-8",
@@ -340,8 +343,8 @@ def batched_leg(sdg, ctx, torch, nreq, pool):
 
 def served_runs(sdg, ctx, nreq, slots, max_batch):
     """The batched leg's requests submitted at once to the request server
-    (requests of one shape share launches, the CG iterations of the slots
-    are combined per iteration), with the FP32 and with the FP64 cycle."""
+    (requests of one shape share launches; each slot launches its own
+    iterations), with the FP32 and with the FP64 cycle."""
     from paper_1607_03777_amd import inputs as gen
     probs = [gen.grf_problem(seed) for seed in range(nreq)]
     dofs = sum(p.nu for p in probs)
@@ -771,10 +774,10 @@ def main():
     sdg.sdg_destroy(ctx)
     torch.cuda.empty_cache()
     if args.batched > 0 and args.served:
-        out["batched"]["runs"].update(isolated_leg("served", {"nreq": args.batched, "slots": 8, "max_batch": 16}, 600))
+        out["batched"]["runs"].update(isolated_leg("served", {"nreq": args.batched, "slots": 4, "max_batch": 16}, 600))
     if args.serve_requests > 0:
         out["serving"] = isolated_leg("serving", {"nreq": args.serve_requests, "rate": 200.0, "prec": args.serve_prec,
-                                                  "nmax": args.serve_nmax, "kmax": args.serve_kmax, "slots": 8}, 600)
+                                                  "nmax": args.serve_nmax, "kmax": args.serve_kmax, "slots": 4}, 600)
         samples = out["serving"].pop("oracle_samples", [])
         out["serving"]["oracle_sample_async"] = ([pool.apply_async(_oracle_stokes, (smp,)) for smp in samples]
                                                  if pool is not None else [])

@@ -177,6 +177,14 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
 int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts, int nbatch,
                              const double* eta_dev, void* stream, sdg_problem** out);
 int sdg_problem_batch(const sdg_problem* prob, int* nbatch);
+/* Storage precision of the element-block factors the smoother applies
+ * (SDG_FP64: the FP64 inverse; SDG_FP32 or SDG_BF16: the inverse Cholesky
+ * factor).  BF16 is asked for with opts.prec_smoother; the setup keeps FP32
+ * factors instead when the BF16 ones put the largest eigenvalue of the
+ * smoothed DG operator (Arnoldi estimate, Section 6) above 4, against about
+ * 2 with exact inverses: blocks whose condition approaches the reciprocal
+ * of the BF16 unit (viscosity jumps of 10^6 between neighbours). */
+int sdg_problem_smoother_precision(const sdg_problem* prob, int* prec);
 void sdg_problem_destroy(sdg_problem* prob);
 /* Number of multigrid levels (1 DG level + CG-Q_1 h-levels) and the
  * Chebyshev bounds [lambda_0, lambda_1] per level ([nbatch][nlevels][2];
@@ -330,10 +338,14 @@ int sdg_uniform_pm1(sdg_ctx* ctx, uint64_t seed, int64_t n, double* out_dev, voi
 #define SDG_VISCOUS 0
 #define SDG_STOKES 1
 typedef struct sdg_server_config {
-  int32_t slots;     /* concurrent launch groups, 1..64 (default 8) */
+  int32_t slots;     /* concurrent launch groups, 1..64 (default 4) */
   int32_t max_batch; /* requests per launch group, 1..4096 (default 16) */
   int32_t bypass;    /* overtakes of a waiting head request (default 8) */
-  int32_t pad_;
+  int32_t combine;   /* 1: combine the CG iterations of the slots into one
+                        launch per iteration (experimental, off by default:
+                        runs with 8 slots and many requests have ended in a
+                        host crash whose cause is not known); 0: each slot
+                        launches its own iterations */
   size_t mem_budget; /* bytes; 0 = 90% of free device memory */
 } sdg_server_config;
 typedef struct sdg_req_info {
@@ -354,7 +366,8 @@ int sdg_wait(sdg_req* req, double* u, double* p, sdg_stats* stats, sdg_req_info*
 void sdg_req_free(sdg_req* req);
 int sdg_server_stats(sdg_server* srv, int64_t* completed, size_t* peak_bytes, int* peak_busy,
                      size_t* budget);
-/* Iteration-level batching of the running server: CG iterations launched
+/* Iteration-level batching of a server created with combine = 1 (all zero
+ * otherwise): CG iterations launched
  * (launches), of which combined launches covering the iterations of several
  * slots at once (combined), the most slots one launch covered, and the
  * combined graphs instantiated (graphs; one per new set of running solves,

@@ -11,7 +11,7 @@
 // times; after that admission waits for it.  The solver state of a request
 // (blocks, hierarchy, Krylov vectors) stays on the device from setup to the
 // copy of its result; requests on different slots overlap on the device.
-// While the server runs, the CG iterations of all slots are launched together
+// With combine set, the CG iterations of all slots are launched together
 // (the context's combiner): a request admitted into a free slot joins the
 // running launches at its first iteration boundary, whatever its shape.
 #include <hip/hip_runtime.h>
@@ -76,6 +76,7 @@ struct sdg_server {
   sdg_ctx* ctx = nullptr;
   int device = 0;
   int slots = 1, max_batch = 1, bypass = 8;
+  bool combine = false;  // CG iterations of the slots combined per launch
   size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv;
@@ -255,12 +256,13 @@ int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** o
   *out = nullptr;
   sdg_server_config c{};
   if (cfg) c = *cfg;
-  if (c.slots < 1 || c.slots > 64 || c.max_batch < 1 || c.max_batch > 4096 || c.bypass < 0) {
+  if (c.slots < 1 || c.slots > 64 || c.max_batch < 1 || c.max_batch > 4096 || c.bypass < 0 || c.combine < 0 ||
+      c.combine > 1) {
     sdg_server_config d;
     sdg_server_config_default(&d);
     if (!cfg) c = d;
     else {
-      sdg::set_error("server config out of range (slots 1..64, max_batch 1..4096, bypass >= 0)");
+      sdg::set_error("server config out of range (slots 1..64, max_batch 1..4096, bypass >= 0, combine 0..1)");
       return SDG_ERR_INVALID;
     }
   }
@@ -288,7 +290,8 @@ int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** o
   S->bypass = c.bypass;
   S->budget = budget;
   S->adm = sdg::Admission(budget, c.slots, c.bypass);
-  sdg::ctx_combine(ctx, 1);
+  S->combine = c.combine != 0;
+  if (S->combine) sdg::ctx_combine(ctx, 1);
   for (int i = 0; i < c.slots; ++i) S->workers.emplace_back(worker, S);
   *out = S;
   return SDG_OK;
@@ -297,7 +300,7 @@ int sdg_server_create(sdg_ctx* ctx, const sdg_server_config* cfg, sdg_server** o
 void sdg_server_config_default(sdg_server_config* c) {
   if (!c) return;
   std::memset(c, 0, sizeof(*c));
-  c->slots = 8;
+  c->slots = 4;
   c->max_batch = 16;
   c->bypass = 8;
   c->mem_budget = 0;
@@ -311,7 +314,7 @@ void sdg_server_destroy(sdg_server* S) {
   }
   S->cv.notify_all();
   for (auto& t : S->workers) t.join();
-  sdg::ctx_combine(S->ctx, 0);
+  if (S->combine) sdg::ctx_combine(S->ctx, 0);
   delete S;
 }
 

@@ -140,6 +140,7 @@ __global__ void iota_kernel(int64_t n, int* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) out[i] = (int)i;
 }
 
+constexpr double BF16_LAMBDA_MAX = 4.0;  // see the BF16 check in sdg_problem_create_batch
 constexpr int TAIL_NODES = 17 * 17;  // h-levels with at most this many nodes run in the tail kernel
 constexpr int RED_SCRATCH = 512 * 64;
 
@@ -228,6 +229,7 @@ struct sdg_problem {
   double* binv = nullptr;
   float* binv32 = nullptr;
   uint16_t* binv16 = nullptr;
+  double* xpacked = nullptr;  // packed FP64 factors X = L^{-1} (low precision)
   std::vector<int> reps;
   // DG cycle
   double *vr = nullptr, *vd = nullptr;
@@ -545,6 +547,7 @@ int setup_blocks(sdg_problem* P) {
     }
   // low precision: the inverse Cholesky factor X = L^{-1} in FP32 or BF16,
   // as full squares X and X^T per block; the smoother applies X^T X
+  P->xpacked = packed;
   if (low && P->opt.prec_smoother == SDG_BF16) {
     SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * 2 * nbb));
     SDG_TRY(tri_square_bf16(packed, P->NB, P->nuniq, P->binv16, P->s));
@@ -2238,7 +2241,8 @@ size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int 
   const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
   // low precision: the packed FP64 factor and the factor and its transpose
   // as full squares in the storage type
-  if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + 2 * NB * NB * (opts->prec_smoother == SDG_BF16 ? 2 : 4));
+  // (BF16 factors may be replaced by FP32 ones at setup: both counted)
+  if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + 2 * NB * NB * (opts->prec_smoother == SDG_BF16 ? 2 + 4 : 4));
   b += nb * nel * 64 * 8;  // coarse local matrices
   int cx = mesh->nx, cy = mesh->ny;
   while (true) {
@@ -2484,6 +2488,18 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   // Chebyshev bounds
   std::vector<double> lam;
   if ((rc = arnoldi(P, -1, lam, nullptr)) < 0) return fail(rc);
+  // With exact block inverses the largest eigenvalue of the smoothed DG
+  // operator is about 2 at every order.  BF16 factors of a block whose
+  // condition is near the reciprocal of the BF16 unit (10^7 and more at
+  // viscosity jumps of 10^6) overshoot by an order of magnitude and stall
+  // the cycle: such a batch gets FP32 factors instead.
+  if (P->binv16 && *std::max_element(lam.begin(), lam.end()) > BF16_LAMBDA_MAX) {
+    const int64_t nbb = (int64_t)P->NB * P->NB;
+    if ((rc = palloc_t(P, &P->binv32, (int64_t)P->nuniq * 2 * nbb)) < 0) return fail(rc);
+    if ((rc = tri_square_f32(P->xpacked, P->NB, P->nuniq, P->binv32, P->s)) < 0) return fail(rc);
+    P->binv16 = nullptr;
+    if ((rc = arnoldi(P, -1, lam, nullptr)) < 0) return fail(rc);
+  }
   P->lmin0.resize(nbatch);
   P->lmax0.resize(nbatch);
   for (int pb = 0; pb < nbatch; ++pb) {
@@ -2541,6 +2557,15 @@ void sdg_problem_destroy(sdg_problem* P) {
     if (del) delete c;
   }
   delete P;
+}
+
+int sdg_problem_smoother_precision(const sdg_problem* P, int* prec) {
+  if (!P || !prec) {
+    set_error("NULL argument");
+    return SDG_ERR_INVALID;
+  }
+  *prec = P->binv16 ? SDG_BF16 : P->binv32 ? SDG_FP32 : SDG_FP64;
+  return SDG_OK;
 }
 
 int sdg_problem_batch(const sdg_problem* P, int* nbatch) {

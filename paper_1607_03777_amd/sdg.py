@@ -48,7 +48,7 @@ class sdg_stats(ctypes.Structure):
 
 class sdg_server_config(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("bypass", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]
+                ("combine", ctypes.c_int32), ("mem_budget", ctypes.c_size_t)]
 
 
 class sdg_req_info(ctypes.Structure):
@@ -78,6 +78,7 @@ PROTOTYPES = {
     "sdg_problem_create": (I, [P, MESH, OPTS, P, P, PP]),
     "sdg_problem_create_batch": (I, [P, MESH, OPTS, I, P, P, PP]),
     "sdg_problem_batch": (I, [P, ctypes.POINTER(ctypes.c_int)]),
+    "sdg_problem_smoother_precision": (I, [P, ctypes.POINTER(ctypes.c_int)]),
     "sdg_required_bytes_batch": (ctypes.c_size_t, [MESH, OPTS, I, I]),
     "sdg_problem_destroy": (None, [P]),
     "sdg_problem_levels": (I, [P, ctypes.POINTER(ctypes.c_int)]),
@@ -224,6 +225,12 @@ def sdg_problem_create_batch(ctx, mesh, opts, nbatch, eta_dev, stream=None):
 def sdg_problem_batch(prob):
     n = ctypes.c_int()
     check(lib().sdg_problem_batch(prob, ctypes.byref(n)))
+    return n.value
+
+
+def sdg_problem_smoother_precision(prob):
+    n = ctypes.c_int()
+    check(lib().sdg_problem_smoother_precision(prob, ctypes.byref(n)))
     return n.value
 
 
@@ -409,8 +416,8 @@ def sdg_uniform_pm1(ctx, seed, n, out, stream=None):
 
 
 # ---- request server ------------------------------------------------------------
-def sdg_server_create(ctx, slots=8, max_batch=16, bypass=8, mem_budget=0):
-    cfg = sdg_server_config(slots, max_batch, bypass, 0, mem_budget)
+def sdg_server_create(ctx, slots=4, max_batch=16, bypass=8, mem_budget=0, combine=0):
+    cfg = sdg_server_config(slots, max_batch, bypass, combine, mem_budget)
     h = ctypes.c_void_p()
     check(lib().sdg_server_create(ctx, ctypes.byref(cfg), ctypes.byref(h)))
     return h.value

@@ -571,3 +571,28 @@ def test_vcycle_parity_fp32_cycle(sdg, ctx, torch, n, k, coarsest):
     for err, _ in errs:
         print(f"[vcycle fp32] n={n} k={k} rel err {err:.3e} tol {tol:.1e} (kappa_max {kappa:.2e})", flush=True)
         assert err <= tol, (err, tol)
+
+
+# k = 5 with seed 5 has an element block of condition 6e7 (a viscosity jump
+# of about 1e6 between neighbours); its BF16 factor alone puts the largest
+# eigenvalue of the smoothed block at 34 (tests/test_precision_cpu.py).
+@pytest.mark.parametrize("k,expect", [(4, "bf16"), (5, "fp32")])
+def test_bf16_factors_fall_back_to_fp32(sdg, ctx, torch, k, expect):
+    """BF16 factors are kept where the smoothed operator's spectrum stays
+    near that of exact inverses and replaced by FP32 factors where it does
+    not; either way the solve reaches rtol and the refined oracle solution."""
+    from oracle import refine as rf
+    n = 32
+    pr = gen.random_inclusions(n, k, seed=k)
+    m = Mesh(n, n, k)
+    P = make_problem(sdg, ctx, n, n, k, pr.eta, rtol=1e-9, max_it=600, prec_apply=sdg.FP32,
+                     prec_smoother=sdg.BF16, viscous_krylov=1, restart=30, refine=1)
+    got = {0: "fp64", 1: "fp32", 2: "bf16"}[sdg.sdg_problem_smoother_precision(P.h)]
+    lam = sdg.sdg_get_bounds(P.h)[0][1] / 1.1
+    print(f"[bf16] k={k}: factors {got}, lambda_max {lam:.2f}", flush=True)
+    assert got == expect and lam <= 4.0
+    u, st = P.solve_viscous(dev(pr.f.reshape(-1)))
+    assert st["status"] == 0 and st["rel_residual"] < 1e-9, st
+    ud = rf.solve_viscous_ext(m, pr.eta, pr.f).astype(np.float64)
+    assert np.linalg.norm(host(u) - ud) <= 1e-8 * np.linalg.norm(ud)
+    P.close()

@@ -103,18 +103,25 @@ def test_server_rejects_request_over_budget(sdg, torch):
         sdg.sdg_destroy(ctx)
 
 
-def test_server_staggered_mixed_precision_matches_alone_and_oracle(sdg, torch):
+# Combined launches (combine = 1) passed this test at this size, but runs of
+# the request server with 8 slots and many requests (512 random-field
+# viscous requests; 24 Poisson-arrival Stokes requests) ended in a host
+# segmentation fault whose cause is not known; the option is off by default
+# and its test stays skipped until the cause is found.
+@pytest.mark.parametrize("combine", [
+    0, pytest.param(1, marks=pytest.mark.skip(reason="combined launches: host crash at scale, cause not found"))])
+def test_server_staggered_mixed_precision_matches_alone_and_oracle(sdg, torch, combine):
     """Requests of different shapes and kinds arriving one after another
     (staggered by a few milliseconds, while earlier ones run) with the
     mixed-precision options the serving workload uses (FP32 fine-level
-    cycle, extended refinement): the later ones join the running combined
-    launches (some launch covers several slots), requests overlap in time,
-    and every result equals the same solve alone and the refined oracle
-    solution."""
+    cycle, extended refinement): requests overlap in time (with combine,
+    the later ones join the running combined launches, some launch covering
+    several slots), and every result equals the same solve alone and the
+    refined oracle solution."""
     import time
     from oracle import refine as rf
     ctx = sdg.sdg_create(0, 0)
-    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=2)
+    srv = sdg.sdg_server_create(ctx, slots=4, max_batch=2, combine=combine)
     try:
         # the pressure amplifies the residual by about 2e4 on the random
         # problems (measured: rtol 1e-10 leaves 2e-6 in p), so rtol is 1e-13
@@ -137,7 +144,10 @@ def test_server_staggered_mixed_precision_matches_alone_and_oracle(sdg, torch):
             results.append((u, p, info))
         ls = sdg.sdg_server_launch_stats(srv)
         print(f"[staggered] launch stats {ls}", flush=True)
-        assert ls["combined"] >= 1 and ls["max_width"] >= 2
+        if combine:
+            assert ls["combined"] >= 1 and ls["max_width"] >= 2
+        else:
+            assert ls["launches"] == 0
         iv = [(r[2]["start_ms"], r[2]["end_ms"]) for r in results]
         overlap = max(min(a[1], b[1]) - max(a[0], b[0]) for i, a in enumerate(iv) for b in iv[i + 1:])
         assert overlap > 0  # at least two requests ran at the same time
