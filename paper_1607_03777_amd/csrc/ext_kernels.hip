@@ -35,6 +35,21 @@
 #include "sdg_common.h"
 #include "ext_kernels.h"
 
+// elements per workgroup of the velocity-row kernel (k <= 4, k >= 5) and the
+// unroll depth of its column loop
+// (measured at 64 x 64 x 16, k = 4, and 256 x 256, k = 3..6: two elements
+// per workgroup were fastest at every order, 1.2-3.4x faster than one, and
+// 8 the slowest; the unroll depth made no difference)
+#ifndef EXT_G_LOW
+#define EXT_G_LOW 2
+#endif
+#ifndef EXT_G_HIGH
+#define EXT_G_HIGH 2
+#endif
+#ifndef EXT_UNROLL
+#define EXT_UNROLL 4
+#endif
+
 namespace sdg {
 
 // ---------------------------------------------------------------------------
@@ -375,7 +390,64 @@ __device__ __forceinline__ int nbr(int S, int ix, int iy, int nx, int ny) {
 }
 
 // Velocity rows: r = F - A x - B p (ABS: |A||x| + |B||p|), x = xh + xl.
-// One workgroup per (element, problem); thread a = row a.
+// One workgroup per row of G consecutive elements of one problem (the last
+// group of a mesh row may be partial), thread a = row a of every element of
+// the group: each entry of a unit block is read once and applied to all
+// elements that use that block, with their own scalars.  The vectors of the
+// group, its two x-neighbours outside it and the elements above and below it
+// are staged in LDS as (hi, lo) pairs.
+//
+// The sum over a block's columns is formed by Dot2 (Ogita, Rump and Oishi,
+// "Accurate sum and dot product", 2005), adapted to operands given as
+// double-FP64 pairs: the product of the high parts is split exactly by an
+// FMA (TwoProduct), the running sum by TwoSum, and the two cross products
+// with the low parts (whose own rounding is far below the result's
+// accuracy) go into the low word with the error terms.  The block's sum is
+// then scaled by its scalar and subtracted from the row in full double-FP64.
+// Sums of one block's row a against the vectors VS(e) of the group members
+// in mask, into (sh, sl) per member; then acc -= SC(e) * sum per member.
+template <int N, int G, bool ABS, typename VS, typename SC>
+__device__ __forceinline__ void blk_apply(const double2* __restrict__ T, int a, int ld, unsigned mask, VS vs, SC sc,
+                                          dd (&acc)[G]) {
+  double sh[G], sl[G];
+#pragma unroll
+  for (int e = 0; e < G; ++e) sh[e] = sl[e] = 0.0;
+  // unrolled EXT_UNROLL columns deep: the loads of the next columns are in
+  // flight while the current ones are summed
+#pragma unroll EXT_UNROLL
+  for (int b = 0; b < N; ++b) {
+    const double2 c = T[(size_t)b * ld + a];
+    // every member is summed (slots of absent elements hold zeros): no
+    // branch in the loop; the mask applies when the sums are used
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const double2 x = vs(e)[b];
+      if (ABS) {
+        sh[e] += fabs(c.x) * fabs(x.x);
+      } else {
+        const double p = c.x * x.x;
+        const double pe = __builtin_fma(c.x, x.x, -p);
+        const double cross = __builtin_fma(c.x, x.y, c.y * x.x);
+        const dd s = two_sum(sh[e], p);
+        sh[e] = s.hi;
+        sl[e] += s.lo + (pe + cross);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    if (!(mask & (1u << e))) continue;
+    const dd scal = sc(e);
+    if (ABS) {
+      acc[e].hi += fabs(scal.hi) * sh[e];
+    } else {
+      acc[e] = dd_add(acc[e], dd_neg(dd_mul(scal, two_sum(sh[e], sl[e]))));
+    }
+  }
+}
+
+template <int K1> struct ExtGroup { static constexpr int G = K1 <= 5 ? EXT_G_LOW : EXT_G_HIGH; };
+
 template <int K1, bool ABS>
 __global__ __launch_bounds__(128) void ext_u_kernel(MeshDev M, const double* __restrict__ eta,
                                                      const double* __restrict__ F, const double* __restrict__ xh,
@@ -384,17 +456,31 @@ __global__ __launch_bounds__(128) void ext_u_kernel(MeshDev M, const double* __r
                                                      const double2* __restrict__ TB, double2 cx, double2 cy,
                                                      double* __restrict__ r) {
   constexpr int NB = 2 * K1 * K1, NP = (K1 - 1) * (K1 - 1), NPm = NP > 0 ? NP : 1;
-  __shared__ double2 xs[5][NB];
-  __shared__ double2 ps[5][NPm];
-  const int nel = M.nx * M.ny;
-  const int e = blockIdx.x, pb = blockIdx.y;
-  const int ix = e % M.nx, iy = e / M.nx;
+  constexpr int G = ExtGroup<K1>::G;
+  // slots: 0..G-1 the group, G left of it, G+1 right of it, G+2.. below, 2G+2.. above
+  constexpr int NSLOT = 3 * G + 2;
+  __shared__ double2 xs[NSLOT][NB];
+  __shared__ double2 ps[NSLOT][NPm];
+  __shared__ double es[NSLOT];
+  const int nx = M.nx, ny = M.ny, nel = nx * ny;
+  const int ngx = (nx + G - 1) / G;
+  const int iy = blockIdx.x / ngx, ix0 = (blockIdx.x - iy * ngx) * G;
+  const int pb = blockIdx.y;
   const int64_t off = (int64_t)pb * nel;
-  int nbs[4];
-  for (int S = 0; S < 4; ++S) nbs[S] = nbr(S, ix, iy, M.nx, M.ny);
-  for (int i = threadIdx.x; i < 5 * NB; i += blockDim.x) {
-    const int slot = i / NB, a = i - slot * NB;
-    const int el = slot == 0 ? e : nbs[slot - 1];
+  const int ng = nx - ix0 < G ? nx - ix0 : G;  // elements in this group
+  // element of slot q, or -1
+  auto slot_el = [&](int q) -> int {
+    if (q < G) return q < ng ? iy * nx + ix0 + q : -1;
+    if (q == G) return ix0 > 0 ? iy * nx + ix0 - 1 : -1;
+    if (q == G + 1) return ix0 + G < nx ? iy * nx + ix0 + G : -1;
+    const int i = (q - G - 2) % G, above = (q - G - 2) / G;
+    if (i >= ng) return -1;
+    const int jy = above ? iy + 1 : iy - 1;
+    return (jy >= 0 && jy < ny) ? jy * nx + ix0 + i : -1;
+  };
+  for (int q = threadIdx.x; q < NSLOT * NB; q += blockDim.x) {
+    const int slot = q / NB, a = q - slot * NB;
+    const int el = slot_el(slot);
     double2 v = make_double2(0.0, 0.0);
     if (el >= 0) {
       const int64_t g = (off + el) * NB + a;
@@ -403,9 +489,9 @@ __global__ __launch_bounds__(128) void ext_u_kernel(MeshDev M, const double* __r
     xs[slot][a] = v;
   }
   if (ph && NP > 0)
-    for (int i = threadIdx.x; i < 5 * NP; i += blockDim.x) {
-      const int slot = i / NP, m = i - slot * NP;
-      const int el = slot == 0 ? e : nbs[slot - 1];
+    for (int q = threadIdx.x; q < NSLOT * NP; q += blockDim.x) {
+      const int slot = q / NP, m = q - slot * NP;
+      const int el = slot_el(slot);
       double2 v = make_double2(0.0, 0.0);
       if (el >= 0) {
         const int64_t g = (off + el) * NP + m;
@@ -413,55 +499,93 @@ __global__ __launch_bounds__(128) void ext_u_kernel(MeshDev M, const double* __r
       }
       ps[slot][m] = v;
     }
+  for (int q = threadIdx.x; q < NSLOT; q += blockDim.x) {
+    const int el = slot_el(q);
+    es[q] = el >= 0 ? eta[off + el] : 0.0;
+  }
   __syncthreads();
   const int a = threadIdx.x;
   if (a >= NB) return;
-  const double ee = eta[off + e];
-  const dd de = {ee, 0.0};
-  dd acc = {0.0, 0.0};
-  if (!ABS) acc = {F[(off + e) * NB + a], 0.0};
-  acc = acc_sub<ABS>(acc, de, col_dot<NB, ABS>(TA + (size_t)EXT_V * NB * NB, a, NB, xs[0]));
+  unsigned own = 0;  // elements of the group
+#pragma unroll
+  for (int e = 0; e < G; ++e)
+    if (e < ng) own |= 1u << e;
+  dd acc[G];
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const double F0 = (!ABS && e < ng) ? F[(off + iy * nx + ix0 + e) * NB + a] : 0.0;
+    acc[e] = {F0, 0.0};
+  }
+  auto self = [&](int e) -> const double2* { return xs[e]; };
+  auto selfp = [&](int e) -> const double2* { return ps[e]; };
+  auto de = [&](int e) -> dd { return {es[e], 0.0}; };
+  auto one = [&](int) -> dd { return {1.0, 0.0}; };
+  blk_apply<NB, G, ABS>(TA + (size_t)EXT_V * NB * NB, a, NB, own, self, de, acc);
   for (int S = 0; S < 4; ++S) {
     const int dir = S >> 1;
     const dd cpen = mk(dir == 0 ? cx : cy);
-    const int N = nbs[S];
-    if (N >= 0) {
+    // the neighbour's slot of member e across side S
+    auto nslot = [&](int e) -> int {
+      return S == 0 ? (e > 0 ? e - 1 : G) : S == 1 ? (e + 1 < ng ? e + 1 : G + 1) : S == 2 ? G + 2 + e : 2 * G + 2 + e;
+    };
+    unsigned inner = 0;
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int ixe = ix0 + e;
+      const bool has = e < ng && (S == 0 ? ixe > 0 : S == 1 ? ixe + 1 < nx : S == 2 ? iy > 0 : iy + 1 < ny);
+      if (has) inner |= 1u << e;
+    }
+    const unsigned bnd = (M.bc[S] != SDG_NEUMANN) ? (own & ~inner) : 0u;
+    auto nbv = [&](int e) -> const double2* { return xs[nslot(e)]; };
+    auto nbp = [&](int e) -> const double2* { return ps[nslot(e)]; };
+    auto en = [&](int e) -> dd { return {es[nslot(e)], 0.0}; };
+    auto sig = [&](int e) -> dd {
+      const double ee = es[e], enb = es[nslot(e)];
+      return dd_mul({4.0 * (ee > enb ? ee : enb), 0.0}, cpen);
+    };
+    auto sigb = [&](int e) -> dd { return dd_mul({8.0 * es[e], 0.0}, cpen); };
+    if (inner) {
       const int t = (S & 1) ? 0 : 1;  // right/top side: the element is the minus side
-      const double en = eta[off + N];
-      const dd sig = dd_mul({4.0 * (ee > en ? ee : en), 0.0}, cpen);
       const double2* base = TA + (size_t)ext_face_base(dir, t) * NB * NB;
-      acc = acc_sub<ABS>(acc, de, col_dot<NB, ABS>(base + (size_t)EXT_SELF12 * NB * NB, a, NB, xs[0]));
-      acc = acc_sub<ABS>(acc, sig, col_dot<NB, ABS>(base + (size_t)EXT_SELF3 * NB * NB, a, NB, xs[0]));
-      acc = acc_sub<ABS>(acc, {en, 0.0}, col_dot<NB, ABS>(base + (size_t)EXT_NB1 * NB * NB, a, NB, xs[1 + S]));
-      acc = acc_sub<ABS>(acc, de, col_dot<NB, ABS>(base + (size_t)EXT_NB2 * NB * NB, a, NB, xs[1 + S]));
-      acc = acc_sub<ABS>(acc, sig, col_dot<NB, ABS>(base + (size_t)EXT_NB3 * NB * NB, a, NB, xs[1 + S]));
+      blk_apply<NB, G, ABS>(base + (size_t)EXT_SELF12 * NB * NB, a, NB, inner, self, de, acc);
+      blk_apply<NB, G, ABS>(base + (size_t)EXT_SELF3 * NB * NB, a, NB, inner, self, sig, acc);
+      blk_apply<NB, G, ABS>(base + (size_t)EXT_NB1 * NB * NB, a, NB, inner, nbv, en, acc);
+      blk_apply<NB, G, ABS>(base + (size_t)EXT_NB2 * NB * NB, a, NB, inner, nbv, de, acc);
+      blk_apply<NB, G, ABS>(base + (size_t)EXT_NB3 * NB * NB, a, NB, inner, nbv, sig, acc);
       if (ph && NP > 0) {
         const double2* bb = TB + (size_t)ext_bface(dir, t) * NB * NPm;
-        acc = acc_sub<ABS>(acc, {1.0, 0.0}, col_dot<NP, ABS>(bb, a, NB, ps[0]));
-        acc = acc_sub<ABS>(acc, {1.0, 0.0}, col_dot<NP, ABS>(bb + (size_t)NB * NPm, a, NB, ps[1 + S]));
+        blk_apply<NP, G, ABS>(bb, a, NB, inner, selfp, one, acc);
+        blk_apply<NP, G, ABS>(bb + (size_t)NB * NPm, a, NB, inner, nbp, one, acc);
       }
-    } else if (M.bc[S] != SDG_NEUMANN) {
-      const dd sig = dd_mul({8.0 * ee, 0.0}, cpen);
-      acc = acc_sub<ABS>(acc, de, col_dot<NB, ABS>(TA + (size_t)(EXT_BND + 2 * S) * NB * NB, a, NB, xs[0]));
-      acc = acc_sub<ABS>(acc, sig, col_dot<NB, ABS>(TA + (size_t)(EXT_BND + 2 * S + 1) * NB * NB, a, NB, xs[0]));
-      if (ph && NP > 0)
-        acc = acc_sub<ABS>(acc, {1.0, 0.0},
-                           col_dot<NP, ABS>(TB + (size_t)(EXT_BBND + S) * NB * NPm, a, NB, ps[0]));
+    }
+    if (bnd) {
+      blk_apply<NB, G, ABS>(TA + (size_t)(EXT_BND + 2 * S) * NB * NB, a, NB, bnd, self, de, acc);
+      blk_apply<NB, G, ABS>(TA + (size_t)(EXT_BND + 2 * S + 1) * NB * NB, a, NB, bnd, self, sigb, acc);
+      if (ph && NP > 0) blk_apply<NP, G, ABS>(TB + (size_t)(EXT_BBND + S) * NB * NPm, a, NB, bnd, selfp, one, acc);
     }
   }
-  if (ph && NP > 0)
-    acc = acc_sub<ABS>(acc, {1.0, 0.0}, col_dot<NP, ABS>(TB + (size_t)EXT_BVOL * NB * NPm, a, NB, ps[0]));
-  r[(off + e) * NB + a] = acc.hi + acc.lo;
+  if (ph && NP > 0) blk_apply<NP, G, ABS>(TB + (size_t)EXT_BVOL * NB * NPm, a, NB, own, selfp, one, acc);
+#pragma unroll
+  for (int e = 0; e < G; ++e)
+    if (e < ng) r[(off + iy * nx + ix0 + e) * NB + a] = acc[e].hi + acc[e].lo;
 }
 
-// Pressure rows: r = G - B^T u (ABS: |B^T||u|).  One workgroup per
-// (element, problem); thread m = pressure mode m.  Row-major B blocks: entry
-// (a, m) at a * NP + m.
+// Pressure rows: r = G - B^T u (ABS: |B^T||u|).  One 64-lane workgroup per
+// (element, problem); every pressure row m has L = 64 / NP lanes (a power of
+// two) that share its columns: lane (m, l) sums the columns b = l mod L of
+// all of the row's blocks by Dot2 (the blocks' scalars are all 1), and the
+// L partial sums are combined in double-FP64 through lane shuffles.
+// Row-major B blocks: entry (a, m) at a * NP + m.
+template <int NP>
+struct PRowLanes {
+  static constexpr int L = NP <= 1 ? 64 : NP <= 2 ? 32 : NP <= 4 ? 16 : NP <= 8 ? 8 : NP <= 16 ? 4 : NP <= 32 ? 2 : 1;
+};
 template <int K1, bool ABS>
 __global__ __launch_bounds__(64) void ext_p_kernel(MeshDev M, const double* __restrict__ G,
                                                     const double* __restrict__ uh, const double* __restrict__ ul,
                                                     const double2* __restrict__ TBp, double* __restrict__ r) {
   constexpr int NB = 2 * K1 * K1, NP = (K1 - 1) * (K1 - 1), NPm = NP > 0 ? NP : 1;
+  constexpr int L = PRowLanes<NPm>::L;
   __shared__ double2 us[5][NB];
   const int nel = M.nx * M.ny;
   const int e = blockIdx.x, pb = blockIdx.y;
@@ -480,25 +604,49 @@ __global__ __launch_bounds__(64) void ext_p_kernel(MeshDev M, const double* __re
     us[slot][a] = v;
   }
   __syncthreads();
-  const int m = threadIdx.x;
-  if (m >= NP) return;
-  const dd one = {1.0, 0.0};
-  dd acc = {0.0, 0.0};
-  if (!ABS) acc = {G[(off + e) * NP + m], 0.0};
-  acc = acc_sub<ABS>(acc, one, col_dot<NB, ABS>(TBp + (size_t)EXT_BVOL * NB * NPm, m, NPm, us[0]));
+  const int m = threadIdx.x / L, l = threadIdx.x - m * L;
+  const bool row = m < NP;
+  double sh = 0.0, sl = 0.0;
+  // columns l, l + L, ... of block blk against slot vector u
+  auto blk = [&](int bi, const double2* u) {
+    const double2* T = TBp + (size_t)bi * NB * NPm;
+    for (int b = l; b < NB; b += L) {
+      const double2 c = T[(size_t)b * NPm + (row ? m : 0)];
+      const double2 x = u[b];
+      if (ABS) {
+        sh += fabs(c.x) * fabs(x.x);
+      } else {
+        const double p = c.x * x.x;
+        const double pe = __builtin_fma(c.x, x.x, -p);
+        const double cross = __builtin_fma(c.x, x.y, c.y * x.x);
+        const dd s2 = two_sum(sh, p);
+        sh = s2.hi;
+        sl += s2.lo + (pe + cross);
+      }
+    }
+  };
+  blk(EXT_BVOL, us[0]);
   for (int S = 0; S < 4; ++S) {
     const int dir = S >> 1;
-    const int N = nbs[S];
-    if (N >= 0) {
+    if (nbs[S] >= 0) {
       const int s = (S & 1) ? 0 : 1;  // the element's side of the face
       // self: pressure side s, velocity side s; neighbour: velocity side 1 - s
-      acc = acc_sub<ABS>(acc, one, col_dot<NB, ABS>(TBp + (size_t)ext_bface(dir, s) * NB * NPm, m, NPm, us[0]));
-      acc = acc_sub<ABS>(acc, one,
-                         col_dot<NB, ABS>(TBp + (size_t)(ext_bface(dir, 1 - s) + 1) * NB * NPm, m, NPm, us[1 + S]));
+      blk(ext_bface(dir, s), us[0]);
+      blk(ext_bface(dir, 1 - s) + 1, us[1 + S]);
     } else if (M.bc[S] != SDG_NEUMANN) {
-      acc = acc_sub<ABS>(acc, one, col_dot<NB, ABS>(TBp + (size_t)(EXT_BBND + S) * NB * NPm, m, NPm, us[0]));
+      blk(EXT_BBND + S, us[0]);
     }
   }
+  // combine the row's L lanes (adjacent lanes) in double-FP64
+  dd t = ABS ? dd{sh, 0.0} : two_sum(sh, sl);
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) {
+    const double oh = __shfl_xor(t.hi, o, 64), ol = __shfl_xor(t.lo, o, 64);
+    t = ABS ? dd{t.hi + oh, 0.0} : dd_add(t, {oh, ol});
+  }
+  if (!row || l != 0) return;
+  dd acc = ABS ? dd{0.0, 0.0} : dd{G[(off + e) * NP + m], 0.0};
+  acc = ABS ? dd{t.hi, 0.0} : dd_add(acc, dd_neg(t));
   r[(off + e) * NP + m] = acc.hi + acc.lo;
 }
 
@@ -517,14 +665,17 @@ template <int K1>
 int ext_launch(const MeshDev& M, int nbatch, bool abs_mode, const double* eta, const double* F, const double* xh,
                const double* xl, const double* ph, const double* pl, const double* G, const ExtTables& T,
                double* r_u, double* r_p, hipStream_t s) {
-  const dim3 grid(M.nx * M.ny, nbatch);
+  constexpr int GE = ExtGroup<K1>::G;
+  constexpr int NTU = (2 * K1 * K1 + 63) / 64 * 64;  // one thread per row, whole wavefronts
+  const dim3 grid_u(((M.nx + GE - 1) / GE) * M.ny, nbatch);
   if (abs_mode)
-    hipLaunchKernelGGL((ext_u_kernel<K1, true>), grid, dim3(128), 0, s, M, eta, F, xh, xl, ph, pl, T.A, T.Bu,
+    hipLaunchKernelGGL((ext_u_kernel<K1, true>), grid_u, dim3(NTU), 0, s, M, eta, F, xh, xl, ph, pl, T.A, T.Bu,
                        T.cpen[0], T.cpen[1], r_u);
   else
-    hipLaunchKernelGGL((ext_u_kernel<K1, false>), grid, dim3(128), 0, s, M, eta, F, xh, xl, ph, pl, T.A, T.Bu,
+    hipLaunchKernelGGL((ext_u_kernel<K1, false>), grid_u, dim3(NTU), 0, s, M, eta, F, xh, xl, ph, pl, T.A, T.Bu,
                        T.cpen[0], T.cpen[1], r_u);
   SDG_CHECK_LAUNCH();
+  const dim3 grid(M.nx * M.ny, nbatch);
   if (r_p && K1 > 1) {
     if (abs_mode)
       hipLaunchKernelGGL((ext_p_kernel<K1, true>), grid, dim3(64), 0, s, M, G, xh, xl, T.Bp, r_p);
