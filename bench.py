@@ -265,6 +265,53 @@ def sinker_leg(sdg, ctx, torch, sizes, ks):
     return {"workload": "six-sinkers-eta1e6-gcr-rtol1e-6-inner1e-3", "runs": rows}
 
 
+def sweep_leg(sdg, ctx, torch, full):
+    """Sections 8.1 and 8.2 with the paper's solver settings (FGMRES rtol
+    1e-6 on the Stokes system, inner CG rtol 1e-3, a 16 x 16 coarsest
+    h-level as its level counts imply, FP64 with the extended refinement,
+    which contrast 1e8 needs to reach 1e-6, Section 8.3.1): the SolCx-shaped field
+    (jump along x = 0.5) at k = 2, contrast 1 and 1e6, and the 2 x 2
+    checkerboard at k = 1..3, contrast 1e3, 1e6, 1e8, with this library's
+    own smooth force; per solve the outer and inner iteration counts and
+    the time with setup, next to Tables 2 and 3 (context, one core of the
+    paper's machine)."""
+    from paper_1607_03777_amd import inputs as gen
+    tables = json.load(open(os.path.join(ROOT, "tests", "golden", "solcx_tables.json")))
+    t2, t3 = tables["table2_solcx_k2"], tables["table3_checkerboard"]
+    cases = [("solcx", 2, d, n) for d in (1.0, 1e6) for n in (64, 128, 256, 512)]
+    cases += [("checker", k, d, n) for d in (1e3, 1e6, 1e8) for k in (1, 2, 3)
+              for n in ((64, 128, 256, 512, 1024) if full else (64, 256))]
+    if not full:
+        cases += [("checker", 1, d, 1024) for d in (1e3, 1e6, 1e8)]
+    rows = []
+    for shape, k, d, n in cases:
+        pr = (gen.solcx_like if shape == "solcx" else gen.checkerboard)(n, k, d)
+        eta = torch.as_tensor(pr.eta, device="cuda")
+        f = torch.as_tensor(pr.f.reshape(-1), device="cuda")
+        u = torch.zeros(pr.nu, dtype=torch.float64, device="cuda")
+        p = torch.zeros(pr.np_, dtype=torch.float64, device="cuda")
+        ul, pl = torch.zeros_like(u), torch.zeros_like(p)
+        opts = sdg.make_options(rtol=1e-6, inner_rtol=1e-3, max_it=400, coarsest_n=16, refine=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = sdg.sdg_problem_create(ctx, sdg.make_mesh(n, n, k), opts, eta, sdg.current_stream())
+        rc, st = sdg.sdg_solve_stokes_ext_dev(h, f, None, u, ul, p, pl)
+        sdg.sdg_problem_destroy(h)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        dkey = "1" if d == 1.0 else f"1e{int(round(np.log10(d)))}"
+        paper = (t2.get(str(n), {}).get(dkey) if shape == "solcx" else t3.get(dkey, {}).get(str(n), {}).get(str(k)))
+        row = {"shape": shape, "k": k, "deta": d, "n": n, "seconds": t, "status": st["status"],
+               "outer_its": st["outer_its"], "inner_avg": st["inner_its_total"] / max(st["outer_its"], 1),
+               "inner_max": st["inner_its_max"], "rel_residual": st["rel_residual"]}
+        if paper:
+            row["paper"] = {"outer_its": paper[0], "inner_avg": paper[1], "inner_max": paper[2], "seconds": paper[3]}
+        rows.append(row)
+        log(f"[bench] {shape} k={k} deta={d:g} {n}x{n}: {t:.2f} s outer {st['outer_its']} inner avg "
+            f"{row['inner_avg']:.1f} max {st['inner_its_max']} status {st['status']}" + (f" (paper: {paper})" if paper else ""))
+    return {"workload": "solcx-shaped-and-checkerboard-fgmres1e-6-inner1e-3-coarsest16", "runs": rows}
+
+
 def batched_leg(sdg, ctx, torch, nreq, pool):
     """Batching form: nreq independent viscous solves, n in {16, 32, 64,
     128}, k in 2..5, log10 viscosity a Gaussian random field (correlation
@@ -573,6 +620,8 @@ def main():
     ap.add_argument("--serve-kmax", type=int, default=6)
     ap.add_argument("--serve-prec", choices=list(PRECS), default="fp32")
     ap.add_argument("--sinkers", default="64,128,256", help="mesh sizes of the six-inclusion leg ('' = skip)")
+    ap.add_argument("--sweeps", choices=["default", "full", "none"], default="default",
+                    help="SolCx-shaped and checkerboard sweeps (full: up to 1024^2 at every k)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle's accuracy checks")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the traced step after the timed region (per-kernel breakdown)")
@@ -767,6 +816,8 @@ def main():
         out["c3"] = c3_leg(sdg, ctx, torch, [int(x) for x in args.c3.split(",")], args.c3_prec)
     if args.sinkers:
         out["sinkers"] = sinker_leg(sdg, ctx, torch, [int(x) for x in args.sinkers.split(",")], (1, 2, 3))
+    if args.sweeps != "none":
+        out["sweeps"] = sweep_leg(sdg, ctx, torch, args.sweeps == "full")
     if args.batched > 0:
         out["batched"] = batched_leg(sdg, ctx, torch, args.batched, pool)
     # the request-server legs run in child processes with contexts of their

@@ -340,3 +340,52 @@ def six_sinkers(n, k, eta2=1e6, rho2=1.2, eta1=1.0, rho1=1.0, g=10.0):
     f = constant_force_modes(np.zeros(n * n), -g * rho, n, n, k)
     return Problem(n, n, k, eta, f, None, bc=(NAVIER, NAVIER, NAVIER, NEUMANN),
                    name=f"sinkers-{n}x{n}-k{k}-eta{eta2:g}", meta={"eta2": eta2, "rho2": rho2, "g": g})
+
+
+def smooth_force_elements(n, seed, nmodes=8):
+    """Element-wise constant force: the seeded low Fourier modes of
+    smooth_force sampled at the element centres (cheap at any mesh size);
+    a force of this library's own, not a benchmark's."""
+    rng = np.random.default_rng(seed + 7919)
+    kx = rng.integers(1, 4, (nmodes, 2))
+    ky = rng.integers(1, 4, (nmodes, 2))
+    amp = rng.normal(0.0, 1.0, (nmodes, 2))
+    ph = rng.uniform(0.0, 2 * np.pi, (nmodes, 2))
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c)  # [iy][ix]
+    fx = np.zeros_like(X)
+    fy = np.zeros_like(X)
+    for i in range(nmodes):
+        fx += amp[i, 0] * np.sin(np.pi * kx[i, 0] * X + ph[i, 0]) * np.cos(np.pi * ky[i, 0] * Y)
+        fy += amp[i, 1] * np.cos(np.pi * kx[i, 1] * X) * np.sin(np.pi * ky[i, 1] * Y + ph[i, 1])
+    return fx.reshape(-1), fy.reshape(-1)
+
+
+def solcx_like(n, k, deta, seed=0):
+    """The viscosity structure of the SolCx runs (Sections 7 and 8.1): one
+    jump along x = 0.5, viscosity deta for x < 0.5 and 1 for x > 0.5
+    (contrast eta_1 : eta_2 = deta, eta_2 = 1), Navier on all sides; with an
+    even n the jump lies on element edges.  The force is this library's
+    seeded smooth field (smooth_force_elements): the benchmark's own
+    forcing and analytic solution are not used."""
+    c = (np.arange(n) + 0.5) / n
+    X, _ = np.meshgrid(c, c)
+    eta = np.where(X.reshape(-1) < 0.5, float(deta), 1.0)
+    fx, fy = smooth_force_elements(n, seed)
+    f = constant_force_modes(fx, fy, n, n, k)
+    return Problem(n, n, k, eta, f, None, name=f"solcx-like-{n}x{n}-k{k}-deta{deta:g}", meta={"deta": deta})
+
+
+def checkerboard(n, k, deta, seed=0):
+    """The 2 x 2 checkerboard of Section 8.2: the SolCx jump along x = 0.5
+    and a second one along y = 0.5; viscosity deta on the quadrants
+    x < 0.5, y < 0.5 and x > 0.5, y > 0.5, and 1 on the other two; Navier on
+    all sides; the force as in solcx_like."""
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c)
+    hi = (X < 0.5) == (Y < 0.5)
+    eta = np.where(hi.reshape(-1), float(deta), 1.0)
+    fx, fy = smooth_force_elements(n, seed)
+    f = constant_force_modes(fx, fy, n, n, k)
+    return Problem(n, n, k, eta, f, None, name=f"checkerboard-{n}x{n}-k{k}-deta{deta:g}", meta={"deta": deta})
+

@@ -1,0 +1,109 @@
+"""SolCx-shaped and checkerboard viscosity structures (Sections 8.1 and
+8.2) through the C ABI: solutions against the refined oracle on small
+meshes, and, with the paper's solver settings (FGMRES rtol 1e-6, inner CG
+rtol 1e-3, a 16 x 16 coarsest h-level as the paper's level counts imply,
+extended refinement where FP64 alone stalls, Section 8.3.1), the
+iteration-count trends of Tables 2 and 3: outer iterations nearly
+independent of the mesh, inner iterations growing with k.  The counts
+are compared with the tables only qualitatively (parity unpinned: the
+force here is this library's own smooth field, not the benchmark's)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import refine as rf
+from oracle.mesh import Mesh
+from paper_1607_03777_amd import inputs as gen
+
+from gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sdg(torch):
+    from paper_1607_03777_amd import sdg as s
+    s.lib()
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(sdg):
+    c = sdg.sdg_create(0, 0)
+    yield c
+    sdg.sdg_destroy(c)
+
+
+@pytest.mark.parametrize("shape,k,deta", [("solcx", 2, 1e6), ("checker", 1, 1e6), ("checker", 2, 1e8),
+                                          ("checker", 3, 1e3)])
+def test_sweep_shapes_match_oracle(sdg, ctx, torch, shape, k, deta):
+    n = 16
+    pr = (gen.solcx_like if shape == "solcx" else gen.checkerboard)(n, k, deta)
+    m = Mesh(n, n, k)
+    print(f"[case] {pr.name}", flush=True)
+    P = sdg.Problem(ctx, n, n, k, pr.eta, rtol=1e-13, inner_rtol=1e-3, max_it=1500, refine=1)
+    u, ul, p, pl = P.zeros(P.nu), P.zeros(P.nu), P.zeros(P.np), P.zeros(P.np)
+    rc, st = sdg.sdg_solve_stokes_ext_dev(P.h, dev(pr.f.reshape(-1)), None, u, ul, p, pl)
+    assert st["status"] == 0, st
+    uref, pref = rf.solve_stokes_ext(m, pr.eta, pr.f, method="lu")
+    uref, pref = uref.astype(np.float64), pref.astype(np.float64)
+    eu = np.linalg.norm(host(u) - uref) / np.linalg.norm(uref)
+    ep = np.linalg.norm(host(p) - pref) / np.linalg.norm(pref)
+    res = rf.stokes_residual(m, pr.eta, pr.f, host(u), host(p), host(ul), host(pl))
+    print(f"[sweep] {pr.name}: residual {res:.2e} velocity {eu:.2e} pressure {ep:.2e}", flush=True)
+    assert eu <= 1e-9 and ep <= 1e-7
+    P.close()
+
+
+# At contrast 1e8 and k >= 2 the FP64 rounding floor of the true residual
+# is about 1e-6 (measured 1.03e-6), the breakdown of Section 8.3.1: the
+# solves use the extended refinement so that 1e-6 is reached.
+def _paper_solve(sdg, ctx, pr):
+    P = sdg.Problem(ctx, pr.nx, pr.ny, pr.k, pr.eta, rtol=1e-6, inner_rtol=1e-3, max_it=400, coarsest_n=16,
+                    refine=1)
+    u, p, st = P.solve_stokes(dev(pr.f.reshape(-1)))
+    P.close()
+    assert st["status"] == 0 and st["rel_residual"] < 1e-6, st
+    return st["outer_its"], st["inner_its_total"] / max(st["outer_its"], 1), st["inner_its_max"]
+
+
+def test_checkerboard_iteration_trends(sdg, ctx, torch):
+    t3 = json.load(open(os.path.join(GOLDEN, "solcx_tables.json")))["table3_checkerboard"]
+    for deta, dkey in ((1e3, "1e3"), (1e8, "1e8")):
+        avg_by_k = {}
+        for k in (1, 2, 3):
+            outer = []
+            for n in (32, 64, 128):
+                o, avg, mx = _paper_solve(sdg, ctx, gen.checkerboard(n, k, deta))
+                print(f"[checker] deta={deta:g} k={k} n={n}: outer {o} inner avg {avg:.1f} max {mx} "
+                      f"(Table 3 at 64^2: {t3[dkey]['64'][str(k)][:3]})", flush=True)
+                outer.append(o)
+                avg_by_k.setdefault(k, []).append(avg)
+            assert max(outer) <= 2 * min(outer)  # nearly mesh independent
+            assert max(outer) <= 2 * t3[dkey]["64"][str(k)][0]
+        means = [np.mean(avg_by_k[k]) for k in (1, 2, 3)]
+        assert means[0] < means[1] < means[2]  # more inner iterations per order
+
+
+def test_solcx_shape_iteration_trends(sdg, ctx, torch):
+    t2 = json.load(open(os.path.join(GOLDEN, "solcx_tables.json")))["table2_solcx_k2"]
+    for deta, dkey in ((1.0, "1"), (1e6, "1e6")):
+        outer = []
+        for n in (32, 64, 128):
+            o, avg, mx = _paper_solve(sdg, ctx, gen.solcx_like(n, 2, deta))
+            print(f"[solcx] deta={deta:g} n={n}: outer {o} inner avg {avg:.1f} max {mx} "
+                  f"(Table 2 at 64^2: {t2['64'][dkey][:3]})", flush=True)
+            outer.append(o)
+        assert max(outer) <= 2 * min(outer)
+        assert max(outer) <= 3 * t2["64"][dkey][0]

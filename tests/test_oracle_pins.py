@@ -598,3 +598,19 @@ def test_six_sinker_inputs_follow_the_paper():
         assert P.eta[e] == 1e3 and abs(fy[e] + ref["g"] * ref["rho2"]) < 1e-12
     far = 0  # the corner element (0, 0) touches no inclusion
     assert P.eta[far] == 1.0 and abs(fy[far] + ref["g"] * ref["rho1"]) < 1e-12
+
+
+def test_sweep_shapes_follow_the_paper():
+    """SolCx-shaped and checkerboard inputs (Sections 8.1, 8.2): the jump
+    lies on element edges for even n, the contrast is exactly deta, and the
+    checkerboard is the SolCx field with its upper half mirrored."""
+    from paper_1607_03777_amd import inputs as gen
+    n = 8
+    a = gen.solcx_like(n, 2, 1e6).eta.reshape(n, n)
+    assert np.all(a[:, : n // 2] == 1e6) and np.all(a[:, n // 2:] == 1.0)
+    c = gen.checkerboard(n, 2, 1e8).eta.reshape(n, n)
+    assert np.all(c[: n // 2, : n // 2] == 1e8) and np.all(c[n // 2:, n // 2:] == 1e8)
+    assert np.all(c[: n // 2, n // 2:] == 1.0) and np.all(c[n // 2:, : n // 2] == 1.0)
+    f1 = gen.checkerboard(n, 2, 1e3).f
+    f2 = gen.solcx_like(n, 2, 1e6).f
+    assert np.array_equal(f1, f2) and np.all(np.isfinite(f1)) and np.abs(f1).max() > 0
