@@ -105,6 +105,18 @@ def p_cd(mesh: Mesh):
     return sp.csr_matrix((vals, (rows, cols)), shape=(mesh.nel * 8, 2 * nn))
 
 
+def p_q0(mesh: Mesh):
+    """P_k^0: the element-wise constants (Section 6, p-coarse space Q_0^2)
+    in the hierarchical orthonormal basis are the (0, 0) modes, so the
+    prolongation is their injection (nu x 2 nel; coarse unknown 2 e + d,
+    the element index e = iy nx + ix read as a node of the nx x ny grid of
+    element centres)."""
+    k1 = mesh.k1
+    rows = [e * mesh.nbu + d * k1 * k1 for e in range(mesh.nel) for d in range(2)]
+    cols = [2 * e + d for e in range(mesh.nel) for d in range(2)]
+    return sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(mesh.nu, 2 * mesh.nel))
+
+
 def h_prolongation(ncx, ncy):
     """Bilinear interpolation from the (ncx+1)(ncy+1) coarse nodes to the
     (2ncx+1)(2ncy+1) fine nodes, two interleaved components."""
@@ -214,23 +226,35 @@ class Level:
 
 
 class Hierarchy:
-    """hp-multilevel preconditioner A_hp(Q_1) for the viscous block."""
+    """hp-multilevel preconditioner for the viscous block: A_hp(Q_1)
+    (coarse_space 'q1', Section 6.1.2) or A_hp(Q_0) (coarse_space 'q0',
+    Section 6.1.1: Galerkin A_0 = (P_k^0)^T A P_k^0 on the element-wise
+    constants, an h-hierarchy on the grid of element centres, which
+    coarsens while its node count per direction is odd, i.e. on meshes
+    with an odd number of elements; on other meshes A_0 is the coarsest
+    level and is solved directly, the variant A_p(Q_0))."""
 
     def __init__(self, mesh: Mesh, eta, smooth_dg=2, smooth_h=3, coarsest_n=8,
-                 seed=0, eig_steps=10, lo=0.1, hi=1.1, bounds=None, A=None):
+                 seed=0, eig_steps=10, lo=0.1, hi=1.1, bounds=None, A=None, coarse_space="q1"):
         self.mesh = mesh
         self.smooth_dg, self.smooth_h = smooth_dg, smooth_h
         self.A = A if A is not None else assemble_A(mesh, eta)
         self.Acsr = self.A.tocsr()
         self.M = BlockJacobi(self.A, mesh.nbu)
-        self.Pp = p_prolongation(mesh)
-        self.Pcd = p_cd(mesh)
-        self.Pfull = (self.Pp @ self.Pcd).tocsr()  # CG-Q1 nodal -> DG-Q_k
-        A1 = (self.Pp.T @ self.Acsr @ self.Pp).tocsr()
-        self.A1 = A1
-        Ac = (self.Pcd.T @ A1 @ self.Pcd).tocsr()
+        if coarse_space == "q0":
+            self.Pfull = p_q0(mesh)  # element constants -> DG-Q_k
+            Ac = (self.Pfull.T @ self.Acsr @ self.Pfull).tocsr()
+            # the centres form a grid of nx x ny nodes: nx - 1 intervals
+            nx, ny = mesh.nx - 1, mesh.ny - 1
+        else:
+            self.Pp = p_prolongation(mesh)
+            self.Pcd = p_cd(mesh)
+            self.Pfull = (self.Pp @ self.Pcd).tocsr()  # CG-Q1 nodal -> DG-Q_k
+            A1 = (self.Pp.T @ self.Acsr @ self.Pp).tocsr()
+            self.A1 = A1
+            Ac = (self.Pcd.T @ A1 @ self.Pcd).tocsr()
+            nx, ny = mesh.nx, mesh.ny
         self.levels = []
-        nx, ny = mesh.nx, mesh.ny
         Al = Ac
         while True:
             lev = Level()
