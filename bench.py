@@ -270,7 +270,8 @@ def sweep_leg(sdg, ctx, torch, full):
     1e-6 on the Stokes system, inner CG rtol 1e-3, a 16 x 16 coarsest
     h-level as its level counts imply, FP64 with the extended refinement,
     which contrast 1e8 needs to reach 1e-6, Section 8.3.1): the SolCx-shaped field
-    (jump along x = 0.5) at k = 2, contrast 1 and 1e6, and the 2 x 2
+    (jump along x = 0.5) at k = 2, contrast 1 and 1e6, with the Q_1 coarse
+    space on even meshes and the Q_0 one on odd meshes, and the 2 x 2
     checkerboard at k = 1..3, contrast 1e3, 1e6, 1e8, with this library's
     own smooth force; per solve the outer and inner iteration counts and
     the time with setup, next to Tables 2 and 3 (context, one core of the
@@ -279,19 +280,21 @@ def sweep_leg(sdg, ctx, torch, full):
     tables = json.load(open(os.path.join(ROOT, "tests", "golden", "solcx_tables.json")))
     t2, t3 = tables["table2_solcx_k2"], tables["table3_checkerboard"]
     cases = [("solcx", 2, d, n) for d in (1.0, 1e6) for n in (64, 128, 256, 512)]
+    cases += [("solcx-q0", 2, d, n) for d in (1.0, 1e6) for n in (65, 129, 257, 513)]
     cases += [("checker", k, d, n) for d in (1e3, 1e6, 1e8) for k in (1, 2, 3)
               for n in ((64, 128, 256, 512, 1024) if full else (64, 256))]
     if not full:
         cases += [("checker", 1, d, 1024) for d in (1e3, 1e6, 1e8)]
     rows = []
     for shape, k, d, n in cases:
-        pr = (gen.solcx_like if shape == "solcx" else gen.checkerboard)(n, k, d)
+        pr = (gen.checkerboard if shape == "checker" else gen.solcx_like)(n, k, d)
         eta = torch.as_tensor(pr.eta, device="cuda")
         f = torch.as_tensor(pr.f.reshape(-1), device="cuda")
         u = torch.zeros(pr.nu, dtype=torch.float64, device="cuda")
         p = torch.zeros(pr.np_, dtype=torch.float64, device="cuda")
         ul, pl = torch.zeros_like(u), torch.zeros_like(p)
-        opts = sdg.make_options(rtol=1e-6, inner_rtol=1e-3, max_it=400, coarsest_n=16, refine=1)
+        opts = sdg.make_options(rtol=1e-6, inner_rtol=1e-3, max_it=400, coarsest_n=16, refine=1,
+                                coarse_space=1 if shape == "solcx-q0" else 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = sdg.sdg_problem_create(ctx, sdg.make_mesh(n, n, k), opts, eta, sdg.current_stream())
@@ -300,7 +303,12 @@ def sweep_leg(sdg, ctx, torch, full):
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         dkey = "1" if d == 1.0 else f"1e{int(round(np.log10(d)))}"
-        paper = (t2.get(str(n), {}).get(dkey) if shape == "solcx" else t3.get(dkey, {}).get(str(n), {}).get(str(k)))
+        if shape == "solcx":
+            paper = t2.get(str(n), {}).get(dkey)
+        elif shape == "solcx-q0":
+            paper = tables["table2_solcx_k2_q0"]["A_hp(Q0)"].get(str(n), {}).get(dkey)
+        else:
+            paper = t3.get(dkey, {}).get(str(n), {}).get(str(k))
         row = {"shape": shape, "k": k, "deta": d, "n": n, "seconds": t, "status": st["status"],
                "outer_its": st["outer_its"], "inner_avg": st["inner_its_total"] / max(st["outer_its"], 1),
                "inner_max": st["inner_its_max"], "rel_residual": st["rel_residual"]}

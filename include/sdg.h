@@ -93,7 +93,8 @@ typedef struct sdg_options {
   int32_t restart;        /* FGMRES restart length */
   int32_t smooth_dg;      /* Chebyshev steps before and after on the DG level (Section 8: 2) */
   int32_t smooth_h;       /* Chebyshev steps on each h-level (Section 8: 3) */
-  int32_t coarsest_n;     /* h-coarsening stops at <= this many elements per direction */
+  int32_t coarsest_n;     /* h-coarsening stops at <= this many elements per direction (Q_0: node
+                             intervals of the element-centre grid, one less than the elements) */
   int32_t eig_steps;      /* Arnoldi steps for lambda* (Section 6: 10) */
   double cheb_lo, cheb_hi;/* Chebyshev bounds as fractions of lambda* (Section 6: 0.1, 1.1) */
   int32_t prec_smoother;  /* SDG_FP64: full block inverses; SDG_FP32 / SDG_BF16: inverse Cholesky
@@ -117,7 +118,14 @@ typedef struct sdg_options {
                              correction in FP64.  rtol then bounds the residual of the pair. */
   int32_t outer_krylov;   /* Stokes solve: 0: right-preconditioned FGMRES (Section 5, 8.1);
                              1: GCR (Section 8.3, six-inclusion experiment) */
-  int32_t reserved_;
+  int32_t coarse_space;   /* p-coarse space of the viscous preconditioner (Section 6): 0: Q_1^2
+                             projected to continuous bilinears, with an h-hierarchy on the
+                             mesh vertices (A_hp(Q_1), Section 6.1.2); 1: element-wise
+                             constants Q_0^2, Galerkin A_0, with an h-hierarchy on the grid
+                             of element centres, which coarsens on meshes with an odd
+                             number of elements per direction (A_hp(Q_0), Section 6.1.1);
+                             on other meshes A_0 is solved directly (A_p(Q_0), at most
+                             2048 unknowns) */
 } sdg_options;
 
 typedef struct sdg_stats {

@@ -116,6 +116,115 @@ int p_prolong_add_f32(const MeshDev& M, int k, int nbatch, const double* ec, flo
 }
 
 // ---------------------------------------------------------------------------
+// Q_0 coarse space (Section 6.1.1): the element-wise constants are the (0, 0)
+// modes of the hierarchical basis, so P_k^0 injects them and its transpose
+// picks them; the coarse unknowns live on the grid of element centres
+// (node = element index, two components per node).
+// ---------------------------------------------------------------------------
+// v = (0, 0) mode of component d set to 1 on the elements of colour
+// (cx, cy) = (ix mod 3, iy mod 3), every other entry 0
+__global__ void q0_probe_vec_kernel(int nx, int ny, int64_t ntot, int NB, int KK, int cx, int cy, int d,
+                                    double* __restrict__ v) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ntot * NB) return;
+  const int64_t ge = g / NB;
+  const int a = (int)(g - ge * NB);
+  const int e = (int)(ge % ((int64_t)nx * ny));
+  const int ix = e % nx, iy = e / nx;
+  v[g] = (a == d * KK && ix % 3 == cx && iy % 3 == cy) ? 1.0 : 0.0;
+}
+// A couples an element only with itself and its four face neighbours, and
+// those five have five different colours: the (0, 0) response of element g
+// to the probe of colour (cx, cy), component d, is the entry of A_0 between
+// g and the one element of that colour among them.  Stencil layout as in
+// stencil_kernel: st[(s 4 + row 2 + col) NN + g], s = (sy + 1) 3 + (sx + 1).
+__global__ void q0_probe_gather_kernel(int nx, int ny, int nbatch, int NB, int KK, int cx, int cy, int d,
+                                       const double* __restrict__ y, double* __restrict__ st) {
+  const int nel = nx * ny;
+  const int64_t NN = (int64_t)nel * nbatch;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= NN) return;
+  const int e = (int)(g % nel);
+  const int ix = e % nx, iy = e / nx;
+  const int off[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+  for (int o = 0; o < 5; ++o) {
+    const int sx = off[o][0], sy = off[o][1];
+    const int jx = ix + sx, jy = iy + sy;
+    if (jx < 0 || jx >= nx || jy < 0 || jy >= ny || jx % 3 != cx || jy % 3 != cy) continue;
+    const int sidx = (sy + 1) * 3 + (sx + 1);
+    for (int row = 0; row < 2; ++row) st[(sidx * 4 + row * 2 + d) * NN + g] = y[g * NB + row * KK];
+  }
+}
+int q0_probe_vec(int nx, int ny, int nbatch, int k, int cx, int cy, int d, double* v, hipStream_t s) {
+  const int K1 = k + 1, NB = 2 * K1 * K1;
+  const int64_t ntot = (int64_t)nx * ny * nbatch;
+  hipLaunchKernelGGL(q0_probe_vec_kernel, dim3(ceil_div(ntot * NB, 256)), dim3(256), 0, s, nx, ny, ntot, NB, K1 * K1,
+                     cx, cy, d, v);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int q0_probe_gather(int nx, int ny, int nbatch, int k, int cx, int cy, int d, const double* y, double* st,
+                    hipStream_t s) {
+  const int K1 = k + 1, NB = 2 * K1 * K1;
+  const int64_t n = (int64_t)nx * ny * nbatch;
+  hipLaunchKernelGGL(q0_probe_gather_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, nx, ny, nbatch, NB, K1 * K1, cx,
+                     cy, d, y, st);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+// rc[g][d] = mode (0, 0) of component d of element g of a vector with
+// `stride` values per element and `cstride` per component (the residual's
+// Q_1 modes: 8 and 4; a full Q_k vector: n_b and (k+1)^2)
+template <typename TV>
+__global__ void q0_restrict_kernel(int64_t n, int stride, int cstride, const TV* __restrict__ rq,
+                                   double* __restrict__ rc) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 2 * n) return;
+  rc[g] = double(rq[(g >> 1) * stride + (g & 1) * cstride]);
+}
+// x[g][d][0][0] += ec[g][d]
+template <typename TV>
+__global__ void q0_prolong_kernel(int64_t n, int NB, int KK, const double* __restrict__ ec, TV* __restrict__ x) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 2 * n) return;
+  TV* p = x + (g >> 1) * NB + (g & 1) * KK;
+  *p = TV(double(*p) + ec[g]);
+}
+int q0_restrict(int64_t nel_total, const double* rq1, double* rc, hipStream_t s) {
+  hipLaunchKernelGGL(q0_restrict_kernel<double>, dim3(ceil_div(2 * nel_total, 256)), dim3(256), 0, s, nel_total, 8,
+                     4, rq1, rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int q0_restrict_f32(int64_t nel_total, const float* rq1, double* rc, hipStream_t s) {
+  hipLaunchKernelGGL(q0_restrict_kernel<float>, dim3(ceil_div(2 * nel_total, 256)), dim3(256), 0, s, nel_total, 8, 4,
+                     rq1, rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int q0_restrict_full(int64_t nel_total, int k, const double* r, double* rc, hipStream_t s) {
+  const int K1 = k + 1;
+  hipLaunchKernelGGL(q0_restrict_kernel<double>, dim3(ceil_div(2 * nel_total, 256)), dim3(256), 0, s, nel_total,
+                     2 * K1 * K1, K1 * K1, r, rc);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int q0_prolong_add(int64_t nel_total, int k, const double* ec, double* x, hipStream_t s) {
+  const int K1 = k + 1;
+  hipLaunchKernelGGL(q0_prolong_kernel<double>, dim3(ceil_div(2 * nel_total, 256)), dim3(256), 0, s, nel_total,
+                     2 * K1 * K1, K1 * K1, ec, x);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+int q0_prolong_add_f32(int64_t nel_total, int k, const double* ec, float* x, hipStream_t s) {
+  const int K1 = k + 1;
+  hipLaunchKernelGGL(q0_prolong_kernel<float>, dim3(ceil_div(2 * nel_total, 256)), dim3(256), 0, s, nel_total,
+                     2 * K1 * K1, K1 * K1, ec, x);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // A_{1,c} stencil from element-local 8x8 matrices (rows/cols vertex*2 + comp)
 // ---------------------------------------------------------------------------
 __global__ void stencil_from_local_kernel(int nx, int ny, int nbatch, const double* __restrict__ cl,

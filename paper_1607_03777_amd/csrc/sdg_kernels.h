@@ -94,6 +94,18 @@ int stencil_residual(int nx, int ny, int nbatch, const double* st, const double*
 int stencil_diag_inv(int nx, int ny, int nbatch, const double* st, double* dinv, hipStream_t s);
 int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s);
 int h_prolong_add(int ncx, int ncy, int nbatch, const double* ec, double* xf, hipStream_t s);
+// Q_0 coarse space (Section 6.1.1): probe vectors and the gather of A_0's
+// stencil from A v (3 x 3 colouring of the elements), and the injection of
+// the (0, 0) modes (restriction from the residual's Q_1 modes, 8 per
+// element; prolongation into the (0, 0) modes)
+int q0_probe_vec(int nx, int ny, int nbatch, int k, int cx, int cy, int d, double* v, hipStream_t s);
+int q0_probe_gather(int nx, int ny, int nbatch, int k, int cx, int cy, int d, const double* y, double* st,
+                    hipStream_t s);
+int q0_restrict(int64_t nel_total, const double* rq1, double* rc, hipStream_t s);
+int q0_restrict_f32(int64_t nel_total, const float* rq1, double* rc, hipStream_t s);
+int q0_restrict_full(int64_t nel_total, int k, const double* r, double* rc, hipStream_t s);
+int q0_prolong_add(int64_t nel_total, int k, const double* ec, double* x, hipStream_t s);
+int q0_prolong_add_f32(int64_t nel_total, int k, const double* ec, float* x, hipStream_t s);
 int stencil_to_dense(int nx, int ny, int nbatch, const double* st, double* dense, hipStream_t s);
 int dense_matvec(int n, int nbatch, const double* A, const double* x, double* y, hipStream_t s);
 

@@ -558,12 +558,19 @@ int setup_blocks(sdg_problem* P) {
   return SDG_OK;
 }
 
+int q0_stencil(sdg_problem* P, double* st);
+
 int setup_coarse(sdg_problem* P) {
   const int nx = P->mesh.nx, ny = P->mesh.ny, nb = P->nb;
+  const bool q0 = P->opt.coarse_space == 1;
   double* clocal = nullptr;
-  SDG_TRY(palloc_t(P, &clocal, (int64_t)P->nel * nb * 64));
-  SDG_TRY(sip_coarse_local(P->M, P->k, nb, P->eta, clocal, P->s));
-  int cx = nx, cy = ny;
+  if (!q0) {
+    SDG_TRY(palloc_t(P, &clocal, (int64_t)P->nel * nb * 64));
+    SDG_TRY(sip_coarse_local(P->M, P->k, nb, P->eta, clocal, P->s));
+  }
+  // Q_1: the (nx + 1) x (ny + 1) vertices; Q_0: the nx x ny element centres,
+  // a node grid of nx - 1 by ny - 1 intervals
+  int cx = q0 ? nx - 1 : nx, cy = q0 ? ny - 1 : ny;
   P->lev.clear();
   while (true) {
     CLevel L;
@@ -574,7 +581,8 @@ int setup_coarse(sdg_problem* P) {
     SDG_TRY(palloc_t(P, &L.st, (int64_t)36 * L.nn * nb));
     for (double** v : {&L.b, &L.x, &L.xalt, &L.r, &L.d}) SDG_TRY(palloc_t(P, v, nv));
     if (P->lev.empty()) {
-      SDG_TRY(coarse_stencil_from_local(cx, cy, nb, clocal, L.st, P->s));
+      if (q0) SDG_TRY(q0_stencil(P, L.st));
+      else SDG_TRY(coarse_stencil_from_local(cx, cy, nb, clocal, L.st, P->s));
     } else {
       const CLevel& F = P->lev.back();
       SDG_TRY(galerkin_coarsen(F.nx, F.ny, nb, F.st, L.st, P->s));
@@ -625,6 +633,31 @@ int run_sip_apply(sdg_problem* P, const double* u, double* y) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8),
                 [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s, P->tile[0][0]); });
 }
+// A_0 = (P_k^0)^T A P_k^0 (Section 6.1.1) by probing: A applied to the unit
+// (0, 0) mode of one component on every element of one colour of a 3 x 3
+// colouring (18 applies); the (0, 0) responses are the stencil entries.
+int q0_stencil(sdg_problem* P, double* st) {
+  const int nx = P->mesh.nx, ny = P->mesh.ny, nb = P->nb;
+  const int64_t U = P->nu * nb;
+  double *v = nullptr, *y = nullptr;
+  if (tmp_get(P, &v, U) < 0 || tmp_get(P, &y, U) < 0) {
+    tmp_put(P, v, U);
+    set_error("allocation of the Q_0 probe vectors failed");
+    return SDG_ERR_NOMEM;
+  }
+  int rc = SDG_OK;
+  if (hipMemsetAsync(st, 0, (size_t)36 * P->nel * nb * sizeof(double), P->s) != hipSuccess) rc = SDG_ERR_DEVICE;
+  for (int c = 0; c < 9 && rc >= 0; ++c)
+    for (int d = 0; d < 2 && rc >= 0; ++d) {
+      rc = q0_probe_vec(nx, ny, nb, P->k, c % 3, c / 3, d, v, P->s);
+      if (rc >= 0) rc = sip_apply(P->M, P->k, nb, P->eta, v, y, P->s, 0);
+      if (rc >= 0) rc = q0_probe_gather(nx, ny, nb, P->k, c % 3, c / 3, d, y, st, P->s);
+    }
+  tmp_put(P, v, U);  // synchronises the stream first
+  tmp_put(P, y, U);
+  return rc;
+}
+
 // y = A u and out[pb] = u.y.  With the wavefront kernel the product is
 // summed inside the operator kernel (per-tile partials, then a fixed-order
 // sum), which saves a pass over u and y; otherwise apply, then dot.
@@ -873,9 +906,12 @@ int vcycle64(sdg_problem* P, const double* b, double* x) {
   // algorithmic bytes: u, eta, the Q1 modes of b, the 8 values written
   SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 8) + 17 * elem_bytes(P, 8),
                  [&] { return sip_residual_q1(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s); }));
-  SDG_TRY(p_restrict(P->M, 1, P->nb, P->vr, P->lev[0].b, P->s));
+  const int64_t nelt = (int64_t)P->nel * P->nb;
+  if (P->opt.coarse_space == 1) SDG_TRY(q0_restrict(nelt, P->vr, P->lev[0].b, P->s));
+  else SDG_TRY(p_restrict(P->M, 1, P->nb, P->vr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
-  SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
+  if (P->opt.coarse_space == 1) SDG_TRY(q0_prolong_add(nelt, P->k, P->lev[0].x, x, P->s));
+  else SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
   SDG_TRY(cheb_dg64(P, b, x, false));
   return SDG_OK;
 }
@@ -888,9 +924,12 @@ int vcycle32(sdg_problem* P, const double* b, double* x) {
   // the residual's Q1 modes only (as in the FP64 cycle)
   SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 4) + 9 * elem_bytes(P, 8),
                  [&] { return sip_residual_q1_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s); }));
-  SDG_TRY(p_restrict_f32(P->M, 1, P->nb, P->fr, P->lev[0].b, P->s));
+  const int64_t nelt = (int64_t)P->nel * P->nb;
+  if (P->opt.coarse_space == 1) SDG_TRY(q0_restrict_f32(nelt, P->fr, P->lev[0].b, P->s));
+  else SDG_TRY(p_restrict_f32(P->M, 1, P->nb, P->fr, P->lev[0].b, P->s));
   SDG_TRY(hcycle(P, 0));
-  SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
+  if (P->opt.coarse_space == 1) SDG_TRY(q0_prolong_add_f32(nelt, P->k, P->lev[0].x, P->fx, P->s));
+  else SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, false));
   SDG_TRY(f2d(n, P->fx, x, P->s));
   return SDG_OK;
@@ -2243,8 +2282,10 @@ size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int 
   // as full squares in the storage type
   // (BF16 factors may be replaced by FP32 ones at setup: both counted)
   if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + 2 * NB * NB * (opts->prec_smoother == SDG_BF16 ? 2 + 4 : 4));
-  b += nb * nel * 64 * 8;  // coarse local matrices
-  int cx = mesh->nx, cy = mesh->ny;
+  const bool q0 = opts->coarse_space == 1;
+  if (q0) b += nb * nu * 8 * 2;  // probe vectors of A_0
+  else b += nb * nel * 64 * 8;    // coarse local matrices
+  int cx = q0 ? mesh->nx - 1 : mesh->nx, cy = q0 ? mesh->ny - 1 : mesh->ny;
   while (true) {
     const int64_t nn = (int64_t)(cx + 1) * (cy + 1);
     b += nb * nn * (36 + 14) * 8 + opts->smooth_h * nb * 16;
@@ -2354,6 +2395,7 @@ static bool opts_ok(const sdg_options* o) {
   if (o->prec_smoother < 0 || o->prec_smoother > 2 || o->prec_apply < 0 || o->prec_apply > 1) return false;
   if (o->refine < 0 || o->refine > 1 || o->viscous_krylov < 0 || o->viscous_krylov > 2) return false;
   if (o->outer_krylov < 0 || o->outer_krylov > 1) return false;
+  if (o->coarse_space < 0 || o->coarse_space > 1) return false;
   return true;
 }
 
@@ -2719,10 +2761,12 @@ int sdg_get_blocks_noalloc(sdg_problem* P, double* blocks) {
 }
 int sdg_p_restrict(sdg_problem* P, const double* r, double* rc) {
   PCHECK(r, rc);
+  if (P->opt.coarse_space == 1) return q0_restrict_full((int64_t)P->nel * P->nb, P->k, r, rc, P->s);
   return p_restrict(P->M, P->k, P->nb, r, rc, P->s);
 }
 int sdg_p_prolong_add(sdg_problem* P, const double* ec, double* u) {
   PCHECK(ec, u);
+  if (P->opt.coarse_space == 1) return q0_prolong_add((int64_t)P->nel * P->nb, P->k, ec, u, P->s);
   return p_prolong_add(P->M, P->k, P->nb, ec, u, P->s);
 }
 int sdg_get_coarse_stencil(sdg_problem* P, int level, double* st, int* nx_out, int* ny_out) {

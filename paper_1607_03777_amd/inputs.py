@@ -361,16 +361,23 @@ def smooth_force_elements(n, seed, nmodes=8):
     return fx.reshape(-1), fy.reshape(-1)
 
 
+def _below_half(n):
+    """Fraction of each element interval [i/n, (i+1)/n] below 1/2."""
+    return np.clip(n / 2.0 - np.arange(n), 0.0, 1.0)
+
+
 def solcx_like(n, k, deta, seed=0):
     """The viscosity structure of the SolCx runs (Sections 7 and 8.1): one
     jump along x = 0.5, viscosity deta for x < 0.5 and 1 for x > 0.5
     (contrast eta_1 : eta_2 = deta, eta_2 = 1), Navier on all sides; with an
-    even n the jump lies on element edges.  The force is this library's
-    seeded smooth field (smooth_force_elements): the benchmark's own
-    forcing and analytic solution are not used."""
-    c = (np.arange(n) + 0.5) / n
-    X, _ = np.meshgrid(c, c)
-    eta = np.where(X.reshape(-1) < 0.5, float(deta), 1.0)
+    even n the jump lies on element edges, with an odd n the elements of
+    the middle column take the L2 projection onto constants, their mean
+    (Section 8.1).  The force is this library's seeded smooth field
+    (smooth_force_elements): the benchmark's own forcing and analytic
+    solution are not used."""
+    fl = _below_half(n)
+    FL, _ = np.meshgrid(fl, fl)
+    eta = (float(deta) * FL + (1.0 - FL)).reshape(-1)
     fx, fy = smooth_force_elements(n, seed)
     f = constant_force_modes(fx, fy, n, n, k)
     return Problem(n, n, k, eta, f, None, name=f"solcx-like-{n}x{n}-k{k}-deta{deta:g}", meta={"deta": deta})
@@ -379,12 +386,13 @@ def solcx_like(n, k, deta, seed=0):
 def checkerboard(n, k, deta, seed=0):
     """The 2 x 2 checkerboard of Section 8.2: the SolCx jump along x = 0.5
     and a second one along y = 0.5; viscosity deta on the quadrants
-    x < 0.5, y < 0.5 and x > 0.5, y > 0.5, and 1 on the other two; Navier on
-    all sides; the force as in solcx_like."""
-    c = (np.arange(n) + 0.5) / n
-    X, Y = np.meshgrid(c, c)
-    hi = (X < 0.5) == (Y < 0.5)
-    eta = np.where(hi.reshape(-1), float(deta), 1.0)
+    x < 0.5, y < 0.5 and x > 0.5, y > 0.5, and 1 on the other two (element
+    means where an odd n puts an element across a jump); Navier on all
+    sides; the force as in solcx_like."""
+    fl = _below_half(n)
+    FX, FY = np.meshgrid(fl, fl)
+    hi = FX * FY + (1.0 - FX) * (1.0 - FY)  # area fraction of the deta quadrants (odd n: L2 mean)
+    eta = (float(deta) * hi + (1.0 - hi)).reshape(-1)
     fx, fy = smooth_force_elements(n, seed)
     f = constant_force_modes(fx, fy, n, n, k)
     return Problem(n, n, k, eta, f, None, name=f"checkerboard-{n}x{n}-k{k}-deta{deta:g}", meta={"deta": deta})

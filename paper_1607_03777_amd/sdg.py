@@ -33,7 +33,7 @@ class sdg_options(ctypes.Structure):
                 ("cheb_hi", ctypes.c_double), ("prec_smoother", ctypes.c_int32),
                 ("prec_apply", ctypes.c_int32), ("viscous_krylov", ctypes.c_int32),
                 ("dedup", ctypes.c_int32), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
-                ("refine", ctypes.c_int32), ("outer_krylov", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("refine", ctypes.c_int32), ("outer_krylov", ctypes.c_int32), ("coarse_space", ctypes.c_int32)]
 
 
 class sdg_stats(ctypes.Structure):

@@ -69,9 +69,9 @@ def test_sweep_shapes_match_oracle(sdg, ctx, torch, shape, k, deta):
 # At contrast 1e8 and k >= 2 the FP64 rounding floor of the true residual
 # is about 1e-6 (measured 1.03e-6), the breakdown of Section 8.3.1: the
 # solves use the extended refinement so that 1e-6 is reached.
-def _paper_solve(sdg, ctx, pr):
+def _paper_solve(sdg, ctx, pr, coarse_space=0):
     P = sdg.Problem(ctx, pr.nx, pr.ny, pr.k, pr.eta, rtol=1e-6, inner_rtol=1e-3, max_it=400, coarsest_n=16,
-                    refine=1)
+                    refine=1, coarse_space=coarse_space)
     u, p, st = P.solve_stokes(dev(pr.f.reshape(-1)))
     P.close()
     assert st["status"] == 0 and st["rel_residual"] < 1e-6, st
@@ -107,3 +107,26 @@ def test_solcx_shape_iteration_trends(sdg, ctx, torch):
             outer.append(o)
         assert max(outer) <= 2 * min(outer)
         assert max(outer) <= 3 * t2["64"][dkey][0]
+
+
+def test_solcx_shape_q0_coarse_space_trends(sdg, ctx, torch):
+    """A_hp(Q_0) (Section 6.1.1) on odd meshes, where the SolCx jump cuts the
+    middle column (viscosity projected onto element constants): outer
+    iterations as for A_hp(Q_1) and nearly mesh independent, inner
+    iterations several times those of A_hp(Q_1), as in Table 2."""
+    tab = json.load(open(os.path.join(GOLDEN, "solcx_tables.json")))
+    t2q0, t2 = tab["table2_solcx_k2_q0"]["A_hp(Q0)"], tab["table2_solcx_k2"]
+    for deta, dkey in ((1.0, "1"), (1e6, "1e6")):
+        outer, inner = [], []
+        for n in (33, 65, 129):
+            o, avg, mx = _paper_solve(sdg, ctx, gen.solcx_like(n, 2, deta), coarse_space=1)
+            o1, avg1, _ = _paper_solve(sdg, ctx, gen.solcx_like(n - 1, 2, deta))
+            print(f"[solcx q0] deta={deta:g} n={n}: outer {o} inner avg {avg:.1f} max {mx}; Q1 at {n - 1}: "
+                  f"outer {o1} inner avg {avg1:.1f} (Table 2 at 65^2: {t2q0['65'][dkey][:3]}, Q1 at 64^2: "
+                  f"{t2['64'][dkey][:3]})", flush=True)
+            outer.append(o)
+            inner.append(avg / avg1)
+        assert max(outer) <= 2 * min(outer)
+        assert min(inner) >= 2.0  # the element-wise constant coarse space is much weaker
+        assert max(outer) <= 3 * t2q0["65"][dkey][0]
+

@@ -611,6 +611,11 @@ def test_sweep_shapes_follow_the_paper():
     c = gen.checkerboard(n, 2, 1e8).eta.reshape(n, n)
     assert np.all(c[: n // 2, : n // 2] == 1e8) and np.all(c[n // 2:, n // 2:] == 1e8)
     assert np.all(c[: n // 2, n // 2:] == 1.0) and np.all(c[n // 2:, : n // 2] == 1.0)
+    # odd meshes (Section 8.1): the elements across a jump take the mean
+    o = gen.solcx_like(5, 1, 9.0).eta.reshape(5, 5)
+    assert np.all(o[:, :2] == 9.0) and np.all(o[:, 2] == 5.0) and np.all(o[:, 3:] == 1.0)
+    q = gen.checkerboard(3, 1, 9.0).eta.reshape(3, 3)
+    assert q[1, 1] == 5.0 and q[0, 0] == 9.0 and q[2, 2] == 9.0 and q[0, 2] == 1.0
     f1 = gen.checkerboard(n, 2, 1e3).f
     f2 = gen.solcx_like(n, 2, 1e6).f
     assert np.array_equal(f1, f2) and np.all(np.isfinite(f1)) and np.abs(f1).max() > 0
