@@ -553,18 +553,29 @@ def isolated_leg(which, kw, timeout_s):
     return msg[1]
 
 
-def kernel_probe(sdg, ctx, torch, B, reps):
-    """Only the operator kernels at the headline's shape (batch B of 64 x 64,
-    k = 4 variants): `reps` launches each of the SIP residual, the SIP apply
-    and the block-Jacobi apply, then `reps` plain device copies of the
-    residual's vector (known bytes) that calibrate the HBM counters.  For
-    rocprofv3 counter runs."""
+def kernel_probe(sdg, ctx, torch, B, reps, phases="all"):
+    """Only the kernels of the hot path, for rocprofv3 counter runs, in
+    phases separated by marker copies (torch.neg over 4096 (i + 1) doubles
+    before phase i > 0, so a per-dispatch counter file splits by grid size):
+      0. at the headline's shape (batch B of 64 x 64, k = 4 variants, FP64):
+         `reps` launches each of the SIP residual, the SIP apply and the
+         block-Jacobi apply, then `reps` plain device copies of the
+         residual's vector (known bytes) that calibrate the HBM counters;
+      1. `reps` FP64 V-cycles at the same shape (p-transfers, h-level
+         Chebyshev, restriction, prolongation, the LDS coarse tail);
+      2. the FP32-factor smoother: `reps` block-Jacobi applies and V-cycles
+         (FP32 apply and smoother);
+      3. the same with BF16 factors;
+      4. distinct blocks: B problems of 64 x 64, k = 4 with log-normal
+         random viscosity (no two elements share a block), `reps`
+         block-Jacobi applies with FP64, FP32 and BF16 factors.
+    `phases` = "all" or "0" (the first phase alone)."""
     from paper_1607_03777_amd import inputs as gen
     probs = [gen.c2_variant(s) for s in range(B)]
     nel, nb = N * N, 2 * (K + 1) ** 2
     eta = torch.as_tensor(np.concatenate([p.eta for p in probs]), device="cuda")
-    h = sdg.sdg_problem_create_batch(ctx, sdg.make_mesh(N, N, K), sdg.make_options(), B, eta,
-                                     sdg.current_stream())
+    mesh = sdg.make_mesh(N, N, K)
+    h = sdg.sdg_problem_create_batch(ctx, mesh, sdg.make_options(), B, eta, sdg.current_stream())
     u = torch.randn(B * nel * nb, dtype=torch.float64, device="cuda")
     b = torch.randn_like(u)
     r = torch.empty_like(u)
@@ -578,12 +589,54 @@ def kernel_probe(sdg, ctx, torch, B, reps):
         torch.neg(u, out=r)  # plain elementwise copy: reads and writes one vector
     torch.cuda.synchronize()
     var = sdg.sdg_get_tile(h, sdg.TILE_RESIDUAL, sdg.FP64)
-    sdg.sdg_problem_destroy(h)
-    print(json.dumps({"kernel_probe": {"batch": B, "reps": reps, "vector_bytes": u.numel() * 8,
-                                       "tile": sdg.sdg_tile_shape(K, var), "variant": var,
-                                       "residual_bytes": B * nel * (3 * nb * 8 + 8),
-                                       "apply_bytes": B * nel * (2 * nb * 8 + 8),
-                                       "blockjacobi_bytes": B * nel * (2 * nb * 8 + 12)}}), flush=True)
+    info = {"batch": B, "reps": reps, "vector_bytes": u.numel() * 8,
+            "tile": sdg.sdg_tile_shape(K, var), "variant": var,
+            "residual_bytes": B * nel * (3 * nb * 8 + 8),
+            "apply_bytes": B * nel * (2 * nb * 8 + 8),
+            "blockjacobi_bytes": B * nel * (2 * nb * 8 + 12)}
+
+    def marker(i):
+        torch.cuda.synchronize()
+        m = torch.zeros(4096 * (i + 1), dtype=torch.float64, device="cuda")
+        torch.neg(m, out=m)
+        torch.cuda.synchronize()
+
+    if phases == "all":
+        marker(1)
+        for _ in range(reps):
+            sdg.sdg_vcycle(h, b, r)
+        torch.cuda.synchronize()
+        sdg.sdg_problem_destroy(h)
+        h = None
+        precs = {}
+        for ph, prec in ((2, sdg.FP32), (3, sdg.BF16)):
+            marker(ph)
+            hp = sdg.sdg_problem_create_batch(ctx, mesh, sdg.make_options(prec_apply=sdg.FP32, prec_smoother=prec),
+                                              B, eta, sdg.current_stream())
+            precs[ph] = sdg.sdg_problem_smoother_precision(hp)
+            for _ in range(reps):
+                sdg.sdg_apply_blockjacobi(hp, u, r)
+            for _ in range(reps):
+                sdg.sdg_vcycle(hp, b, r)
+            torch.cuda.synchronize()
+            sdg.sdg_problem_destroy(hp)
+        rng = np.random.default_rng(7)
+        eta_d = torch.as_tensor(10.0 ** rng.uniform(-2.0, 2.0, B * nel), device="cuda")
+        marker(4)
+        for prec in (sdg.FP64, sdg.FP32, sdg.BF16):
+            hd = sdg.sdg_problem_create_batch(ctx, mesh, sdg.make_options(prec_apply=sdg.FP32 if prec else sdg.FP64,
+                                                                          prec_smoother=prec),
+                                              B, eta_d, sdg.current_stream())
+            precs[f"distinct_{prec}"] = sdg.sdg_problem_smoother_precision(hd)
+            for _ in range(reps):
+                sdg.sdg_apply_blockjacobi(hd, u, r)
+            torch.cuda.synchronize()
+            sdg.sdg_problem_destroy(hd)
+        info["smoother_precision"] = precs
+        info["markers"] = {i: 4096 * (i + 1) for i in range(1, 5)}
+    if h is not None:
+        sdg.sdg_problem_destroy(h)
+    print(json.dumps({"kernel_probe": info}), flush=True)
 
 
 def recorded_traffic(kernel):
@@ -618,6 +671,8 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=5)
     ap.add_argument("--kernel-probe", type=int, default=0,
                     help="only launch the operator kernels this many times (counter runs)")
+    ap.add_argument("--probe-phases", choices=["0", "all"], default="0",
+                    help="kernel probe: the operator kernels alone (0) or every kernel class (all)")
     ap.add_argument("--c3", default="3,4,5,6", help="orders of the 256 x 256 leg ('' = skip)")
     ap.add_argument("--c3-prec", choices=list(PRECS), default="bf16")
     ap.add_argument("--batched", type=int, default=512, help="requests of the random-field leg (0 = skip)")
@@ -647,7 +702,7 @@ def main():
     torch.cuda.set_device(0)
     ctx = sdg.sdg_create(0, 0)
     if args.kernel_probe:
-        kernel_probe(sdg, ctx, torch, args.batch, args.kernel_probe)
+        kernel_probe(sdg, ctx, torch, args.batch, args.kernel_probe, args.probe_phases)
         sdg.sdg_destroy(ctx)
         return
     model, ncpu = host_cpu()

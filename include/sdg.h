@@ -98,7 +98,8 @@ typedef struct sdg_options {
   int32_t eig_steps;      /* Arnoldi steps for lambda* (Section 6: 10) */
   double cheb_lo, cheb_hi;/* Chebyshev bounds as fractions of lambda* (Section 6: 0.1, 1.1) */
   int32_t prec_smoother;  /* SDG_FP64: full block inverses; SDG_FP32 / SDG_BF16: inverse Cholesky
-                             factors X = L^{-1} (stored as X and X^T), smoother X^T X */
+                             factors X = L^{-1} (stored once, packed lower triangle),
+                             smoother X^T X */
   int32_t prec_apply;     /* SDG_FP64 / SDG_FP32: operator apply inside the cycle */
   int32_t viscous_krylov; /* viscous solves and the inner solve of the Stokes preconditioner:
                              0: CG (Section 8.1); 1: FGMRES (standalone viscous solves; needed

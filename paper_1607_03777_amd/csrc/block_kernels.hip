@@ -101,47 +101,57 @@ int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, doubl
 
 
 // Low-precision factors: from the packed FP64 X = L^{-1} (row a holds
-// X[a][0..a] at offset a(a+1)/2) to two full square matrices per block in
-// the storage type, out[u][0] = X (zeros above the diagonal) and
-// out[u][1] = X^T (zeros below), so that both products of the smoother read
-// their operands as contiguous row pairs.
+// X[a][0..a] at offset a(a+1)/2) to the storage type, once, as the lower
+// triangle of 2 x 2 quads: quad (m, p), p <= m < NB/2, holds
+// X[2m][2p], X[2m][2p+1], X[2m+1][2p], X[2m+1][2p+1] at offset
+// 4 (m(m+1)/2 + p), NB(NB+2)/2 values per block (X[2m][2m+1] is a stored
+// zero).  The product y = X r reads a quad's row pair (contiguous), the
+// product z = X^T y its column pair (the whole quad, then a select).
 __device__ __forceinline__ uint16_t to_bf16(double v) {
   // round to nearest even from the FP32 value
   const uint32_t u = __float_as_uint((float)v);
   const uint32_t lsb = (u >> 16) & 1u;
   return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
+int64_t tri_quad_size(int n) { return (int64_t)n * (n + 2) / 2; }
 template <typename TM>
-__global__ void tri_square_kernel(const double* __restrict__ packed, int n, int64_t nmat, TM* __restrict__ out) {
+__global__ void tri_quad_kernel(const double* __restrict__ packed, int n, int64_t nmat, TM* __restrict__ out) {
+  const int64_t per = (int64_t)n * (n + 2) / 2;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nn = (int64_t)n * n;
-  if (g >= nmat * nn) return;
-  const int64_t u = g / nn;
-  const int a = (int)((g - u * nn) / n), b = (int)(g - u * nn - (int64_t)a * n);
+  if (g >= nmat * per) return;
+  const int64_t u = g / per;
+  const int e = (int)(g - u * per), qd = e >> 2, ab = e & 3;
+  int m = 0;  // quad (m, p) with m(m+1)/2 <= qd < (m+1)(m+2)/2
+  while ((m + 1) * (m + 2) / 2 <= qd) ++m;
+  const int p = qd - m * (m + 1) / 2;
+  const int a = 2 * m + (ab >> 1), b = 2 * p + (ab & 1);
   const double* pk = packed + u * ((int64_t)n * (n + 1) / 2);
-  const double x = b <= a ? pk[(int64_t)a * (a + 1) / 2 + b] : 0.0;   // X[a][b]
-  const double xt = a <= b ? pk[(int64_t)b * (b + 1) / 2 + a] : 0.0;  // X^T[a][b] = X[b][a]
-  TM* o = out + u * 2 * nn + (int64_t)a * n + b;
-  if constexpr (sizeof(TM) == 2) {
-    o[0] = to_bf16(x);
-    o[nn] = to_bf16(xt);
-  } else {
-    o[0] = TM(x);
-    o[nn] = TM(xt);
-  }
+  const double x = b <= a ? pk[(int64_t)a * (a + 1) / 2 + b] : 0.0;  // X[a][b]
+  if constexpr (sizeof(TM) == 2)
+    out[g] = to_bf16(x);
+  else
+    out[g] = TM(x);
 }
-int tri_square_f32(const double* packed, int n, int nmat, float* out, hipStream_t s) {
-  const int64_t tot = (int64_t)nmat * n * n;
+int tri_quad_f32(const double* packed, int n, int nmat, float* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nmat * tri_quad_size(n);
   if (tot <= 0) return SDG_OK;
-  hipLaunchKernelGGL(tri_square_kernel<float>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n, (int64_t)nmat,
+  if (n % 2) {
+    set_error("low-precision factors: odd block size");
+    return SDG_ERR_INVALID;
+  }
+  hipLaunchKernelGGL(tri_quad_kernel<float>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n, (int64_t)nmat,
                      out);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
-int tri_square_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s) {
-  const int64_t tot = (int64_t)nmat * n * n;
+int tri_quad_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nmat * tri_quad_size(n);
   if (tot <= 0) return SDG_OK;
-  hipLaunchKernelGGL(tri_square_kernel<uint16_t>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n,
+  if (n % 2) {
+    set_error("low-precision factors: odd block size");
+    return SDG_ERR_INVALID;
+  }
+  hipLaunchKernelGGL(tri_quad_kernel<uint16_t>, dim3(ceil_div(tot, 256)), dim3(256), 0, s, packed, n,
                      (int64_t)nmat, out);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
@@ -352,8 +362,8 @@ __global__ __launch_bounds__(256, (K1 == 5 ? 4 : K1 == 6 ? 3 : K1 == 7 ? 2 : 1))
 // ---------------------------------------------------------------------------
 // Factored low-precision smoother, one wavefront per work item of up to 16
 // elements: y = X r, then z = X^T y, on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32), X = L^{-1} and X^T stored as full squares in
-// FP32 or BF16, vectors in FP32.  The rows follow the pair order of the
+// (v_mfma_f32_16x16x4f32), X = L^{-1} stored once as the lower triangle of
+// 2 x 2 quads in FP32 or BF16 (layout at tri_quad_kernel), vectors in FP32.  The rows follow the pair order of the
 // FP64 kernel (lane group q holds rows 16g + 8h + 2q + s), so vectors and
 // factor rows move as pairs.  The FP32 product puts D row 4q + r in
 // component r of lane group q (checked on the GPU), so block row
@@ -367,13 +377,25 @@ __global__ __launch_bounds__(256, (K1 == 5 ? 4 : K1 == 6 ? 3 : K1 == 7 ? 2 : 1))
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ int permf(int i) { return 8 * ((i & 3) >> 1) + 2 * (i >> 2) + (i & 1); }
+// row pair (q[2s], q[2s + 1]) and column pair (q[s], q[2 + s]) of the quad q
 template <typename TM>
-__device__ __forceinline__ v2f ld_pair(const TM* p) {
+__device__ __forceinline__ v2f ld_row_pair(const TM* q, int s) {
   if constexpr (sizeof(TM) == 2) {
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(q + 2 * s);
     return v2f{__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u)};
   } else {
-    return *reinterpret_cast<const v2f*>(p);
+    return *reinterpret_cast<const v2f*>(q + 2 * s);
+  }
+}
+template <typename TM>
+__device__ __forceinline__ v2f ld_col_pair(const TM* q, int s) {
+  if constexpr (sizeof(TM) == 2) {
+    const uint2 w = *reinterpret_cast<const uint2*>(q);
+    return s ? v2f{__uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y & 0xFFFF0000u)}
+             : v2f{__uint_as_float(w.x << 16), __uint_as_float(w.y << 16)};
+  } else {
+    const v4f v = *reinterpret_cast<const v4f*>(q);
+    return s ? v2f{v.y, v.w} : v2f{v.x, v.z};
   }
 }
 
@@ -386,8 +408,8 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
   const int c = lane & 15, q = lane >> 4;
   const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
-  const TM* X = A.mat + (int64_t)uid * 2 * NB * NB;
-  const TM* XT = X + NB * NB;
+  constexpr int QS = NB * (NB + 2) / 2;
+  const TM* X = A.mat + (int64_t)uid * QS;
   const int prow = permf(c);
   const int flags = A.flags;
   // y = X r, then z = X^T y; the k-step (g, h, s) of z = X^T y takes
@@ -406,13 +428,17 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
       rb = *reinterpret_cast<const v2f*>(A.r + gsafe * NB + (kin ? k0 : 0));
       if (!(ge >= 0 && kin)) rb = v2f{0.f, 0.f};
     }
-    const TM* M = second ? XT : X;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (second ? g < t : g > t) continue;  // X is zero above, X^T below the diagonal
       const int arow = 16 * t + prow;
-      const bool ok = arow < NB && kin;
-      a[t] = ld_pair(M + (ok ? arow * NB + k0 : 0));
+      // X[arow][k0, k0 + 1]: row pair arow & 1 of quad (arow / 2, k0 / 2);
+      // X^T[arow][k0, k0 + 1] = X[k0, k0 + 1][arow]: column pair arow & 1 of
+      // quad (k0 / 2, arow / 2); quads above the diagonal are not stored
+      const int qm = second ? k0 >> 1 : arow >> 1, qp = second ? arow >> 1 : k0 >> 1;
+      const bool ok = arow < NB && kin && qp <= qm;
+      const TM* qa = X + (ok ? 4 * (qm * (qm + 1) / 2 + qp) : 0);
+      a[t] = second ? ld_col_pair(qa, arow & 1) : ld_row_pair(qa, arow & 1);
       if (!ok) a[t] = v2f{0.f, 0.f};
     }
   };
@@ -494,14 +520,138 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Factored low-precision smoother for blocks that few elements share (a
+// viscosity that varies per element, where every element has a block of its
+// own and reading the factors is the whole cost): one wavefront per work
+// item copies the item's quad-packed factor X into LDS once, with coalesced
+// 16-byte (FP32) or 8-byte (BF16) loads, widened to FP32; then, for each
+// element of the item, lane i forms row i of y = X r and of z = X^T y from
+// LDS (quad row pairs for X, quad column pairs for X^T), accumulating in
+// FP32 (even and odd terms apart, then added), and applies the same update
+// as the matrix-core kernel.  Used up to k = 4 (at k = 5, 6 the per-lane
+// triangular loops and the LDS per wavefront made it slower than the
+// matrix-core kernel on distinct blocks: 253 vs 245, 305 vs 243 us for
+// 65536 and 32768 elements).
+// ---------------------------------------------------------------------------
+template <int K1, typename TM>
+__global__ __launch_bounds__(64) void bj_stream_lp_kernel(BjArgs<TM, float> A, int nwork) {
+  constexpr int NB = 2 * K1 * K1, NP = NB / 2, QS = NB * (NB + 2) / 2, NQ = QS / 4;
+  constexpr int RJ = (NB + 63) / 64;  // rows per lane (one up to k = 4)
+  __shared__ __align__(16) float sq[QS];
+  __shared__ __align__(16) float sr[NB];
+  __shared__ __align__(16) float sy[NB];
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  if (w >= nwork) return;  // the grid has exactly nwork workgroups
+  const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  const TM* X = A.mat + (int64_t)uid * QS;
+  for (int e = lane; e < NQ; e += 64) {
+    v4f v;
+    if constexpr (sizeof(TM) == 2) {
+      const uint2 u = *reinterpret_cast<const uint2*>(X + 4 * e);
+      v = v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u), __uint_as_float(u.y << 16),
+              __uint_as_float(u.y & 0xFFFF0000u)};
+    } else {
+      v = *reinterpret_cast<const v4f*>(X + 4 * e);
+    }
+    *reinterpret_cast<v4f*>(sq + 4 * e) = v;
+  }
+  const int flags = A.flags;
+  for (int c = 0; c < cnt; ++c) {
+    const int64_t ge = A.perm[start + c];
+    const float* rr = A.r + ge * NB;
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int i = lane + 64 * j;
+      if (i < NB) sr[i] = rr[i];
+    }
+    __syncthreads();  // one wavefront: orders the LDS writes before the reads
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int i = lane + 64 * j;
+      if (i < NB) {
+        // y_i = sum_{p <= m} X[i][2p, 2p + 1] . r[2p, 2p + 1], m = i / 2
+        const int m = i >> 1;
+        const float* qr = sq + 2 * m * (m + 1) + 2 * (i & 1);
+        float a0 = 0.f, a1 = 0.f;  // even and odd columns
+#pragma unroll 4
+        for (int p = 0; p <= m; ++p) {
+          const v2f xv = *reinterpret_cast<const v2f*>(qr + 4 * p);
+          const v2f rv = *reinterpret_cast<const v2f*>(sr + 2 * p);
+          a0 = __builtin_fmaf(xv.x, rv.x, a0);
+          a1 = __builtin_fmaf(xv.y, rv.y, a1);
+        }
+        sy[i] = a0 + a1;
+      }
+    }
+    __syncthreads();
+    float zr[RJ];
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int i = lane + 64 * j;
+      zr[j] = 0.f;
+      if (i < NB) {
+        // z_i = sum_{m >= p} X[2m, 2m + 1][i] . y[2m, 2m + 1], p = i / 2
+        const int p = i >> 1, b = i & 1;
+        float a0 = 0.f, a1 = 0.f;  // even and odd rows of X
+#pragma unroll 4
+        for (int m = p; m < NP; ++m) {
+          const float* qq = sq + 2 * m * (m + 1) + 4 * p + b;
+          const v2f yv = *reinterpret_cast<const v2f*>(sy + 2 * m);
+          a0 = __builtin_fmaf(qq[0], yv.x, a0);
+          a1 = __builtin_fmaf(qq[2], yv.y, a1);
+        }
+        zr[j] = a0 + a1;
+      }
+    }
+    const double sc = A.scale[ge];
+    float* xx = A.x + ge * NB;
+    float* dd = A.d + ge * NB;
+    double ca = 0.0, cb = 1.0;
+    if (!(flags & BJ_APPLY)) {
+      const int64_t pb = ge / A.nel;
+      ca = A.ab[2 * pb];
+      cb = A.ab[2 * pb + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int i = lane + 64 * j;
+      if (i >= NB) continue;
+      const double z = double(zr[j]) * sc;
+      if (flags & BJ_APPLY) {
+        xx[i] = float(z);
+        continue;
+      }
+      double dv = cb * z;
+      if (flags & BJ_READ_D) dv += ca * double(dd[i]);
+      const double xo = (flags & (BJ_READ_X | BJ_FOLD)) ? double(xx[i]) : 0.0;
+      if (flags & BJ_FOLD) dv += ca * xo;
+      if (flags & BJ_WRITE_D) dd[i] = float(dv);
+      xx[i] = (flags & BJ_READ_X) ? float(xo + dv) : float(dv);
+    }
+    // the next element's r and y reuse the LDS rows: all lanes are done
+    // with this element's (one wavefront; the barrier orders LDS access)
+    __syncthreads();
+  }
+}
+
 template <int K1, typename TM, typename TV, bool TRI>
 static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                      hipStream_t s) {
   BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
   if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
     hipLaunchKernelGGL((bj_wave_kernel<K1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
-  else
-    hipLaunchKernelGGL((bj_wave_lp_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+  else {
+    bool streamed = false;
+    if constexpr (K1 <= 5)
+      if (P.stream) {
+        hipLaunchKernelGGL((bj_stream_lp_kernel<K1, TM>), dim3(P.nwork), dim3(64), 0, s, A, P.nwork);
+        streamed = true;
+      }
+    if (!streamed)
+      hipLaunchKernelGGL((bj_wave_lp_kernel<K1, TM>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+  }
 }
 
 template <typename TM, typename TV, bool TRI>

@@ -59,6 +59,9 @@ struct BjPlan {
   const int* perm;
   const int* work;
   const double* scale;
+  // low precision: stream the factors through LDS, one row per lane
+  // (blocks that few elements share) instead of the matrix-core products
+  int stream = 0;
 };
 // largest G for an element block of nb unknowns (one wavefront per work item)
 int bj_group_size(int nb);
@@ -75,9 +78,11 @@ int bj_tri_cheb_bf16(const BjPlan& P, const uint16_t* X, const float* r, const d
 int bj_tri_apply_f32(const BjPlan& P, const float* X, const float* r, float* z, hipStream_t s);
 int bj_tri_apply_bf16(const BjPlan& P, const uint16_t* X, const float* r, float* z, hipStream_t s);
 // Convert FP64 inverses to FP32 / BF16 storage.
-// packed FP64 factors X -> [nmat][2][n][n] squares (X, then X^T) in FP32 / BF16
-int tri_square_f32(const double* packed, int n, int nmat, float* out, hipStream_t s);
-int tri_square_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s);
+// packed FP64 factors X -> [nmat][n (n + 2) / 2] lower triangles of 2 x 2
+// quads in FP32 / BF16 (tri_quad_size(n) values per block, n even)
+int64_t tri_quad_size(int n);
+int tri_quad_f32(const double* packed, int n, int nmat, float* out, hipStream_t s);
+int tri_quad_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s);
 
 // Transfers and coarse levels (coarse_kernels.hip)
 int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s);

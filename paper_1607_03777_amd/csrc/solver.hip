@@ -525,6 +525,10 @@ int setup_blocks(sdg_problem* P) {
   SDG_TRY(to_dev(P, dwork, work.data(), work.size() * sizeof(int)));
   SDG_TRY(to_dev(P, P->scale, scale.data(), ntot * sizeof(double)));
   P->bj = BjPlan{P->NB, G, (int)(work.size() / 3), P->nel, dperm, dwork, P->scale};
+  // fewer than two elements per work item on average (a viscosity that
+  // varies per element): the factored smoother is bound by reading the
+  // factors, which the streaming kernel reads once, coalesced
+  P->bj.stream = ntot < 2 * (int64_t)P->bj.nwork;
   int* dreps = nullptr;
   int* dstat = nullptr;
   SDG_TRY(palloc_t(P, &dreps, P->nuniq));
@@ -546,14 +550,15 @@ int setup_blocks(sdg_problem* P) {
       return SDG_ERR_UNSUPPORTED;
     }
   // low precision: the inverse Cholesky factor X = L^{-1} in FP32 or BF16,
-  // as full squares X and X^T per block; the smoother applies X^T X
+  // once per block as a packed lower triangle of 2 x 2 quads; the smoother
+  // applies X^T X
   P->xpacked = packed;
   if (low && P->opt.prec_smoother == SDG_BF16) {
-    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * 2 * nbb));
-    SDG_TRY(tri_square_bf16(packed, P->NB, P->nuniq, P->binv16, P->s));
+    SDG_TRY(palloc_t(P, &P->binv16, (int64_t)P->nuniq * tri_quad_size(P->NB)));
+    SDG_TRY(tri_quad_bf16(packed, P->NB, P->nuniq, P->binv16, P->s));
   } else if (low) {
-    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * 2 * nbb));
-    SDG_TRY(tri_square_f32(packed, P->NB, P->nuniq, P->binv32, P->s));
+    SDG_TRY(palloc_t(P, &P->binv32, (int64_t)P->nuniq * tri_quad_size(P->NB)));
+    SDG_TRY(tri_quad_f32(packed, P->NB, P->nuniq, P->binv32, P->s));
   }
   return SDG_OK;
 }
@@ -2278,10 +2283,10 @@ size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int 
   b += nuniq * NB * NB * 8 + nuniq * 8;
   b += 12 * (nel * nb / 16 + nuniq + 1);  // smoother work list (16 elements per item at least)
   const bool low = opts->prec_apply == SDG_FP32 || opts->prec_smoother != SDG_FP64;
-  // low precision: the packed FP64 factor and the factor and its transpose
-  // as full squares in the storage type
-  // (BF16 factors may be replaced by FP32 ones at setup: both counted)
-  if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + 2 * NB * NB * (opts->prec_smoother == SDG_BF16 ? 2 + 4 : 4));
+  // low precision: the packed FP64 factor and the quad-packed factor in the
+  // storage type (BF16 factors may be replaced by FP32 ones at setup: both
+  // counted)
+  if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + NB * (NB + 2) / 2 * (opts->prec_smoother == SDG_BF16 ? 2 + 4 : 4));
   const bool q0 = opts->coarse_space == 1;
   if (q0) b += nb * nu * 8 * 2;  // probe vectors of A_0
   else b += nb * nel * 64 * 8;    // coarse local matrices
@@ -2536,9 +2541,8 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   // viscosity jumps of 10^6) overshoot by an order of magnitude and stall
   // the cycle: such a batch gets FP32 factors instead.
   if (P->binv16 && *std::max_element(lam.begin(), lam.end()) > BF16_LAMBDA_MAX) {
-    const int64_t nbb = (int64_t)P->NB * P->NB;
-    if ((rc = palloc_t(P, &P->binv32, (int64_t)P->nuniq * 2 * nbb)) < 0) return fail(rc);
-    if ((rc = tri_square_f32(P->xpacked, P->NB, P->nuniq, P->binv32, P->s)) < 0) return fail(rc);
+    if ((rc = palloc_t(P, &P->binv32, (int64_t)P->nuniq * tri_quad_size(P->NB))) < 0) return fail(rc);
+    if ((rc = tri_quad_f32(P->xpacked, P->NB, P->nuniq, P->binv32, P->s)) < 0) return fail(rc);
     P->binv16 = nullptr;
     if ((rc = arnoldi(P, -1, lam, nullptr)) < 0) return fail(rc);
   }

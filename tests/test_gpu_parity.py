@@ -158,23 +158,32 @@ def test_blocks_and_blockjacobi(sdg, ctx, torch, k, dedup):
 
 
 @pytest.mark.parametrize("k", [2, 4, 6])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_blockjacobi_grouped(sdg, ctx, torch, k, prec):
+@pytest.mark.parametrize("prec,field", [("fp64", "shared"), ("fp32", "shared"), ("bf16", "shared"),
+                                        ("fp64", "distinct"), ("fp32", "distinct"), ("bf16", "distinct")])
+def test_blockjacobi_grouped(sdg, ctx, torch, k, prec, field):
     """Grouped apply: one block shared by more elements than a workgroup
     takes (several work items and a ragged last one), shared across the
-    problems of a batch.  FP64: the inverse applied to rounding accuracy.
-    FP32/BF16: z = s X~^T (X~ r~) with X = L^{-1} and r rounded to the
-    storage type; checked against the FP64 inverse within the bound that
-    rounding X and r by a unit u implies, |X~^T X~ - X^T X| <= (2u + u^2)
-    |X|^T |X|, plus FP32 accumulation."""
+    problems of a batch; or (distinct) a viscosity that differs on every
+    element, so that no two elements share a block and the low-precision
+    smoother streams its factors through LDS.  FP64: the inverse applied to
+    rounding accuracy.  FP32/BF16: z = s X~^T (X~ r~) with X = L^{-1} and r
+    rounded to the storage type; checked against the FP64 inverse within
+    the bound that rounding X and r by a unit u implies,
+    |X~^T X~ - X^T X| <= (2u + u^2) |X|^T |X|, plus FP32 accumulation."""
     n, nbatch = 12, 2
     m = Mesh(n, n, k)
-    eta1 = np.ones(m.nel)
-    eta1[::7] = 30.0  # a few elements with other blocks
-    etas = np.stack([eta1, 2.5 * eta1])
+    if field == "shared":
+        eta1 = np.ones(m.nel)
+        eta1[::7] = 30.0  # a few elements with other blocks
+        etas = np.stack([eta1, 2.5 * eta1])
+    else:
+        # contrast about 4: blocks well conditioned, so BF16 factors stay
+        etas = 10.0 ** np.random.default_rng(5).uniform(-0.3, 0.3, size=(nbatch, m.nel))
     prec_s = {"fp64": sdg.FP64, "fp32": sdg.FP32, "bf16": sdg.BF16}[prec]
     P = make_problem(sdg, ctx, n, n, k, etas, prec_smoother=prec_s,
                      prec_apply=sdg.FP64 if prec == "fp64" else sdg.FP32)
+    if prec == "bf16":
+        assert sdg.sdg_problem_smoother_precision(P.h) == sdg.BF16
     rng = np.random.default_rng(11)
     r = rng.normal(size=(nbatch, m.nu))
     z = P.zeros(nbatch * m.nu)

@@ -94,8 +94,9 @@ def test_required_bytes_bounds_the_element_blocks(sdg, prec_s, width):
     """The admission figure is an upper bound: every element block counted as
     distinct (a viscosity that varies per element leaves nothing to
     deduplicate), each stored as its FP64 inverse and, in low precision, as
-    the packed FP64 factor plus the factor and its transpose as full squares
-    (the setup's allocations)."""
+    the packed FP64 factor plus the factor in the storage type as a lower
+    triangle of 2 x 2 quads, NB (NB + 2) / 2 values (the setup's
+    allocations)."""
     n, k, nbatch = 64, 5, 3
     NB = 2 * (k + 1) ** 2
     o = sdg.make_options(prec_apply=1 if prec_s else 0, prec_smoother=prec_s)
@@ -103,6 +104,6 @@ def test_required_bytes_bounds_the_element_blocks(sdg, prec_s, width):
     nblk = n * n * nbatch
     blocks = nblk * NB * NB * 8
     if prec_s:
-        blocks += nblk * (NB * (NB + 1) // 2 * 8 + 2 * NB * NB * width)
+        blocks += nblk * (NB * (NB + 1) // 2 * 8 + NB * (NB + 2) // 2 * width)
     vectors = nbatch * n * n * NB * 8 * 7  # at least the CG and cycle vectors
     assert need >= blocks + vectors
