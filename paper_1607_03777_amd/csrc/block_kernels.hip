@@ -158,6 +158,33 @@ int tri_quad_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStrea
 }
 
 
+// FP64 block inverses for the streaming smoother: the symmetric B^{-1} once,
+// as the lower triangle of 2 x 2 quads in the layout above (quad (m, p),
+// p <= m, rows 2m, 2m+1 and columns 2p, 2p+1; the diagonal quads whole).
+__global__ void sym_quad_kernel(const double* __restrict__ full, int n, int64_t nmat, double* __restrict__ out) {
+  const int64_t per = (int64_t)n * (n + 2) / 2;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nmat * per) return;
+  const int64_t u = g / per;
+  const int e = (int)(g - u * per), qd = e >> 2, ab = e & 3;
+  int m = 0;
+  while ((m + 1) * (m + 2) / 2 <= qd) ++m;
+  const int p = qd - m * (m + 1) / 2;
+  out[g] = full[u * n * n + (int64_t)(2 * m + (ab >> 1)) * n + 2 * p + (ab & 1)];
+}
+int sym_quad_f64(const double* full, int n, int nmat, double* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nmat * tri_quad_size(n);
+  if (tot <= 0) return SDG_OK;
+  if (n % 2) {
+    set_error("packed block inverses: odd block size");
+    return SDG_ERR_INVALID;
+  }
+  hipLaunchKernelGGL(sym_quad_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, s, full, n, (int64_t)nmat, out);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
+
+
 // ---------------------------------------------------------------------------
 // grouped apply
 //
@@ -636,13 +663,87 @@ __global__ __launch_bounds__(64) void bj_stream_lp_kernel(BjArgs<TM, float> A, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 smoother for blocks that few elements share (k <= 4): as the
+// streaming factored kernel above, with the symmetric inverse B^{-1} stored
+// once as lower-triangle quads (half the bytes of the full square) and one
+// product per element: lane i forms row i of z = B^{-1} r from quad row pairs
+// (columns up to its own row pair) and quad column pairs (the transposes of
+// the quads below), in FP64 with two accumulators.
+// ---------------------------------------------------------------------------
+template <int K1>
+__global__ __launch_bounds__(64) void bj_stream_f64_kernel(BjArgs<double, double> A, int nwork) {
+  constexpr int NB = 2 * K1 * K1, NP = NB / 2, QS = NB * (NB + 2) / 2;
+  static_assert(NB <= 64, "one row per lane");
+  __shared__ __align__(16) double sq[QS];
+  __shared__ __align__(16) double sr[NB];
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  if (w >= nwork) return;  // the grid has exactly nwork workgroups
+  const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  const double* B = A.mat + (int64_t)uid * QS;
+  for (int e = lane; e < QS / 2; e += 64)
+    *reinterpret_cast<v2d*>(sq + 2 * e) = *reinterpret_cast<const v2d*>(B + 2 * e);
+  const int flags = A.flags;
+  const int m = lane >> 1, a = lane & 1;
+  for (int c = 0; c < cnt; ++c) {
+    const int64_t ge = A.perm[start + c];
+    if (lane < NB) sr[lane] = A.r[ge * NB + lane];
+    __syncthreads();  // one wavefront: orders the LDS writes before the reads
+    double z = 0.0;
+    if (lane < NB) {
+      double a0 = 0.0, a1 = 0.0;  // even and odd columns
+      const double* qr = sq + 2 * m * (m + 1) + 2 * a;
+#pragma unroll 4
+      for (int p = 0; p <= m; ++p) {  // B[i][2p, 2p + 1]: row pair a of quad (m, p)
+        const v2d xv = *reinterpret_cast<const v2d*>(qr + 4 * p);
+        const v2d rv = *reinterpret_cast<const v2d*>(sr + 2 * p);
+        a0 = __builtin_fma(xv.x, rv.x, a0);
+        a1 = __builtin_fma(xv.y, rv.y, a1);
+      }
+#pragma unroll 4
+      for (int p = m + 1; p < NP; ++p) {  // B[2p, 2p + 1][i]: column pair a of quad (p, m)
+        const double* qq = sq + 2 * p * (p + 1) + 4 * m + a;
+        const v2d rv = *reinterpret_cast<const v2d*>(sr + 2 * p);
+        a0 = __builtin_fma(qq[0], rv.x, a0);
+        a1 = __builtin_fma(qq[2], rv.y, a1);
+      }
+      z = (a0 + a1) * A.scale[ge];
+    }
+    if (lane < NB) {
+      double* xx = A.x + ge * NB;
+      if (flags & BJ_APPLY) {
+        xx[lane] = z;
+      } else {
+        const int64_t pb = ge / A.nel;
+        const double ca = A.ab[2 * pb], cb = A.ab[2 * pb + 1];
+        double* dd = A.d + ge * NB;
+        double dv = cb * z;
+        if (flags & BJ_READ_D) dv += ca * dd[lane];
+        const double xo = (flags & (BJ_READ_X | BJ_FOLD)) ? xx[lane] : 0.0;
+        if (flags & BJ_FOLD) dv += ca * xo;
+        if (flags & BJ_WRITE_D) dd[lane] = dv;
+        xx[lane] = (flags & BJ_READ_X) ? xo + dv : dv;
+      }
+    }
+    __syncthreads();  // the next element's r reuses the LDS row
+  }
+}
+
 template <int K1, typename TM, typename TV, bool TRI>
 static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                      hipStream_t s) {
   BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
-  if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8)
-    hipLaunchKernelGGL((bj_wave_kernel<K1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
-  else {
+  if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8) {
+    bool streamed = false;
+    if constexpr (K1 <= 5)
+      if (P.stream) {  // mat: the quad-packed inverses (sym_quad_f64)
+        hipLaunchKernelGGL((bj_stream_f64_kernel<K1>), dim3(P.nwork), dim3(64), 0, s, A, P.nwork);
+        streamed = true;
+      }
+    if (!streamed)
+      hipLaunchKernelGGL((bj_wave_kernel<K1>), dim3((P.nwork + 3) / 4), dim3(256), 0, s, A, P.nwork);
+  } else {
     bool streamed = false;
     if constexpr (K1 <= 5)
       if (P.stream) {

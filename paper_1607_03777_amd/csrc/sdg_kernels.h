@@ -59,8 +59,9 @@ struct BjPlan {
   const int* perm;
   const int* work;
   const double* scale;
-  // low precision: stream the factors through LDS, one row per lane
-  // (blocks that few elements share) instead of the matrix-core products
+  // blocks that few elements share (k <= 4): stream the quad-packed
+  // inverses or factors through LDS, one row per lane, instead of the
+  // matrix-core products (the FP64 smoother then takes the packed inverses)
   int stream = 0;
 };
 // largest G for an element block of nb unknowns (one wavefront per work item)
@@ -81,6 +82,9 @@ int bj_tri_apply_bf16(const BjPlan& P, const uint16_t* X, const float* r, float*
 // packed FP64 factors X -> [nmat][n (n + 2) / 2] lower triangles of 2 x 2
 // quads in FP32 / BF16 (tri_quad_size(n) values per block, n even)
 int64_t tri_quad_size(int n);
+// full symmetric FP64 inverses [nmat][n][n] -> [nmat][n (n + 2) / 2] lower
+// triangles of 2 x 2 quads (the streaming FP64 smoother's operand)
+int sym_quad_f64(const double* full, int n, int nmat, double* out, hipStream_t s);
 int tri_quad_f32(const double* packed, int n, int nmat, float* out, hipStream_t s);
 int tri_quad_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s);
 

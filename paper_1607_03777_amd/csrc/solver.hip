@@ -230,6 +230,7 @@ struct sdg_problem {
   float* binv32 = nullptr;
   uint16_t* binv16 = nullptr;
   double* xpacked = nullptr;  // packed FP64 factors X = L^{-1} (low precision)
+  double* binvq = nullptr;    // quad-packed FP64 inverses (streamed smoother plans)
   std::vector<int> reps;
   // DG cycle
   double *vr = nullptr, *vd = nullptr;
@@ -526,9 +527,10 @@ int setup_blocks(sdg_problem* P) {
   SDG_TRY(to_dev(P, P->scale, scale.data(), ntot * sizeof(double)));
   P->bj = BjPlan{P->NB, G, (int)(work.size() / 3), P->nel, dperm, dwork, P->scale};
   // fewer than two elements per work item on average (a viscosity that
-  // varies per element): the factored smoother is bound by reading the
-  // factors, which the streaming kernel reads once, coalesced
-  P->bj.stream = ntot < 2 * (int64_t)P->bj.nwork;
+  // varies per element): the smoother is bound by reading the blocks, which
+  // the streaming kernels read once, coalesced, from a packed triangle
+  // (k <= 4; above, the matrix-core kernels measured faster)
+  P->bj.stream = P->k <= 4 && ntot < 2 * (int64_t)P->bj.nwork;
   int* dreps = nullptr;
   int* dstat = nullptr;
   SDG_TRY(palloc_t(P, &dreps, P->nuniq));
@@ -542,6 +544,10 @@ int setup_blocks(sdg_problem* P) {
   SDG_TRY(palloc_t(P, &P->binv, (int64_t)P->nuniq * nbb));
   SDG_TRY(sip_block_list(P->M, P->k, P->eta, dreps, P->nuniq, P->binv, P->s));
   SDG_TRY(spd_inverse(P->binv, P->NB, P->nuniq, dstat, P->s, packed));
+  if (P->bj.stream) {
+    SDG_TRY(palloc_t(P, &P->binvq, (int64_t)P->nuniq * tri_quad_size(P->NB)));
+    SDG_TRY(sym_quad_f64(P->binv, P->NB, P->nuniq, P->binvq, P->s));
+  }
   std::vector<int> st(P->nuniq);
   SDG_TRY(to_host(P, st.data(), dstat, P->nuniq * sizeof(int)));
   for (int i = 0; i < P->nuniq; ++i)
@@ -769,8 +775,14 @@ void drop_graphs(sdg_problem* P) {
 }
 double smoother_bytes(const sdg_problem* P, int flags, int w) {
   const int nvec = 2 + !!(flags & BJ_READ_X) + !!(flags & BJ_READ_D) + !!(flags & BJ_WRITE_D);
-  return nvec * vec_bytes(P, w) + elem_bytes(P, 12);  // + scale and permutation
+  double b = nvec * vec_bytes(P, w) + elem_bytes(P, 12);  // + scale and permutation
+  // streamed plans: every block read once from HBM (packed triangle)
+  if (P->bj.stream)
+    b += (double)P->nuniq * tri_quad_size(P->NB) * (P->binv16 ? 2 : w == 4 ? 4 : 8);
+  return b;
 }
+// the FP64 smoother's operand: quad-packed inverses for streamed plans
+const double* bj_inverses(const sdg_problem* P) { return P->bj.stream ? P->binvq : P->binv; }
 
 // Chebyshev coefficients: step 0 -> (0, 1/theta); step s >= 1 ->
 // (rho_s rho_{s-1}, 2 rho_s / delta) with rho_0 = 1/sigma,
@@ -836,7 +848,7 @@ int bj_flags(int s, int m, bool zero) {
 int bj_step64(sdg_problem* P, const double* r, int s, double* x, bool zero) {
   const int f = bj_flags(s, P->opt.smooth_dg, zero);
   return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, f, 8),
-                [&] { return bj_cheb_f64(P->bj, P->binv, r, ab0_step(P, s), P->vd, x, f, P->s); });
+                [&] { return bj_cheb_f64(P->bj, bj_inverses(P), r, ab0_step(P, s), P->vd, x, f, P->s); });
 }
 int bj_step32(sdg_problem* P, const float* r, int s, float* x, bool zero) {
   const int f = bj_flags(s, P->opt.smooth_dg, zero);
@@ -853,7 +865,7 @@ int bj_apply32(sdg_problem* P, const float* r, float* z) {
 }
 int bj_apply64(sdg_problem* P, const double* r, double* z) {
   return traced(P->ctx, P->s, SDG_TRACE_SMOOTHER, smoother_bytes(P, BJ_APPLY, 8),
-                [&] { return bj_apply_f64(P->bj, P->binv, r, z, P->s); });
+                [&] { return bj_apply_f64(P->bj, bj_inverses(P), r, z, P->s); });
 }
 
 int cheb_dg64(sdg_problem* P, const double* b, double* x, bool zero) {
@@ -2287,6 +2299,8 @@ size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int 
   // storage type (BF16 factors may be replaced by FP32 ones at setup: both
   // counted)
   if (low) b += nuniq * (NB * (NB + 1) / 2 * 8 + NB * (NB + 2) / 2 * (opts->prec_smoother == SDG_BF16 ? 2 + 4 : 4));
+  // quad-packed FP64 inverses of a streamed smoother plan (k <= 4)
+  if (mesh->k <= 4) b += nuniq * NB * (NB + 2) / 2 * 8;
   const bool q0 = opts->coarse_space == 1;
   if (q0) b += nb * nu * 8 * 2;  // probe vectors of A_0
   else b += nb * nel * 64 * 8;    // coarse local matrices
