@@ -413,17 +413,45 @@ int hessenberg_max_eig(const double* H, int m, int ld, double* out, hipStream_t 
 // ===========================================================================
 namespace sdg {
 
-// partial[pb][j][blk] = slice of <V_j[pb], w[pb]>; V_j at V + j * ldv
+// partial[pb][j][blk] = slice of <V_j[pb], w[pb]>; V_j at V + j * ldv.
+// PAIRS (n and ldv even, V and w 16-byte aligned): 16-byte loads of value
+// pairs, four strides unrolled so that their loads are in flight together
+// (each thread has only a few strides), even and odd values summed apart.
+template <bool PAIRS>
 __global__ __launch_bounds__(VT) void bmultidot_stage1(int64_t n, int m, const double* __restrict__ V,
                                                        int64_t ldv, const double* __restrict__ w,
                                                        double* __restrict__ part) {
   const int j = blockIdx.y % m, pb = blockIdx.y / m;
   const double* v = V + j * ldv + (int64_t)pb * n;
   const double* ww = w + (int64_t)pb * n;
+  const int64_t st = (int64_t)gridDim.x * VT;
   double s = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) s += v[g] * ww[g];
+  if constexpr (PAIRS) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2* v2p = reinterpret_cast<const v2*>(v);
+    const v2* w2p = reinterpret_cast<const v2*>(ww);
+    double s1 = 0.0;
+#pragma unroll 4
+    for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < (n >> 1); g += st) {
+      const v2 a = v2p[g], b = w2p[g];
+      s = __builtin_fma(a.x, b.x, s);
+      s1 = __builtin_fma(a.y, b.y, s1);
+    }
+    s += s1;
+  } else {
+    for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += st) s += v[g] * ww[g];
+  }
   s = block_sum(s);
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+static void launch_multidot(dim3 grid, int64_t n, int m, const double* V, int64_t ldv, const double* w, double* part,
+                            hipStream_t s) {
+  const bool pairs = n % 2 == 0 && (m == 1 || ldv % 2 == 0) && reinterpret_cast<uintptr_t>(V) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(w) % 16 == 0;
+  if (pairs)
+    hipLaunchKernelGGL(bmultidot_stage1<true>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part);
+  else
+    hipLaunchKernelGGL(bmultidot_stage1<false>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part);
 }
 
 int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* w, double* out,
@@ -435,7 +463,7 @@ int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const
   }
   int nb = red_blocks(n);
   if (nb * m * nbatch > 512 * 64) nb = std::max(1, 512 * 64 / (m * nbatch));
-  hipLaunchKernelGGL(bmultidot_stage1, dim3(nb, m * nbatch), dim3(VT), 0, s, n, m, V, ldv, w, scratch);
+  launch_multidot(dim3(nb, m * nbatch), n, m, V, ldv, w, scratch, s);
   SDG_CHECK_LAUNCH();
   hipLaunchKernelGGL(reduce_stage2, dim3(m * nbatch), dim3(VT), 0, s, nb, scratch, out);
   SDG_CHECK_LAUNCH();
@@ -453,7 +481,7 @@ int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* 
   int nb = cg_blocks(n);
   if ((int64_t)nb * nbatch > cap) nb = std::max(1, cap / nbatch);
   *nparts = nb;
-  hipLaunchKernelGGL(bmultidot_stage1, dim3(nb, nbatch), dim3(VT), 0, s, n, 1, x, (int64_t)0, y, part);
+  launch_multidot(dim3(nb, nbatch), n, 1, x, (int64_t)0, y, part, s);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

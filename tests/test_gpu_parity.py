@@ -157,7 +157,7 @@ def test_blocks_and_blockjacobi(sdg, ctx, torch, k, dedup):
     P.close()
 
 
-@pytest.mark.parametrize("k", [2, 4, 6])
+@pytest.mark.parametrize("k", [2, 3, 4, 6])
 @pytest.mark.parametrize("prec,field", [("fp64", "shared"), ("fp32", "shared"), ("bf16", "shared"),
                                         ("fp64", "distinct"), ("fp32", "distinct"), ("bf16", "distinct")])
 def test_blockjacobi_grouped(sdg, ctx, torch, k, prec, field):
