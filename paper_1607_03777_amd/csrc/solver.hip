@@ -251,6 +251,13 @@ struct sdg_problem {
   unsigned* dcount = nullptr;
   unsigned seq = 0;
   int* active = nullptr;  // device [nb]
+  // pinned staging ring of the small uploads made between launches (active
+  // flags, coefficients): a slot is reused once its copy has completed
+  static constexpr int STAGE_SLOTS = 8;
+  static constexpr size_t STAGE_BYTES = 8192;
+  char* hstage = nullptr;
+  hipEvent_t stage_ev[STAGE_SLOTS] = {};
+  int stage_next = 0;
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
   double *gV = nullptr, *gZ = nullptr, *gw = nullptr, *gt = nullptr;
   double* gcoef = nullptr;  // FGMRES coefficients on the device
@@ -1024,11 +1031,25 @@ int vs_norms(sdg_problem* P, const VSpec& S, const double* x, std::vector<double
   for (auto& v : out) v = std::sqrt(v > 0 ? v : 0.0);
   return SDG_OK;
 }
+// host -> device without waiting: the bytes are copied into a slot of the
+// pinned staging ring and the copy is queued on the problem's stream, ahead
+// of the launches that read dst (larger uploads wait, as to_dev)
+int to_dev_async(sdg_problem* P, void* dst, const void* src, size_t bytes) {
+  if (!P->hstage || bytes > sdg_problem::STAGE_BYTES) return to_dev(P, dst, src, bytes);
+  const int k = P->stage_next;
+  P->stage_next = (k + 1) % sdg_problem::STAGE_SLOTS;
+  SDG_HIP(hipEventSynchronize(P->stage_ev[k]));  // the slot's previous copy is done
+  char* slot = P->hstage + (size_t)k * sdg_problem::STAGE_BYTES;
+  std::memcpy(slot, src, bytes);
+  SDG_HIP(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, P->s));
+  SDG_HIP(hipEventRecord(P->stage_ev[k], P->s));
+  return SDG_OK;
+}
 int upload_scalars(sdg_problem* P, double* dst, const std::vector<double>& v) {
-  return to_dev(P, dst, v.data(), v.size() * sizeof(double));
+  return to_dev_async(P, dst, v.data(), v.size() * sizeof(double));
 }
 int upload_active(sdg_problem* P, const std::vector<int>& act) {
-  return to_dev(P, P->active, act.data(), act.size() * sizeof(int));
+  return to_dev_async(P, P->active, act.data(), act.size() * sizeof(int));
 }
 
 // ---------------------------------------------------------------------------
@@ -2544,6 +2565,19 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   }
   P->hseq = reinterpret_cast<unsigned*>(P->hpub + 2 * nbatch);
   *P->hseq = 0u;
+  if (hipHostMalloc((void**)&P->hstage, sdg_problem::STAGE_SLOTS * sdg_problem::STAGE_BYTES) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("pinned allocation failed");
+    return fail(SDG_ERR_NOMEM);
+  }
+  for (hipEvent_t& e : P->stage_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      set_error("event creation failed");
+      return fail(SDG_ERR_DEVICE);
+    }
+    if (hipEventRecord(e, P->s) != hipSuccess) return fail(SDG_ERR_DEVICE);
+  }
   if ((rc = palloc_t(P, &P->dcount, 1)) < 0) return fail(rc);
   SDG_HIP(hipMemsetAsync(P->dcount, 0, sizeof(unsigned), P->s));
   // Chebyshev bounds
@@ -2606,6 +2640,9 @@ void sdg_problem_destroy(sdg_problem* P) {
     for (auto& a : P->allocs) (void)hipFree(a.first);
   if (P->hsc) (void)hipHostFree(P->hsc);
   if (P->hpub) (void)hipHostFree(P->hpub);
+  for (hipEvent_t e : P->stage_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (P->hstage) (void)hipHostFree(P->hstage);
   if (sdg_ctx* c = P->ctx) {
     bool del;
     {
