@@ -207,7 +207,13 @@ struct BjArgs {
   TV* d;
   TV* x;
   int flags;
+  const int* active;  // null, or per problem: 0 = skip its elements
 };
+// element ge of the plan, or -1 for a converged problem of a batched CG
+// iteration (active[pb] == 0)
+__device__ __forceinline__ int64_t bj_elem(const int* active, int nel, int64_t ge) {
+  return ge >= 0 && active && !active[ge / nel] ? -1 : ge;
+}
 
 int bj_group_size(int nb) {
   (void)nb;
@@ -263,7 +269,7 @@ __global__ __launch_bounds__(256, (K1 == 5 ? 4 : K1 == 6 ? 3 : K1 == 7 ? 2 : 1))
   const int uid = wvalid ? A.work[3 * w] : -1;
   const int start = wvalid ? A.work[3 * w + 1] : 0, cnt = wvalid ? A.work[3 * w + 2] : 0;
   const int c = lane & 15, q = lane >> 4;
-  const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
+  const int64_t ge = bj_elem(A.active, A.nel, (c < cnt) ? A.perm[start + c] : -1);
   const int flags = A.flags;
   // operands of the update (rows 16t + 8h + 2q, +1): requested first, or,
   // with the pipelined product, right after its first k-step's loads
@@ -292,6 +298,7 @@ __global__ __launch_bounds__(256, (K1 == 5 ? 4 : K1 == 6 ? 3 : K1 == 7 ? 2 : 1))
     __syncthreads();
   }
   if (!wvalid) return;
+  if (__ballot(ge >= 0) == 0) return;  // every element skipped (after the barrier)
   const double* B = A.mat + (int64_t)uid * NB * NB;
   const bool from_lds = STAGE && uid == uid0;
   const int prow = perm16(c);
@@ -434,7 +441,8 @@ __global__ __launch_bounds__(256) void bj_wave_lp_kernel(BjArgs<TM, float> A, in
   if (w >= nwork) return;
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
   const int c = lane & 15, q = lane >> 4;
-  const int64_t ge = (c < cnt) ? A.perm[start + c] : -1;
+  const int64_t ge = bj_elem(A.active, A.nel, (c < cnt) ? A.perm[start + c] : -1);
+  if (__ballot(ge >= 0) == 0) return;  // every element skipped
   constexpr int QS = NB * (NB + 2) / 2;
   const TM* X = A.mat + (int64_t)uid * QS;
   const int prow = permf(c);
@@ -572,6 +580,11 @@ __global__ __launch_bounds__(64) void bj_stream_lp_kernel(BjArgs<TM, float> A, i
   const int w = blockIdx.x;
   if (w >= nwork) return;  // the grid has exactly nwork workgroups
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  if (A.active) {  // every element skipped: not even the factor is read
+    bool any = false;
+    for (int c = 0; c < cnt; ++c) any = any || bj_elem(A.active, A.nel, A.perm[start + c]) >= 0;
+    if (!any) return;
+  }
   const TM* X = A.mat + (int64_t)uid * QS;
   for (int e = lane; e < NQ; e += 64) {
     v4f v;
@@ -587,6 +600,7 @@ __global__ __launch_bounds__(64) void bj_stream_lp_kernel(BjArgs<TM, float> A, i
   const int flags = A.flags;
   for (int c = 0; c < cnt; ++c) {
     const int64_t ge = A.perm[start + c];
+    if (bj_elem(A.active, A.nel, ge) < 0) continue;  // the same for the whole workgroup
     const float* rr = A.r + ge * NB;
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
@@ -681,6 +695,11 @@ __global__ __launch_bounds__(64) void bj_stream_f64_kernel(BjArgs<double, double
   const int w = blockIdx.x;
   if (w >= nwork) return;  // the grid has exactly nwork workgroups
   const int uid = A.work[3 * w], start = A.work[3 * w + 1], cnt = A.work[3 * w + 2];
+  if (A.active) {  // every element skipped: not even the inverse is read
+    bool any = false;
+    for (int c = 0; c < cnt; ++c) any = any || bj_elem(A.active, A.nel, A.perm[start + c]) >= 0;
+    if (!any) return;
+  }
   const double* B = A.mat + (int64_t)uid * QS;
   for (int e = lane; e < QS / 2; e += 64)
     *reinterpret_cast<v2d*>(sq + 2 * e) = *reinterpret_cast<const v2d*>(B + 2 * e);
@@ -688,6 +707,7 @@ __global__ __launch_bounds__(64) void bj_stream_f64_kernel(BjArgs<double, double
   const int m = lane >> 1, a = lane & 1;
   for (int c = 0; c < cnt; ++c) {
     const int64_t ge = A.perm[start + c];
+    if (bj_elem(A.active, A.nel, ge) < 0) continue;  // the same for the whole workgroup
     if (lane < NB) sr[lane] = A.r[ge * NB + lane];
     __syncthreads();  // one wavefront: orders the LDS writes before the reads
     double z = 0.0;
@@ -733,7 +753,7 @@ __global__ __launch_bounds__(64) void bj_stream_f64_kernel(BjArgs<double, double
 template <int K1, typename TM, typename TV, bool TRI>
 static void launch_k(const BjPlan& P, const TM* mat, const TV* r, const double* ab, TV* d, TV* x, int flags,
                      hipStream_t s) {
-  BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags};
+  BjArgs<TM, TV> A{P.G, P.nel, P.perm, P.work, P.scale, mat, r, ab, d, x, flags, P.active};
   if constexpr (!TRI && sizeof(TM) == 8 && sizeof(TV) == 8) {
     bool streamed = false;
     if constexpr (K1 <= 5)

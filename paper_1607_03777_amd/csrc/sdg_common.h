@@ -90,6 +90,9 @@ struct MeshDev {
   int nx, ny;
   double hx, hy;
   int bc[4];  // left, right, bottom, top
+  // inside a batched CG iteration: problems with active[pb] == 0 have
+  // converged, and the operator kernels skip them (null: none skipped)
+  const int* active = nullptr;
 };
 
 }  // namespace sdg

@@ -63,6 +63,9 @@ struct BjPlan {
   // inverses or factors through LDS, one row per lane, instead of the
   // matrix-core products (the FP64 smoother then takes the packed inverses)
   int stream = 0;
+  // inside a batched CG iteration: elements of problems with active[pb] == 0
+  // are skipped (null: none)
+  const int* active = nullptr;
 };
 // largest G for an element block of nb unknowns (one wavefront per work item)
 int bj_group_size(int nb);
@@ -174,7 +177,7 @@ int cg_update2(int64_t n, int nbatch, const double* z, double* p, const double* 
 // same summation order as reduce_stage2, one launch fewer each):
 // partials of <x[pb], y[pb]>, *nparts per problem (first stage only)
 int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* part, int cap, int* nparts,
-               hipStream_t s);
+               hipStream_t s, const int* active = nullptr);
 // rz_new[pb] = sum of rzpart[pb * nparts ..]; then cg_update2
 int cg_update2_red(int64_t n, int nbatch, const double* z, double* p, const double* rzpart, int nparts,
                    double* rz_new, const double* rz_old, const int* active, hipStream_t s);

@@ -285,6 +285,8 @@ __global__ __launch_bounds__(NT, (K1 >= 7 ? 3 : 1)) void sip_tile_kernel(MeshDev
     ix0 = (blockIdx.x % ntx) * TX;
     iy0 = (blockIdx.x / ntx) * TY;
     pb = blockIdx.y;
+    // a converged problem of a batched CG iteration (the whole block)
+    if ((MODE == M_APPLY || MODE == M_RESID) && M.active && !M.active[pb]) return;
   }
   const double* eta = eta_all + pb * (int64_t)nx * ny;
   if (MODE == M_APPLY || MODE == M_RESID) {
@@ -762,6 +764,10 @@ __global__ __launch_bounds__(64, (K1 <= 5 ? 4 : 1)) void sip_wave_kernel(MeshDev
   const int tile = (int)(lt % gridDim.x);
   const int ix0 = (tile % ntx) * TX, iy0 = (tile / ntx) * TY;
   const int64_t pb = lt / gridDim.x;
+  if (M.active && !M.active[pb]) {  // a converged problem of a batched CG iteration
+    if (MODE == M_APPLY && dotp && lane == 0) dotp[pb * gridDim.x + tile] = 0.0;
+    return;
+  }
   const double* eta = eta_all + pb * (int64_t)nx * ny;
   constexpr bool RES = MODE == M_RESID || MODE == M_RESQ1;
   u += pb * vec_stride;

@@ -251,6 +251,7 @@ struct sdg_problem {
   unsigned* dcount = nullptr;
   unsigned seq = 0;
   int* active = nullptr;  // device [nb]
+  int nact_host = 0;      // ones in the last upload of `active`
   // pinned staging ring of the small uploads made between launches (active
   // flags, coefficients): a slot is reused once its copy has completed
   static constexpr int STAGE_SLOTS = 8;
@@ -645,8 +646,11 @@ int setup_coarse(sdg_problem* P) {
 }
 
 // traced launches of the hot kernels (algorithmic bytes: vectors once each)
-double vec_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * P->NB * w; }
-double elem_bytes(const sdg_problem* P, int w) { return (double)P->nel * P->nb * w; }
+// problems the traced launch works on: inside a CG iteration the converged
+// ones are skipped
+double traced_problems(const sdg_problem* P) { return P->M.active ? P->nact_host : P->nb; }
+double vec_bytes(const sdg_problem* P, int w) { return (double)P->nel * traced_problems(P) * P->NB * w; }
+double elem_bytes(const sdg_problem* P, int w) { return (double)P->nel * traced_problems(P) * w; }
 int run_sip_apply(sdg_problem* P, const double* u, double* y) {
   return traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8),
                 [&] { return sip_apply(P->M, P->k, P->nb, P->eta, u, y, P->s, P->tile[0][0]); });
@@ -697,7 +701,7 @@ int run_sip_apply_dot_parts(sdg_problem* P, const double* u, double* y, int cap,
   const int parts = sip_apply_dot_parts(P->M, P->k, P->nb);
   if (P->tile[0][0] != 0 || parts <= 0 || parts > cap) {
     SDG_TRY(run_sip_apply(P, u, y));
-    return bdot_parts(P->nu, P->nb, u, y, P->red, cap, nparts, P->s);
+    return bdot_parts(P->nu, P->nb, u, y, P->red, cap, nparts, P->s, P->M.active);
   }
   SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_APPLY, 2 * vec_bytes(P, 8) + elem_bytes(P, 8), [&] {
     return sip_apply_dot(P->M, P->k, P->nb, P->eta, u, y, P->red, cap, P->s);
@@ -785,7 +789,7 @@ double smoother_bytes(const sdg_problem* P, int flags, int w) {
   double b = nvec * vec_bytes(P, w) + elem_bytes(P, 12);  // + scale and permutation
   // streamed plans: every block read once from HBM (packed triangle)
   if (P->bj.stream)
-    b += (double)P->nuniq * tri_quad_size(P->NB) * (P->binv16 ? 2 : w == 4 ? 4 : 8);
+    b += (double)P->nuniq * tri_quad_size(P->NB) * (P->binv16 ? 2 : w == 4 ? 4 : 8) * traced_problems(P) / P->nb;
   return b;
 }
 // the FP64 smoother's operand: quad-packed inverses for streamed plans
@@ -1049,6 +1053,7 @@ int upload_scalars(sdg_problem* P, double* dst, const std::vector<double>& v) {
   return to_dev_async(P, dst, v.data(), v.size() * sizeof(double));
 }
 int upload_active(sdg_problem* P, const std::vector<int>& act) {
+  P->nact_host = (int)std::count(act.begin(), act.end(), 1);
   return to_dev_async(P, P->active, act.data(), act.size() * sizeof(int));
 }
 
@@ -1162,7 +1167,23 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
 // V-cycle z = B r, r.z, p = z + beta p, q = A p, p.q, the x/r update and
 // ||r||^2, then the copy of (p.q, ||r||^2) to the pinned mirror.  rzA holds
 // the previous r.z, rzB receives the new one.
+// While a CG iteration is issued (or captured), the operator kernels, the
+// smoother, the dot products and the updates skip the problems whose active
+// flag is 0: they have converged, their x and r stay as they are, and their
+// other vectors are not read again in this solve.
+struct CgMask {
+  sdg_problem* P;
+  explicit CgMask(sdg_problem* p) : P(p) {
+    P->M.active = P->active;
+    P->bj.active = P->active;
+  }
+  ~CgMask() {
+    P->M.active = nullptr;
+    P->bj.active = nullptr;
+  }
+};
 int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
+  const CgMask mask(P);
   const int nb = P->nb;
   const int64_t n = P->nu;
   // partial sums live in the two halves of the reduction scratch: r.z and
@@ -1171,7 +1192,7 @@ int cg_body(sdg_problem* P, double* x, double* rzA, double* rzB) {
   double* part_rr = P->red + HALF;
   SDG_TRY(vcycle(P, P->cg_r, P->cg_z));
   int nrz = 0, npq = 0, nrr = 0;
-  SDG_TRY(bdot_parts(n, nb, P->cg_r, P->cg_z, P->red, HALF, &nrz, P->s));
+  SDG_TRY(bdot_parts(n, nb, P->cg_r, P->cg_z, P->red, HALF, &nrz, P->s, P->active));
   SDG_TRY(cg_update2_red(n, nb, P->cg_z, P->cg_p, P->red, nrz, rzB, rzA, P->active, P->s));
   SDG_TRY(run_sip_apply_dot_parts(P, P->cg_p, P->cg_q, HALF, &npq));
   SDG_TRY(cg_update1_red(n, nb, P->cg_p, P->cg_q, x, P->cg_r, rzB, P->red, npq, sc(P, SC_PQ), P->active, part_rr,

@@ -420,8 +420,12 @@ namespace sdg {
 template <bool PAIRS>
 __global__ __launch_bounds__(VT) void bmultidot_stage1(int64_t n, int m, const double* __restrict__ V,
                                                        int64_t ldv, const double* __restrict__ w,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, const int* __restrict__ active) {
   const int j = blockIdx.y % m, pb = blockIdx.y / m;
+  if (active && !active[pb]) {  // a converged problem of a batched CG iteration (the whole block)
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const double* v = V + j * ldv + (int64_t)pb * n;
   const double* ww = w + (int64_t)pb * n;
   const int64_t st = (int64_t)gridDim.x * VT;
@@ -445,13 +449,13 @@ __global__ __launch_bounds__(VT) void bmultidot_stage1(int64_t n, int m, const d
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 static void launch_multidot(dim3 grid, int64_t n, int m, const double* V, int64_t ldv, const double* w, double* part,
-                            hipStream_t s) {
+                            hipStream_t s, const int* active = nullptr) {
   const bool pairs = n % 2 == 0 && (m == 1 || ldv % 2 == 0) && reinterpret_cast<uintptr_t>(V) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(w) % 16 == 0;
   if (pairs)
-    hipLaunchKernelGGL(bmultidot_stage1<true>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part);
+    hipLaunchKernelGGL(bmultidot_stage1<true>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part, active);
   else
-    hipLaunchKernelGGL(bmultidot_stage1<false>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part);
+    hipLaunchKernelGGL(bmultidot_stage1<false>, grid, dim3(VT), 0, s, n, m, V, ldv, w, part, active);
 }
 
 int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const double* w, double* out,
@@ -473,7 +477,7 @@ int bmulti_dot(int64_t n, int nbatch, int m, const double* V, int64_t ldv, const
 // first stage of <x[pb], y[pb]>: *nparts partials per problem at
 // part[pb * nparts + i] (at most cap in all)
 int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* part, int cap, int* nparts,
-               hipStream_t s) {
+               hipStream_t s, const int* active) {
   if (nbatch <= 0 || nbatch > cap) {
     set_error("reduction scratch too small for this batch");
     return SDG_ERR_INVALID;
@@ -481,7 +485,7 @@ int bdot_parts(int64_t n, int nbatch, const double* x, const double* y, double* 
   int nb = cg_blocks(n);
   if ((int64_t)nb * nbatch > cap) nb = std::max(1, cap / nbatch);
   *nparts = nb;
-  launch_multidot(dim3(nb, nbatch), n, 1, x, (int64_t)0, y, part, s);
+  launch_multidot(dim3(nb, nbatch), n, 1, x, (int64_t)0, y, part, s, active);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
@@ -715,7 +719,11 @@ __global__ __launch_bounds__(VT) void cg_update1_red_kernel(int64_t n, const dou
   const int pb = blockIdx.y;
   const double pq = block_total(npq, pqpart + (int64_t)pb * npq);
   if (blockIdx.x == 0 && threadIdx.x == 0) pq_out[pb] = pq;
-  const double a = (active[pb] && pq > 0.0) ? rz[pb] / pq : 0.0;
+  if (!active[pb]) {  // converged: x and r stay as they are (the whole block)
+    if (threadIdx.x == 0) rrpart[(int64_t)pb * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
+  const double a = pq > 0.0 ? rz[pb] / pq : 0.0;
   const int64_t off = (int64_t)pb * n;
   double s = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
