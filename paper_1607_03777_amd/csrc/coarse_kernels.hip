@@ -389,8 +389,14 @@ int stencil_diag_inv(int nx, int ny, int nbatch, const double* st, double* dinv,
 }
 
 // rc[I] = sum_{i in supp(I)} w_I(i) rf[i]
+// rc = R rf (full weighting).  With x0 non-null, also the coarse level's
+// first Chebyshev step from a zero start, fused: x0 = d0 = cb D^{-1} rc
+// (cb = ab0[2 pb + 1], the step's coefficient), as the zero-start mode of
+// hcheb_kernel computes it.
 __global__ void h_restrict_kernel(int ncx, int ncy, int nbatch, const double* __restrict__ rf,
-                                  double* __restrict__ rc) {
+                                  double* __restrict__ rc, const double* __restrict__ dinv,
+                                  const double* __restrict__ ab0, double* __restrict__ x0,
+                                  double* __restrict__ d0) {
   const int nfx = 2 * ncx, nfy = 2 * ncy;
   const int nnc = (ncx + 1) * (ncy + 1), nnf = (nfx + 1) * (nfy + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -413,6 +419,11 @@ __global__ void h_restrict_kernel(int ncx, int ncy, int nbatch, const double* __
       s += in ? t : 0.0;
     }
   rc[g] = s;
+  if (x0) {
+    const double dv = ab0[2 * pb + 1] * (dinv[g] * s);
+    d0[g] = dv;
+    x0[g] = dv;
+  }
 }
 // xf[i] += sum_{parents J} w_J(i) ec[J]
 __global__ void h_prolong_kernel(int ncx, int ncy, int nbatch, const double* __restrict__ ec,
@@ -443,9 +454,13 @@ __global__ void h_prolong_kernel(int ncx, int ncy, int nbatch, const double* __r
   xf[g] += s;
 }
 int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s) {
+  return h_restrict_first(ncx, ncy, nbatch, rf, rc, nullptr, nullptr, nullptr, nullptr, s);
+}
+int h_restrict_first(int ncx, int ncy, int nbatch, const double* rf, double* rc, const double* dinv,
+                     const double* ab0, double* x0, double* d0, hipStream_t s) {
   const int64_t n = (int64_t)nbatch * (ncx + 1) * (ncy + 1) * 2;
   hipLaunchKernelGGL(h_restrict_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, ncx, ncy, nbatch, rf,
-                     rc);
+                     rc, dinv, ab0, x0, d0);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

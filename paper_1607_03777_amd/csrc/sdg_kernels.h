@@ -105,6 +105,10 @@ int stencil_residual(int nx, int ny, int nbatch, const double* st, const double*
                      const double* x, double* r, hipStream_t s);
 int stencil_diag_inv(int nx, int ny, int nbatch, const double* st, double* dinv, hipStream_t s);
 int h_restrict(int ncx, int ncy, int nbatch, const double* rf, double* rc, hipStream_t s);
+// the same, with the coarse level's zero-start Chebyshev step fused:
+// x0 = d0 = cb D^{-1} rc (ab0: the step's coefficients, [nbatch][2])
+int h_restrict_first(int ncx, int ncy, int nbatch, const double* rf, double* rc, const double* dinv,
+                     const double* ab0, double* x0, double* d0, hipStream_t s);
 int h_prolong_add(int ncx, int ncy, int nbatch, const double* ec, double* xf, hipStream_t s);
 // Q_0 coarse space (Section 6.1.1): probe vectors and the gather of A_0's
 // stencil from A v (3 x 3 colouring of the elements), and the injection of

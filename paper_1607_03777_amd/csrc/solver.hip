@@ -902,8 +902,10 @@ int cheb_dg32(sdg_problem* P, const float* b, float* x, bool zero) {
   return SDG_OK;
 }
 
-int cheb_h(sdg_problem* P, CLevel& L, bool zero) {
-  for (int s = 0; s < P->opt.smooth_h; ++s) {
+// Chebyshev steps s0 .. smooth_h - 1 of an h-level (steps before s0 were
+// done by a fused kernel, which leaves its result in L.xalt for the swap)
+int cheb_h(sdg_problem* P, CLevel& L, bool zero, int s0 = 0) {
+  for (int s = s0; s < P->opt.smooth_h; ++s) {
     const int mode = s == 0 ? (zero ? 1 : 2) : 0;
     const double* ab = L.ab + (int64_t)s * P->nb * 2;
     SDG_TRY(hcheb_step(L.nx, L.ny, P->nb, L.st, L.dinv, L.b, L.x, L.xalt, L.d, ab, mode, P->s));
@@ -912,15 +914,30 @@ int cheb_h(sdg_problem* P, CLevel& L, bool zero) {
   return SDG_OK;
 }
 
-int hcycle(sdg_problem* P, int li) {
+// first_done: the level's first Chebyshev step (from zero) was fused into
+// the kernel that restricted its right-hand side.  The coarse level's first
+// pre-smoothing step rides on the restriction (same arithmetic, one launch
+// fewer per level; the fused step still swaps x and xalt, so every cycle
+// swaps an even number of times and captured graphs see the same buffers on
+// every replay).  (Folding the prolongation into the first post-smoothing
+// step as well, forming x + P e at the nine stencil nodes, took the
+// headline step from 289 to 333 ms: far dearer than the launch it saved.)
+int hcycle(sdg_problem* P, int li, bool first_done = false) {
   if (li >= P->tail_start)
     return traced(P->ctx, P->s, SDG_TRACE_COARSE_TAIL, 0.0, [&] { return coarse_tail(P->tail, P->s); });
   CLevel& L = P->lev[li];
   CLevel& C = P->lev[li + 1];
-  SDG_TRY(cheb_h(P, L, true));
+  const bool steps = P->opt.smooth_h > 0;
+  SDG_TRY(cheb_h(P, L, true, first_done ? 1 : 0));
   SDG_TRY(stencil_residual(L.nx, L.ny, P->nb, L.st, L.b, L.x, L.r, P->s));
-  SDG_TRY(h_restrict(C.nx, C.ny, P->nb, L.r, C.b, P->s));
-  SDG_TRY(hcycle(P, li + 1));
+  const bool fuse_c = steps && li + 1 < P->tail_start;  // the tail smooths its levels itself
+  if (fuse_c) {
+    SDG_TRY(h_restrict_first(C.nx, C.ny, P->nb, L.r, C.b, C.dinv, C.ab, C.xalt, C.d, P->s));
+    std::swap(C.x, C.xalt);
+  } else {
+    SDG_TRY(h_restrict(C.nx, C.ny, P->nb, L.r, C.b, P->s));
+  }
+  SDG_TRY(hcycle(P, li + 1, fuse_c));
   SDG_TRY(h_prolong_add(C.nx, C.ny, P->nb, C.x, L.x, P->s));
   SDG_TRY(cheb_h(P, L, false));
   return SDG_OK;
