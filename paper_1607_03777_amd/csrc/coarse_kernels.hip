@@ -27,10 +27,14 @@ __device__ __forceinline__ double pcd_coef(int i, int j, int va, int vb, double 
   return 0.25 * si * sj / cij;
 }
 
-// rc[pb][node][c] = sum over adjacent elements of P_cd^T (Q1 modes of r)
+// rc[pb][node][c] = sum over adjacent elements of P_cd^T (Q1 modes of r).
+// With x0 non-null, also the first h-level's first Chebyshev step from a
+// zero start, fused: x0 = d0 = cb D^{-1} rc (cb = ab0[2 pb + 1]).
 template <typename TV>
 __global__ void p_restrict_kernel(int nx, int ny, int k1, double hx, double hy, int nbatch,
-                                  const TV* __restrict__ r, double* __restrict__ rc) {
+                                  const TV* __restrict__ r, double* __restrict__ rc,
+                                  const double* __restrict__ dinv, const double* __restrict__ ab0,
+                                  double* __restrict__ x0, double* __restrict__ d0) {
   const int nn = (nx + 1) * (ny + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)nbatch * nn * 2) return;
@@ -59,6 +63,11 @@ __global__ void p_restrict_kernel(int nx, int ny, int k1, double hx, double hy, 
         }
     }
   rc[g] = s;
+  if (x0) {
+    const double dv = ab0[2 * pb + 1] * (dinv[g] * s);
+    d0[g] = dv;
+    x0[g] = dv;
+  }
 }
 
 // u[pb][e][c][j][i] += sum_vertices P_cd ec, i, j <= 1
@@ -86,17 +95,21 @@ __global__ void p_prolong_kernel(int nx, int ny, int k1, double hx, double hy, i
   *ue = TV(double(*ue) + s);
 }
 
-int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s) {
+int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s,
+               const FirstStep* first) {
   const int64_t n = (int64_t)nbatch * (M.nx + 1) * (M.ny + 1) * 2;
   hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
-                     k + 1, M.hx, M.hy, nbatch, r, rc);
+                     k + 1, M.hx, M.hy, nbatch, r, rc, first ? first->dinv : nullptr, first ? first->ab0 : nullptr,
+                     first ? first->x0 : nullptr, first ? first->d0 : nullptr);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
-int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s) {
+int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s,
+                   const FirstStep* first) {
   const int64_t n = (int64_t)nbatch * (M.nx + 1) * (M.ny + 1) * 2;
   hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M.nx, M.ny,
-                     k + 1, M.hx, M.hy, nbatch, r, rc);
+                     k + 1, M.hx, M.hy, nbatch, r, rc, first ? first->dinv : nullptr, first ? first->ab0 : nullptr,
+                     first ? first->x0 : nullptr, first ? first->d0 : nullptr);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }

@@ -92,9 +92,18 @@ int tri_quad_f32(const double* packed, int n, int nmat, float* out, hipStream_t 
 int tri_quad_bf16(const double* packed, int n, int nmat, uint16_t* out, hipStream_t s);
 
 // Transfers and coarse levels (coarse_kernels.hip)
-int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s);
+// the first h-level's zero-start Chebyshev step, fused into the kernel that
+// restricts its right-hand side: x0 = d0 = cb D^{-1} rc, cb = ab0[2 pb + 1]
+struct FirstStep {
+  const double* dinv;
+  const double* ab0;
+  double *x0, *d0;
+};
+int p_restrict(const MeshDev& M, int k, int nbatch, const double* r, double* rc, hipStream_t s,
+               const FirstStep* first = nullptr);
 int p_prolong_add(const MeshDev& M, int k, int nbatch, const double* ec, double* u, hipStream_t s);
-int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s);
+int p_restrict_f32(const MeshDev& M, int k, int nbatch, const float* r, double* rc, hipStream_t s,
+                   const FirstStep* first = nullptr);
 int p_prolong_add_f32(const MeshDev& M, int k, int nbatch, const double* ec, float* u, hipStream_t s);
 int coarse_stencil_from_local(int nx, int ny, int nbatch, const double* clocal, double* st,
                               hipStream_t s);

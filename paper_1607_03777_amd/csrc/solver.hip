@@ -943,6 +943,14 @@ int hcycle(sdg_problem* P, int li, bool first_done = false) {
   return SDG_OK;
 }
 
+// the operands of level 0's zero-start step when the p-restriction can do it
+// (level 0 smoothed by the per-level kernels, not by the tail)
+bool first_step(sdg_problem* P, FirstStep& fs) {
+  if (P->tail_start == 0 || P->opt.smooth_h <= 0) return false;
+  CLevel& L = P->lev[0];
+  fs = FirstStep{L.dinv, L.ab, L.xalt, L.d};
+  return true;
+}
 int vcycle64(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(cheb_dg64(P, b, x, true));
   // only the Q1 modes of the residual reach the coarse space: the operator
@@ -952,9 +960,16 @@ int vcycle64(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 8) + 17 * elem_bytes(P, 8),
                  [&] { return sip_residual_q1(P->M, P->k, P->nb, P->eta, b, x, P->vr, P->s); }));
   const int64_t nelt = (int64_t)P->nel * P->nb;
-  if (P->opt.coarse_space == 1) SDG_TRY(q0_restrict(nelt, P->vr, P->lev[0].b, P->s));
-  else SDG_TRY(p_restrict(P->M, 1, P->nb, P->vr, P->lev[0].b, P->s));
-  SDG_TRY(hcycle(P, 0));
+  bool first_done = false;
+  if (P->opt.coarse_space == 1) {
+    SDG_TRY(q0_restrict(nelt, P->vr, P->lev[0].b, P->s));
+  } else {
+    FirstStep fs;
+    first_done = first_step(P, fs);
+    SDG_TRY(p_restrict(P->M, 1, P->nb, P->vr, P->lev[0].b, P->s, first_done ? &fs : nullptr));
+  }
+  if (first_done) std::swap(P->lev[0].x, P->lev[0].xalt);
+  SDG_TRY(hcycle(P, 0, first_done));
   if (P->opt.coarse_space == 1) SDG_TRY(q0_prolong_add(nelt, P->k, P->lev[0].x, x, P->s));
   else SDG_TRY(p_prolong_add(P->M, P->k, P->nb, P->lev[0].x, x, P->s));
   SDG_TRY(cheb_dg64(P, b, x, false));
@@ -970,9 +985,16 @@ int vcycle32(sdg_problem* P, const double* b, double* x) {
   SDG_TRY(traced(P->ctx, P->s, SDG_TRACE_SIP_RESIDUAL, vec_bytes(P, 4) + 9 * elem_bytes(P, 8),
                  [&] { return sip_residual_q1_f32(P->M, P->k, P->nb, P->eta, P->fb, P->fx, P->fr, P->s); }));
   const int64_t nelt = (int64_t)P->nel * P->nb;
-  if (P->opt.coarse_space == 1) SDG_TRY(q0_restrict_f32(nelt, P->fr, P->lev[0].b, P->s));
-  else SDG_TRY(p_restrict_f32(P->M, 1, P->nb, P->fr, P->lev[0].b, P->s));
-  SDG_TRY(hcycle(P, 0));
+  bool first_done = false;
+  if (P->opt.coarse_space == 1) {
+    SDG_TRY(q0_restrict_f32(nelt, P->fr, P->lev[0].b, P->s));
+  } else {
+    FirstStep fs;
+    first_done = first_step(P, fs);
+    SDG_TRY(p_restrict_f32(P->M, 1, P->nb, P->fr, P->lev[0].b, P->s, first_done ? &fs : nullptr));
+  }
+  if (first_done) std::swap(P->lev[0].x, P->lev[0].xalt);
+  SDG_TRY(hcycle(P, 0, first_done));
   if (P->opt.coarse_space == 1) SDG_TRY(q0_prolong_add_f32(nelt, P->k, P->lev[0].x, P->fx, P->s));
   else SDG_TRY(p_prolong_add_f32(P->M, P->k, P->nb, P->lev[0].x, P->fx, P->s));
   SDG_TRY(cheb_dg32(P, P->fb, P->fx, false));
