@@ -154,6 +154,10 @@ int publish_scalars(const double* src, int n, double* host_dst, unsigned* dev_co
 int seg_sum(int64_t n, int nseg, const double* parts, double* out, hipStream_t s);
 // hs[pb] = done[pb] ? 0 : sqrt(max(sq[pb], 0))
 int norm_mask(int nb, const double* sq, const int* done, double* hs, hipStream_t s);
+// column j of the batched Arnoldi Hessenberg matrices from two Gram-Schmidt
+// passes and ||w||^2, with the stopping test (layout at the kernel)
+int arnoldi_col(int nb, int j, int m, const double* h0, const double* h1, const double* hsq, int* stop, int* ms,
+                double* H, double* hs, hipStream_t s);
 // out[j] = sum of part[j * nparts .. (j + 1) * nparts), in a fixed order
 int reduce_parts(int nparts, int nout, const double* part, double* out, hipStream_t s);
 int multi_dot(int64_t n, int m, const double* V, int64_t ldv, const double* w, double* out,

@@ -1100,6 +1100,8 @@ int upload_active(sdg_problem* P, const std::vector<int>& act) {
 // Chebyshev bounds: Arnoldi (classical Gram-Schmidt twice) on M^{-1} A for
 // every problem of the batch; level -1 = DG level, li >= 0 = CG level li
 // ---------------------------------------------------------------------------
+int vs_dots_dev(sdg_problem* P, const VSpec& S, int mj, const double* V, int64_t ldv, const double* w,
+                double* dst, double* segb);
 int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<double>* hess_out) {
   const int m = P->opt.eig_steps, nb = P->nb;
   const int64_t n = li < 0 ? P->nu : 2 * (int64_t)P->lev[li].nn;
@@ -1108,34 +1110,49 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
   S.seg[1] = {0, 0};
   S.nseg = 1;
   S.total = n * nb;
-  double *V = nullptr, *w = nullptr, *dH = nullptr, *lam = nullptr;
-  int* dms = nullptr;
+  double *V = nullptr, *w = nullptr, *dH = nullptr, *lam = nullptr, *hb = nullptr;
+  int *dms = nullptr, *dstop = nullptr;
   const int64_t nV = (int64_t)(m + 1) * S.total, nH = (int64_t)(m + 1) * m * nb;
+  // hb: the two passes' coefficients [2][nb][m], ||w||^2 [nb], divisors [nb]
+  const int64_t nhb = (int64_t)(2 * m + 2) * nb;
   auto release = [&] {
     tmp_put(P, V, nV);
     tmp_put(P, w, S.total);
     tmp_put(P, dH, nH);
     tmp_put(P, lam, nb);
     tmp_put(P, dms, nb);
+    tmp_put(P, hb, nhb);
+    tmp_put(P, dstop, nb);
   };
   if (tmp_get(P, &V, nV) < 0 || tmp_get(P, &w, S.total) < 0 || tmp_get(P, &dH, nH) < 0 ||
-      tmp_get(P, &lam, nb) < 0 || tmp_get(P, &dms, nb) < 0) {
+      tmp_get(P, &lam, nb) < 0 || tmp_get(P, &dms, nb) < 0 || tmp_get(P, &hb, nhb) < 0 ||
+      tmp_get(P, &dstop, nb) < 0) {
     release();
     set_error("allocation of the Arnoldi workspace failed");
     return SDG_ERR_NOMEM;
   }
+  double* hsq = hb + (int64_t)2 * m * nb;
+  double* hs = hsq + nb;
   const uint64_t seed = P->opt.seed + ((uint64_t)(li + 1) << 32);
   int rc = SDG_OK;
-  std::vector<double> H((size_t)nb * (m + 1) * m, 0.0);  // [pb][col j][row i], ld m+1
-  std::vector<int> ms(nb, m);
-  std::vector<char> stopped(nb, 0);
+  // The whole iteration stays on the device (coefficients, norms, the
+  // Hessenberg matrices and each problem's stopping test); the host reads
+  // the largest eigenvalues once at the end.
   do {
     for (int pb = 0; pb < nb && rc >= 0; ++pb) rc = uniform_pm1(seed, n, V + pb * n, P->s);
     if (rc < 0) break;
-    std::vector<double> nv;
-    if ((rc = vs_norms(P, S, V, nv)) < 0) break;
-    if ((rc = upload_scalars(P, sc(P, SC_BN), nv)) < 0) break;
-    if ((rc = vs_div(P, S, sc(P, SC_BN), V, V)) < 0) break;
+    const std::vector<int> ms0(nb, m);
+    if (hipMemsetAsync(dH, 0, nH * sizeof(double), P->s) != hipSuccess ||
+        hipMemsetAsync(dstop, 0, nb * sizeof(int), P->s) != hipSuccess) {
+      set_error("clearing the Arnoldi workspace failed");
+      rc = SDG_ERR_DEVICE;
+      break;
+    }
+    if ((rc = to_dev_async(P, dms, ms0.data(), nb * sizeof(int))) < 0) break;
+    // v_0 = v / ||v||
+    if ((rc = vs_dots_dev(P, S, 1, V, 0, V, hsq, nullptr)) < 0) break;
+    if ((rc = norm_mask(nb, hsq, dstop, hs, P->s)) < 0) break;
+    if ((rc = vs_div(P, S, hs, V, V)) < 0) break;
     for (int j = 0; j < m; ++j) {
       double* vj = V + (int64_t)j * S.total;
       if (li < 0 && low_precision(P)) {
@@ -1152,48 +1169,30 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
         if ((rc = stencil_apply(L.nx, L.ny, nb, L.st, vj, L.r, P->s)) < 0) break;
         if ((rc = vec_mul(S.total, L.dinv, L.r, w, P->s)) < 0) break;
       }
-      std::vector<double> h((size_t)nb * (j + 1), 0.0), part;
+      // classical Gram-Schmidt twice, then column j of H and the next basis
+      // vector (zero for a problem that has stopped)
+      const int mj = j + 1;
       for (int pass = 0; pass < 2 && rc >= 0; ++pass) {
-        if ((rc = vs_dots(P, S, j + 1, V, S.total, w, part)) < 0) break;
-        if ((rc = upload_scalars(P, sc_h(P), part)) < 0) break;
-        if ((rc = vs_axpy(P, S, j + 1, V, S.total, sc_h(P), w)) < 0) break;
-        for (size_t i = 0; i < h.size(); ++i) h[i] += part[i];
+        double* hp = hb + (int64_t)pass * m * nb;
+        if ((rc = vs_dots_dev(P, S, mj, V, S.total, w, hp, nullptr)) < 0) break;
+        rc = vs_axpy(P, S, mj, V, S.total, hp, w);
       }
       if (rc < 0) break;
-      std::vector<double> hn;
-      if ((rc = vs_norms(P, S, w, hn)) < 0) break;
-      for (int pb = 0; pb < nb; ++pb) {
-        if (stopped[pb]) {
-          hn[pb] = 0.0;
-          continue;
-        }
-        double* col = H.data() + ((size_t)pb * m + j) * (m + 1);
-        for (int i = 0; i <= j; ++i) col[i] = h[(size_t)pb * (j + 1) + i];
-        col[j + 1] = hn[pb];
-        if (hn[pb] <= 1e-14 * std::fabs(h[(size_t)pb * (j + 1) + j])) {
-          ms[pb] = j + 1;
-          stopped[pb] = 1;
-          hn[pb] = 0.0;
-        }
-      }
-      if ((rc = upload_scalars(P, sc(P, SC_BN), hn)) < 0) break;
-      if ((rc = vs_div(P, S, sc(P, SC_BN), w, V + (int64_t)(j + 1) * S.total)) < 0) break;
+      if ((rc = vs_dots_dev(P, S, 1, w, 0, w, hsq, nullptr)) < 0) break;
+      if ((rc = arnoldi_col(nb, j, m, hb, hb + (int64_t)m * nb, hsq, dstop, dms, dH, hs, P->s)) < 0) break;
+      if ((rc = vs_div(P, S, hs, w, V + (int64_t)(j + 1) * S.total)) < 0) break;
     }
     if (rc < 0) break;
-    if (hipMemcpyAsync(dH, H.data(), H.size() * sizeof(double), hipMemcpyHostToDevice, P->s) != hipSuccess ||
-        hipMemcpyAsync(dms, ms.data(), nb * sizeof(int), hipMemcpyHostToDevice, P->s) != hipSuccess) {
-      set_error("copy of the Hessenberg matrices failed");
-      rc = SDG_ERR_DEVICE;
-      break;
-    }
     if ((rc = bhessenberg_max_eig(nb, dH, dms, m + 1, (int64_t)(m + 1) * m, lam, P->s)) < 0) break;
     lambda.resize(nb);
     if ((rc = read_dev(P, lam, nb, lambda.data())) < 0) break;
+    if (hess_out) {
+      hess_out->resize((size_t)nH);
+      if ((rc = read_dev(P, dH, (int)nH, hess_out->data())) < 0) break;
+    }
   } while (0);
   release();  // synchronises the stream first
-  if (rc < 0) return rc;
-  if (hess_out) *hess_out = H;
-  return SDG_OK;
+  return rc < 0 ? rc : SDG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2408,6 +2407,7 @@ size_t required_bytes_blocks(const sdg_mesh* mesh, const sdg_options* opts, int 
   if (stokes || opts->viscous_krylov >= 1) b += nb * ((2 * (int64_t)opts->restart + 2) * n + nu) * 8;
   if (stokes && opts->viscous_krylov == 2) b += nb * (2 * (int64_t)opts->restart + 2) * nu * 8;  // inner GCR
   b += nb * (int64_t)(opts->eig_steps + 2) * std::max<int64_t>(nu, 1) * 8;  // transient Arnoldi
+  b += nb * (int64_t)(2 * opts->eig_steps + 2) * 8 + nb * 4;  // its coefficients and stopping flags
   if (opts->refine) b += nb * 3 * n * 8;  // low part of the iterate, refinement residual and correction
   return b;
 }

@@ -152,6 +152,44 @@ __global__ void norm_mask_kernel(int nb, const double* __restrict__ sq, const in
   const double v = sq[pb];
   hs[pb] = done[pb] ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
 }
+// Column j of every problem's Arnoldi Hessenberg matrix (H: [pb][column]
+// [row], leading dimension m + 1), from the two Gram-Schmidt passes'
+// coefficients h0, h1 ([pb][i], i <= j) and ||w||^2 after them (hsq): rows
+// 0..j take (0 + h0) + h1 and row j + 1 takes ||w||.  A problem stops at the
+// first j where ||w|| <= 1e-14 |H[j][j]| (ms[pb] = j + 1, later columns stay
+// zero); hs receives the divisor of the next basis vector, 0 for a stopped
+// problem (its basis vector becomes zero).
+__global__ void arnoldi_col_kernel(int nb, int j, int m, const double* __restrict__ h0,
+                                   const double* __restrict__ h1, const double* __restrict__ hsq,
+                                   int* __restrict__ stop, int* __restrict__ ms, double* __restrict__ H,
+                                   double* __restrict__ hs) {
+  const int pb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pb >= nb) return;
+  if (stop[pb]) {
+    hs[pb] = 0.0;
+    return;
+  }
+  const int mj = j + 1;
+  double* col = H + ((int64_t)pb * m + j) * (m + 1);
+  for (int i = 0; i <= j; ++i) col[i] = (0.0 + h0[(int64_t)pb * mj + i]) + h1[(int64_t)pb * mj + i];
+  const double v = hsq[pb];
+  const double hn = sqrt(v > 0.0 ? v : 0.0);
+  col[j + 1] = hn;
+  if (hn <= 1e-14 * fabs(col[j])) {
+    ms[pb] = j + 1;
+    stop[pb] = 1;
+    hs[pb] = 0.0;
+  } else {
+    hs[pb] = hn;
+  }
+}
+int arnoldi_col(int nb, int j, int m, const double* h0, const double* h1, const double* hsq, int* stop, int* ms,
+                double* H, double* hs, hipStream_t s) {
+  hipLaunchKernelGGL(arnoldi_col_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, s, nb, j, m, h0, h1, hsq, stop, ms,
+                     H, hs);
+  SDG_CHECK_LAUNCH();
+  return SDG_OK;
+}
 int norm_mask(int nb, const double* sq, const int* done, double* hs, hipStream_t s) {
   hipLaunchKernelGGL(norm_mask_kernel, dim3(ceil_div(nb, 256)), dim3(256), 0, s, nb, sq, done, hs);
   SDG_CHECK_LAUNCH();
