@@ -169,7 +169,8 @@ int multi_axpy(int64_t n, int m, const double* V, int64_t ldv, const double* h, 
 int multi_combine(int64_t n, int m, const double* V, int64_t ldv, const double* h, double* y,
                   hipStream_t s);
 int dot(int64_t n, const double* x, const double* y, double* out, double* scratch, hipStream_t s);
-int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s);
+// reps consecutive copies of the same n values
+int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s, int reps = 1);
 int d2f(int64_t n, const double* x, float* y, hipStream_t s);
 int f2d(int64_t n, const float* x, double* y, hipStream_t s);
 int pressure_project(int64_t nel, int np, double* p, double* scratch, hipStream_t s);

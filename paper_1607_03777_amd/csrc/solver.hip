@@ -270,6 +270,12 @@ struct sdg_problem {
   std::vector<int> inner_total, inner_max;
   // tile shape of the SIP kernels: [apply, residual][FP64, FP32]
   int tile[2][2] = {{0, 0}, {0, 0}};
+  // the dense inverse of the coarsest level runs on a side stream beside the
+  // eigenvalue estimates: ds_ev = {fork, join}; dense_stat: its flags of
+  // positive definiteness, checked when setup joins it
+  hipStream_t ds = nullptr;
+  hipEvent_t ds_ev[2] = {nullptr, nullptr};
+  int* dense_stat = nullptr;
   // captured CG iteration (two graphs: the roles of the two r.z slots alternate)
   hipStream_t gs = nullptr;  // private stream used only to capture
   hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
@@ -579,6 +585,22 @@ int setup_blocks(sdg_problem* P) {
 
 int q0_stencil(sdg_problem* P, double* st);
 
+// the problem's stream waits for the coarsest level's inverse, whose flags
+// are then checked
+int join_dense(sdg_problem* P) {
+  if (!P->dense_stat) return SDG_OK;
+  SDG_HIP(hipStreamWaitEvent(P->s, P->ds_ev[1], 0));
+  std::vector<int> st(P->nb);
+  SDG_TRY(to_host(P, st.data(), P->dense_stat, P->nb * sizeof(int)));
+  P->dense_stat = nullptr;
+  for (int i = 0; i < P->nb; ++i)
+    if (st[i]) {
+      set_error("coarsest operator is not positive definite (a rigid motion is not restrained)");
+      return SDG_ERR_UNSUPPORTED;
+    }
+  return SDG_OK;
+}
+
 int setup_coarse(sdg_problem* P) {
   const int nx = P->mesh.nx, ny = P->mesh.ny, nb = P->nb;
   const bool q0 = P->opt.coarse_space == 1;
@@ -619,14 +641,17 @@ int setup_coarse(sdg_problem* P) {
       SDG_TRY(palloc_t(P, &L.dense, (int64_t)n2 * n2 * nb));
       SDG_TRY(palloc_t(P, &dstat, nb));
       SDG_TRY(stencil_to_dense(cx, cy, nb, L.st, L.dense, P->s));
-      SDG_TRY(spd_inverse(L.dense, n2, nb, dstat, P->s));
-      std::vector<int> st(nb);
-      SDG_TRY(to_host(P, st.data(), dstat, nb * sizeof(int)));
-      for (int i = 0; i < nb; ++i)
-        if (st[i]) {
-          set_error("coarsest operator is not positive definite (a rigid motion is not restrained)");
-          return SDG_ERR_UNSUPPORTED;
-        }
+      // one workgroup per problem (about 4 ms for 16 problems of 9 x 9
+      // nodes): on the side stream it overlaps the eigenvalue estimates,
+      // which do not read it; join_dense ends setup with it
+      if (!P->ds) SDG_HIP(hipStreamCreateWithFlags(&P->ds, hipStreamNonBlocking));
+      for (hipEvent_t& e : P->ds_ev)
+        if (!e) SDG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      SDG_HIP(hipEventRecord(P->ds_ev[0], P->s));
+      SDG_HIP(hipStreamWaitEvent(P->ds, P->ds_ev[0], 0));
+      SDG_TRY(spd_inverse(L.dense, n2, nb, dstat, P->ds));
+      SDG_HIP(hipEventRecord(P->ds_ev[1], P->ds));
+      P->dense_stat = dstat;
     } else {
       SDG_TRY(palloc_t(P, &L.dinv, nv));
       SDG_TRY(stencil_diag_inv(cx, cy, nb, L.st, L.dinv, P->s));
@@ -1139,8 +1164,8 @@ int arnoldi(sdg_problem* P, int li, std::vector<double>& lambda, std::vector<dou
   // Hessenberg matrices and each problem's stopping test); the host reads
   // the largest eigenvalues once at the end.
   do {
-    for (int pb = 0; pb < nb && rc >= 0; ++pb) rc = uniform_pm1(seed, n, V + pb * n, P->s);
-    if (rc < 0) break;
+    // every problem starts from the same vector
+    if ((rc = uniform_pm1(seed, n, V, P->s, nb)) < 0) break;
     const std::vector<int> ms0(nb, m);
     if (hipMemsetAsync(dH, 0, nH * sizeof(double), P->s) != hipSuccess ||
         hipMemsetAsync(dstop, 0, nb * sizeof(int), P->s) != hipSuccess) {
@@ -2671,6 +2696,7 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
       L.lmax[pb] = o.cheb_hi * lam[pb];
     }
   }
+  if ((rc = join_dense(P)) < 0) return fail(rc);
   if ((rc = upload_cheb(P)) < 0) return fail(rc);
   if (hipStreamSynchronize(P->s) != hipSuccess) {
     (void)hipGetLastError();
@@ -2690,6 +2716,12 @@ int sdg_problem_create(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* op
 void sdg_problem_destroy(sdg_problem* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->s);
+  if (P->ds) {  // a setup that failed before joining the side stream
+    (void)hipStreamSynchronize(P->ds);
+    (void)hipStreamDestroy(P->ds);
+  }
+  for (hipEvent_t e : P->ds_ev)
+    if (e) (void)hipEventDestroy(e);
   drop_graphs(P);
   if (P->ctx) comb_drop(P->ctx, P);
   if (P->gs) (void)hipStreamDestroy(P->gs);

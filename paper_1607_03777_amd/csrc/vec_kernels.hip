@@ -258,17 +258,22 @@ int multi_combine(int64_t n, int m, const double* V, int64_t ldv, const double* 
 // ---------------------------------------------------------------------------
 // SplitMix64 in counter form: z_i = mix(seed + (i+1) * 0x9E3779B97F4A7C15)
 // ---------------------------------------------------------------------------
-__global__ void splitmix_kernel(int64_t n, uint64_t seed, double* __restrict__ out) {
-  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
+// entry g of the sequence: the g-th output of SplitMix64 started at seed,
+// mapped to [-1, 1); out holds reps copies of the first n entries
+__global__ void splitmix_kernel(int64_t tot, int64_t n, uint64_t seed, double* __restrict__ out) {
+  for (int64_t q = (int64_t)blockIdx.x * VT + threadIdx.x; q < tot; q += (int64_t)gridDim.x * VT) {
+    const int64_t g = q % n;
     uint64_t z = seed + (uint64_t)(g + 1) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z = z ^ (z >> 31);
-    out[g] = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    out[q] = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
   }
 }
-int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s) {
-  VLAUNCH(splitmix_kernel, n, seed, out);
+int uniform_pm1(uint64_t seed, int64_t n, double* out, hipStream_t s, int reps) {
+  if (n <= 0 || reps <= 0) return SDG_OK;
+  const int64_t tot = n * reps;
+  VLAUNCH(splitmix_kernel, tot, n, seed, out);
   return SDG_OK;
 }
 
