@@ -136,6 +136,8 @@ int dense_matvec(int n, int nbatch, const double* A, const double* x, double* y,
 
 // Vector kernels (vec_kernels.hip)
 int vec_copy(int64_t n, const double* x, double* y, hipStream_t s);
+// y[i rep + j] = x[i] for j < rep (rep copies of every value, in place order)
+int vec_expand(int64_t n, int rep, const double* x, double* y, hipStream_t s);
 int vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y = a x
 int vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);        // y += a x
 int vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);  // y = a x + b y

@@ -493,6 +493,8 @@ int setup_blocks(sdg_problem* P) {
   std::vector<double> scale(ntot);
   P->reps.clear();
   std::unordered_map<BlockKey, int, BlockKeyHash> map;
+  BlockKey prev_key{};
+  int prev_id = -1;
   for (int64_t ge = 0; ge < ntot; ++ge) {
     const int64_t pb = ge / nel;
     const int e = (int)(ge - pb * nel);
@@ -500,7 +502,9 @@ int setup_blocks(sdg_problem* P) {
     const double ee = et[e];
     const BlockKey key = block_key(P->mesh, et, e);
     int id;
-    if (P->opt.dedup) {
+    if (P->opt.dedup && ge > 0 && key == prev_key) {
+      id = prev_id;  // neighbouring elements mostly share a block: no hashing
+    } else if (P->opt.dedup) {
       auto it = map.find(key);
       if (it == map.end()) {
         id = (int)P->reps.size();
@@ -515,6 +519,8 @@ int setup_blocks(sdg_problem* P) {
     }
     ids[ge] = id;
     scale[ge] = P->eta_host[P->reps[id]] / ee;
+    prev_key = key;
+    prev_id = id;
   }
   P->nuniq = (int)P->reps.size();
   // group the elements by block (counting sort, element order kept inside
@@ -2621,16 +2627,17 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
                 std::to_string(e / P->nel) + ")");
       return fail(SDG_ERR_INVALID);
     }
-  if ((rc = to_dev(P, P->eta, P->eta_host.data(), ntot * sizeof(double))) < 0) return fail(rc);
-  {
-    std::vector<double> ep((size_t)P->np * nbatch);
-    for (int64_t ge = 0; ge < ntot; ++ge)
-      for (int m = 0; m < P->NPE; ++m) ep[(size_t)ge * P->NPE + m] = P->eta_host[ge];
-    if ((rc = palloc_t(P, &P->etap, (int64_t)ep.size())) < 0) return fail(rc);
-    if ((rc = to_dev(P, P->etap, ep.data(), ep.size() * sizeof(double))) < 0) return fail(rc);
-  }
+  // the viscosity per element and per pressure mode, copied and expanded on
+  // the device
+  if ((rc = vec_copy(ntot, eta_dev, P->eta, P->s)) < 0) return fail(rc);
+  if ((rc = palloc_t(P, &P->etap, (int64_t)P->np * nbatch)) < 0) return fail(rc);
+  if ((rc = vec_expand(ntot, P->NPE, P->eta, P->etap, P->s)) < 0) return fail(rc);
+  // the Q_1 hierarchy does not read the blocks: its kernels run while the
+  // host groups the elements by block
+  const bool coarse_first = o.coarse_space == 0;
+  if (coarse_first && (rc = setup_coarse(P)) < 0) return fail(rc);
   if ((rc = setup_blocks(P)) < 0) return fail(rc);
-  if ((rc = setup_coarse(P)) < 0) return fail(rc);
+  if (!coarse_first && (rc = setup_coarse(P)) < 0) return fail(rc);
   const int64_t U = P->nu * nbatch;
   for (double** v : {&P->vr, &P->vd, &P->cg_r, &P->cg_z, &P->cg_p, &P->cg_q, &P->cg_x})
     if ((rc = palloc_t(P, v, U)) < 0) return fail(rc);

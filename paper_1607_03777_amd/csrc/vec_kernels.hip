@@ -57,6 +57,15 @@ static inline int grid_for(int64_t n) {
   } while (0)
 
 int vec_copy(int64_t n, const double* x, double* y, hipStream_t s) { VLAUNCH(copy_kernel, n, x, y); return SDG_OK; }
+// y[i rep + j] = x[i], j < rep
+__global__ void expand_kernel(int64_t tot, int rep, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < tot; g += (int64_t)gridDim.x * VT) y[g] = x[g / rep];
+}
+int vec_expand(int64_t n, int rep, const double* x, double* y, hipStream_t s) {
+  const int64_t tot = n * rep;
+  VLAUNCH(expand_kernel, tot, rep, x, y);
+  return SDG_OK;
+}
 int vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) { VLAUNCH(scale_copy_kernel, n, a, x, y); return SDG_OK; }
 int vec_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) { VLAUNCH(axpy_kernel, n, a, x, y); return SDG_OK; }
 int vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) { VLAUNCH(axpby_kernel, n, a, x, b, y); return SDG_OK; }
