@@ -2015,7 +2015,7 @@ int fgmres(sdg_problem* P, const VSpec& S, const double* b_in, double* x, double
       if (done_changed) {
         std::vector<int> di(nb);
         for (int pb = 0; pb < nb; ++pb) di[pb] = done[pb] ? 1 : 0;
-        SDG_TRY(to_dev(P, P->gdone, di.data(), nb * sizeof(int)));
+        SDG_TRY(to_dev_async(P, P->gdone, di.data(), nb * sizeof(int)));
         done_changed = false;
       }
       SDG_TRY(vs_dots_dev(P, S, 1, w, 0, w, hsq, segb));
@@ -2203,7 +2203,7 @@ int gcr(sdg_problem* P, const VSpec& S, const GcrWork& W, const double* b_in, do
       di[pb] = act[pb] ? 0 : 1;
       est_conv[pb] = 0;
     }
-    SDG_TRY(to_dev(P, W.done, di.data(), nb * sizeof(int)));
+    SDG_TRY(to_dev_async(P, W.done, di.data(), nb * sizeof(int)));
     bool all_done = false;
     for (int j = 0; j < m && !all_done && total < maxit; ++j) {
       double* pj = W.Pd + (int64_t)j * ldv;
@@ -2250,7 +2250,7 @@ int gcr(sdg_problem* P, const VSpec& S, const GcrWork& W, const double* b_in, do
         }
         all_done = all_done && di[pb];
       }
-      if (changed) SDG_TRY(to_dev(P, W.done, di.data(), nb * sizeof(int)));
+      if (changed) SDG_TRY(to_dev_async(P, W.done, di.data(), nb * sizeof(int)));
     }
     if (xlo) SDG_TRY(dd_accumulate(S.total, W.c, x, xlo, P->s));
     // true residual, the next cycle's start
