@@ -244,6 +244,7 @@ struct sdg_problem {
   double* red = nullptr;
   double* dsc = nullptr;  // device scalars (see SC_* offsets)
   double* hsc = nullptr;  // pinned host mirror
+  int64_t nsc = 0;        // its size in doubles (that of dsc)
   // published CG scalars: pinned copy, sequence number written by the
   // device after them, the device-side counter and the host's count
   double* hpub = nullptr;
@@ -433,6 +434,7 @@ int wait_published(sdg_problem* P, unsigned seq, int n, double* out) {
   return SDG_OK;
 }
 int read_dev(sdg_problem* P, const double* src, int n, double* out) {
+  if (n > P->nsc) return to_host(P, out, src, (size_t)n * sizeof(double));  // beyond the pinned mirror
   SDG_HIP(hipMemcpyAsync(P->hsc, src, n * sizeof(double), hipMemcpyDeviceToHost, P->s));
   SDG_HIP(hipStreamSynchronize(P->s));
   std::memcpy(out, P->hsc, n * sizeof(double));
@@ -2648,6 +2650,7 @@ int sdg_problem_create_batch(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_optio
   if ((rc = palloc_t(P, &P->red, RED_SCRATCH)) < 0) return fail(rc);
   const int64_t nsc = (int64_t)(SC_COUNT_FIXED + std::max(o.restart, o.eig_steps) + 4) * nbatch * 2;
   if ((rc = palloc_t(P, &P->dsc, nsc)) < 0) return fail(rc);
+  P->nsc = nsc;
   if ((rc = palloc_t(P, &P->active, nbatch)) < 0) return fail(rc);
   if (hipHostMalloc((void**)&P->hsc, nsc * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&P->hpub, (2 * nbatch + 2) * sizeof(double)) != hipSuccess) {

@@ -265,6 +265,41 @@ def test_eig_estimates_parity(sdg, ctx, torch):
     P.close()
 
 
+# The batched Arnoldi of every smoothed level (classical Gram-Schmidt twice,
+# coefficients, Hessenberg columns and the stopping test on the device)
+# against the oracle's Arnoldi (modified Gram-Schmidt; the same Hessenberg
+# matrix in exact arithmetic) problem by problem.  A 1 x 1 mesh at k = 1 has
+# 8 velocity unknowns, fewer than the 10 steps: its Krylov space runs out and
+# both stop at the same step.
+@pytest.mark.parametrize("nx,k,bc", [(8, 2, (NAVIER, NEUMANN, DIRICHLET, NAVIER)), (1, 1, (DIRICHLET,) * 4)])
+def test_eig_estimate_hessenberg_batched(sdg, ctx, torch, nx, k, bc):
+    nb, seed, steps = 3, 91, 10
+    etas = [rand_eta(nx * nx, 40 + i, 3) for i in range(nb)]
+    m = Mesh(nx, nx, k, bc=bc)
+    P = make_problem(sdg, ctx, nx, nx, k, np.stack(etas), bc, coarsest_n=2, seed=seed)
+    nlev = sdg.sdg_problem_levels(P.h)
+    for level in range(nlev):
+        if level > 0 and level == nlev - 1:
+            break  # the coarsest level has no smoother
+        print(f"[case] level {level}", flush=True)
+        lam, Hg = sdg.sdg_eig_estimate(P.h, level, steps)
+        for pb in range(nb):
+            Ho = Hierarchy(m, etas[pb], coarsest_n=2, seed=seed)
+            if level == 0:
+                lo, Hr = arnoldi_lambda_max(Ho.Acsr, Ho.M, seed, 0, steps)
+            else:
+                lev = Ho.levels[level - 1]
+                lo, Hr = arnoldi_lambda_max(lev.A, lev.J, seed, level, steps)
+            mm = Hr.shape[1]
+            if nx == 1:
+                assert mm < steps, mm  # the Krylov space ran out
+            scale = np.abs(Hr).max()
+            assert np.abs(Hg[pb, :mm + 1, :mm] - Hr).max() <= 1e-9 * scale, (level, pb)
+            assert np.all(Hg[pb, :, mm:] == 0.0), (level, pb)  # no column after the stop
+            assert lam[pb] == pytest.approx(lo, rel=1e-9), (level, pb)
+    P.close()
+
+
 # k = 4, 5, 6 cover the pipelined FP64 smoother's Chebyshev steps (the
 # update operands read after the product)
 @pytest.mark.parametrize("k", [2, 4, 5, 6])
