@@ -2,9 +2,9 @@
 //
 // Setup inverts each (deduplicated) diagonal block in place: Cholesky
 // factor L (right-looking), in-place triangular inverse X = L^{-1}, then
-// B^{-1} = X^T X.  One workgroup per matrix; the matrices stay in global
-// memory (L2-resident during the factorisation), so the same kernel serves
-// element blocks (n <= 98) and the dense coarsest-level operator.
+// B^{-1} = X^T X.  One workgroup per matrix; element blocks (n <= 98) are
+// factored in LDS, the larger dense coarsest-level operator in global
+// memory (L2-resident during the factorisation), by the same kernel.
 //
 // The apply is z_e = s_e * Binv[id_e] r_e, where id_e is the element's
 // unique block and s_e = eta_rep / eta_e rescales a shared block to the
@@ -23,14 +23,20 @@ constexpr int INV_NT = 256;
 
 // packed (optional): receives X = L^{-1} as a packed lower triangle
 // (row a holds X[a][0..a] at offset a(a+1)/2), n(n+1)/2 entries per matrix.
+// in_lds: the matrix is staged in LDS for the factorisation (element blocks,
+// n <= SPD_LDS_MAX); otherwise it is worked on in global memory.
 __global__ __launch_bounds__(INV_NT) void spd_inverse_kernel(double* __restrict__ mats, int n,
                                                              int* __restrict__ status,
-                                                             double* __restrict__ packed) {
-  double* A = mats + (int64_t)blockIdx.x * n * n;
-  extern __shared__ double tmp[];  // n doubles
+                                                             double* __restrict__ packed, int in_lds) {
+  double* const G = mats + (int64_t)blockIdx.x * n * n;
+  extern __shared__ double smem[];  // tmp[n], then the matrix [n][n] when in_lds
+  double* const tmp = smem;
+  double* const A = in_lds ? smem + n : G;
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
+  if (in_lds)
+    for (int idx = tid; idx < n * n; idx += INV_NT) A[idx] = G[idx];
   __syncthreads();
   // Cholesky, lower triangle, in place
   for (int k = 0; k < n; ++k) {
@@ -88,13 +94,30 @@ __global__ __launch_bounds__(INV_NT) void spd_inverse_kernel(double* __restrict_
     const int a = idx / n, b = idx % n;
     if (b < a) A[(int64_t)a * n + b] = A[(int64_t)b * n + a];
   }
+  if (in_lds) {
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += INV_NT) G[idx] = A[idx];
+  }
   if (tid == 0 && status) status[blockIdx.x] = bad;
 }
 
+// element blocks up to k = 6 (98 x 98, 77 KB) are factored in LDS: every
+// step of the factorisation then waits on LDS instead of L2 (many small
+// matrices, as with a viscosity that varies per element)
+constexpr int SPD_LDS_MAX = 98;
 int spd_inverse(double* mats, int n, int nmat, int* status, hipStream_t s, double* packed) {
   if (nmat <= 0) return SDG_OK;
-  hipLaunchKernelGGL(spd_inverse_kernel, dim3(nmat), dim3(INV_NT), n * sizeof(double), s, mats, n,
-                     status, packed);
+  // the LDS form above 64 KB needs the kernel's dynamic LDS limit raised
+  static int lds_ok = -1;  // once per process: -1 unknown, 0 no, 1 yes
+  if (lds_ok < 0) {
+    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&spd_inverse_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+    if (!lds_ok) (void)hipGetLastError();
+  }
+  const size_t lds_bytes = ((size_t)n * n + n) * sizeof(double);
+  const int in_lds = n <= SPD_LDS_MAX && (lds_bytes <= 64 * 1024 || lds_ok == 1);
+  hipLaunchKernelGGL(spd_inverse_kernel, dim3(nmat), dim3(INV_NT), in_lds ? lds_bytes : n * sizeof(double), s,
+                     mats, n, status, packed, in_lds);
   SDG_CHECK_LAUNCH();
   return SDG_OK;
 }
