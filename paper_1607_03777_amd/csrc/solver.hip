@@ -32,6 +32,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -3225,28 +3226,79 @@ int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const s
   hipStream_t s = nullptr;
   SDG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   auto bytes_of = [](int64_t cnt) { return cache_size((size_t)std::max<int64_t>(cnt, 1) * sizeof(double)); };
-  int rc = SDG_OK;
-  for (Grp& g : G) {
+  // The groups are set up from up to 8 host threads, each group on a stream
+  // of its own, so that the host parts of setup (block grouping, the reads
+  // of the eigenvalue estimates) of different groups overlap, and so do
+  // their kernels.  Every group then joins s, on which the solve runs.
+  auto setup_group = [&](Grp& g, hipStream_t gst) -> int {
     const sdg_mesh& m = meshes[g.idx[0]];
     const int nb = (int)g.idx.size();
     g.ne = (int64_t)m.nx * m.ny;
     g.nu = g.ne * 2 * (m.k + 1) * (m.k + 1);
     g.np = g.ne * m.k * m.k;
-    for (double** q : {&g.de}) rc = rc < 0 ? rc : ctx_get(ctx, bytes_of(nb * g.ne), (void**)q);
-    for (double** q : {&g.df, &g.dF, &g.du, &g.dul}) rc = rc < 0 ? rc : ctx_get(ctx, bytes_of(nb * g.nu), (void**)q);
-    if (rc >= 0) rc = ctx_get(ctx, bytes_of(nb * g.np), (void**)&g.dG);
-    for (int i = 0; i < nb && rc >= 0; ++i) {
+    int grc = SDG_OK;
+    for (double** q : {&g.de}) grc = grc < 0 ? grc : ctx_get(ctx, bytes_of(nb * g.ne), (void**)q);
+    for (double** q : {&g.df, &g.dF, &g.du, &g.dul}) grc = grc < 0 ? grc : ctx_get(ctx, bytes_of(nb * g.nu), (void**)q);
+    if (grc >= 0) grc = ctx_get(ctx, bytes_of(nb * g.np), (void**)&g.dG);
+    for (int i = 0; i < nb && grc >= 0; ++i) {
       const int r = g.idx[i];
-      if (hipMemcpyAsync(g.de + i * g.ne, eta[r], g.ne * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(g.df + i * g.nu, f[r], g.nu * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+      if (hipMemcpyAsync(g.de + i * g.ne, eta[r], g.ne * 8, hipMemcpyHostToDevice, gst) != hipSuccess ||
+          hipMemcpyAsync(g.df + i * g.nu, f[r], g.nu * 8, hipMemcpyHostToDevice, gst) != hipSuccess) {
         (void)hipGetLastError();
         set_error("host to device copy failed");
-        rc = SDG_ERR_DEVICE;
+        grc = SDG_ERR_DEVICE;
       }
     }
-    if (rc >= 0) rc = sdg_problem_create_batch(ctx, &m, &o, nb, g.de, s, &g.P);
-    if (rc >= 0) rc = rhs_assemble(g.P->M, g.P->k, nb, g.P->eta, g.df, nullptr, g.dF, g.dG, s);
-    if (rc < 0) break;
+    if (grc >= 0) grc = sdg_problem_create_batch(ctx, &m, &o, nb, g.de, gst, &g.P);
+    if (grc >= 0) grc = rhs_assemble(g.P->M, g.P->k, nb, g.P->eta, g.df, nullptr, g.dF, g.dG, gst);
+    return grc;
+  };
+  int rc = SDG_OK;
+  std::vector<hipStream_t> gstr(G.size(), nullptr);
+  for (hipStream_t& q : gstr)
+    if (rc >= 0 && hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      q = nullptr;
+      set_error("stream creation failed");
+      rc = SDG_ERR_DEVICE;
+    }
+  if (rc >= 0) {
+    std::vector<int> grc(G.size(), SDG_OK);
+    std::vector<std::string> gerr(G.size());
+    std::atomic<size_t> next{0};
+    auto work = [&] {
+      const bool dev_ok = hipSetDevice(ctx->device) == hipSuccess;
+      for (size_t gi; (gi = next.fetch_add(1)) < G.size();) {
+        grc[gi] = dev_ok ? setup_group(G[gi], gstr[gi]) : SDG_ERR_DEVICE;
+        if (grc[gi] < 0) gerr[gi] = dev_ok ? std::string(sdg_last_error()) : std::string("hipSetDevice failed");
+      }
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < std::min<size_t>(G.size(), 8); ++t) th.emplace_back(work);
+    work();
+    for (std::thread& t : th) t.join();
+    for (size_t gi = 0; gi < G.size() && rc >= 0; ++gi)
+      if (grc[gi] < 0) {
+        rc = grc[gi];
+        set_error(gerr[gi]);  // the message was set on the worker's thread
+      }
+  }
+  // s waits for every group's setup; the groups' problems then run on s
+  hipEvent_t joined = nullptr;
+  if (rc >= 0 && hipEventCreateWithFlags(&joined, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    joined = nullptr;
+    set_error("event creation failed");
+    rc = SDG_ERR_DEVICE;
+  }
+  for (size_t gi = 0; gi < G.size() && rc >= 0; ++gi) {
+    if (hipEventRecord(joined, gstr[gi]) != hipSuccess || hipStreamWaitEvent(s, joined, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("joining the groups' streams failed");
+      rc = SDG_ERR_DEVICE;
+      break;
+    }
+    G[gi].P->s = s;
   }
   // solve: CG groups in lockstep (combined graph per iteration); other
   // Krylov choices group after group
@@ -3324,6 +3376,8 @@ int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const s
     for (int v : sv)
       if (rank(v) > rank(worst)) worst = v;
   (void)hipStreamSynchronize(s);
+  for (hipStream_t q : gstr)  // a group whose setup failed may still have work there
+    if (q) (void)hipStreamSynchronize(q);
   for (Grp& g : G) {
     sdg_problem_destroy(g.P);  // drains the stream
     const int nb = (int)g.idx.size();
@@ -3332,6 +3386,9 @@ int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const s
       if (q) ctx_put(ctx, q, bytes_of(nb * g.nu));
     if (g.dG) ctx_put(ctx, g.dG, bytes_of(nb * g.np));
   }
+  if (joined) (void)hipEventDestroy(joined);
+  for (hipStream_t q : gstr)
+    if (q) (void)hipStreamDestroy(q);
   (void)hipStreamDestroy(s);
   return rc < 0 ? rc : worst;
 }
