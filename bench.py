@@ -683,6 +683,7 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=128)
     ap.add_argument("--serve-kmax", type=int, default=6)
     ap.add_argument("--serve-prec", choices=list(PRECS), default="fp32")
+    ap.add_argument("--serve-slots", type=int, default=4, help="request-server slots of the serving leg")
     ap.add_argument("--sinkers", default="64,128,256", help="mesh sizes of the six-inclusion leg ('' = skip)")
     ap.add_argument("--sweeps", choices=["default", "full", "none"], default="default",
                     help="SolCx-shaped and checkerboard sweeps (full: up to 1024^2 at every k)")
@@ -892,7 +893,8 @@ def main():
         out["batched"]["runs"].update(isolated_leg("served", {"nreq": args.batched, "slots": 4, "max_batch": 16}, 600))
     if args.serve_requests > 0:
         out["serving"] = isolated_leg("serving", {"nreq": args.serve_requests, "rate": 200.0, "prec": args.serve_prec,
-                                                  "nmax": args.serve_nmax, "kmax": args.serve_kmax, "slots": 4}, 600)
+                                                  "nmax": args.serve_nmax, "kmax": args.serve_kmax,
+                                                  "slots": args.serve_slots}, 600)
         samples = out["serving"].pop("oracle_samples", [])
         out["serving"]["oracle_sample_async"] = ([pool.apply_async(_oracle_stokes, (smp,)) for smp in samples]
                                                  if pool is not None else [])
