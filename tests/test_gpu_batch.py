@@ -68,3 +68,28 @@ def test_heterogeneous_batch_matches_alone_and_oracle(sdg, torch, prec, refine):
                 assert not np.any(lo)
     finally:
         sdg.sdg_destroy(ctx)
+
+
+def test_heterogeneous_batch_setup_error_reported(sdg, torch):
+    """The shape groups are set up on several host threads: a group whose
+    setup fails (every side traction-free: problem creation rejects the
+    rigid motions) fails the call with its own code and the message set on
+    the thread that set it up, and the context then serves a valid batch."""
+    from oracle.mesh import NEUMANN
+    ctx = sdg.sdg_create(0, 0)
+    try:
+        opts = sdg.make_options(rtol=1e-8, max_it=3000, refine=1)
+        probs = [gen.grf_problem(seed, n=n, k=k) for n, k, seed in SHAPES[:4]]
+        meshes = [sdg.make_mesh(p.nx, p.ny, p.k) for p in probs]
+        meshes[2] = sdg.make_mesh(probs[2].nx, probs[2].ny, probs[2].k, bc=(NEUMANN,) * 4)
+        print("[case] batch with one traction-free group", flush=True)
+        with pytest.raises(sdg.SDGError) as e:
+            sdg.sdg_solve_viscous_batch(ctx, meshes, opts, [p.eta for p in probs], [p.f for p in probs])
+        assert e.value.code == sdg.ERR_UNSUPPORTED
+        assert "singular (rigid motions)" in str(e.value)
+        good = [sdg.make_mesh(p.nx, p.ny, p.k) for p in probs]
+        rc, us, _, stats = sdg.sdg_solve_viscous_batch(ctx, good, opts, [p.eta for p in probs],
+                                                       [p.f for p in probs])
+        assert all(st["status"] == 0 for st in stats), stats
+    finally:
+        sdg.sdg_destroy(ctx)
