@@ -310,7 +310,10 @@ int sdg_solve_stokes(sdg_ctx* ctx, const sdg_mesh* mesh, const sdg_options* opts
  * lockstep and every iteration of every group is one replay of a combined
  * HIP graph with one parallel branch per group, so problems of different
  * sizes and orders overlap on the device in a single launch.  Other Krylov
- * choices solve the groups one after another.  stats: n entries, in request
+ * choices solve the groups one after another.  The groups are set up from
+ * up to 8 host threads that the call starts and joins (each group on a
+ * stream of its own until the solve); an error in one group's setup is
+ * returned, with its message, by the call.  stats: n entries, in request
  * order.  Returns SDG_OK when all converged, else the largest soft outcome,
  * or a negative error. */
 int sdg_solve_viscous_batch(sdg_ctx* ctx, int n, const sdg_mesh* meshes, const sdg_options* opts,
